@@ -1,0 +1,236 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds input generation only: sparse SPD test matrices in CSR form
+(full symmetric storage, sorted unique column indices per row), geometric
+partitions and right-hand sides.  It contains none of the preconditioner's
+arithmetic.  The matrices stand in for the paper's workloads (SuiteSparse SPD
+matrices and FreeFEM diffusion / elasticity problems, Section 4), which are
+not available here.
+
+Conventions
+-----------
+* A matrix is returned as ``CSR(n, rowptr int32[n+1], colind int32[nnz], val f64[nnz])``.
+* Stencils are unscaled (no h^2 factor); Dirichlet neighbours are eliminated,
+  so boundary rows keep their full diagonal.
+* Every random draw comes from ``numpy.random.default_rng(seed)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class CSR:
+    n: int
+    rowptr: np.ndarray  # int32[n+1]
+    colind: np.ndarray  # int32[nnz]
+    val: np.ndarray     # float64[nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.colind, self.rowptr), shape=(self.n, self.n))
+
+
+def _from_coo(n: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray) -> CSR:
+    """Sum duplicates, sort by (row, col) and return CSR with int32 indices."""
+    key = rows.astype(np.int64) * n + cols.astype(np.int64)
+    order = np.argsort(key, kind="stable")
+    key = key[order]
+    vals = vals[order]
+    uniq, start = np.unique(key, return_index=True)
+    summed = np.add.reduceat(vals, start) if len(vals) else vals
+    r = (uniq // n).astype(np.int64)
+    c = (uniq % n).astype(np.int32)
+    counts = np.bincount(r, minlength=n)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    if rowptr[-1] >= 2**31:
+        raise ValueError("nnz exceeds int32 range")
+    return CSR(n, rowptr.astype(np.int32), c, summed.astype(np.float64))
+
+
+# --------------------------------------------------------------------------
+# 2-D Poisson, 5-point finite differences
+# --------------------------------------------------------------------------
+def poisson2d(m: int) -> CSR:
+    """5-point Laplacian [-1,-1,4,-1,-1] on an m x m grid, node k = iy*m + ix.
+
+    Dirichlet neighbours are eliminated, so every row has diagonal 4 and the
+    matrix is integer valued.
+    """
+    n = m * m
+    iy, ix = np.divmod(np.arange(n, dtype=np.int64), m)
+    rows = [np.arange(n)]
+    cols = [np.arange(n)]
+    vals = [np.full(n, 4.0)]
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        jy, jx = iy + dy, ix + dx
+        ok = (jy >= 0) & (jy < m) & (jx >= 0) & (jx < m)
+        rows.append(np.arange(n)[ok])
+        cols.append((jy * m + jx)[ok])
+        vals.append(np.full(int(ok.sum()), -1.0))
+    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def grid2d_partition(m: int, px: int, py: int) -> np.ndarray:
+    """Geometric partition of an m x m grid into py x px blocks.
+
+    part(k) = (iy // (m/py)) * px + (ix // (m/px)) for node k = iy*m + ix.
+    """
+    iy, ix = np.divmod(np.arange(m * m, dtype=np.int64), m)
+    by = (iy * py) // m
+    bx = (ix * px) // m
+    return (by * px + bx).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# 1-D Laplacian (tiny pins)
+# --------------------------------------------------------------------------
+def laplace1d(n: int) -> CSR:
+    """Tridiagonal [-1, 2, -1] with Dirichlet ends eliminated."""
+    i = np.arange(n)
+    rows = np.concatenate([i, i[1:], i[:-1]])
+    cols = np.concatenate([i, i[1:] - 1, i[:-1] + 1])
+    vals = np.concatenate([np.full(n, 2.0), np.full(n - 1, -1.0), np.full(n - 1, -1.0)])
+    return _from_coo(n, rows, cols, vals)
+
+
+def contiguous_partition(n: int, N: int) -> np.ndarray:
+    """part(k) = floor(k*N/n): N contiguous blocks of nearly equal size."""
+    return ((np.arange(n, dtype=np.int64) * N) // n).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# Random sparse SPD matrix with an unstructured pattern
+# --------------------------------------------------------------------------
+def random_spd(n: int, avg_deg: int, seed: int, positive_offdiag: bool = False) -> CSR:
+    """Unstructured sparse SPD matrix.
+
+    A random symmetric pattern with about ``avg_deg`` off-diagonal entries per
+    row; off-diagonal values uniform in [-1, 1] (or [0, 1] when
+    ``positive_offdiag``), diagonal = 1 + row sum of |off-diagonal|, which
+    makes the matrix strictly diagonally dominant and therefore SPD.
+    """
+    rng = np.random.default_rng(seed)
+    m = n * avg_deg // 2
+    r = rng.integers(0, n, size=m)
+    c = rng.integers(0, n, size=m)
+    keep = r != c
+    r, c = r[keep], c[keep]
+    v = rng.uniform(0.0 if positive_offdiag else -1.0, 1.0, size=r.size)
+    rows = np.concatenate([r, c])
+    cols = np.concatenate([c, r])
+    vals = np.concatenate([v, v])
+    off = _from_coo(n, rows, cols, vals)
+    offrows = np.repeat(np.arange(n), np.diff(off.rowptr))
+    absrow = np.bincount(offrows, weights=np.abs(off.val), minlength=n)
+    rows_all = np.concatenate([offrows, np.arange(n)])
+    cols_all = np.concatenate([off.colind, np.arange(n)])
+    vals_all = np.concatenate([off.val, 1.0 + absrow])
+    return _from_coo(n, rows_all, cols_all, vals_all)
+
+
+# --------------------------------------------------------------------------
+# 3-D heterogeneous diffusion, 7-point finite volumes
+# --------------------------------------------------------------------------
+def diffusion3d_coefficient(m: int, seed: int, sigma: float = 2.0, channels: int = 8,
+                            contrast: float = 1e6) -> np.ndarray:
+    """Node coefficient c = exp(sigma*g), g iid N(0,1), then ``channels``
+    axis-aligned straight channels of 2x2 nodes in cross-section, running the
+    full length of the grid, set to ``contrast``.  Layout c[iz, iy, ix].
+    All draws come from one default_rng(seed) stream: first the n normals,
+    then for each channel its axis in {0,1,2} and two transverse offsets in
+    [0, m-2].
+    """
+    rng = np.random.default_rng(seed)
+    c = np.exp(sigma * rng.standard_normal((m, m, m)))
+    for _ in range(channels):
+        axis = int(rng.integers(0, 3))
+        a, b = (int(t) for t in rng.integers(0, m - 1, size=2))
+        if axis == 0:      # along x: fixed (iz, iy)
+            c[a:a + 2, b:b + 2, :] = contrast
+        elif axis == 1:    # along y: fixed (iz, ix)
+            c[a:a + 2, :, b:b + 2] = contrast
+        else:              # along z: fixed (iy, ix)
+            c[:, a:a + 2, b:b + 2] = contrast
+    return c
+
+
+def diffusion3d(m: int, seed: int, sigma: float = 2.0, channels: int = 8,
+                contrast: float = 1e6) -> CSR:
+    """7-point finite-volume diffusion on an m^3 grid, node k = (iz*m+iy)*m+ix.
+
+    Face coefficient = harmonic mean of the two node coefficients; a face on
+    the Dirichlet boundary adds the node's own coefficient to the diagonal.
+    """
+    c = diffusion3d_coefficient(m, seed, sigma, channels, contrast).reshape(-1)
+    n = m ** 3
+    k = np.arange(n, dtype=np.int64)
+    iz, rem = np.divmod(k, m * m)
+    iy, ix = np.divmod(rem, m)
+    diag = np.zeros(n)
+    rows, cols, vals = [], [], []
+    for dz, dy, dx in ((0, 0, 1), (0, 0, -1), (0, 1, 0), (0, -1, 0), (1, 0, 0), (-1, 0, 0)):
+        jz, jy, jx = iz + dz, iy + dy, ix + dx
+        ok = (jz >= 0) & (jz < m) & (jy >= 0) & (jy < m) & (jx >= 0) & (jx < m)
+        j = (jz * m + jy) * m + jx
+        w = np.where(ok, 2.0 * c * c[np.where(ok, j, 0)] / (c + c[np.where(ok, j, 0)]), c)
+        diag += w
+        rows.append(k[ok])
+        cols.append(j[ok])
+        vals.append(-w[ok])
+    rows.append(k)
+    cols.append(k)
+    vals.append(diag)
+    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+# --------------------------------------------------------------------------
+# Right-hand sides and configuration helpers
+# --------------------------------------------------------------------------
+def rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """b iid N(0,1) from default_rng(seed); shape (n,) or column-major (n, nrhs)."""
+    rng = np.random.default_rng(seed)
+    if nrhs == 1:
+        return rng.standard_normal(n)
+    return np.asfortranarray(rng.standard_normal((nrhs, n)).T)
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    A: CSR
+    part: np.ndarray | None   # None: seeded greedy graph growing (computed by the method)
+    N: int
+    overlap: int
+    tau: float                # the paper's tau: keep lambda > 1/tau
+    levels: int
+    ggg_seed: int = 0
+
+
+def config_c1() -> Config:
+    """2-D Poisson 64x64, 4x4 geometric subdomains, overlap 1, lambda > 10, 2 levels."""
+    m = 64
+    return Config("poisson2d_64x64_N16", poisson2d(m), grid2d_partition(m, 4, 4), 16, 1, 0.1, 2)
+
+
+def config_c2(m: int = 64, N: int = 256, seed: int = 0) -> Config:
+    """3-D log-normal diffusion with 1e6 channels, GGG partition, overlap 2, lambda > 50."""
+    return Config(f"diffusion3d_{m}^3_N{N}", diffusion3d(m, seed), None, N, 2, 0.02, 2, ggg_seed=0)
+
+
+def config_small3d(m: int = 16, N: int = 16, seed: int = 0) -> Config:
+    """Down-scaled version of the 3-D diffusion workload (oracle-sized)."""
+    return Config(f"diffusion3d_{m}^3_N{N}", diffusion3d(m, seed), None, N, 2, 0.02, 2, ggg_seed=0)
+
+
+def log_uniform_sizes(count: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
