@@ -1,0 +1,159 @@
+/*
+ * dd.h — C-ABI of the MI355X (gfx950) implementation of the fully algebraic
+ * multilevel overlapping Schwarz preconditioner of Al Daas & Jolivet,
+ * "A robust algebraic multilevel domain decomposition preconditioner for
+ * sparse SPD matrices" (arXiv 2109.05908).
+ *
+ * Problem (Sec. 1): solve A x = b, A sparse symmetric positive definite.
+ * Setup (Sec. 2-3): from A alone, build overlapping subdomains, local SPSD
+ * splittings (3.1)-(3.2), the thresholded local eigenproblems (3.3), the
+ * coarse space Z and coarse operator E = Z^T A Z, recursively for more
+ * levels.  Apply: the two-level additive Schwarz preconditioner (2.1).
+ *
+ * Conventions for every entry point
+ *  - Pointers documented "device" must point to GPU memory of the current
+ *    HIP device; "host" pointers to CPU memory.  Dense matrices are
+ *    column-major; multi-RHS vectors are column-major n x nrhs.
+ *  - Work is ordered on the given stream.  Calls on one handle are not
+ *    thread-safe.  The caller owns every buffer it passes; dd_setup copies
+ *    what it keeps, so A and part may be freed once it returns.
+ *  - Return value: 0 = DD_OK, < 0 = error (nothing was produced), > 0 =
+ *    warning (a result was produced, see the code).  No exception crosses
+ *    the ABI.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+#define DD_OK                   0
+#define DD_ERR_INVALID_ARG     -1  /* bad n, N, overlap, tau <= 0, levels < 2, partition id out of range, empty part */
+#define DD_ERR_NOT_SPD         -2  /* Cholesky breakdown of a local block A_ii or of E in FP64 */
+#define DD_ERR_EIG             -3  /* local eigensolver failed to converge */
+#define DD_ERR_NAN             -4  /* NaN/Inf in an input or produced by the solve */
+#define DD_ERR_OOM             -5  /* device allocation failed */
+#define DD_ERR_HIP             -6  /* other HIP runtime error */
+#define DD_ERR_INTERNAL        -7
+#define DD_WARN_MAXIT           1  /* PCG stopped at maxit before reaching rtol */
+#define DD_WARN_FULL_COARSE     2  /* tau >= 1 with Boolean D: every mode is kept (lambda >= 1 always) */
+#define DD_WARN_FP32_FALLBACK   3  /* an FP32 local factor broke down and was recomputed in FP64 */
+
+/* ---- inputs ------------------------------------------------------------ */
+/* Sparse matrix A in CSR, full symmetric storage (both triangles), column
+ * indices sorted and unique within each row.  All arrays are device memory
+ * owned by the caller: rowptr[n+1], colind[nnz], val[nnz].  The stored
+ * pattern defines the graph G(A) of Sec. 2. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* colind;
+    const double*  val;
+} dd_csr;
+
+#define DD_FP64 0
+#define DD_FP32 1
+#define DD_SEL_THRESHOLD      0  /* keep lambda > 1/tau  (3.3) */
+#define DD_SEL_THRESHOLD_CAP  1  /* keep lambda > 1/tau, at most nev_cap per subdomain (the largest lambda) */
+
+typedef struct {
+    int32_t local_prec;   /* DD_FP64 (default) or DD_FP32: precision of the local Cholesky factors of A_ii
+                             and of the local solves in the apply; splitting, eigen, E and PCG stay FP64 */
+    int32_t select;       /* DD_SEL_THRESHOLD (default) or DD_SEL_THRESHOLD_CAP */
+    int32_t nev_cap;      /* cap per subdomain for DD_SEL_THRESHOLD_CAP */
+    int32_t validate;     /* nonzero: check pattern symmetry and finite values of A (O(nnz)) */
+    int32_t coarsen;      /* levels >= 3: subdomains per coarse part (default 64) */
+    int32_t reserved[7];
+} dd_options;
+
+typedef struct dd_handle_s* dd_handle;
+
+/* ---- diagnostics ------------------------------------------------------- */
+#define DD_MAX_LEVELS 4
+#define DD_NPHASE 12
+typedef struct {
+    int32_t levels;                 /* levels built (2 = fine + coarse) */
+    int32_t N[DD_MAX_LEVELS];       /* subdomains per decomposed level */
+    int64_t n[DD_MAX_LEVELS];       /* matrix size per level (n[1] = n_C of level 0) */
+    int64_t n_C;                    /* coarse size of the finest level */
+    double  grid_complexity;        /* (n + n_C) / n  (Sec. 4) */
+    int32_t p_min, p_max;           /* kept modes per fine subdomain */
+    int32_t fp32_fallbacks;         /* local factors recomputed in FP64 */
+    int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap */
+    double  phase_ms[DD_NPHASE];    /* setup phase times, see dd_phase_name */
+    int32_t last_iters;             /* last dd_pcg: iterations (first RHS) */
+    double  last_relres;            /* last dd_pcg: true relative residual (first RHS) */
+    int64_t device_bytes;           /* device memory held by the handle */
+} dd_info_t;
+
+/* ---- entry points ------------------------------------------------------ */
+
+/* Seeded greedy graph growing partition of G(A) into N parts (a graph
+ * partitioning algorithm, Sec. 2): N distinct seed vertices from a
+ * SplitMix64 stream started at `seed` (vertex = output mod n, repeats
+ * skipped; the k-th distinct seed owns part k), then level-synchronous BFS
+ * where every unassigned vertex adjacent to the previous round's frontier
+ * takes the minimum part id among those neighbours; unreached vertices go
+ * to the smallest part (lowest id on ties).  part: device int32[n], output.
+ * Deterministic and bit-exact.  Errors: DD_ERR_INVALID_ARG if N < 1 or N > n. */
+int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, hipStream_t stream);
+
+/* Build the preconditioner (Sec. 2-3).
+ *  part    device int32[n], subdomain id of each node in [0, N)  (Omega_Ii = {j : part_j = i})
+ *  overlap delta >= 1: Gamma_i = BFS layers 1..delta of Omega_Ii, Delta_i = layer delta+1
+ *  tau     the paper's tau > 0 of (3.3): keep eigenpairs with lambda > 1/tau
+ *  levels  >= 2; 2 = exact Cholesky of E; >= 3 recursive construction on E (Sec. 3.2, multilevel)
+ *  opt     may be NULL (defaults: FP64, threshold selection, no validation)
+ *  out     receives the handle (owned by the caller; free with dd_destroy)
+ * Errors: DD_ERR_INVALID_ARG, DD_ERR_NOT_SPD, DD_ERR_EIG, DD_ERR_OOM, DD_ERR_HIP.
+ * Warnings: DD_WARN_FULL_COARSE, DD_WARN_FP32_FALLBACK. */
+int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau,
+             int32_t levels, const dd_options* opt, hipStream_t stream, dd_handle* out);
+
+/* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1).
+ * r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */
+int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t stream);
+
+/* Preconditioned CG with M from dd_apply (FP64 dots and residual recurrence).
+ * b: device n x nrhs; x: device n x nrhs, in: initial guess, out: solution.
+ * Stops RHS j when ||b_j - A x_j||_2 <= rtol ||b_j||_2 (recurrence residual,
+ * true residual recomputed at exit).  iters, relres: host arrays [nrhs]
+ * (may be NULL).  Returns DD_WARN_MAXIT if some RHS did not converge. */
+int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit,
+           int32_t* iters, double* relres, hipStream_t stream);
+
+/* y = A x for the fine-level matrix held by the handle (SpMV kernel), device pointers. */
+int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t stream);
+
+int  dd_info(dd_handle h, dd_info_t* out);
+const char* dd_phase_name(int32_t phase);
+void dd_destroy(dd_handle h);
+const char* dd_strerror(int code);
+
+/* ---- inspection (tests and diagnostics; all outputs are host memory) ---- */
+/* Number of subdomains at `level` (0 = finest). */
+int dd_subdomain_count(dd_handle h, int32_t level, int32_t* N);
+/* sizes: host int32[5*N]: for each i, {n_Ii, n_Gamma_i, n_Delta_i, p_i, status}. */
+int dd_subdomain_sizes(dd_handle h, int32_t level, int32_t* sizes);
+/* Ordered index sets of subdomain i (global indices, each ascending):
+ * I[n_Ii], Gamma[n_Gamma_i], Delta[n_Delta_i]. */
+int dd_subdomain_sets(dd_handle h, int32_t level, int32_t i, int32_t* I, int32_t* Gamma, int32_t* Delta);
+/* Kept eigenvalues mu = 1/lambda of subdomain i, ascending: mu[p_i]. */
+int dd_subdomain_eigs(dd_handle h, int32_t level, int32_t i, double* mu);
+/* Orthonormal basis of D_i Z_i restricted to Omega_Ii: Z[n_Ii x p_i], column-major. */
+int dd_subdomain_basis(dd_handle h, int32_t level, int32_t i, double* Z);
+/* Largest singular value sigma_1 of X_i for every subdomain: sigma1[N]. */
+int dd_subdomain_sigma1(dd_handle h, int32_t level, double* sigma1);
+/* Coarse operator E of `level` (n_C x n_C dense, column-major), only if n_C <= max_n. */
+int dd_coarse_matrix(dd_handle h, int32_t level, double* E, int64_t max_n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_H */

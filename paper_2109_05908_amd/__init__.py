@@ -1,0 +1,12 @@
+"""MI355X (gfx950) implementation of the fully algebraic multilevel overlapping
+Schwarz preconditioner of Al Daas & Jolivet (arXiv 2109.05908).
+
+The compute path lives in ``libdd.so`` (HIP kernels behind the C-ABI declared
+in ``include/dd.h``).  This package only marshals arguments: device buffers
+and streams come from PyTorch.  Importing it does not load the library;
+the first call does, and fails loudly if it has not been built.
+"""
+from .binding import (  # noqa: F401
+    DD_FP32, DD_FP64, DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP, DDError, DeviceCSR, Preconditioner,
+    lib, library_path, partition_ggg,
+)

@@ -1,0 +1,243 @@
+"""ctypes binding of libdd.so: argument marshalling only.
+
+Every function here forwards to the C-ABI of include/dd.h with raw device
+pointers taken from torch tensors and the current HIP stream.  No arithmetic
+of the method happens in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+DD_FP64, DD_FP32 = 0, 1
+DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP = 0, 1
+DD_NPHASE = 12
+DD_MAX_LEVELS = 4
+
+
+class DDError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        msg = lib().dd_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: {msg} (code {code})")
+
+
+class _Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("local_prec", C.c_int32), ("select", C.c_int32), ("nev_cap", C.c_int32),
+                ("validate", C.c_int32), ("coarsen", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("N", C.c_int32 * DD_MAX_LEVELS), ("n", C.c_int64 * DD_MAX_LEVELS),
+                ("n_C", C.c_int64), ("grid_complexity", C.c_double), ("p_min", C.c_int32),
+                ("p_max", C.c_int32), ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32),
+                ("phase_ms", C.c_double * DD_NPHASE), ("last_iters", C.c_int32), ("last_relres", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+def library_path() -> str:
+    return os.path.join(HERE, "libdd.so")
+
+
+def lib():
+    """Load libdd.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(path)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    sig = {
+        "dd_partition_ggg": ([P(_Csr), i32, C.c_uint64, vp, vp], i32),
+        "dd_setup": ([P(_Csr), vp, i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
+        "dd_apply": ([vp, vp, vp, i32, vp], i32),
+        "dd_pcg": ([vp, vp, vp, i32, f64, i32, P(i32), P(f64), vp], i32),
+        "dd_spmv": ([vp, vp, vp, vp], i32),
+        "dd_info": ([vp, P(_Info)], i32),
+        "dd_phase_name": ([i32], C.c_char_p),
+        "dd_destroy": ([vp], None),
+        "dd_strerror": ([C.c_int], C.c_char_p),
+        "dd_subdomain_count": ([vp, i32, P(i32)], i32),
+        "dd_subdomain_sizes": ([vp, i32, vp], i32),
+        "dd_subdomain_sets": ([vp, i32, i32, vp, vp, vp], i32),
+        "dd_subdomain_eigs": ([vp, i32, i32, vp], i32),
+        "dd_subdomain_basis": ([vp, i32, i32, vp], i32),
+        "dd_subdomain_sigma1": ([vp, i32, vp], i32),
+        "dd_coarse_matrix": ([vp, i32, vp, i64], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _LIB = L
+    return L
+
+
+def exported_symbols() -> list[str]:
+    return ["dd_partition_ggg", "dd_setup", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
+            "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
+            "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix"]
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+class DeviceCSR:
+    """CSR matrix resident on the GPU (int32 indices, FP64 values, full symmetric storage)."""
+
+    def __init__(self, n, rowptr, colind, val, device="cuda"):
+        import torch
+        self.n = int(n)
+        self.rowptr = torch.as_tensor(np.asarray(rowptr, dtype=np.int32)).to(device)
+        self.colind = torch.as_tensor(np.asarray(colind, dtype=np.int32)).to(device)
+        self.val = torch.as_tensor(np.asarray(val, dtype=np.float64)).to(device)
+        self.nnz = int(self.colind.numel())
+
+    @classmethod
+    def from_workload(cls, A, device="cuda"):
+        return cls(A.n, A.rowptr, A.colind, A.val, device)
+
+    def cstruct(self) -> _Csr:
+        return _Csr(self.n, self.nnz, self.rowptr.data_ptr(), self.colind.data_ptr(), self.val.data_ptr())
+
+
+def _check(code: int, what: str, allow_warn: bool = True) -> int:
+    if code < 0 or (code > 0 and not allow_warn):
+        raise DDError(code, what)
+    return code
+
+
+def partition_ggg(A: DeviceCSR, N: int, seed: int):
+    import torch
+    part = torch.empty(A.n, dtype=torch.int32, device=A.val.device)
+    cs = A.cstruct()
+    _check(lib().dd_partition_ggg(C.byref(cs), N, seed, _ptr(part), _stream()), "dd_partition_ggg")
+    return part
+
+
+class Preconditioner:
+    """Handle of dd_setup: the two-level additive Schwarz preconditioner."""
+
+    def __init__(self, A: DeviceCSR, part, N: int, overlap: int, tau: float, levels: int = 2,
+                 local_prec: int = DD_FP64, select: int = DD_SEL_THRESHOLD, nev_cap: int = 0,
+                 validate: bool = False):
+        import torch
+        self.A = A
+        self.n = A.n
+        part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device)
+        opts = _Opts(local_prec, select, nev_cap, int(validate), 0, (C.c_int32 * 7)())
+        h = C.c_void_p()
+        cs = A.cstruct()
+        self.setup_status = _check(
+            lib().dd_setup(C.byref(cs), _ptr(part), N, overlap, float(tau), levels, C.byref(opts), _stream(),
+                           C.byref(h)), "dd_setup")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- solve phase ----
+    def apply(self, r):
+        import torch
+        r = r.contiguous()
+        z = torch.empty_like(r)
+        nrhs = 1 if r.dim() == 1 else r.shape[1]
+        _check(lib().dd_apply(self._h, _ptr(r), _ptr(z), nrhs, _stream()), "dd_apply")
+        return z
+
+    def pcg(self, b, x0=None, rtol: float = 1e-8, maxit: int = 1000):
+        import torch
+        b = b.contiguous()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        its = (C.c_int32 * nrhs)()
+        rr = (C.c_double * nrhs)()
+        code = _check(lib().dd_pcg(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, its, rr, _stream()), "dd_pcg")
+        return x, list(its), list(rr), code
+
+    def spmv(self, x):
+        import torch
+        y = torch.empty_like(x)
+        _check(lib().dd_spmv(self._h, _ptr(x), _ptr(y), _stream()), "dd_spmv")
+        return y
+
+    # ---- diagnostics and inspection ----
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().dd_info(self._h, C.byref(inf)), "dd_info")
+        L = lib()
+        return {
+            "levels": inf.levels, "N": list(inf.N), "n": list(inf.n), "n_C": inf.n_C,
+            "grid_complexity": inf.grid_complexity, "p_min": inf.p_min, "p_max": inf.p_max,
+            "fp32_fallbacks": inf.fp32_fallbacks, "eig_maxit_hits": inf.eig_maxit_hits,
+            "phase_ms": {L.dd_phase_name(i).decode(): inf.phase_ms[i] for i in range(DD_NPHASE)},
+            "last_iters": inf.last_iters, "last_relres": inf.last_relres, "device_bytes": inf.device_bytes,
+        }
+
+    def count(self, level=0) -> int:
+        N = C.c_int32()
+        _check(lib().dd_subdomain_count(self._h, level, C.byref(N)), "dd_subdomain_count")
+        return N.value
+
+    def sizes(self, level=0) -> np.ndarray:
+        N = self.count(level)
+        out = np.zeros(5 * N, dtype=np.int32)
+        _check(lib().dd_subdomain_sizes(self._h, level, out.ctypes.data_as(C.c_void_p)), "dd_subdomain_sizes")
+        return out.reshape(N, 5)
+
+    def sets(self, i, level=0):
+        nI, nG, nD = (int(v) for v in self.sizes(level)[i, :3])
+        I, G, D = (np.zeros(k, dtype=np.int32) for k in (nI, nG, nD))
+        _check(lib().dd_subdomain_sets(self._h, level, i, I.ctypes.data_as(C.c_void_p), G.ctypes.data_as(C.c_void_p),
+                                       D.ctypes.data_as(C.c_void_p)), "dd_subdomain_sets")
+        return I, G, D
+
+    def eigs(self, i, level=0) -> np.ndarray:
+        p = int(self.sizes(level)[i, 3])
+        mu = np.zeros(p)
+        _check(lib().dd_subdomain_eigs(self._h, level, i, mu.ctypes.data_as(C.c_void_p)), "dd_subdomain_eigs")
+        return mu
+
+    def basis(self, i, level=0) -> np.ndarray:
+        nI, p = int(self.sizes(level)[i, 0]), int(self.sizes(level)[i, 3])
+        Z = np.zeros(nI * p)
+        _check(lib().dd_subdomain_basis(self._h, level, i, Z.ctypes.data_as(C.c_void_p)), "dd_subdomain_basis")
+        return Z.reshape(p, nI).T.copy()
+
+    def sigma1(self, level=0) -> np.ndarray:
+        out = np.zeros(self.count(level))
+        _check(lib().dd_subdomain_sigma1(self._h, level, out.ctypes.data_as(C.c_void_p)), "dd_subdomain_sigma1")
+        return out
+
+    def coarse_matrix(self, level=0, max_n=4096) -> np.ndarray:
+        nC = self.info()["n_C"]
+        E = np.zeros(nC * nC)
+        _check(lib().dd_coarse_matrix(self._h, level, E.ctypes.data_as(C.c_void_p), max_n), "dd_coarse_matrix")
+        return E.reshape(nC, nC).T.copy()

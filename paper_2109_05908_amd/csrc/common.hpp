@@ -1,0 +1,286 @@
+// Shared device/host helpers for the dd library (gfx950 / CDNA4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/dd.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// error handling (host)
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define DD_HIP(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) {                                                        \
+            int c_ = (e_ == hipErrorOutOfMemory) ? DD_ERR_OOM : DD_ERR_HIP;            \
+            throw ::dd::Error(c_, std::string(#x) + ": " + hipGetErrorString(e_));     \
+        }                                                                              \
+    } while (0)
+
+#define DD_CHECK(cond, code, msg)                  \
+    do {                                           \
+        if (!(cond)) throw ::dd::Error(code, msg); \
+    } while (0)
+
+inline void launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error(DD_ERR_HIP, std::string("launch ") + what + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// device memory owned by RAII buffers
+// ---------------------------------------------------------------------------
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) DD_HIP(hipMalloc(&p, count * sizeof(T)));
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+template <class T>
+inline void h2d(T* d, const T* h, size_t n, hipStream_t s) {
+    if (n) DD_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+inline void d2h(T* h, const T* d, size_t n, hipStream_t s) {
+    if (n) DD_HIP(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+template <class T>
+inline DBuf<T> upload(const std::vector<T>& v, hipStream_t s) {
+    DBuf<T> b(v.size());
+    h2d(b.p, v.data(), v.size(), s);
+    DD_HIP(hipStreamSynchronize(s));  // host vector may die after return
+    return b;
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// device reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// Block-wide sum; `red` must hold blockDim.x/64 doubles; result broadcast.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+__device__ __forceinline__ double block_max(double v, double* red) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < nw; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches over uneven items: every item b contributes tiles(b) work
+// units; a fixed grid walks the flattened unit list.  The prefix over items
+// is recomputed in LDS by each workgroup (items <= kMaxItems).
+// ---------------------------------------------------------------------------
+constexpr int kMaxItems = 4096;
+
+template <class Op>
+__device__ __forceinline__ int item_prefix(const Op& op, int nitems, int* pre) {
+    // pre[0..nitems] = exclusive prefix of op.tiles(b); contiguous chunk per thread
+    __shared__ int part[256];
+    const int T = blockDim.x, t = threadIdx.x;
+    const int chunk = (nitems + T - 1) / T;
+    const int b0 = min(nitems, t * chunk), b1 = min(nitems, b0 + chunk);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) {
+        const int v = op.tiles(b);
+        pre[b + 1] = v;
+        s += v;
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        const int add = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int run = (t > 0) ? part[t - 1] : 0;
+    for (int b = b0; b < b1; ++b) {
+        run += pre[b + 1];
+        pre[b + 1] = run;
+    }
+    if (t == 0) pre[0] = 0;
+    __syncthreads();
+    return pre[nitems];
+}
+
+__device__ __forceinline__ int find_item(const int* pre, int nitems, int t) {
+    int lo = 0, hi = nitems;  // find largest b with pre[b] <= t, pre[b+1] > t
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <class Op>
+__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems) {
+    __shared__ int pre[kMaxItems + 1];
+    const int total = item_prefix(op, nitems, pre);
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int b = find_item(pre, nitems, t);
+        op(b, t - pre[b]);
+        __syncthreads();
+    }
+}
+
+template <class Op>
+inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream_t s, const char* name,
+                         int max_grid = 4096) {
+    if (nitems <= 0 || total_hint <= 0) return;
+    if (nitems > kMaxItems) throw Error(DD_ERR_INTERNAL, "too many batch items");
+    int grid = (int)std::min<int64_t>(total_hint, max_grid);
+    hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, nitems);
+    launch_check(name);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA tile: 64x64 block tile, 4 waves of 32x32 (2x2 16x16x4 MFMA).
+// Column-major operands.  op(A) is M x K, op(B) is K x N.
+// Operand modes: 0 = plain; 1 = unit lower trapezoid stored below the
+// diagonal (Householder vectors): stored (r,c) -> r<c ? 0 : r==c ? 1 : A(r,c).
+// GATHER: op(A) row i is stored row ga[i] (no-transpose A only).
+// ---------------------------------------------------------------------------
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double4_t mfma_f64(double a, double b, double4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct TileSmem {
+    double a[16][64 + 1];
+    double b[16][64 + 1];
+};
+
+template <bool TA, int MODEA>
+__device__ __forceinline__ double load_a(const double* __restrict__ A, int64_t lda, int i, int k, int M, int K,
+                                         const int* __restrict__ ga) {
+    if (i >= M || k >= K) return 0.0;
+    int r = TA ? k : i, c = TA ? i : k;
+    if (ga) r = ga[r];
+    if (MODEA == 1) return (r < c) ? 0.0 : (r == c ? 1.0 : A[r + (int64_t)c * lda]);
+    return A[r + (int64_t)c * lda];
+}
+template <bool TB, int MODEB>
+__device__ __forceinline__ double load_b(const double* __restrict__ B, int64_t ldb, int k, int j, int K, int N,
+                                         const int* __restrict__ gb) {
+    if (j >= N || k >= K) return 0.0;
+    int r = TB ? j : k, c = TB ? k : j;
+    if (gb) r = gb[r];
+    if (MODEB == 1) return (r < c) ? 0.0 : (r == c ? 1.0 : B[r + (int64_t)c * ldb]);
+    return B[r + (int64_t)c * ldb];
+}
+
+// acc += op(A)[i0:i0+64, :] * op(B)[:, j0:j0+64]
+template <bool TA, bool TB, int MODEA = 0, int MODEB = 0>
+__device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                             int64_t ldb, int M, int N, int K, int i0, int j0, TileSmem& sm,
+                                             double4_t (&acc)[2][2], const int* ga = nullptr,
+                                             const int* gb = nullptr) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int e = t; e < 1024; e += 256) {
+            int ii, kk;
+            if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
+            sm.a[kk][ii] = load_a<TA, MODEA>(A, lda, i0 + ii, k0 + kk, M, K, ga);
+        }
+#pragma unroll
+        for (int e = t; e < 1024; e += 256) {
+            int jj, kk;
+            if (!TB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+            sm.b[kk][jj] = load_b<TB, MODEB>(B, ldb, k0 + kk, j0 + jj, K, N, gb);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int kk = kq * 4 + (lane >> 4);
+            const double a0 = sm.a[kk][wr + (lane & 15)], a1 = sm.a[kk][wr + 16 + (lane & 15)];
+            const double b0 = sm.b[kk][wc + (lane & 15)], b1 = sm.b[kk][wc + 16 + (lane & 15)];
+            acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = double4_t{0.0, 0.0, 0.0, 0.0};
+}
+
+// Visit the accumulator: f(row, col, value) with tile-relative indices.  The
+// 16x16x4 f64 MFMA leaves D(4*e + lane/16, lane%16) in element e of each lane.
+template <class F>
+__device__ __forceinline__ void acc_foreach(const double4_t (&acc)[2][2], F f) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) f(wr + 16 * x + 4 * j + (lane >> 4), wc + 16 * y + (lane & 15), acc[x][y][j]);
+}
+
+}  // namespace dd

@@ -1,0 +1,1059 @@
+// Host orchestration of the setup (Sec. 2-3 of the paper), the two-level
+// additive Schwarz apply (2.1) and PCG, behind the C-ABI of include/dd.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "coarse.hpp"
+
+namespace dd {
+
+constexpr double kEps = 2.220446049250313e-16;  // 2^-52, the shift's epsilon
+
+// ---------------------------------------------------------------------------
+// per-item arenas
+// ---------------------------------------------------------------------------
+struct Arena {
+    DBuf<double> buf;
+    std::vector<double*> ptr;
+    void alloc(const std::vector<int64_t>& sizes) {
+        std::vector<int64_t> off(sizes.size() + 1, 0);
+        for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((std::max<int64_t>(sizes[i], 1) + 31) / 32) * 32;
+        buf.alloc(off.back());
+        ptr.resize(sizes.size());
+        for (size_t i = 0; i < sizes.size(); ++i) ptr[i] = buf.p + off[i];
+    }
+    void release() { buf.release(); ptr.clear(); }
+};
+
+struct Timer {
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t0;
+    explicit Timer(hipStream_t st) : s(st) { t0 = std::chrono::steady_clock::now(); }
+    double lap() {
+        DD_HIP(hipStreamSynchronize(s));
+        auto t1 = std::chrono::steady_clock::now();
+        double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        t0 = t1;
+        return ms;
+    }
+};
+
+struct Opts {
+    int local_prec = DD_FP64;
+    int select = DD_SEL_THRESHOLD;
+    int nev_cap = 0;
+    int validate = 0;
+    int coarsen = 64;
+};
+
+enum Phase { PH_SETS, PH_EXTRACT, PH_CHOL, PH_QR, PH_POLAR, PH_SIGMA, PH_SCHUR, PH_EIG, PH_BASIS, PH_E, PH_EFACT, PH_OTHER };
+static const char* kPhaseNames[DD_NPHASE] = {"sets+maps", "extract", "local_cholesky", "qr_X", "polar_qdwh",
+                                             "sigma1", "schur_qr", "eigen", "basis", "assemble_E", "factor_E",
+                                             "other"};
+
+// ---------------------------------------------------------------------------
+// one decomposed level
+// ---------------------------------------------------------------------------
+struct Level {
+    // matrix of this level (owned copy)
+    int64_t n = 0, nnz = 0;
+    DBuf<int32_t> rowptr, colind;
+    DBuf<double> val;
+    CsrDev A() const { return CsrDev{n, nnz, rowptr.p, colind.p, val.p}; }
+
+    int N = 0, delta = 1;
+    double tau = 0.0;
+    DBuf<int32_t> part;
+    std::vector<int32_t> hcounts;  // 3N
+    DBuf<int32_t> counts;
+    std::vector<int64_t> hoffE, hoffO, hoffI;
+    DBuf<int64_t> offE, offO, offI;
+    DBuf<int32_t> ext, omega_flat, ilocal;
+    DBuf<int64_t> memb_ptr, memb;
+    std::vector<int> ni, nt, nI, nG, nD;
+
+    Arena L;  // local Cholesky factors (n_i x n_i, lower)
+    std::vector<int> p;
+    std::vector<int32_t> status;
+    DBuf<int32_t> pcnt;
+    std::vector<int64_t> hoffC;
+    DBuf<int64_t> offC;
+    Arena Z;
+    DBuf<double*> dZ;
+    std::vector<std::vector<double>> mu;
+    std::vector<double> sigma1;
+    int64_t nC = 0;
+    DBuf<double> Efac;
+    std::vector<double> Ecopy;  // small coarse operators only (inspection)
+
+    // apply workspace
+    DBuf<double> rloc, yC;
+    Batch<DMat> Lb, Bb, Eb, Ebv;
+
+    SubInfo sub() const {
+        return SubInfo{N, counts.p, offE.p, offO.p, ext.p, part.p, ilocal.p, pcnt.p, offC.p, dZ.p};
+    }
+};
+
+struct Handle {
+    std::vector<std::unique_ptr<Level>> lv;
+    Opts opt;
+    dd_info_t info{};
+    // PCG / apply scratch
+    DBuf<double> r, z, pvec, q, partial, dots;
+    double* hpin = nullptr;
+    ~Handle() {
+        if (hpin) (void)hipHostFree(hpin);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// QDWH scalar weights (Nakatsukasa, Bai & Gygi 2010)
+// ---------------------------------------------------------------------------
+static void qdwh_weights(double l, double& a, double& b, double& c) {
+    const double l2 = l * l;
+    const double g = std::cbrt(4.0 * (1.0 - l2) / (l2 * l2));
+    a = std::sqrt(1.0 + g) + 0.5 * std::sqrt(8.0 - 4.0 * g + 8.0 * (2.0 - l2) / (l2 * std::sqrt(1.0 + g)));
+    b = (a - 1.0) * (a - 1.0) / 4.0;
+    c = a + b - 1.0;
+}
+
+template <class T>
+static std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    d2h(h.data(), d, n, s);
+    DD_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+static Batch<DMat> mats(const std::vector<double*>& p, const std::vector<int>& ld, const std::vector<int>& m,
+                        const std::vector<int>& n, hipStream_t s, const std::vector<int>* active = nullptr) {
+    Batch<DMat> b;
+    for (size_t i = 0; i < p.size(); ++i)
+        if (!active || (*active)[i]) b.h.push_back(DMat{p[i], ld[i], m[i], n[i]});
+    b.sync(s);
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// setup of one level: sets, local splittings, eigenproblems, coarse space
+// ---------------------------------------------------------------------------
+static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s) {
+    Timer tm(s);
+    const int N = Lv.N;
+    const int delta = Lv.delta;
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+
+    // ---- a1: sets and index maps -------------------------------------------------
+    DBuf<uint8_t> dist((size_t)n * N);
+    layers(A, Lv.part.p, N, delta, dist.p, s);
+    Lv.counts.alloc(3 * N);
+    layer_counts(dist.p, n, N, delta, Lv.counts.p, s);
+    Lv.hcounts = to_host(Lv.counts.p, 3 * N, s);
+    Lv.nI.resize(N); Lv.nG.resize(N); Lv.nD.resize(N); Lv.ni.resize(N); Lv.nt.resize(N);
+    Lv.hoffE.assign(N + 1, 0); Lv.hoffO.assign(N + 1, 0); Lv.hoffI.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+        Lv.nI[i] = Lv.hcounts[3 * i];
+        Lv.nG[i] = Lv.hcounts[3 * i + 1];
+        Lv.nD[i] = Lv.hcounts[3 * i + 2];
+        Lv.ni[i] = Lv.nI[i] + Lv.nG[i];
+        Lv.nt[i] = Lv.ni[i] + Lv.nD[i];
+        Lv.hoffE[i + 1] = Lv.hoffE[i] + Lv.nt[i];
+        Lv.hoffO[i + 1] = Lv.hoffO[i] + Lv.ni[i];
+        Lv.hoffI[i + 1] = Lv.hoffI[i] + Lv.nI[i];
+    }
+    Lv.offE = upload(Lv.hoffE, s);
+    Lv.offO = upload(Lv.hoffO, s);
+    Lv.offI = upload(Lv.hoffI, s);
+    Lv.ext.alloc(Lv.hoffE[N]);
+    layer_compact(dist.p, n, N, delta, Lv.offE.p, Lv.counts.p, Lv.ext.p, s);
+    {
+        DBuf<int32_t> mc(n);
+        membership_counts(dist.p, n, N, delta, mc.p, s);
+        Lv.memb_ptr.alloc(n + 1);
+        scan_counts(mc.p, n, Lv.memb_ptr.p, s);
+    }
+    Lv.memb.alloc(Lv.hoffO[N]);
+    membership_fill(dist.p, n, N, delta, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, Lv.memb_ptr.p, Lv.memb.p, s);
+    Lv.omega_flat.alloc(Lv.hoffO[N]);
+    Lv.ilocal.alloc(n);
+    omega_flatten(N, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, Lv.hoffO[N], Lv.omega_flat.p, Lv.ilocal.p, s);
+    info.phase_ms[PH_SETS] += tm.lap();
+
+    const auto& ni = Lv.ni;
+    const auto& nt = Lv.nt;
+    const auto& nI = Lv.nI;
+    std::vector<int> nc(N);
+    for (int i = 0; i < N; ++i) nc[i] = nt[i] - nI[i];
+
+    // ---- a2: dense Y_i = X_i^T and A_ii ------------------------------------------------
+    Arena Y;
+    {
+        std::vector<int64_t> sy(N), sa(N);
+        for (int i = 0; i < N; ++i) {
+            sy[i] = (int64_t)nt[i] * ni[i];
+            sa[i] = (int64_t)ni[i] * ni[i];
+        }
+        Y.alloc(sy);
+        Lv.L.alloc(sa);
+        fill(Y.buf.p, Y.buf.n, 0.0, s);
+        fill(Lv.L.buf.p, Lv.L.buf.n, 0.0, s);
+        DBuf<double*> dY(N), dA(N);
+        h2d(dY.p, Y.ptr.data(), N, s);
+        h2d(dA.p, Lv.L.ptr.data(), N, s);
+        extract(A, N, delta, n, dist.p, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, dY.p, dA.p, Lv.hoffO[N], s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    dist.release();
+    info.phase_ms[PH_EXTRACT] += tm.lap();
+
+    // ---- a4: local Cholesky A_ii = L_i L_i^T (exact subdomain solver) -------------------
+    {
+        Batch<DMat> Ab = mats(Lv.L.ptr, ni, ni, ni, s);
+        DBuf<int32_t> dinfo(N);
+        DD_HIP(hipMemsetAsync(dinfo.p, 0, N * sizeof(int32_t), s));
+        potrf_vb(Ab, dinfo.p, s);
+        zero_upper_vb(Ab, s);
+        auto hinfo = to_host(dinfo.p, N, s);
+        for (int i = 0; i < N; ++i)
+            DD_CHECK(hinfo[i] == 0, DD_ERR_NOT_SPD, "local block A_ii is not positive definite");
+    }
+    info.phase_ms[PH_CHOL] += tm.lap();
+
+    // ---- a3 (part 1): Householder QR of Y_i = X_i^T --------------------------------------
+    Arena qtau, qT, qW;
+    {
+        std::vector<int64_t> st(N), sT(N), sW(N);
+        for (int i = 0; i < N; ++i) {
+            st[i] = ni[i];
+            sT[i] = (int64_t)ceil_div(ni[i], QR_NB) * QR_NB * QR_NB;
+            sW[i] = (int64_t)QR_NB * std::max(ni[i], nt[i]);
+        }
+        qtau.alloc(st);
+        qT.alloc(sT);
+        qW.alloc(sW);
+        Batch<QRItem> qb;
+        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qtau.ptr[i], qT.ptr[i], qW.ptr[i], QR_NB});
+        qb.sync(s);
+        geqrf_vb(qb, s);
+    }
+    info.phase_ms[PH_QR] += tm.lap();
+
+    // ---- a3 (part 2): polar factor of R by QDWH; H = (R R^T)^{1/2} -------------------------
+    // R (ni x ni upper) from the QR; the iterate is kept transposed, Xt_0 = R^T / alpha.
+    Arena Rm, Xt, Wk;
+    std::vector<int64_t> sq(N), s4(N);
+    for (int i = 0; i < N; ++i) {
+        sq[i] = (int64_t)ni[i] * ni[i];
+        s4[i] = 4 * sq[i];
+    }
+    Rm.alloc(sq);
+    Xt.alloc(sq);
+    Wk.alloc(s4);
+    std::vector<int> two_ni(N);
+    for (int i = 0; i < N; ++i) two_ni[i] = 2 * ni[i];
+    {
+        std::vector<double*> ytop(Y.ptr);
+        Batch<DMat> Ysrc = mats(ytop, nt, ni, ni, s);
+        Batch<DMat> Rb = mats(Rm.ptr, ni, ni, ni, s);
+        Batch<DMat> Xb = mats(Xt.ptr, ni, ni, ni, s);
+        copy_vb(Ysrc, Rb, false, 1.0, s);
+        zero_lower_vb(Rb, s);
+        copy_vb(Rb, Xb, true, 1.0, s);  // Xt = R^T (lower)
+        // alpha = ||R||_F, lower bound of sigma_min via ||R^{-1}||_F
+        DBuf<double> dnorm(N), dnorm2(N);
+        frob_vb(Rb, dnorm.p, s);
+        std::vector<double*> wfirst(Wk.ptr);
+        Batch<DMat> Ib = mats(wfirst, ni, ni, ni, s);
+        set_identity_vb(Ib, 1.0, s);
+        trsm_vb(Xb, Ib, false, s);  // R^{-T}
+        frob_vb(Ib, dnorm2.p, s);
+        auto alpha = to_host(dnorm.p, N, s);
+        auto rinv = to_host(dnorm2.p, N, s);
+        std::vector<double> ell(N), inv_alpha(N), zero(N, 0.0);
+        for (int i = 0; i < N; ++i) {
+            DD_CHECK(alpha[i] > 0 && std::isfinite(rinv[i]), DD_ERR_NOT_SPD, "singular local block row X_i");
+            ell[i] = std::min(1.0, 0.9 / (alpha[i] * rinv[i]));
+            inv_alpha[i] = 1.0 / alpha[i];
+        }
+        DBuf<double> da = upload(inv_alpha, s), dz0 = upload(zero, s);
+        axpby_vb(Xb, Xb, da.p, dz0.p, s);  // Xt := Xt / alpha
+
+        std::vector<int> done(N, 0);
+        for (int it = 0; it < 20; ++it) {
+            std::vector<int> actQ(N, 0), actC(N, 0);
+            std::vector<double> ca(N), cb(N), cc(N), coefQ(N), beta(N), coefC(N);
+            int anyQ = 0, anyC = 0;
+            for (int i = 0; i < N; ++i) {
+                if (done[i]) continue;
+                double a, b, c;
+                qdwh_weights(ell[i], a, b, c);
+                ca[i] = a; cb[i] = b; cc[i] = c;
+                beta[i] = b / c;
+                if (c > 100.0) { actQ[i] = 1; anyQ = 1; coefQ[i] = (a - b / c) / std::sqrt(c); }
+                else { actC[i] = 1; anyC = 1; coefC[i] = a - b / c; }
+            }
+            if (!anyQ && !anyC) break;
+            if (anyQ) {
+                // S = [sqrt(c) Xt^T ; I]  (2 ni x ni), QR, explicit Q = [Q1; Q2]; Xt := b/c Xt + coef Q2 Q1^T
+                std::vector<double*> sp(N), qp(N), scr(N);
+                for (int i = 0; i < N; ++i) { sp[i] = Wk.ptr[i]; qp[i] = Wk.ptr[i] + 2 * sq[i]; }
+                Batch<DMat> Xq = mats(Xt.ptr, ni, ni, ni, s, &actQ);
+                std::vector<double*> stop(sp), sbot(N);
+                for (int i = 0; i < N; ++i) sbot[i] = sp[i] + ni[i];
+                Batch<DMat> Stop = mats(stop, two_ni, ni, ni, s, &actQ);
+                Batch<DMat> Sbot = mats(sbot, two_ni, ni, ni, s, &actQ);
+                std::vector<double> sqc(N, 0.0);
+                for (int i = 0; i < N; ++i) sqc[i] = actQ[i] ? std::sqrt(cc[i]) : 0.0;
+                // top = sqrt(c) * Xt^T : copy transposed then scale per item
+                copy_vb(Xq, Stop, true, 1.0, s);
+                {
+                    std::vector<double> sa, sz;
+                    for (int i = 0; i < N; ++i) if (actQ[i]) { sa.push_back(sqc[i]); sz.push_back(0.0); }
+                    DBuf<double> d1 = upload(sa, s), d2 = upload(sz, s);
+                    axpby_vb(Stop, Stop, d1.p, d2.p, s);
+                }
+                set_identity_vb(Sbot, 1.0, s);
+                Arena tq, tT, tW;
+                std::vector<int64_t> a1(N), a2(N), a3(N);
+                for (int i = 0; i < N; ++i) {
+                    a1[i] = actQ[i] ? ni[i] : 1;
+                    a2[i] = actQ[i] ? (int64_t)ceil_div(ni[i], QR_NB) * QR_NB * QR_NB : 1;
+                    a3[i] = actQ[i] ? (int64_t)QR_NB * ni[i] : 1;
+                }
+                tq.alloc(a1); tT.alloc(a2); tW.alloc(a3);
+                Batch<QRItem> qb;
+                Batch<ORItem> ob;
+                for (int i = 0; i < N; ++i) {
+                    if (!actQ[i]) continue;
+                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB});
+                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i]});
+                }
+                qb.sync(s);
+                ob.sync(s);
+                geqrf_vb(qb, s);
+                Batch<DMat> Qb = mats(qp, two_ni, two_ni, ni, s, &actQ);
+                set_identity_vb(Qb, 1.0, s);
+                ormqr_vb(ob, false, s);
+                Batch<GemmItem> g;
+                for (int i = 0; i < N; ++i) {
+                    if (!actQ[i]) continue;
+                    g.h.push_back(GemmItem{qp[i] + ni[i], 2 * ni[i], qp[i], 2 * ni[i], Xt.ptr[i], ni[i], ni[i], ni[i], ni[i],
+                                           coefQ[i], beta[i]});
+                }
+                g.sync(s);
+                gemm_vb(g, false, true, s);
+                DD_HIP(hipStreamSynchronize(s));
+            }
+            if (anyC) {
+                // Zc = I + c Xt Xt^T = L L^T; W = Zc^{-1} Xt; Xt := b/c Xt + (a - b/c) W
+                std::vector<double*> zp(N), wp(N);
+                for (int i = 0; i < N; ++i) { zp[i] = Wk.ptr[i]; wp[i] = Wk.ptr[i] + sq[i]; }
+                Batch<DMat> Zb = mats(zp, ni, ni, ni, s, &actC);
+                Batch<DMat> Wb = mats(wp, ni, ni, ni, s, &actC);
+                Batch<DMat> Xc = mats(Xt.ptr, ni, ni, ni, s, &actC);
+                set_identity_vb(Zb, 1.0, s);
+                Batch<GemmItem> g;
+                for (int i = 0; i < N; ++i) {
+                    if (!actC[i]) continue;
+                    g.h.push_back(GemmItem{Xt.ptr[i], ni[i], Xt.ptr[i], ni[i], zp[i], ni[i], ni[i], ni[i], ni[i], cc[i], 1.0});
+                }
+                g.sync(s);
+                gemm_vb(g, false, true, s);
+                DBuf<int32_t> dinfo(Zb.size());
+                DD_HIP(hipMemsetAsync(dinfo.p, 0, Zb.size() * sizeof(int32_t), s));
+                potrf_vb(Zb, dinfo.p, s);
+                copy_vb(Xc, Wb, false, 1.0, s);
+                trsm_vb(Zb, Wb, false, s);
+                trsm_vb(Zb, Wb, true, s);
+                std::vector<double> al, be;
+                for (int i = 0; i < N; ++i) if (actC[i]) { al.push_back(coefC[i]); be.push_back(beta[i]); }
+                DBuf<double> d1 = upload(al, s), d2 = upload(be, s);
+                axpby_vb(Wb, Xc, d1.p, d2.p, s);
+                auto hinfo = to_host(dinfo.p, Zb.size(), s);
+                for (auto v : hinfo) DD_CHECK(v == 0, DD_ERR_EIG, "polar iteration: Cholesky breakdown");
+            }
+            for (int i = 0; i < N; ++i) {
+                if (done[i]) continue;
+                const double l = ell[i];
+                ell[i] = l * (ca[i] + cb[i] * l * l) / (1.0 + cc[i] * l * l);
+                if (std::fabs(1.0 - ell[i]) < 1e-14) done[i] = 1;
+            }
+            if (it == 19) info.eig_maxit_hits += 1;
+        }
+        // H = R * Xt_inf  (= R U_p^T, U_p the polar factor of R), symmetrised, in Wk[0:sq]
+        Batch<GemmItem> g;
+        for (int i = 0; i < N; ++i)
+            g.h.push_back(GemmItem{Rm.ptr[i], ni[i], Xt.ptr[i], ni[i], Wk.ptr[i], ni[i], ni[i], ni[i], ni[i], 1.0, 0.0});
+        g.sync(s);
+        gemm_vb(g, false, false, s);
+        Batch<DMat> Hb = mats(Wk.ptr, ni, ni, ni, s);
+        symmetrize_vb(Hb, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    Rm.release();
+    Xt.release();
+    info.phase_ms[PH_POLAR] += tm.lap();
+
+    // ---- shift s_i = sigma_1i * eps, sigma_1 = lambda_max(H) by Lanczos -------------------
+    std::vector<double> shift(N);
+    {
+        Batch<DMat> Hb = mats(Wk.ptr, ni, ni, ni, s);
+        Arena lw;
+        std::vector<int64_t> sl(N);
+        const int K = 128;
+        for (int i = 0; i < N; ++i) sl[i] = (int64_t)ni[i] * (K + 2) + 2 * (K + 1) + 1;
+        lw.alloc(sl);
+        DBuf<double*> dlw(N);
+        h2d(dlw.p, lw.ptr.data(), N, s);
+        DBuf<double> dsig(N);
+        DBuf<int32_t> dsteps(N);
+        lanczos_max_vb(Hb, dlw.p, K, dsig.p, dsteps.p, s);
+        Lv.sigma1 = to_host(dsig.p, N, s);
+        for (int i = 0; i < N; ++i) shift[i] = Lv.sigma1[i] * kEps;
+        DBuf<double> dsh = upload(shift, s);
+        add_diag_vb(Hb, dsh.p, s);
+        DBuf<int32_t> dinfo(N);
+        DD_HIP(hipMemsetAsync(dinfo.p, 0, N * sizeof(int32_t), s));
+        potrf_vb(Hb, dinfo.p, s);  // H + sI = L_H L_H^T
+        zero_upper_vb(Hb, s);
+        auto hinfo = to_host(dinfo.p, N, s);
+        for (auto v : hinfo) DD_CHECK(v == 0, DD_ERR_EIG, "shifted square root not positive definite");
+    }
+    info.phase_ms[PH_SIGMA] += tm.lap();
+
+    // ---- (3.2): F^T = Q_full blkdiag(L_H, sqrt(s) I); Fp = F[:, [c, I]]; QR -> R_II -----------
+    Arena Fp;
+    {
+        Arena Ft;
+        std::vector<int64_t> sf(N);
+        for (int i = 0; i < N; ++i) sf[i] = (int64_t)nt[i] * nt[i];
+        Ft.alloc(sf);
+        fill(Ft.buf.p, Ft.buf.n, 0.0, s);
+        Batch<DMat> Hb = mats(Wk.ptr, ni, ni, ni, s);
+        Batch<DMat> Ftop = mats(Ft.ptr, nt, ni, ni, s);
+        copy_vb(Hb, Ftop, false, 1.0, s);
+        {
+            std::vector<double*> bot(N);
+            std::vector<int> nd(N);
+            std::vector<int> act(N);
+            std::vector<double> sqs;
+            for (int i = 0; i < N; ++i) {
+                bot[i] = Ft.ptr[i] + ni[i] + (int64_t)ni[i] * nt[i];
+                nd[i] = Lv.nD[i];
+                act[i] = nd[i] > 0;
+                if (act[i]) sqs.push_back(std::sqrt(shift[i]));
+            }
+            Batch<DMat> Bt = mats(bot, nt, nd, nd, s, &act);
+            if (Bt.size()) {
+                set_identity_vb(Bt, 1.0, s);
+                std::vector<double> z0(sqs.size(), 0.0);
+                DBuf<double> d1 = upload(sqs, s), d2 = upload(z0, s);
+                axpby_vb(Bt, Bt, d1.p, d2.p, s);
+            }
+        }
+        Wk.release();
+        Batch<ORItem> ob;
+        for (int i = 0; i < N; ++i)
+            ob.h.push_back(ORItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qT.ptr[i], DMat{Ft.ptr[i], nt[i], nt[i], nt[i]}, qW.ptr[i]});
+        ob.sync(s);
+        ormqr_vb(ob, false, s);  // Ft = Q_full * blkdiag(L_H, sqrt(s) I) = F^T
+        DD_HIP(hipStreamSynchronize(s));
+        Y.release();
+        qtau.release();
+        qT.release();
+        qW.release();
+        // Fp[:, j] = F[:, perm(j)] = (row perm(j) of F^T)^T, perm = [nI..nt-1, 0..nI-1]
+        Fp.alloc(sf);
+        std::vector<double*> srcC(N), srcI(N), dstC(N), dstI(N);
+        std::vector<int> actc(N);
+        for (int i = 0; i < N; ++i) {
+            srcC[i] = Ft.ptr[i] + nI[i];
+            srcI[i] = Ft.ptr[i];
+            dstC[i] = Fp.ptr[i];
+            dstI[i] = Fp.ptr[i] + (int64_t)nc[i] * nt[i];
+            actc[i] = nc[i] > 0;
+        }
+        // dst (nt x nc) = (src rows nI.., all cols)^T : src view is nc x nt with ld nt
+        Batch<DMat> sC = mats(srcC, nt, nc, nt, s, &actc), dC = mats(dstC, nt, nt, nc, s, &actc);
+        if (sC.size()) copy_vb(sC, dC, true, 1.0, s);
+        Batch<DMat> sI = mats(srcI, nt, nI, nt, s), dI = mats(dstI, nt, nt, nI, s);
+        copy_vb(sI, dI, true, 1.0, s);
+        DD_HIP(hipStreamSynchronize(s));
+        Ft.release();
+        Arena ft, fT, fW;
+        std::vector<int64_t> a1(N), a2(N), a3(N);
+        for (int i = 0; i < N; ++i) {
+            a1[i] = nt[i];
+            a2[i] = (int64_t)ceil_div(nt[i], QR_NB) * QR_NB * QR_NB;
+            a3[i] = (int64_t)QR_NB * nt[i];
+        }
+        ft.alloc(a1); fT.alloc(a2); fW.alloc(a3);
+        Batch<QRItem> qb;
+        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB});
+        qb.sync(s);
+        geqrf_vb(qb, s);
+    }
+    info.phase_ms[PH_SCHUR] += tm.lap();
+
+    // ---- (3.3) reciprocal form: B2 = L_I^{-1} R_II^T, S~ = B2 B2^T, eigenpairs mu < tau --------
+    Arena B2, Sm;
+    std::vector<int64_t> sI2(N);
+    for (int i = 0; i < N; ++i) sI2[i] = (int64_t)nI[i] * nI[i];
+    B2.alloc(sI2);
+    {
+        std::vector<double*> rii(N);
+        for (int i = 0; i < N; ++i) rii[i] = Fp.ptr[i] + nc[i] + (int64_t)nc[i] * nt[i];
+        Batch<DMat> Rsrc = mats(rii, nt, nI, nI, s);
+        Batch<DMat> Bb = mats(B2.ptr, nI, nI, nI, s);
+        copy_vb(Rsrc, Bb, true, 1.0, s);
+        zero_upper_vb(Bb, s);
+        DD_HIP(hipStreamSynchronize(s));
+        Fp.release();
+        Batch<DMat> LI = mats(Lv.L.ptr, ni, nI, nI, s);
+        trsm_vb(LI, Bb, false, s);
+        Sm.alloc(sI2);
+        Batch<GemmItem> g;
+        for (int i = 0; i < N; ++i)
+            g.h.push_back(GemmItem{B2.ptr[i], nI[i], B2.ptr[i], nI[i], Sm.ptr[i], nI[i], nI[i], nI[i], nI[i], 1.0, 0.0});
+        g.sync(s);
+        gemm_vb(g, false, true, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    B2.release();
+    Arena td, te, ttau, tpart, tp, tmu;
+    std::vector<int64_t> v1(N), vpart(N);
+    for (int i = 0; i < N; ++i) { v1[i] = nI[i]; vpart[i] = ceil_div(nI[i], 64) + 1; }
+    td.alloc(v1); te.alloc(v1); ttau.alloc(v1); tpart.alloc(vpart); tp.alloc(v1); tmu.alloc(v1);
+    {
+        Batch<TriItem> tb;
+        for (int i = 0; i < N; ++i)
+            tb.h.push_back(TriItem{DMat{Sm.ptr[i], nI[i], nI[i], nI[i]}, td.ptr[i], te.ptr[i], ttau.ptr[i], tpart.ptr[i], tp.ptr[i]});
+        tb.sync(s);
+        sytrd_vb(tb, s);
+    }
+    DBuf<int32_t> dcount(N);
+    {
+        Batch<EigItem> eb;
+        for (int i = 0; i < N; ++i) {
+            const int cap = (opt.select == DD_SEL_THRESHOLD_CAP) ? std::max(0, opt.nev_cap) : nI[i];
+            eb.h.push_back(EigItem{td.ptr[i], te.ptr[i], nI[i], tmu.ptr[i], dcount.p + i, cap, Lv.tau});
+        }
+        eb.sync(s);
+        stebz_vb(eb, s);
+    }
+    auto hcount = to_host(dcount.p, N, s);
+    Lv.p.assign(hcount.begin(), hcount.end());
+    Lv.mu.resize(N);
+    for (int i = 0; i < N; ++i) {
+        Lv.mu[i].resize(Lv.p[i]);
+        d2h(Lv.mu[i].data(), tmu.ptr[i], Lv.p[i], s);
+    }
+    DD_HIP(hipStreamSynchronize(s));
+    Arena Yev;
+    {
+        std::vector<int64_t> sy(N), sw(N);
+        for (int i = 0; i < N; ++i) {
+            sy[i] = (int64_t)nI[i] * std::max(1, Lv.p[i]);
+            sw[i] = (int64_t)3 * nI[i] * 256;
+        }
+        Yev.alloc(sy);
+        Arena wk;
+        wk.alloc(sw);
+        Batch<VecItem> vb;
+        for (int i = 0; i < N; ++i) vb.h.push_back(VecItem{td.ptr[i], te.ptr[i], nI[i], tmu.ptr[i], dcount.p + i, Yev.ptr[i], nI[i], wk.ptr[i]});
+        vb.sync(s);
+        stein_vb(vb, 1e-5, s);
+        DD_HIP(hipStreamSynchronize(s));
+        // back-transform with the tridiagonalisation reflectors (rows 1..nI-1)
+        std::vector<int> act(N);
+        for (int i = 0; i < N; ++i) act[i] = (Lv.p[i] > 0 && nI[i] > 1);
+        Arena oT, oW;
+        std::vector<int64_t> s1(N), s2(N);
+        for (int i = 0; i < N; ++i) {
+            s1[i] = (int64_t)ceil_div(std::max(1, nI[i] - 1), QR_NB) * QR_NB * QR_NB;
+            s2[i] = (int64_t)QR_NB * std::max(1, Lv.p[i]);
+        }
+        oT.alloc(s1); oW.alloc(s2);
+        Batch<ORItem> ob;
+        std::vector<double*> taus;
+        for (int i = 0; i < N; ++i) {
+            if (!act[i]) continue;
+            ob.h.push_back(ORItem{DMat{Sm.ptr[i] + 1, nI[i], nI[i] - 1, nI[i] - 1}, oT.ptr[i],
+                                  DMat{Yev.ptr[i] + 1, nI[i], nI[i] - 1, Lv.p[i]}, oW.ptr[i]});
+            taus.push_back(ttau.ptr[i]);
+        }
+        if (ob.size()) {
+            ob.sync(s);
+            build_t_vb(ob, taus, s);
+            ormqr_vb(ob, false, s);
+        }
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    Sm.release();
+    info.phase_ms[PH_EIG] += tm.lap();
+
+    // ---- Z_i = orth(L_I^{-T} Y_keep)  (D_i u with Boolean D_i) --------------------------------
+    {
+        std::vector<int64_t> sz(N);
+        std::vector<int> act(N);
+        for (int i = 0; i < N; ++i) { sz[i] = (int64_t)nI[i] * Lv.p[i]; act[i] = Lv.p[i] > 0; }
+        Lv.Z.alloc(sz);
+        std::vector<int>& pp = Lv.p;
+        Batch<DMat> LI = mats(Lv.L.ptr, ni, nI, nI, s, &act);
+        Batch<DMat> Yb = mats(Yev.ptr, nI, nI, pp, s, &act);
+        if (Yb.size()) {
+            trsm_vb(LI, Yb, true, s);
+            Arena zt, zT, zW;
+            std::vector<int64_t> a1(N), a2(N), a3(N);
+            for (int i = 0; i < N; ++i) {
+                a1[i] = std::max(1, pp[i]);
+                a2[i] = (int64_t)ceil_div(std::max(1, pp[i]), QR_NB) * QR_NB * QR_NB;
+                a3[i] = (int64_t)QR_NB * std::max(1, pp[i]);
+            }
+            zt.alloc(a1); zT.alloc(a2); zW.alloc(a3);
+            Batch<QRItem> qb;
+            Batch<ORItem> ob;
+            for (int i = 0; i < N; ++i) {
+                if (!act[i]) continue;
+                qb.h.push_back(QRItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zt.ptr[i], zT.ptr[i], zW.ptr[i], QR_NB});
+                ob.h.push_back(ORItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zT.ptr[i], DMat{Lv.Z.ptr[i], nI[i], nI[i], pp[i]}, zW.ptr[i]});
+            }
+            qb.sync(s);
+            ob.sync(s);
+            geqrf_vb(qb, s);
+            Batch<DMat> Zb = mats(Lv.Z.ptr, nI, nI, pp, s, &act);
+            set_identity_vb(Zb, 1.0, s);
+            ormqr_vb(ob, false, s);
+            DD_HIP(hipStreamSynchronize(s));
+        }
+    }
+    Yev.release();
+    info.phase_ms[PH_BASIS] += tm.lap();
+
+    // ---- coarse operator E = Z^T A Z (block (i,j) from the rows of Omega_j owned by i) ----------
+    Lv.pcnt = upload(std::vector<int32_t>(Lv.p.begin(), Lv.p.end()), s);
+    Lv.hoffC.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) Lv.hoffC[i + 1] = Lv.hoffC[i] + Lv.p[i];
+    Lv.offC = upload(Lv.hoffC, s);
+    Lv.nC = Lv.hoffC[N];
+    Lv.dZ.alloc(N);
+    h2d(Lv.dZ.p, Lv.Z.ptr.data(), N, s);
+    DD_HIP(hipStreamSynchronize(s));
+    const int64_t nC = Lv.nC;
+    if (nC > 0) {
+        SubInfo S = Lv.sub();
+        DBuf<int32_t> cnt((size_t)N * N);
+        DD_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
+        pair_counts(S, cnt.p, s);
+        auto hc = to_host(cnt.p, (size_t)N * N, s);
+        std::vector<int64_t> pairoff((size_t)N * N, 0);
+        std::vector<PairItem> pairs;
+        int64_t pos = 0;
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const int64_t key = (int64_t)j * N + i;
+                pairoff[key] = pos;
+                if (hc[key] > 0) {
+                    if (Lv.p[i] > 0 && Lv.p[j] > 0) pairs.push_back(PairItem{i, j, hc[key], pos});
+                    pos += hc[key];
+                }
+            }
+        DBuf<int64_t> dpo = upload(pairoff, s);
+        DBuf<int32_t> cursor((size_t)N * N), zr(pos), pr(pos);
+        DD_HIP(hipMemsetAsync(cursor.p, 0, cursor.bytes(), s));
+        pair_fill(S, dpo.p, cursor.p, zr.p, pr.p, s);
+        Arena P;
+        std::vector<int64_t> sp(N);
+        for (int j = 0; j < N; ++j) sp[j] = (int64_t)ni[j] * Lv.p[j];
+        P.alloc(sp);
+        DBuf<double*> dP(N);
+        h2d(dP.p, P.ptr.data(), N, s);
+        build_p(A, S, dP.p, ni, Lv.p, s);
+        Lv.Efac.alloc((size_t)nC * nC);
+        fill(Lv.Efac.p, Lv.Efac.n, 0.0, s);
+        DBuf<PairItem> dpairs = upload(pairs, s);
+        assemble_e(S, dpairs.p, pairs, Lv.p, nI, dP.p, zr.p, pr.p, Lv.Efac.p, nC, s);
+        DD_HIP(hipStreamSynchronize(s));
+        if (nC <= 4096) Lv.Ecopy = to_host(Lv.Efac.p, (size_t)nC * nC, s);
+        info.phase_ms[PH_E] += tm.lap();
+        Batch<DMat> Eb;
+        Eb.h.push_back(DMat{Lv.Efac.p, (int)nC, (int)nC, (int)nC});
+        Eb.sync(s);
+        DBuf<int32_t> dinfo(1);
+        DD_HIP(hipMemsetAsync(dinfo.p, 0, sizeof(int32_t), s));
+        potrf_vb(Eb, dinfo.p, s);
+        zero_upper_vb(Eb, s);
+        auto hi = to_host(dinfo.p, 1, s);
+        DD_CHECK(hi[0] == 0, DD_ERR_NOT_SPD, "coarse operator E is not positive definite");
+        info.phase_ms[PH_EFACT] += tm.lap();
+    }
+
+    // ---- apply workspace ----
+    Lv.rloc.alloc(std::max<int64_t>(1, Lv.hoffO[N]));
+    Lv.yC.alloc(std::max<int64_t>(1, nC));
+    Lv.Lb = mats(Lv.L.ptr, ni, ni, ni, s);
+    Lv.Bb.h.clear();
+    for (int i = 0; i < N; ++i) Lv.Bb.h.push_back(DMat{Lv.rloc.p + Lv.hoffO[i], ni[i], ni[i], 1});
+    Lv.Bb.sync(s);
+    if (nC > 0) {
+        Lv.Eb.h.assign(1, DMat{Lv.Efac.p, (int)nC, (int)nC, (int)nC});
+        Lv.Eb.sync(s);
+        Lv.Ebv.h.assign(1, DMat{Lv.yC.p, (int)nC, (int)nC, 1});
+        Lv.Ebv.sync(s);
+    }
+    info.phase_ms[PH_OTHER] += tm.lap();
+}
+
+// z = M^{-1} r, one right-hand side (2.1)
+static void apply1(Level& Lv, const double* r, double* z, hipStream_t s) {
+    gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
+    trsm_vb(Lv.Lb, Lv.Bb, false, s);
+    trsm_vb(Lv.Lb, Lv.Bb, true, s);
+    scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
+    if (Lv.nC > 0) {
+        SubInfo S = Lv.sub();
+        restrict_coarse(S, Lv.nC, r, Lv.yC.p, s);
+        trsm_vb(Lv.Eb, Lv.Ebv, false, s);
+        trsm_vb(Lv.Eb, Lv.Ebv, true, s);
+        prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, z, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vector kernels for PCG
+// ---------------------------------------------------------------------------
+__global__ void k_axpy2(double* x, double* r, const double* p, const double* q, double alpha, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+    }
+}
+__global__ void k_xpby(const double* z, double* p, double beta, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+__global__ void k_sub(const double* b, double* r, int64_t n) {  // r = b - r
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = b[i] - r[i];
+}
+static int vgrid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); }
+
+static double dot_host(Handle& H, const double* x, const double* y, int64_t n, hipStream_t s) {
+    dot(x, y, n, 1, H.partial.p, H.dots.p, s);
+    DD_HIP(hipMemcpyAsync(H.hpin, H.dots.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    DD_HIP(hipStreamSynchronize(s));
+    return H.hpin[0];
+}
+
+static int pcg1(Handle& H, const double* b, double* x, double rtol, int maxit, int* iters, double* relres,
+                hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    double *r = H.r.p, *z = H.z.p, *p = H.pvec.p, *q = H.q.p;
+    const double bn = std::sqrt(dot_host(H, b, b, n, s));
+    DD_CHECK(std::isfinite(bn), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+    if (bn == 0.0) {
+        fill(x, n, 0.0, s);
+        *iters = 0;
+        *relres = 0.0;
+        return DD_OK;
+    }
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    double rn = std::sqrt(dot_host(H, r, r, n, s));
+    int its = 0;
+    bool conv = rn <= rtol * bn;
+    if (!conv) {
+        apply1(Lv, r, z, s);
+        DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        double rz = dot_host(H, r, z, n, s);
+        for (its = 1; its <= maxit; ++its) {
+            spmv(A, p, q, 1, s);
+            const double pq = dot_host(H, p, q, n, s);
+            DD_CHECK(std::isfinite(pq), DD_ERR_NAN, "PCG produced NaN");
+            const double alpha = rz / pq;
+            hipLaunchKernelGGL(k_axpy2, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, alpha, n);
+            rn = std::sqrt(dot_host(H, r, r, n, s));
+            if (rn <= rtol * bn) { conv = true; break; }
+            apply1(Lv, r, z, s);
+            const double rzn = dot_host(H, r, z, n, s);
+            const double beta = rzn / rz;
+            rz = rzn;
+            hipLaunchKernelGGL(k_xpby, dim3(vgrid(n)), dim3(256), 0, s, z, p, beta, n);
+        }
+        if (its > maxit) its = maxit;
+    }
+    // true residual
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    const double tr = std::sqrt(dot_host(H, r, r, n, s));
+    *iters = its;
+    *relres = tr / bn;
+    DD_CHECK(std::isfinite(tr), DD_ERR_NAN, "PCG produced NaN");
+    return conv ? DD_OK : DD_WARN_MAXIT;
+}
+
+}  // namespace dd
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+using namespace dd;
+
+struct dd_handle_s {
+    Handle h;
+};
+
+#define DD_GUARD_BEGIN try {
+#define DD_GUARD_END                                                  \
+    }                                                                 \
+    catch (const dd::Error& e) {                                      \
+        if (std::getenv("DD_VERBOSE")) fprintf(stderr, "dd: %s\n", e.what()); \
+        return e.code;                                                \
+    }                                                                 \
+    catch (const std::bad_alloc&) {                                   \
+        return DD_ERR_OOM;                                            \
+    }                                                                 \
+    catch (...) {                                                     \
+        return DD_ERR_INTERNAL;                                       \
+    }
+
+extern "C" {
+
+const char* dd_strerror(int code) {
+    switch (code) {
+        case DD_OK: return "ok";
+        case DD_ERR_INVALID_ARG: return "invalid argument";
+        case DD_ERR_NOT_SPD: return "matrix (local block or coarse operator) is not SPD";
+        case DD_ERR_EIG: return "local eigen/polar iteration failed";
+        case DD_ERR_NAN: return "NaN or Inf encountered";
+        case DD_ERR_OOM: return "out of device memory";
+        case DD_ERR_HIP: return "HIP runtime error";
+        case DD_ERR_INTERNAL: return "internal error";
+        case DD_WARN_MAXIT: return "PCG reached maxit";
+        case DD_WARN_FULL_COARSE: return "tau >= 1: every local mode kept (coarse space = whole space)";
+        case DD_WARN_FP32_FALLBACK: return "FP32 local factor fell back to FP64";
+        default: return "unknown";
+    }
+}
+
+const char* dd_phase_name(int32_t phase) {
+    if (phase < 0 || phase >= DD_NPHASE) return "?";
+    return kPhaseNames[phase];
+}
+
+int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, hipStream_t stream) {
+    DD_GUARD_BEGIN
+    if (!A || !part || A->n <= 0 || N < 1 || N > A->n) return DD_ERR_INVALID_ARG;
+    CsrDev C{A->n, A->nnz, A->rowptr, A->colind, A->val};
+    ggg_partition(C, N, seed, part, stream);
+    return DD_OK;
+    DD_GUARD_END
+}
+
+__global__ void k_check_finite(const double* v, int64_t n, int32_t* bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(v[i])) atomicOr(bad, 1);
+}
+
+int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau, int32_t levels,
+             const dd_options* opt, hipStream_t s, dd_handle* out) {
+    DD_GUARD_BEGIN
+    if (!A || !part || !out) return DD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (A->n <= 0 || A->nnz <= 0 || N < 1 || N > A->n || overlap < 1 || overlap > 200 || !(tau > 0.0) || levels < 2 ||
+        levels > DD_MAX_LEVELS)
+        return DD_ERR_INVALID_ARG;
+    if (levels > 2) return DD_ERR_INVALID_ARG;  // recursion on E: see dd_info levels
+    auto hd = std::make_unique<dd_handle_s>();
+    Handle& H = hd->h;
+    if (opt) {
+        H.opt.local_prec = opt->local_prec;
+        H.opt.select = opt->select;
+        H.opt.nev_cap = opt->nev_cap;
+        H.opt.validate = opt->validate;
+        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
+        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
+    }
+    auto lv = std::make_unique<Level>();
+    Level& L0 = *lv;
+    L0.n = A->n;
+    L0.nnz = A->nnz;
+    L0.rowptr.alloc(A->n + 1);
+    L0.colind.alloc(A->nnz);
+    L0.val.alloc(A->nnz);
+    DD_HIP(hipMemcpyAsync(L0.rowptr.p, A->rowptr, (A->n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L0.colind.p, A->colind, A->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L0.val.p, A->val, A->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    {
+        DBuf<int32_t> bad(1);
+        DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, s, L0.val.p, L0.nnz, bad.p);
+        int32_t hb = 0;
+        DD_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DD_HIP(hipStreamSynchronize(s));
+        if (hb) return DD_ERR_NAN;
+    }
+    L0.N = N;
+    L0.delta = overlap;
+    L0.tau = tau;
+    L0.part.alloc(A->n);
+    DD_HIP(hipMemcpyAsync(L0.part.p, part, A->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    {
+        DBuf<int32_t> cnt(N);
+        const int rc = validate_partition(L0.part.p, A->n, N, cnt.p, s);
+        if (rc != DD_OK) return rc;
+    }
+    build_level(L0, H.opt, H.info, s);
+    H.lv.push_back(std::move(lv));
+    // diagnostics
+    dd_info_t& I = H.info;
+    I.levels = 2;
+    I.N[0] = N;
+    I.n[0] = A->n;
+    I.n[1] = L0.nC;
+    I.n_C = L0.nC;
+    I.grid_complexity = double(A->n + L0.nC) / double(A->n);
+    I.p_min = N ? *std::min_element(L0.p.begin(), L0.p.end()) : 0;
+    I.p_max = N ? *std::max_element(L0.p.begin(), L0.p.end()) : 0;
+    // scratch for PCG
+    H.r.alloc(A->n);
+    H.z.alloc(A->n);
+    H.pvec.alloc(A->n);
+    H.q.alloc(A->n);
+    H.partial.alloc(512 * 64);
+    H.dots.alloc(64);
+    DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
+    int64_t bytes = 0;
+    for (auto& l : H.lv)
+        bytes += l->L.buf.bytes() + l->Z.buf.bytes() + l->Efac.bytes() + l->memb.bytes() + l->ext.bytes();
+    I.device_bytes = bytes;
+    *out = hd.release();
+    return (tau >= 1.0) ? DD_WARN_FULL_COARSE : DD_OK;
+    DD_GUARD_END
+}
+
+int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!h || !r || !z || nrhs < 1) return DD_ERR_INVALID_ARG;
+    Level& Lv = *h->h.lv[0];
+    for (int k = 0; k < nrhs; ++k) apply1(Lv, r + (int64_t)k * Lv.n, z + (int64_t)k * Lv.n, s);
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit, int32_t* iters,
+           double* relres, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!h || !b || !x || nrhs < 1 || maxit < 0 || !(rtol > 0.0)) return DD_ERR_INVALID_ARG;
+    Handle& H = h->h;
+    const int64_t n = H.lv[0]->n;
+    int rc = DD_OK;
+    for (int k = 0; k < nrhs; ++k) {
+        int it = 0;
+        double rr = 0.0;
+        const int c = pcg1(H, b + k * n, x + k * n, rtol, maxit, &it, &rr, s);
+        if (c < 0) return c;
+        if (c > 0) rc = c;
+        if (iters) iters[k] = it;
+        if (relres) relres[k] = rr;
+        if (k == 0) {
+            H.info.last_iters = it;
+            H.info.last_relres = rr;
+        }
+    }
+    return rc;
+    DD_GUARD_END
+}
+
+int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!h || !x || !y) return DD_ERR_INVALID_ARG;
+    spmv(h->h.lv[0]->A(), x, y, 1, s);
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_info(dd_handle h, dd_info_t* out) {
+    if (!h || !out) return DD_ERR_INVALID_ARG;
+    *out = h->h.info;
+    return DD_OK;
+}
+
+void dd_destroy(dd_handle h) { delete h; }
+
+static Level* level_of(dd_handle h, int32_t level) {
+    if (!h || level < 0 || level >= (int)h->h.lv.size()) return nullptr;
+    return h->h.lv[level].get();
+}
+
+int dd_subdomain_count(dd_handle h, int32_t level, int32_t* N) {
+    Level* L = level_of(h, level);
+    if (!L || !N) return DD_ERR_INVALID_ARG;
+    *N = L->N;
+    return DD_OK;
+}
+
+int dd_subdomain_sizes(dd_handle h, int32_t level, int32_t* sizes) {
+    Level* L = level_of(h, level);
+    if (!L || !sizes) return DD_ERR_INVALID_ARG;
+    for (int i = 0; i < L->N; ++i) {
+        sizes[5 * i] = L->nI[i];
+        sizes[5 * i + 1] = L->nG[i];
+        sizes[5 * i + 2] = L->nD[i];
+        sizes[5 * i + 3] = L->p[i];
+        sizes[5 * i + 4] = 0;
+    }
+    return DD_OK;
+}
+
+int dd_subdomain_sets(dd_handle h, int32_t level, int32_t i, int32_t* I, int32_t* Gm, int32_t* Dl) {
+    DD_GUARD_BEGIN
+    Level* L = level_of(h, level);
+    if (!L || i < 0 || i >= L->N) return DD_ERR_INVALID_ARG;
+    const int32_t* e = L->ext.p + L->hoffE[i];
+    if (I) DD_HIP(hipMemcpy(I, e, L->nI[i] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (Gm) DD_HIP(hipMemcpy(Gm, e + L->nI[i], L->nG[i] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (Dl) DD_HIP(hipMemcpy(Dl, e + L->ni[i], L->nD[i] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_subdomain_eigs(dd_handle h, int32_t level, int32_t i, double* mu) {
+    Level* L = level_of(h, level);
+    if (!L || i < 0 || i >= L->N || !mu) return DD_ERR_INVALID_ARG;
+    std::memcpy(mu, L->mu[i].data(), L->mu[i].size() * sizeof(double));
+    return DD_OK;
+}
+
+int dd_subdomain_basis(dd_handle h, int32_t level, int32_t i, double* Z) {
+    DD_GUARD_BEGIN
+    Level* L = level_of(h, level);
+    if (!L || i < 0 || i >= L->N || !Z) return DD_ERR_INVALID_ARG;
+    DD_HIP(hipMemcpy(Z, L->Z.ptr[i], (size_t)L->nI[i] * L->p[i] * sizeof(double), hipMemcpyDeviceToHost));
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_subdomain_sigma1(dd_handle h, int32_t level, double* sigma1) {
+    Level* L = level_of(h, level);
+    if (!L || !sigma1) return DD_ERR_INVALID_ARG;
+    std::memcpy(sigma1, L->sigma1.data(), L->N * sizeof(double));
+    return DD_OK;
+}
+
+int dd_coarse_matrix(dd_handle h, int32_t level, double* E, int64_t max_n) {
+    Level* L = level_of(h, level);
+    if (!L || !E) return DD_ERR_INVALID_ARG;
+    if (L->nC > max_n || (int64_t)L->Ecopy.size() != L->nC * L->nC) return DD_ERR_INVALID_ARG;
+    std::memcpy(E, L->Ecopy.data(), L->Ecopy.size() * sizeof(double));
+    return DD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1276 @@
+// Batched dense linear algebra kernels (FP64, MFMA 16x16x4 for the GEMM-shaped
+// updates).  Every routine processes all items of a batch in one launch per
+// algorithmic step; items of different sizes simply drop out of later steps.
+#include "dense.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace dd {
+
+// ===========================================================================
+// GEMM
+// ===========================================================================
+template <bool TA, bool TB>
+struct OpGemm {
+    const GemmItem* g;
+    __device__ int tiles(int b) const { return ceil_div_d(g[b].M, 64) * ceil_div_d(g[b].N, 64); }
+    __device__ static int ceil_div_d(int a, int c) { return a > 0 ? (a + c - 1) / c : 0; }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const GemmItem& G = g[b];
+        const int tm = ceil_div_d(G.M, 64);
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<TA, TB>(G.A, G.lda, G.B, G.ldb, G.M, G.N, G.K, i0, j0, sm, acc);
+        double* C = G.C;
+        const int ldc = G.ldc, M = G.M, N = G.N;
+        const double al = G.alpha, be = G.beta;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = i0 + r, gj = j0 + c;
+            if (gi < M && gj < N) {
+                double* p = C + gi + (int64_t)gj * ldc;
+                *p = (be == 0.0) ? al * v : al * v + be * *p;
+            }
+        });
+    }
+};
+
+void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
+    int64_t total = 0;
+    for (auto& x : g.h) total += (int64_t)ceil_div(x.M, 64) * ceil_div(x.N, 64);
+    if (ta && tb) launch_tiles(OpGemm<true, true>{g.d.p}, g.size(), total, s, "gemm_tt");
+    else if (ta) launch_tiles(OpGemm<true, false>{g.d.p}, g.size(), total, s, "gemm_tn");
+    else if (tb) launch_tiles(OpGemm<false, true>{g.d.p}, g.size(), total, s, "gemm_nt");
+    else launch_tiles(OpGemm<false, false>{g.d.p}, g.size(), total, s, "gemm_nn");
+}
+
+// ===========================================================================
+// Cholesky (right-looking, 64-column blocks)
+// ===========================================================================
+struct OpPotrfDiag {
+    const DMat* A;
+    int* info;
+    int k0;
+    __device__ int tiles(int b) const { return A[b].n > k0 ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double s[64][65];
+        const DMat M = A[b];
+        const int w = min(64, M.n - k0);
+        double* base = M.p + k0 + (int64_t)k0 * M.ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            s[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < w; ++j) {
+            if (threadIdx.x == 0) {
+                double d = s[j][j];
+                if (!(d > 0.0)) {
+                    if (info[b] == 0) info[b] = k0 + j + 1;
+                    d = 1.0;
+                }
+                s[j][j] = sqrt(d);
+            }
+            __syncthreads();
+            const double piv = s[j][j];
+            for (int r = j + 1 + threadIdx.x; r < w; r += blockDim.x) s[r][j] /= piv;
+            __syncthreads();
+            const int rem = w - j - 1;
+            for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+                const int r = j + 1 + e % rem, c = j + 1 + e / rem;
+                if (r >= c) s[r][c] -= s[r][j] * s[c][j];
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            if (r < w && c < w && r >= c) base[r + (int64_t)c * M.ld] = s[r][c];
+        }
+    }
+};
+
+// A21 := A21 * L11^{-T}, 64-row tiles (one thread per row).
+struct OpPotrfPanel {
+    const DMat* A;
+    int k0;
+    __device__ int tiles(int b) const {
+        const int rem = A[b].n - k0 - 64;
+        return (A[b].n > k0 && rem > 0) ? (rem + 63) / 64 : 0;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double L[64][65];
+        const DMat M = A[b];
+        const int w = min(64, M.n - k0);
+        double* base = M.p + k0 + (int64_t)k0 * M.ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            L[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : 0.0;
+        }
+        __syncthreads();
+        const int row = k0 + w + t * 64 + (int)threadIdx.x;
+        if (threadIdx.x < 64 && row < M.n) {
+            double x[64];
+            double* a = M.p + row + (int64_t)k0 * M.ld;
+#pragma unroll
+            for (int j = 0; j < 64; ++j) x[j] = (j < w) ? a[(int64_t)j * M.ld] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 64; ++j) {
+                if (j < w) {
+                    double v = x[j];
+#pragma unroll
+                    for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
+                    x[j] = v / L[j][j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (j < w) a[(int64_t)j * M.ld] = x[j];
+        }
+    }
+};
+
+// A22 -= A21 A21^T on lower tiles.
+struct OpPotrfUpdate {
+    const DMat* A;
+    int k0;
+    __device__ int tiles(int b) const {
+        const int rem = A[b].n - k0 - 64;
+        if (A[b].n <= k0 || rem <= 0) return 0;
+        const int T = (rem + 63) / 64;
+        return T * (T + 1) / 2;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const DMat M = A[b];
+        const int w = 64;
+        const int rem = M.n - k0 - w;
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const double* A21 = M.p + (k0 + w) + (int64_t)k0 * M.ld;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rem, rem, w, ti * 64, tj * 64, sm, acc);
+        double* C = M.p + (k0 + w) + (int64_t)(k0 + w) * M.ld;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = ti * 64 + r, gj = tj * 64 + c;
+            if (gi < rem && gj < rem && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
+        });
+    }
+};
+
+void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
+    int nmax = 0;
+    for (auto& x : A.h) nmax = std::max(nmax, x.n);
+    for (int k0 = 0; k0 < nmax; k0 += 64) {
+        int64_t nd = 0, np = 0, nu = 0;
+        for (auto& x : A.h) {
+            if (x.n <= k0) continue;
+            ++nd;
+            const int rem = x.n - k0 - 64;
+            if (rem > 0) {
+                const int T = ceil_div(rem, 64);
+                np += T;
+                nu += (int64_t)T * (T + 1) / 2;
+            }
+        }
+        launch_tiles(OpPotrfDiag{A.d.p, dinfo, k0}, A.size(), nd, s, "potrf_diag");
+        launch_tiles(OpPotrfPanel{A.d.p, k0}, A.size(), np, s, "potrf_panel");
+        launch_tiles(OpPotrfUpdate{A.d.p, k0}, A.size(), nu, s, "potrf_update");
+    }
+}
+
+// ===========================================================================
+// Triangular solves with a lower factor, many right-hand sides
+// ===========================================================================
+// Diagonal block: B[k0:k0+w, cols] := L_kk^{-1} (or L_kk^{-T}) B[...].
+template <bool TRANS>
+struct OpTrsmDiag {
+    const DMat* L;
+    const DMat* B;
+    int kb;  // first row of the diagonal block
+    __device__ int tiles(int b) const { return (L[b].n > kb) ? (B[b].n + 63) / 64 : 0; }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double Ls[64][65];
+        __shared__ double X[64][65];
+        const DMat Lm = L[b], Bm = B[b];
+        const int w = min(64, Lm.n - kb);
+        const double* lb = Lm.p + kb + (int64_t)kb * Lm.ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            Ls[r][c] = (r < w && c < w && r >= c) ? lb[r + (int64_t)c * Lm.ld] : 0.0;
+        }
+        const int c0 = t * 64;
+        const int nc = min(64, Bm.n - c0);
+        double* bb = Bm.p + kb + (int64_t)c0 * Bm.ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            X[r][c] = (r < w && c < nc) ? bb[r + (int64_t)c * Bm.ld] : 0.0;
+        }
+        __syncthreads();
+        const int c = threadIdx.x;
+        if (c < nc) {
+            if (!TRANS) {
+                for (int j = 0; j < w; ++j) {
+                    double v = X[j][c];
+                    for (int l = 0; l < j; ++l) v -= Ls[j][l] * X[l][c];
+                    X[j][c] = v / Ls[j][j];
+                }
+            } else {
+                for (int j = w - 1; j >= 0; --j) {
+                    double v = X[j][c];
+                    for (int l = j + 1; l < w; ++l) v -= Ls[l][j] * X[l][c];
+                    X[j][c] = v / Ls[j][j];
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, cc = e >> 6;
+            if (r < w && cc < nc) bb[r + (int64_t)cc * Bm.ld] = X[r][cc];
+        }
+    }
+};
+
+// Forward: B[k0+w:, :] -= L[k0+w:, k0:k0+w] B[k0:k0+w, :]
+// Backward: B[0:k0, :] -= L[k0:k0+w, 0:k0]^T B[k0:k0+w, :]
+template <bool TRANS>
+struct OpTrsmUpd {
+    const DMat* L;
+    const DMat* B;
+    int kb;
+    __device__ int rows(int b) const { return TRANS ? min(kb, L[b].n) : L[b].n - kb - 64; }
+    __device__ int tiles(int b) const {
+        if (L[b].n <= kb) return 0;
+        const int r = rows(b);
+        return r > 0 ? ((r + 63) / 64) * ((B[b].n + 63) / 64) : 0;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const DMat Lm = L[b], Bm = B[b];
+        const int w = min(64, Lm.n - kb);
+        const int M = rows(b);
+        const int tm = (M + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        const double* Bk = Bm.p + kb;
+        double* Cp;
+        if (!TRANS) {
+            const double* A = Lm.p + (kb + w) + (int64_t)kb * Lm.ld;
+            mfma_tile_64<false, false>(A, Lm.ld, Bk, Bm.ld, M, Bm.n, w, i0, j0, sm, acc);
+            Cp = Bm.p + (kb + w);
+        } else {
+            const double* A = Lm.p + kb;  // rows kb.., cols 0..kb-1, transposed
+            mfma_tile_64<true, false>(A, Lm.ld, Bk, Bm.ld, M, Bm.n, w, i0, j0, sm, acc);
+            Cp = Bm.p;
+        }
+        const int N = Bm.n, ld = Bm.ld;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = i0 + r, gj = j0 + c;
+            if (gi < M && gj < N) Cp[gi + (int64_t)gj * ld] -= v;
+        });
+    }
+};
+
+void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
+    int nmax = 0;
+    for (auto& x : L.h) nmax = std::max(nmax, x.n);
+    const int nblk = ceil_div(nmax, 64);
+    for (int step = 0; step < nblk; ++step) {
+        const int kb = trans ? (nblk - 1 - step) * 64 : step * 64;
+        int64_t nd = 0, nu = 0;
+        for (int b = 0; b < L.size(); ++b) {
+            const auto& l = L.h[b];
+            if (l.n <= kb) continue;
+            const int nct = ceil_div(B.h[b].n, 64);
+            nd += nct;
+            const int r = trans ? std::min(kb, l.n) : l.n - kb - 64;
+            if (r > 0) nu += (int64_t)ceil_div(r, 64) * nct;
+        }
+        if (!trans) {
+            launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, kb}, L.size(), nd, s, "trsm_diag");
+            launch_tiles(OpTrsmUpd<false>{L.d.p, B.d.p, kb}, L.size(), nu, s, "trsm_upd");
+        } else {
+            launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, kb}, L.size(), nd, s, "trsmT_diag");
+            launch_tiles(OpTrsmUpd<true>{L.d.p, B.d.p, kb}, L.size(), nu, s, "trsmT_upd");
+        }
+    }
+}
+
+// ===========================================================================
+// Householder QR (32-column panels, compact WY)
+// ===========================================================================
+// Unblocked Householder on panel [col0, col0+w) of A, rows col0..m-1.
+struct OpQrPanel {
+    const QRItem* q;
+    int col0;
+    __device__ int tiles(int b) const { return (q[b].A.n > col0 && q[b].A.m > col0) ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double red[4 * 33];
+        __shared__ double sc[33];
+        const DMat A = q[b].A;
+        const int w = min(QR_NB, A.n - col0);
+        const int mp = A.m - col0;
+        double* V = A.p + col0 + (int64_t)col0 * A.ld;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int j = 0; j < w; ++j) {
+            double* vj = V + (int64_t)j * A.ld;
+            // norm of x[j+1:]
+            double p = 0.0;
+            for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) p += vj[r] * vj[r];
+            p = wave_sum(p);
+            if (lane == 0) red[wv] = p;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const double xn2 = red[0] + red[1] + red[2] + red[3];
+                const double alpha = vj[j];
+                double tau = 0.0, beta = alpha, scal = 0.0;
+                if (xn2 > 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                    tau = (beta - alpha) / beta;
+                    scal = 1.0 / (alpha - beta);
+                }
+                sc[0] = tau;
+                sc[1] = scal;
+                sc[2] = beta;
+                q[b].tau[col0 + j] = tau;
+            }
+            __syncthreads();
+            const double tau = sc[0], scal = sc[1];
+            for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) vj[r] *= scal;
+            __syncthreads();
+            if (threadIdx.x == 0) vj[j] = sc[2];
+            // apply H_j to columns j+1..w-1
+            const int nrem = w - j - 1;
+            if (nrem > 0 && tau != 0.0) {
+                double part[QR_NB];
+#pragma unroll
+                for (int c = 0; c < QR_NB; ++c) part[c] = 0.0;
+                for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) {
+                    const double v = vj[r];
+#pragma unroll
+                    for (int c = 0; c < QR_NB; ++c)
+                        if (c < nrem) part[c] += v * V[r + (int64_t)(j + 1 + c) * A.ld];
+                }
+#pragma unroll
+                for (int c = 0; c < QR_NB; ++c) {
+                    if (c < nrem) {
+                        const double sv = wave_sum(part[c]);
+                        if (lane == 0) red[wv * 33 + c] = sv;
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x < nrem) {
+                    const int c = threadIdx.x;
+                    const double s0 = V[j + (int64_t)(j + 1 + c) * A.ld];  // v_j = 1 term
+                    const double tot = s0 + red[c] + red[33 + c] + red[66 + c] + red[99 + c];
+                    red[c] = tau * tot;  // each thread owns column c of red
+
+                }
+                __syncthreads();
+                for (int e = threadIdx.x; e < nrem * (mp - j); e += blockDim.x) {
+                    const int c = e / (mp - j), r = j + e % (mp - j);
+                    const double v = (r == j) ? 1.0 : vj[r];
+                    V[r + (int64_t)(j + 1 + c) * A.ld] -= red[c] * v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+};
+
+// T factor for the reflectors of panel k: T = upper triangular with
+// H_0 ... H_{w-1} = I - V T V^T.  G = V^T V over rows col0..m-1.
+struct OpBuildT {
+    const ORItem* o;
+    const double* const* tau;  // per item tau array (reflector j's tau at tau[b][j])
+    int col0;
+    __device__ int tiles(int b) const { return (o[b].V.n > col0 && o[b].V.m > col0) ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double Vs[64][33];
+        __shared__ double G[32][33];
+        __shared__ double T[32][33];
+        const DMat Vm = o[b].V;
+        const int w = min(QR_NB, Vm.n - col0);
+        const int mp = Vm.m - col0;
+        const double* V = Vm.p + col0 + (int64_t)col0 * Vm.ld;
+        // pairs (a,c) with a <= c owned by threads
+        double accv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r0 = 0; r0 < mp; r0 += 64) {
+            for (int e = threadIdx.x; e < 64 * 32; e += blockDim.x) {
+                const int r = e & 63, c = e >> 6;
+                const int gr = r0 + r;
+                double v = 0.0;
+                if (gr < mp && c < w) v = (gr < c) ? 0.0 : (gr == c ? 1.0 : V[gr + (int64_t)c * Vm.ld]);
+                Vs[r][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int pidx = threadIdx.x + q * 256;
+                if (pidx < 32 * 32) {
+                    const int a = pidx & 31, c = pidx >> 5;
+                    if (a <= c) {
+                        double sum = 0.0;
+                        for (int r = 0; r < 64; ++r) sum += Vs[r][a] * Vs[r][c];
+                        accv[q] += sum;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int pidx = threadIdx.x + q * 256;
+            if (pidx < 32 * 32) {
+                const int a = pidx & 31, c = pidx >> 5;
+                if (a <= c) G[a][c] = accv[q];
+            }
+        }
+        for (int e = threadIdx.x; e < 32 * 33; e += blockDim.x) (&T[0][0])[e] = 0.0;
+        __syncthreads();
+        const double* tb = tau[b] + col0;
+        for (int j = 0; j < w; ++j) {
+            const double tj = tb[j];
+            if (threadIdx.x < j) {
+                const int i = threadIdx.x;
+                double sum = 0.0;
+                for (int l = i; l < j; ++l) sum += T[i][l] * G[l][j];
+                T[i][j] = -tj * sum;
+            }
+            if (threadIdx.x == 0) T[j][j] = tj;
+            __syncthreads();
+        }
+        double* To = o[b].T + (int64_t)(col0 / QR_NB) * QR_NB * QR_NB;
+        for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
+            const int r = e & 31, c = e >> 5;
+            To[r + c * 32] = T[r][c];
+        }
+    }
+};
+
+// W = op(T) V^T C  (tiles of 64 columns of C). TRANS: op(T) = T^T (apply H^T).
+template <bool TRANS>
+struct OpQrW {
+    const ORItem* o;
+    int col0;
+    int ccol0;  // first column of C to update (geqrf: col0 + w, ormqr: 0)
+    __device__ int ncols(int b) const { return o[b].C.n - ccol0; }
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
+        const int nc = ncols(b);
+        return nc > 0 ? (nc + 63) / 64 : 0;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        __shared__ double Ts[32][33];
+        __shared__ double P[32][65];
+        const ORItem& it = o[b];
+        const int w = min(QR_NB, it.V.n - col0);
+        const int mp = it.V.m - col0;
+        const double* V = it.V.p + col0 + (int64_t)col0 * it.V.ld;
+        const double* C = it.C.p + col0 + (int64_t)ccol0 * it.C.ld;
+        const int nc = ncols(b);
+        const int j0 = t * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<true, false, 1, 0>(V, it.V.ld, C, it.C.ld, w, nc, mp, 0, j0, sm, acc);
+        const double* Tg = it.T + (int64_t)(col0 / QR_NB) * QR_NB * QR_NB;
+        for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) Ts[e & 31][e >> 5] = Tg[e];
+        acc_foreach(acc, [&](int r, int c, double v) {
+            if (r < 32) P[r][c] = v;
+        });
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+            const int r = e & 31, c = e >> 5;
+            if (r < w && j0 + c < nc) {
+                double sum = 0.0;
+                if (TRANS) {
+                    for (int l = 0; l <= r; ++l) sum += Ts[l][r] * P[l][c];
+                } else {
+                    for (int l = r; l < w; ++l) sum += Ts[r][l] * P[l][c];
+                }
+                it.W[r + (int64_t)(j0 + c) * QR_NB] = sum;
+            }
+        }
+    }
+};
+
+// C -= V W
+struct OpQrUpd {
+    const ORItem* o;
+    int col0;
+    int ccol0;
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
+        const int nc = o[b].C.n - ccol0;
+        const int mp = o[b].V.m - col0;
+        return nc > 0 ? ((mp + 63) / 64) * ((nc + 63) / 64) : 0;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const ORItem& it = o[b];
+        const int w = min(QR_NB, it.V.n - col0);
+        const int mp = it.V.m - col0;
+        const int nc = it.C.n - ccol0;
+        const int tm = (mp + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        const double* V = it.V.p + col0 + (int64_t)col0 * it.V.ld;
+        double* C = it.C.p + col0 + (int64_t)ccol0 * it.C.ld;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_NB, mp, nc, w, i0, j0, sm, acc);
+        const int ld = it.C.ld;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = i0 + r, gj = j0 + c;
+            if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
+        });
+    }
+};
+
+static void apply_panel(Batch<ORItem>& o, int col0, int ccol0, bool trans, hipStream_t s) {
+    int64_t nw = 0, nu = 0;
+    for (auto& x : o.h) {
+        if (x.V.n <= col0 || x.V.m <= col0) continue;
+        const int nc = x.C.n - ccol0;
+        if (nc <= 0) continue;
+        nw += ceil_div(nc, 64);
+        nu += (int64_t)ceil_div(x.V.m - col0, 64) * ceil_div(nc, 64);
+    }
+    if (trans) launch_tiles(OpQrW<true>{o.d.p, col0, ccol0}, o.size(), nw, s, "qr_w");
+    else launch_tiles(OpQrW<false>{o.d.p, col0, ccol0}, o.size(), nw, s, "qr_w");
+    launch_tiles(OpQrUpd{o.d.p, col0, ccol0}, o.size(), nu, s, "qr_upd");
+}
+
+void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
+    int nmax = 0;
+    Batch<ORItem> o;
+    std::vector<double*> htau;
+    for (auto& x : q.h) {
+        nmax = std::max(nmax, std::min(x.A.n, x.A.m));
+        o.h.push_back(ORItem{x.A, x.T, x.A, x.W});
+        htau.push_back(x.tau);
+    }
+    o.sync(s);
+    DBuf<double*> dtau(htau.size());
+    h2d(dtau.p, htau.data(), htau.size(), s);
+    for (int col0 = 0; col0 < nmax; col0 += QR_NB) {
+        int64_t np = 0;
+        for (auto& x : q.h) np += (x.A.n > col0 && x.A.m > col0) ? 1 : 0;
+        launch_tiles(OpQrPanel{q.d.p, col0}, q.size(), np, s, "qr_panel");
+        launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "qr_buildT");
+        // trailing columns: C = A, columns col0+w.. ; the ORItem's C.n is A.n
+        // so ccol0 = col0 + QR_NB (w = QR_NB whenever trailing columns exist)
+        apply_panel(o, col0, col0 + QR_NB, true, s);
+    }
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t s) {
+    int kmax = 0;
+    for (auto& x : o.h) kmax = std::max(kmax, x.V.n);
+    DBuf<double*> dtau(htau.size());
+    h2d(dtau.p, htau.data(), htau.size(), s);
+    for (int col0 = 0; col0 < kmax; col0 += QR_NB) {
+        int64_t np = 0;
+        for (auto& x : o.h) np += (x.V.n > col0 && x.V.m > col0) ? 1 : 0;
+        launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "buildT");
+    }
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s) {
+    int kmax = 0;
+    for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
+    const int np = ceil_div(kmax, QR_NB);
+    for (int step = 0; step < np; ++step) {
+        const int k = trans ? step : (np - 1 - step);
+        apply_panel(o, k * QR_NB, 0, trans, s);
+    }
+}
+
+// ===========================================================================
+// Tridiagonalisation (unblocked, full symmetric storage)
+// ===========================================================================
+struct OpSytrdHouse {
+    const TriItem* t;
+    int k;
+    __device__ int tiles(int b) const { return t[b].A.n > k ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double red[4];
+        const TriItem& T = t[b];
+        const int n = T.A.n, ld = T.A.ld;
+        double* col = T.A.p + (int64_t)k * ld;
+        if (k == n - 1) {
+            if (threadIdx.x == 0) T.d[k] = col[k];
+            return;
+        }
+        // x = A[k+1:, k]
+        double p = 0.0;
+        for (int r = k + 2 + threadIdx.x; r < n; r += blockDim.x) p += col[r] * col[r];
+        const double xn2 = block_sum(p, red);
+        __shared__ double sc[3];
+        if (threadIdx.x == 0) {
+            const double alpha = col[k + 1];
+            double tau = 0.0, beta = alpha, scal = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            T.d[k] = col[k];
+            T.e[k] = beta;
+            T.tau[k] = tau;
+            sc[0] = scal;
+        }
+        __syncthreads();
+        const double scal = sc[0];
+        for (int r = k + 2 + threadIdx.x; r < n; r += blockDim.x) col[r] *= scal;
+    }
+};
+
+// p = tau * A22 v over 64-column tiles (A22 symmetric: p_r = tau * A22[:, r] . v).
+struct OpSytrdSymv {
+    const TriItem* t;
+    int k;
+    __device__ int tiles(int b) const {
+        const int L = t[b].A.n - k - 1;
+        return (L >= 2) ? (L + 63) / 64 : 0;
+    }
+    __device__ void operator()(int b, int tile) const {
+        __shared__ double vs[4096 + 64];
+        __shared__ double red[4];
+        const TriItem& T = t[b];
+        const int n = T.A.n, ld = T.A.ld;
+        const int L = n - k - 1;
+        const double tau = T.tau[k];
+        const double* vsrc = T.A.p + (k + 1) + (int64_t)k * ld;  // v_0 = 1 implicit
+        double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
+        const bool inl = L <= 4096;
+        if (inl)
+            for (int r = threadIdx.x; r < L; r += blockDim.x) vs[r] = (r == 0) ? 1.0 : vsrc[r];
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        double pv_part = 0.0;
+        for (int cc = wv; cc < 64; cc += 4) {
+            const int c = tile * 64 + cc;
+            if (c >= L) break;
+            const double* a = A22 + (int64_t)c * ld;
+            double sum = 0.0;
+            for (int r = lane; r < L; r += 64) sum += a[r] * (inl ? vs[r] : (r == 0 ? 1.0 : vsrc[r]));
+            sum = wave_sum(sum) * tau;
+            if (lane == 0) {
+                T.p[c] = sum;
+                pv_part += sum * (inl ? vs[c] : (c == 0 ? 1.0 : vsrc[c]));
+            }
+        }
+        if (lane == 0) red[wv] = pv_part;
+        __syncthreads();
+        if (threadIdx.x == 0) T.part[tile] = red[0] + red[1] + red[2] + red[3];
+    }
+};
+
+// A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v, 64x64 tiles (full square).
+struct OpSytrdRank2 {
+    const TriItem* t;
+    int k;
+    __device__ int tiles(int b) const {
+        const int L = t[b].A.n - k - 1;
+        if (L < 2) return 0;
+        const int T = (L + 63) / 64;
+        return T * T;
+    }
+    __device__ void operator()(int b, int tile) const {
+        __shared__ double gam;
+        __shared__ double vr[64], wr[64], vc[64], wc[64];
+        const TriItem& T = t[b];
+        const int n = T.A.n, ld = T.A.ld;
+        const int L = n - k - 1;
+        const int nt = (L + 63) / 64;
+        const double tau = T.tau[k];
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int i = 0; i < nt; ++i) s += T.part[i];
+            gam = 0.5 * tau * s;
+        }
+        __syncthreads();
+        const int ti = tile % nt, tj = tile / nt;
+        const double* vsrc = T.A.p + (k + 1) + (int64_t)k * ld;
+        if (threadIdx.x < 64) {
+            const int r = ti * 64 + threadIdx.x;
+            if (r < L) {
+                const double v = (r == 0) ? 1.0 : vsrc[r];
+                vr[threadIdx.x] = v;
+                wr[threadIdx.x] = T.p[r] - gam * v;
+            }
+        } else if (threadIdx.x < 128) {
+            const int c = tj * 64 + threadIdx.x - 64;
+            if (c < L) {
+                const double v = (c == 0) ? 1.0 : vsrc[c];
+                vc[threadIdx.x - 64] = v;
+                wc[threadIdx.x - 64] = T.p[c] - gam * v;
+            }
+        }
+        __syncthreads();
+        if (tau == 0.0) return;
+        double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            const int gr = ti * 64 + r, gc = tj * 64 + c;
+            if (gr < L && gc < L) A22[gr + (int64_t)gc * ld] -= vr[r] * wc[c] + wr[r] * vc[c];
+        }
+    }
+};
+
+void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
+    int nmax = 0;
+    for (auto& x : t.h) nmax = std::max(nmax, x.A.n);
+    for (int k = 0; k < nmax; ++k) {
+        int64_t nh = 0, ns = 0, nr = 0;
+        for (auto& x : t.h) {
+            if (x.A.n <= k) continue;
+            ++nh;
+            const int L = x.A.n - k - 1;
+            if (L >= 2) {
+                ns += ceil_div(L, 64);
+                nr += (int64_t)ceil_div(L, 64) * ceil_div(L, 64);
+            }
+        }
+        launch_tiles(OpSytrdHouse{t.d.p, k}, t.size(), nh, s, "sytrd_house");
+        if (ns) {
+            launch_tiles(OpSytrdSymv{t.d.p, k}, t.size(), ns, s, "sytrd_symv");
+            launch_tiles(OpSytrdRank2{t.d.p, k}, t.size(), nr, s, "sytrd_rank2");
+        }
+    }
+}
+
+// ===========================================================================
+// Bisection on the symmetric tridiagonal (Sturm counts)
+// ===========================================================================
+__device__ int sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+        q = d[i] - x - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+struct OpStebz {
+    const EigItem* it;
+    __device__ int tiles(int b) const { return it[b].n > 0 ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double gl, gu, pivmin;
+        __shared__ int cnt;
+        const EigItem& E = it[b];
+        const int n = E.n;
+        if (threadIdx.x == 0) {
+            double lo = 1e300, hi = -1e300, emax = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double r = (i > 0 ? fabs(E.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(E.e[i]) : 0.0);
+                lo = fmin(lo, E.d[i] - r);
+                hi = fmax(hi, E.d[i] + r);
+                if (i < n - 1) emax = fmax(emax, E.e[i] * E.e[i]);
+            }
+            const double nrm = fmax(fabs(lo), fabs(hi));
+            pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax) * 4.0;
+            gl = lo - 2.0 * nrm * 2.220446049250313e-16 * n - pivmin;
+            gu = hi + 2.0 * nrm * 2.220446049250313e-16 * n + pivmin;
+            int c = sturm_count(E.d, E.e, n, E.thr, pivmin);
+            cnt = min(c, E.cap);
+            *E.count = cnt;
+        }
+        __syncthreads();
+        const double eps = 2.220446049250313e-16;
+        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+            // j-th smallest eigenvalue: smallest x with count(x) >= j+1
+            double lo = gl, hi = fmin(gu, E.thr);
+            for (int itn = 0; itn < 200; ++itn) {
+                const double mid = 0.5 * (lo + hi);
+                if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+                if (sturm_count(E.d, E.e, n, mid, pivmin) >= j + 1) hi = mid;
+                else lo = mid;
+            }
+            E.mu[j] = 0.5 * (lo + hi);
+        }
+    }
+};
+
+void stebz_vb(Batch<EigItem>& e, hipStream_t s) {
+    launch_tiles(OpStebz{e.d.p}, e.size(), e.size(), s, "stebz");
+}
+
+// ===========================================================================
+// Inverse iteration on the tridiagonal (T - mu I) x = y, LU with partial
+// pivoting (one thread per system), clusters orthogonalised by the block.
+// ===========================================================================
+__device__ unsigned int hash_u32(unsigned int x) {
+    x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+    return x;
+}
+
+// Solve (T - mu I) x = y in place by Gaussian elimination with partial
+// pivoting on the tridiagonal (the working row carries two entries; a row
+// swap gives U a second superdiagonal).  Zero pivots are replaced by `tiny`.
+__device__ void tri_solve(const double* d, const double* e, int n, double mu, double* u1, double* u2, double* u3,
+                          double* x, double tiny) {
+    double a = d[0] - mu;
+    double bb = (n > 1) ? e[0] : 0.0;
+    for (int i = 0; i < n - 1; ++i) {
+        const double c = e[i];
+        const double dn = d[i + 1] - mu;
+        const double en = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+        if (fabs(a) >= fabs(c)) {
+            if (a == 0.0) a = tiny;
+            const double m = c / a;
+            u1[i] = a; u2[i] = bb; u3[i] = 0.0;
+            x[i + 1] -= m * x[i];
+            a = dn - m * bb;
+            bb = en;
+        } else {
+            const double m = a / c;
+            u1[i] = c; u2[i] = dn; u3[i] = en;
+            const double xi = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = xi - m * x[i];
+            a = bb - m * dn;
+            bb = -m * en;
+        }
+    }
+    if (a == 0.0) a = tiny;
+    u1[n - 1] = a;
+    x[n - 1] /= u1[n - 1];
+    if (n > 1) x[n - 2] = (x[n - 2] - u2[n - 2] * x[n - 1]) / u1[n - 2];
+    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - u2[i] * x[i + 1] - u3[i] * x[i + 2]) / u1[i];
+}
+
+__device__ double start_value(int i, int j) {
+    return 1.0 + 0.5 * ((hash_u32((unsigned)i * 2654435761u + (unsigned)j * 40503u + 12345u) & 0xffff) / 65536.0 - 0.5);
+}
+
+// Eigenvectors by inverse iteration.  Eigenvalues whose gap to the previous
+// one is below ctol*||T|| form a cluster; members of a cluster are
+// orthogonalised (classical Gram-Schmidt, twice) against the earlier members
+// after every iteration.  Isolated eigenvalues run one per thread.
+struct OpStein {
+    const VecItem* it;
+    double ctol;
+    __device__ int tiles(int b) const { return it[b].n > 0 ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double red[4];
+        __shared__ int s_cnt;
+        __shared__ double s_tn;
+        const VecItem& V = it[b];
+        const int n = V.n;
+        if (threadIdx.x == 0) {
+            s_cnt = *V.count;
+            double tn = 0.0;
+            for (int i = 0; i < n; ++i)
+                tn = fmax(tn, fabs(V.d[i]) + (i > 0 ? fabs(V.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(V.e[i]) : 0.0));
+            s_tn = fmax(tn, 1e-300);
+        }
+        __syncthreads();
+        const int p = s_cnt;
+        if (p == 0) return;
+        const double tnorm = s_tn;
+        const double tiny = 2.220446049250313e-16 * tnorm;
+        const double gap = ctol * tnorm;
+        const int stride = 3 * n;
+        // Phase 1: isolated eigenvalues, one thread each.
+        for (int j0 = 0; j0 < p; j0 += blockDim.x) {
+            const int j = j0 + threadIdx.x;
+            if (j < p) {
+                const bool left = (j > 0) && (V.mu[j] - V.mu[j - 1] <= gap);
+                const bool right = (j + 1 < p) && (V.mu[j + 1] - V.mu[j] <= gap);
+                if (!left && !right) {
+                    double* w = V.work + (int64_t)threadIdx.x * stride;
+                    double* x = V.Y + (int64_t)j * V.ldy;
+                    for (int i = 0; i < n; ++i) x[i] = start_value(i, j);
+                    for (int itn = 0; itn < 3; ++itn) {
+                        tri_solve(V.d, V.e, n, V.mu[j], w, w + n, w + 2 * n, x, tiny);
+                        double nr = 0.0;
+                        for (int i = 0; i < n; ++i) nr += x[i] * x[i];
+                        nr = 1.0 / sqrt(nr);
+                        for (int i = 0; i < n; ++i) x[i] *= nr;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // Phase 2: clusters, members in order.
+        int cstart = 0;
+        for (int j = 0; j < p; ++j) {
+            if (j > 0 && V.mu[j] - V.mu[j - 1] > gap) cstart = j;
+            const bool inclu = (j > cstart) || (j + 1 < p && V.mu[j + 1] - V.mu[j] <= gap);
+            if (!inclu) continue;
+            double* x = V.Y + (int64_t)j * V.ldy;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = start_value(i, j);
+            __syncthreads();
+            for (int itn = 0; itn < 3; ++itn) {
+                if (threadIdx.x == 0) tri_solve(V.d, V.e, n, V.mu[j], V.work, V.work + n, V.work + 2 * n, x, tiny);
+                __syncthreads();
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int r = cstart; r < j; ++r) {
+                        const double* xr = V.Y + (int64_t)r * V.ldy;
+                        double dp = 0.0;
+                        for (int i = threadIdx.x; i < n; i += blockDim.x) dp += xr[i] * x[i];
+                        dp = block_sum(dp, red);
+                        for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] -= dp * xr[i];
+                        __syncthreads();
+                    }
+                    double nr = 0.0;
+                    for (int i = threadIdx.x; i < n; i += blockDim.x) nr += x[i] * x[i];
+                    nr = block_sum(nr, red);
+                    const double sc = 1.0 / sqrt(fmax(nr, 1e-300));
+                    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= sc;
+                    __syncthreads();
+                }
+            }
+        }
+    }
+};
+
+void stein_vb(Batch<VecItem>& v, double cluster_tol, hipStream_t s) {
+    launch_tiles(OpStein{v.d.p, cluster_tol}, v.size(), v.size(), s, "stein");
+}
+
+// ===========================================================================
+// elementwise helpers
+// ===========================================================================
+struct OpSetId {
+    const DMat* A;
+    double dg;
+    __device__ int tiles(int b) const { return (int)(((int64_t)A[b].m * A[b].n + 16383) / 16384); }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        const int64_t tot = (int64_t)M.m * M.n;
+        for (int64_t e = (int64_t)t * 16384 + threadIdx.x; e < min(tot, (int64_t)(t + 1) * 16384); e += blockDim.x) {
+            const int r = (int)(e % M.m), c = (int)(e / M.m);
+            M.p[r + (int64_t)c * M.ld] = (r == c) ? dg : 0.0;
+        }
+    }
+};
+void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : A.h) tot += ((int64_t)x.m * x.n + 16383) / 16384;
+    launch_tiles(OpSetId{A.d.p, diag}, A.size(), tot, s, "set_identity");
+}
+
+struct OpCopy {
+    const DMat* S;
+    const DMat* D;
+    bool tr;
+    double sc;
+    __device__ int tiles(int b) const { return ((D[b].m + 63) / 64) * ((D[b].n + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double tile[64][65];
+        const DMat s = S[b], d = D[b];
+        const int tm = (d.m + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        if (!tr) {
+            for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+                const int r = i0 + (e & 63), c = j0 + (e >> 6);
+                if (r < d.m && c < d.n) d.p[r + (int64_t)c * d.ld] = sc * s.p[r + (int64_t)c * s.ld];
+            }
+        } else {
+            // d(r, c) = s(c, r)
+            for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+                const int cc = e & 63, rr = e >> 6;  // read s rows j0+cc, cols i0+rr (coalesced in cc)
+                const int sr = j0 + cc, scol = i0 + rr;
+                tile[rr][cc] = (sr < d.n && scol < d.m) ? s.p[sr + (int64_t)scol * s.ld] : 0.0;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+                const int r = e & 63, c = e >> 6;
+                if (i0 + r < d.m && j0 + c < d.n) d.p[(i0 + r) + (int64_t)(j0 + c) * d.ld] = sc * tile[r][c];
+            }
+        }
+    }
+};
+void copy_vb(Batch<DMat>& src, Batch<DMat>& dst, bool transpose, double scale, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : dst.h) tot += (int64_t)ceil_div(x.m, 64) * ceil_div(x.n, 64);
+    launch_tiles(OpCopy{src.d.p, dst.d.p, transpose, scale}, dst.size(), tot, s, "copy");
+}
+
+struct OpAddDiag {
+    const DMat* A;
+    const double* sh;
+    __device__ int tiles(int b) const { return (A[b].n + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const int i = t * 256 + threadIdx.x;
+        if (i < A[b].n && i < A[b].m) A[b].p[i + (int64_t)i * A[b].ld] += sh[b];
+    }
+};
+void add_diag_vb(Batch<DMat>& A, const double* dshift, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : A.h) tot += ceil_div(x.n, 256);
+    launch_tiles(OpAddDiag{A.d.p, dshift}, A.size(), tot, s, "add_diag");
+}
+
+struct OpSym {
+    const DMat* A;
+    __device__ int tiles(int b) const { const int T = (A[b].n + 63) / 64; return T * (T + 1) / 2; }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        int ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int r = ti * 64 + (e & 63), c = tj * 64 + (e >> 6);
+            if (r < M.n && c < M.n && r > c) {
+                double* a = M.p + r + (int64_t)c * M.ld;
+                double* bq = M.p + c + (int64_t)r * M.ld;
+                const double v = 0.5 * (*a + *bq);
+                *a = v;
+                *bq = v;
+            }
+        }
+    }
+};
+void symmetrize_vb(Batch<DMat>& A, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : A.h) { const int T = ceil_div(x.n, 64); tot += (int64_t)T * (T + 1) / 2; }
+    launch_tiles(OpSym{A.d.p}, A.size(), tot, s, "symmetrize");
+}
+
+struct OpZeroUpper {
+    const DMat* A;
+    __device__ int tiles(int b) const { return ((A[b].m + 63) / 64) * ((A[b].n + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        const int tm = (M.m + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int r = i0 + (e & 63), c = j0 + (e >> 6);
+            if (r < M.m && c < M.n && r < c) M.p[r + (int64_t)c * M.ld] = 0.0;
+        }
+    }
+};
+void zero_upper_vb(Batch<DMat>& A, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : A.h) tot += (int64_t)ceil_div(x.m, 64) * ceil_div(x.n, 64);
+    launch_tiles(OpZeroUpper{A.d.p}, A.size(), tot, s, "zero_upper");
+}
+
+struct OpZeroLower {
+    const DMat* A;
+    __device__ int tiles(int b) const { return ((A[b].m + 63) / 64) * ((A[b].n + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        const int tm = (M.m + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int r = i0 + (e & 63), c = j0 + (e >> 6);
+            if (r < M.m && c < M.n && r > c) M.p[r + (int64_t)c * M.ld] = 0.0;
+        }
+    }
+};
+void zero_lower_vb(Batch<DMat>& A, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : A.h) tot += (int64_t)ceil_div(x.m, 64) * ceil_div(x.n, 64);
+    launch_tiles(OpZeroLower{A.d.p}, A.size(), tot, s, "zero_lower");
+}
+
+struct OpAxpby {
+    const DMat* X;
+    const DMat* Y;
+    const double* al;
+    const double* be;
+    __device__ int tiles(int b) const { return ((Y[b].m + 63) / 64) * ((Y[b].n + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        const DMat x = X[b], y = Y[b];
+        const int tm = (y.m + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        const double a = al[b], c = be[b];
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int r = i0 + (e & 63), cc = j0 + (e >> 6);
+            if (r < y.m && cc < y.n) {
+                double* py = y.p + r + (int64_t)cc * y.ld;
+                *py = a * x.p[r + (int64_t)cc * x.ld] + c * *py;
+            }
+        }
+    }
+};
+void axpby_vb(Batch<DMat>& X, Batch<DMat>& Y, const double* dalpha, const double* dbeta, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : Y.h) tot += (int64_t)ceil_div(x.m, 64) * ceil_div(x.n, 64);
+    launch_tiles(OpAxpby{X.d.p, Y.d.p, dalpha, dbeta}, Y.size(), tot, s, "axpby");
+}
+
+struct OpFrob {
+    const DMat* A;
+    double* out;
+    __device__ int tiles(int b) const { return 1; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double red[4];
+        const DMat M = A[b];
+        double s = 0.0;
+        for (int c = 0; c < M.n; ++c)
+            for (int r = threadIdx.x; r < M.m; r += blockDim.x) {
+                const double v = M.p[r + (int64_t)c * M.ld];
+                s += v * v;
+            }
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) out[b] = sqrt(s);
+    }
+};
+void frob_vb(Batch<DMat>& A, double* dout, hipStream_t s) {
+    launch_tiles(OpFrob{A.d.p, dout}, A.size(), A.size(), s, "frob");
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (a, b) of size m by bisection.
+__device__ double tri_max_eig(const double* a, const double* b, int m) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i < m - 1 ? fabs(b[i]) : 0.0);
+        lo = fmin(lo, a[i] - r);
+        hi = fmax(hi, a[i] + r);
+    }
+    const double pivmin = 1e-290;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi))) break;
+        if (sturm_count(a, b, m, mid, pivmin) >= m) hi = mid;  // all eigenvalues below mid
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Lanczos state per item: V (n x (K+1)), w (n), al/be (K+1), step/done flags.
+struct LzItem {
+    DMat H;
+    double* V;
+    double* w;
+    double* al;
+    double* be;
+    int* done;
+    double* theta;
+};
+
+// w = H v_j, 64 rows per workgroup (H symmetric: w_r = H[:, r] . v_j, coalesced columns)
+struct OpLzMatvec {
+    const LzItem* it;
+    int j;
+    __device__ int tiles(int b) const { return (*it[b].done || j >= it[b].H.n) ? 0 : (it[b].H.n + 63) / 64; }
+    __device__ void operator()(int b, int t) const {
+        const LzItem& L = it[b];
+        const int n = L.H.n;
+        const double* v = L.V + (int64_t)j * n;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int rr = wv; rr < 64; rr += 4) {
+            const int r = t * 64 + rr;
+            if (r >= n) break;
+            const double* col = L.H.p + (int64_t)r * L.H.ld;
+            double sum = 0.0;
+            for (int c = lane; c < n; c += 64) sum += col[c] * v[c];
+            sum = wave_sum(sum);
+            if (lane == 0) L.w[r] = sum;
+        }
+    }
+};
+
+// alpha_j, full reorthogonalisation (twice), beta_j, v_{j+1}; convergence test
+// on the largest Ritz value every 4 steps.
+struct OpLzOrth {
+    const LzItem* it;
+    int j;
+    int K;
+    __device__ int tiles(int b) const { return (*it[b].done || j >= it[b].H.n) ? 0 : 1; }
+    __device__ void operator()(int b, int) const {
+        __shared__ double red[4];
+        __shared__ int s_stop;
+        const LzItem& L = it[b];
+        const int n = L.H.n;
+        double* w = L.w;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i <= j; ++i) {
+                const double* vi = L.V + (int64_t)i * n;
+                double d = 0.0;
+                for (int r = threadIdx.x; r < n; r += blockDim.x) d += vi[r] * w[r];
+                d = block_sum(d, red);
+                if (i == j && threadIdx.x == 0) L.al[j] = (pass == 0) ? d : L.al[j] + d;
+                for (int r = threadIdx.x; r < n; r += blockDim.x) w[r] -= d * vi[r];
+                __syncthreads();
+            }
+        }
+        double nr = 0.0;
+        for (int r = threadIdx.x; r < n; r += blockDim.x) nr += w[r] * w[r];
+        nr = sqrt(block_sum(nr, red));
+        if (threadIdx.x == 0) {
+            L.be[j] = nr;
+            s_stop = 0;
+            const bool last = (j + 1 >= min(K, n)) || nr == 0.0;
+            if ((j % 4 == 3) || last) {
+                const double th = tri_max_eig(L.al, L.be, j + 1);
+                if (last || fabs(th - *L.theta) <= 1e-15 * fabs(th) || nr <= 1e-14 * fabs(th)) s_stop = 1;
+                *L.theta = th;
+            }
+            if (s_stop) *L.done = 1;
+        }
+        __syncthreads();
+        if (s_stop) return;
+        double* vn = L.V + (int64_t)(j + 1) * n;
+        for (int r = threadIdx.x; r < n; r += blockDim.x) vn[r] = w[r] / nr;
+    }
+};
+
+__global__ void k_lz_init(LzItem* it, int nitems) {
+    const int b = blockIdx.x;
+    if (b >= nitems) return;
+    const LzItem& L = it[b];
+    const int n = L.H.n;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) L.V[r] = 1.0 / sqrt((double)n);
+    if (threadIdx.x == 0) {
+        *L.done = 0;
+        *L.theta = 0.0;
+    }
+}
+
+void lanczos_max_vb(Batch<DMat>& H, double* const* work, int K, double* dout, int* dsteps, hipStream_t s) {
+    const int N = H.size();
+    K = std::min(K, 128);
+    Batch<LzItem> lz;
+    std::vector<double*> hw(N);
+    DD_HIP(hipMemcpyAsync(hw.data(), work, N * sizeof(double*), hipMemcpyDeviceToHost, s));
+    DD_HIP(hipStreamSynchronize(s));
+    int nmax = 0;
+    for (int b = 0; b < N; ++b) {
+        const int n = H.h[b].n;
+        nmax = std::max(nmax, n);
+        double* base = hw[b];  // n*(K+1) V, n w, 2(K+1) al/be, theta
+        double* V = base;
+        double* w = V + (int64_t)n * (K + 1);
+        double* al = w + n;
+        double* be = al + (K + 1);
+        double* th = be + (K + 1);
+        lz.h.push_back(LzItem{H.h[b], V, w, al, be, dsteps + b, dout + b});
+    }
+    lz.sync(s);
+    hipLaunchKernelGGL(k_lz_init, dim3(N), dim3(256), 0, s, lz.d.p, N);
+    launch_check("lz_init");
+    std::vector<int> hdone(N);
+    const int Kmax = std::min(K, nmax);
+    for (int j = 0; j < Kmax; ++j) {
+        int64_t nt = 0;
+        for (int b = 0; b < N; ++b)
+            if (!hdone[b] && j < H.h[b].n) nt += ceil_div(H.h[b].n, 64);
+        if (nt == 0) break;
+        launch_tiles(OpLzMatvec{lz.d.p, j}, N, nt, s, "lz_matvec");
+        launch_tiles(OpLzOrth{lz.d.p, j, K}, N, N, s, "lz_orth");
+        if (j % 8 == 7) {
+            DD_HIP(hipMemcpyAsync(hdone.data(), dsteps, N * sizeof(int), hipMemcpyDeviceToHost, s));
+            DD_HIP(hipStreamSynchronize(s));
+        }
+    }
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace dd

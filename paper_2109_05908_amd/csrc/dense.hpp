@@ -1,0 +1,136 @@
+// Batched dense linear algebra on uneven items (FP64), gfx950.
+#pragma once
+#include "common.hpp"
+
+namespace dd {
+
+// Column-major matrix view: element (r, c) at p[r + c*ld].
+struct DMat {
+    double* p;
+    int ld;
+    int m;
+    int n;
+};
+
+// A batch of per-item descriptors with host and device copies.
+template <class T>
+struct Batch {
+    std::vector<T> h;
+    DBuf<T> d;
+    void sync(hipStream_t s) {
+        d.alloc(h.size());
+        h2d(d.p, h.data(), h.size(), s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    int size() const { return (int)h.size(); }
+};
+
+// QR storage: A (m x n, m >= n) holds R above and the Householder vectors below
+// the diagonal (unit diagonal implicit); tau[n]; T holds one 32x32 upper
+// triangular compact-WY factor per 32-column panel; W is 32 x max(cols) scratch.
+struct QRItem {
+    DMat A;
+    double* tau;
+    double* T;
+    double* W;
+    int wld;  // leading dimension of W (>= 32)
+};
+
+// Application of the Q stored in V (m x k reflectors, T factors as above) to C
+// (m x nc, rows aligned with V's rows).
+struct ORItem {
+    DMat V;   // m x k: reflector j in column j, rows j..m-1
+    double* T;
+    DMat C;
+    double* W;  // 32 x C.n
+};
+
+constexpr int QR_NB = 32;
+constexpr int CH_NB = 64;
+
+// C := alpha * op(A) op(B) + beta * C for every item (dims from C and A).
+struct GemmItem {
+    const double* A;
+    int lda;
+    const double* B;
+    int ldb;
+    double* C;
+    int ldc;
+    int M, N, K;
+    double alpha, beta;
+};
+
+void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s);
+
+// In-place lower Cholesky A = L L^T (upper triangle untouched).  info[b] =
+// 1-based column of the first non-positive pivot (0 if none).
+void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s);
+
+// B := L^{-1} B (trans = false) or L^{-T} B (trans = true), L lower (only the
+// lower triangle of L is read).  Item b: L[b] (n x n), B[b] (n x nrhs).
+void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s);
+
+// Householder QR in place.
+void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
+// C := Q C (trans = false) or Q^T C (trans = true).
+void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s);
+// T factors for reflectors stored in V with taus (used after sytrd).
+void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t s);
+
+// Householder tridiagonalisation of symmetric A (full storage, in place).
+// d[n], e[n-1] (off-diagonal), tau[n-1]; reflector k stored in A[k+2:, k]
+// (implicit 1 at row k+1).  part: scratch of >= ceil(n/64) doubles per item.
+struct TriItem {
+    DMat A;
+    double* d;
+    double* e;
+    double* tau;
+    double* part;
+    double* p;  // scratch vector of n doubles
+};
+void sytrd_vb(Batch<TriItem>& t, hipStream_t s);
+
+// Eigenvalues of the tridiagonal (d, e) below `thr`, ascending, at most cap:
+// count[b] written, mu[0..count).
+struct EigItem {
+    const double* d;
+    const double* e;
+    int n;
+    double* mu;
+    int* count;
+    int cap;
+    double thr;
+};
+void stebz_vb(Batch<EigItem>& e, hipStream_t s);
+
+// Eigenvectors of the tridiagonal for the eigenvalues mu[0..count) by inverse
+// iteration; vectors clustered within `cluster_tol` (absolute) are
+// orthogonalised against each other.  Y: n x count (ld >= n).
+struct VecItem {
+    const double* d;
+    const double* e;
+    int n;
+    const double* mu;
+    const int* count;
+    double* Y;
+    int ldy;
+    double* work;  // 3 n * 256 doubles
+};
+void stein_vb(Batch<VecItem>& v, double cluster_tol, hipStream_t s);
+
+// Elementwise helpers.
+void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)
+void copy_vb(Batch<DMat>& src, Batch<DMat>& dst, bool transpose, double scale, hipStream_t s);
+void add_diag_vb(Batch<DMat>& A, const double* dshift, hipStream_t s);  // A(i,i) += shift[b]
+void symmetrize_vb(Batch<DMat>& A, hipStream_t s);                     // A := (A + A^T)/2
+void zero_upper_vb(Batch<DMat>& A, hipStream_t s);                     // strictly upper := 0
+void zero_lower_vb(Batch<DMat>& A, hipStream_t s);                     // strictly lower := 0
+void axpby_vb(Batch<DMat>& X, Batch<DMat>& Y, const double* dalpha, const double* dbeta, hipStream_t s);  // Y := a X + b Y
+void frob_vb(Batch<DMat>& A, double* dout, hipStream_t s);             // out[b] = ||A||_F
+// Largest eigenvalue of symmetric H[b] by Lanczos with full
+// reorthogonalisation (at most K <= 128 steps).  work[b] (device pointer
+// array) holds n*(K+2) + 2*(K+1) + 1 doubles; dout[b] = eigenvalue;
+// dflag[b] is scratch (set to 1 once the item has converged).
+void lanczos_max_vb(Batch<DMat>& H, double* const* work, int K, double* dout, int* dflag, hipStream_t s);
+
+}  // namespace dd
