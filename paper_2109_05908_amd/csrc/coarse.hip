@@ -85,8 +85,6 @@ struct OpEBlock {
     double* const* P;
     const int32_t* zr;
     const int32_t* pr;
-    double* E;
-    int64_t ldE;
     __device__ int tiles(int q) const {
         const PairItem& pi = pairs[q];
         return ((S.pcnt[pi.i] + 63) / 64) * ((S.pcnt[pi.j] + 63) / 64);
@@ -103,8 +101,8 @@ struct OpEBlock {
         acc_zero(acc);
         mfma_tile_64<true, false>(S.Z[pi.i], nIi, P[pi.j], nj, p_i, p_j, pi.nrows, i0, j0, sm, acc,
                                   zr + pi.rows, pr + pi.rows);
-        double* Eb = E + S.offC[pi.i] + (int64_t)S.offC[pi.j] * ldE;
-        const int64_t ld = ldE;
+        double* Eb = pi.out;
+        const int64_t ld = pi.ldo;
         acc_foreach(acc, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < p_i && gj < p_j) Eb[gi + gj * ld] = v;
@@ -113,11 +111,26 @@ struct OpEBlock {
 };
 
 void assemble_e(const SubInfo& S, const PairItem* dpairs, const std::vector<PairItem>& hpairs,
-                const std::vector<int>& hp, const std::vector<int>&, double* const* P, const int32_t* zr,
-                const int32_t* pr, double* E, int64_t ldE, hipStream_t s) {
+                const std::vector<int>& hp, double* const* P, const int32_t* zr, const int32_t* pr, hipStream_t s) {
     int64_t tot = 0;
     for (auto& q : hpairs) tot += (int64_t)ceil_div(hp[q.i], 64) * ceil_div(hp[q.j], 64);
-    launch_tiles(OpEBlock{S, dpairs, P, zr, pr, E, ldE}, (int)hpairs.size(), tot, s, "assemble_e");
+    launch_tiles(OpEBlock{S, dpairs, P, zr, pr}, (int)hpairs.size(), tot, s, "assemble_e");
+}
+
+__global__ void k_block_adj(CsrDev A, const int32_t* part, int N, uint8_t* adj) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < A.n; u += (int64_t)gridDim.x * blockDim.x) {
+        const int pu = part[u];
+        for (int e = A.rowptr[u]; e < A.rowptr[u + 1]; ++e) {
+            const int pv = part[A.colind[e]];
+            if (pv != pu) adj[(int64_t)pu * N + pv] = 1;  // every writer stores the same value
+        }
+    }
+}
+
+void block_adjacency(const CsrDev& A, const int32_t* part, int N, uint8_t* adj, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_adj, dim3((unsigned)std::min<int64_t>((A.n + 255) / 256, 65536)), dim3(256), 0, s, A,
+                       part, N, adj);
+    launch_check("block_adjacency");
 }
 
 // one block per coarse dof (i, a)

@@ -31,11 +31,15 @@ struct PairItem {
     int i, j;
     int nrows;
     int64_t rows;  // offset into zr / pr
+    double* out;   // destination of block (i, j): p_i x p_j, leading dimension ldo
+    int64_t ldo;
 };
-// E[offC_i + a, offC_j + b] = sum_k Z_i(zr_k, a) P_j(pr_k, b)  (dense E, ld = nC)
+// out_q(a, b) = sum_k Z_i(zr_k, a) P_j(pr_k, b) for every pair q = (i, j)
 void assemble_e(const SubInfo& S, const PairItem* dpairs, const std::vector<PairItem>& hpairs,
-                const std::vector<int>& hp, const std::vector<int>& hnI, double* const* P, const int32_t* zr,
-                const int32_t* pr, double* E, int64_t ldE, hipStream_t s);
+                const std::vector<int>& hp, double* const* P, const int32_t* zr, const int32_t* pr, hipStream_t s);
+
+// adj[i*N + j] = 1 when an edge of G(A) joins Omega_Ii and Omega_Ij (i != j)
+void block_adjacency(const CsrDev& A, const int32_t* part, int N, uint8_t* adj, hipStream_t s);
 
 // y[offC_i + a] = sum_r Z_i(r, a) x[I_i(r)]
 void restrict_coarse(const SubInfo& S, int64_t nC, const double* x, double* y, hipStream_t s);

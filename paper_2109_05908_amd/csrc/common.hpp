@@ -126,10 +126,10 @@ __device__ __forceinline__ double block_max(double v, double* red) {
 // units; a fixed grid walks the flattened unit list.  The prefix over items
 // is recomputed in LDS by each workgroup (items <= kMaxItems).
 // ---------------------------------------------------------------------------
-constexpr int kMaxItems = 4096;
+constexpr int kMaxItems = 1024;
 
 template <class Op>
-__device__ __forceinline__ int item_prefix(const Op& op, int nitems, int* pre) {
+__device__ __forceinline__ int item_prefix(const Op& op, int nitems, int* pre, int base) {
     // pre[0..nitems] = exclusive prefix of op.tiles(b); contiguous chunk per thread
     __shared__ int part[256];
     const int T = blockDim.x, t = threadIdx.x;
@@ -137,7 +137,7 @@ __device__ __forceinline__ int item_prefix(const Op& op, int nitems, int* pre) {
     const int b0 = min(nitems, t * chunk), b1 = min(nitems, b0 + chunk);
     int s = 0;
     for (int b = b0; b < b1; ++b) {
-        const int v = op.tiles(b);
+        const int v = op.tiles(base + b);
         pre[b + 1] = v;
         s += v;
     }
@@ -169,24 +169,27 @@ __device__ __forceinline__ int find_item(const int* pre, int nitems, int t) {
 }
 
 template <class Op>
-__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems) {
+__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base) {
     __shared__ int pre[kMaxItems + 1];
-    const int total = item_prefix(op, nitems, pre);
+    const int total = item_prefix(op, nitems, pre, base);
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int b = find_item(pre, nitems, t);
-        op(b, t - pre[b]);
+        op(base + b, t - pre[b]);
         __syncthreads();
     }
 }
 
+// Items are processed in chunks of kMaxItems (one launch per chunk).
 template <class Op>
 inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream_t s, const char* name,
                          int max_grid = 4096) {
     if (nitems <= 0 || total_hint <= 0) return;
-    if (nitems > kMaxItems) throw Error(DD_ERR_INTERNAL, "too many batch items");
-    int grid = (int)std::min<int64_t>(total_hint, max_grid);
-    hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, nitems);
-    launch_check(name);
+    for (int base = 0; base < nitems; base += kMaxItems) {
+        const int cnt = std::min(kMaxItems, nitems - base);
+        int grid = (int)std::min<int64_t>(total_hint, max_grid);
+        hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base);
+        launch_check(name);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 
+#include "bchol.hpp"
 #include "coarse.hpp"
 
 namespace dd {
@@ -86,12 +87,12 @@ struct Level {
     std::vector<std::vector<double>> mu;
     std::vector<double> sigma1;
     int64_t nC = 0;
-    DBuf<double> Efac;
+    BlockChol E;                // block-sparse Cholesky factor of the coarse operator
     std::vector<double> Ecopy;  // small coarse operators only (inspection)
 
     // apply workspace
     DBuf<double> rloc, yC;
-    Batch<DMat> Lb, Bb, Eb, Ebv;
+    Batch<DMat> Lb, Bb;
 
     SubInfo sub() const {
         return SubInfo{N, counts.p, offE.p, offO.p, ext.p, part.p, ilocal.p, pcnt.p, offC.p, dZ.p};
@@ -237,7 +238,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         qT.alloc(sT);
         qW.alloc(sW);
         Batch<QRItem> qb;
-        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qtau.ptr[i], qT.ptr[i], qW.ptr[i], QR_NB});
+        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qtau.ptr[i], qT.ptr[i], qW.ptr[i], QR_NB, ni[i]});
         qb.sync(s);
         geqrf_vb(qb, s);
     }
@@ -330,7 +331,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 Batch<ORItem> ob;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
-                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB});
+                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i]});
                     ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i]});
                 }
                 qb.sync(s);
@@ -494,7 +495,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         }
         ft.alloc(a1); fT.alloc(a2); fW.alloc(a3);
         Batch<QRItem> qb;
-        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB});
+        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB, nc[i]});
         qb.sync(s);
         geqrf_vb(qb, s);
     }
@@ -510,8 +511,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         for (int i = 0; i < N; ++i) rii[i] = Fp.ptr[i] + nc[i] + (int64_t)nc[i] * nt[i];
         Batch<DMat> Rsrc = mats(rii, nt, nI, nI, s);
         Batch<DMat> Bb = mats(B2.ptr, nI, nI, nI, s);
-        copy_vb(Rsrc, Bb, true, 1.0, s);
-        zero_upper_vb(Bb, s);
+        copy_vb(Rsrc, Bb, true, 1.0, s);  // B2 = G^T, G = (Q^T F_I)[nc:, :] with G^T G = S_I
         DD_HIP(hipStreamSynchronize(s));
         Fp.release();
         Batch<DMat> LI = mats(Lv.L.ptr, ni, nI, nI, s);
@@ -559,7 +559,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         std::vector<int64_t> sy(N), sw(N);
         for (int i = 0; i < N; ++i) {
             sy[i] = (int64_t)nI[i] * std::max(1, Lv.p[i]);
-            sw[i] = (int64_t)3 * nI[i] * 256;
+            sw[i] = (int64_t)4 * nI[i] * 256;
         }
         Yev.alloc(sy);
         Arena wk;
@@ -567,7 +567,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Batch<VecItem> vb;
         for (int i = 0; i < N; ++i) vb.h.push_back(VecItem{td.ptr[i], te.ptr[i], nI[i], tmu.ptr[i], dcount.p + i, Yev.ptr[i], nI[i], wk.ptr[i]});
         vb.sync(s);
-        stein_vb(vb, 1e-5, s);
+        stein_vb(vb, Lv.mu, 1e-5, s);
         DD_HIP(hipStreamSynchronize(s));
         // back-transform with the tridiagonalisation reflectors (rows 1..nI-1)
         std::vector<int> act(N);
@@ -620,7 +620,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
             Batch<ORItem> ob;
             for (int i = 0; i < N; ++i) {
                 if (!act[i]) continue;
-                qb.h.push_back(QRItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zt.ptr[i], zT.ptr[i], zW.ptr[i], QR_NB});
+                qb.h.push_back(QRItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zt.ptr[i], zT.ptr[i], zW.ptr[i], QR_NB, pp[i]});
                 ob.h.push_back(ORItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zT.ptr[i], DMat{Lv.Z.ptr[i], nI[i], nI[i], pp[i]}, zW.ptr[i]});
             }
             qb.sync(s);
@@ -647,19 +647,40 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     const int64_t nC = Lv.nC;
     if (nC > 0) {
         SubInfo S = Lv.sub();
+        // block graph of E and the symbolic block Cholesky
+        {
+            DBuf<uint8_t> adj((size_t)N * N);
+            DD_HIP(hipMemsetAsync(adj.p, 0, adj.bytes(), s));
+            block_adjacency(A, Lv.part.p, N, adj.p, s);
+            auto hadj = to_host(adj.p, (size_t)N * N, s);
+            Lv.E.symbolic(hadj, Lv.p, Lv.hoffC);
+            Lv.E.allocate(s);
+        }
         DBuf<int32_t> cnt((size_t)N * N);
         DD_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes(), s));
         pair_counts(S, cnt.p, s);
         auto hc = to_host(cnt.p, (size_t)N * N, s);
         std::vector<int64_t> pairoff((size_t)N * N, 0);
-        std::vector<PairItem> pairs;
+        std::vector<PairItem> pairs, dense_pairs;
+        const bool keep_dense = nC <= 4096;
+        DBuf<double> Ed;
+        if (keep_dense) {
+            Ed.alloc((size_t)nC * nC);
+            fill(Ed.p, Ed.n, 0.0, s);
+        }
         int64_t pos = 0;
         for (int j = 0; j < N; ++j)
             for (int i = 0; i < N; ++i) {
                 const int64_t key = (int64_t)j * N + i;
                 pairoff[key] = pos;
                 if (hc[key] > 0) {
-                    if (Lv.p[i] > 0 && Lv.p[j] > 0) pairs.push_back(PairItem{i, j, hc[key], pos});
+                    if (Lv.p[i] > 0 && Lv.p[j] > 0) {
+                        int ld = 0;
+                        double* out = (Lv.E.pos[i] >= Lv.E.pos[j]) ? Lv.E.block(i, j, &ld) : nullptr;
+                        if (out) pairs.push_back(PairItem{i, j, hc[key], pos, out, ld});
+                        if (keep_dense && (i == j || out || Lv.E.block(j, i, &ld)))
+                            dense_pairs.push_back(PairItem{i, j, hc[key], pos, Ed.p + Lv.hoffC[i] + Lv.hoffC[j] * nC, nC});
+                    }
                     pos += hc[key];
                 }
             }
@@ -674,22 +695,17 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         DBuf<double*> dP(N);
         h2d(dP.p, P.ptr.data(), N, s);
         build_p(A, S, dP.p, ni, Lv.p, s);
-        Lv.Efac.alloc((size_t)nC * nC);
-        fill(Lv.Efac.p, Lv.Efac.n, 0.0, s);
         DBuf<PairItem> dpairs = upload(pairs, s);
-        assemble_e(S, dpairs.p, pairs, Lv.p, nI, dP.p, zr.p, pr.p, Lv.Efac.p, nC, s);
+        assemble_e(S, dpairs.p, pairs, Lv.p, dP.p, zr.p, pr.p, s);
+        if (keep_dense) {
+            DBuf<PairItem> dd2 = upload(dense_pairs, s);
+            assemble_e(S, dd2.p, dense_pairs, Lv.p, dP.p, zr.p, pr.p, s);
+            Lv.Ecopy = to_host(Ed.p, (size_t)nC * nC, s);
+        }
         DD_HIP(hipStreamSynchronize(s));
-        if (nC <= 4096) Lv.Ecopy = to_host(Lv.Efac.p, (size_t)nC * nC, s);
         info.phase_ms[PH_E] += tm.lap();
-        Batch<DMat> Eb;
-        Eb.h.push_back(DMat{Lv.Efac.p, (int)nC, (int)nC, (int)nC});
-        Eb.sync(s);
-        DBuf<int32_t> dinfo(1);
-        DD_HIP(hipMemsetAsync(dinfo.p, 0, sizeof(int32_t), s));
-        potrf_vb(Eb, dinfo.p, s);
-        zero_upper_vb(Eb, s);
-        auto hi = to_host(dinfo.p, 1, s);
-        DD_CHECK(hi[0] == 0, DD_ERR_NOT_SPD, "coarse operator E is not positive definite");
+        const int bad = Lv.E.factor(s);
+        DD_CHECK(bad == 0, DD_ERR_NOT_SPD, "coarse operator E is not positive definite");
         info.phase_ms[PH_EFACT] += tm.lap();
     }
 
@@ -700,12 +716,6 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     Lv.Bb.h.clear();
     for (int i = 0; i < N; ++i) Lv.Bb.h.push_back(DMat{Lv.rloc.p + Lv.hoffO[i], ni[i], ni[i], 1});
     Lv.Bb.sync(s);
-    if (nC > 0) {
-        Lv.Eb.h.assign(1, DMat{Lv.Efac.p, (int)nC, (int)nC, (int)nC});
-        Lv.Eb.sync(s);
-        Lv.Ebv.h.assign(1, DMat{Lv.yC.p, (int)nC, (int)nC, 1});
-        Lv.Ebv.sync(s);
-    }
     info.phase_ms[PH_OTHER] += tm.lap();
 }
 
@@ -718,8 +728,7 @@ static void apply1(Level& Lv, const double* r, double* z, hipStream_t s) {
     if (Lv.nC > 0) {
         SubInfo S = Lv.sub();
         restrict_coarse(S, Lv.nC, r, Lv.yC.p, s);
-        trsm_vb(Lv.Eb, Lv.Ebv, false, s);
-        trsm_vb(Lv.Eb, Lv.Ebv, true, s);
+        Lv.E.solve(Lv.yC.p, s);
         prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, z, s);
     }
 }
@@ -932,7 +941,7 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
     int64_t bytes = 0;
     for (auto& l : H.lv)
-        bytes += l->L.buf.bytes() + l->Z.buf.bytes() + l->Efac.bytes() + l->memb.bytes() + l->ext.bytes();
+        bytes += l->L.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
     *out = hd.release();
     return (tau >= 1.0) ? DD_WARN_FULL_COARSE : DD_OK;

@@ -91,13 +91,16 @@ struct OpPotrfDiag {
     }
 };
 
-// A21 := A21 * L11^{-T}, 64-row tiles (one thread per row).
+// A21 := A21 * L11^{-T} for the rows below the diagonal block (tall panels:
+// rows up to m), 64-row tiles, one thread per row.
 struct OpPotrfPanel {
     const DMat* A;
     int k0;
     __device__ int tiles(int b) const {
-        const int rem = A[b].n - k0 - 64;
-        return (A[b].n > k0 && rem > 0) ? (rem + 63) / 64 : 0;
+        if (A[b].n <= k0) return 0;
+        const int w = min(64, A[b].n - k0);
+        const int rem = A[b].m - k0 - w;
+        return rem > 0 ? (rem + 63) / 64 : 0;
     }
     __device__ void operator()(int b, int t) const {
         __shared__ double L[64][65];
@@ -110,7 +113,7 @@ struct OpPotrfPanel {
         }
         __syncthreads();
         const int row = k0 + w + t * 64 + (int)threadIdx.x;
-        if (threadIdx.x < 64 && row < M.n) {
+        if (threadIdx.x < 64 && row < M.m) {
             double x[64];
             double* a = M.p + row + (int64_t)k0 * M.ld;
 #pragma unroll
@@ -131,32 +134,42 @@ struct OpPotrfPanel {
     }
 };
 
-// A22 -= A21 A21^T on lower tiles.
+// Trailing update A22 -= A21 A21^T: columns k0+64..n-1, rows down to m-1,
+// lower part only inside the square block.
 struct OpPotrfUpdate {
     const DMat* A;
     int k0;
+    __device__ static void dims(const DMat& M, int k0, int& TR, int& TC) {
+        const int rows = M.m - k0 - 64, cols = M.n - k0 - 64;
+        TR = rows > 0 ? (rows + 63) / 64 : 0;
+        TC = cols > 0 ? (cols + 63) / 64 : 0;
+    }
     __device__ int tiles(int b) const {
-        const int rem = A[b].n - k0 - 64;
-        if (A[b].n <= k0 || rem <= 0) return 0;
-        const int T = (rem + 63) / 64;
-        return T * (T + 1) / 2;
+        if (A[b].n <= k0 + 64) return 0;
+        int TR, TC;
+        dims(A[b], k0, TR, TC);
+        return TC * TR - TC * (TC - 1) / 2;
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
         const DMat M = A[b];
-        const int w = 64;
-        const int rem = M.n - k0 - w;
-        int ti = 0;
-        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-        const int tj = t - ti * (ti + 1) / 2;
-        const double* A21 = M.p + (k0 + w) + (int64_t)k0 * M.ld;
+        int TR, TC;
+        dims(M, k0, TR, TC);
+        int tj = 0, rem_t = t;
+        while (rem_t >= TR - tj) {
+            rem_t -= TR - tj;
+            ++tj;
+        }
+        const int ti = tj + rem_t;
+        const int rows = M.m - k0 - 64, cols = M.n - k0 - 64;
+        const double* A21 = M.p + (k0 + 64) + (int64_t)k0 * M.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rem, rem, w, ti * 64, tj * 64, sm, acc);
-        double* C = M.p + (k0 + w) + (int64_t)(k0 + w) * M.ld;
+        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, 64, ti * 64, tj * 64, sm, acc);
+        double* C = M.p + (k0 + 64) + (int64_t)(k0 + 64) * M.ld;
         acc_foreach(acc, [&](int r, int c, double v) {
             const int gi = ti * 64 + r, gj = tj * 64 + c;
-            if (gi < rem && gj < rem && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
+            if (gi < rows && gj < cols && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
         });
     }
 };
@@ -169,11 +182,12 @@ void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
         for (auto& x : A.h) {
             if (x.n <= k0) continue;
             ++nd;
-            const int rem = x.n - k0 - 64;
-            if (rem > 0) {
-                const int T = ceil_div(rem, 64);
-                np += T;
-                nu += (int64_t)T * (T + 1) / 2;
+            const int w = std::min(64, x.n - k0);
+            const int rem = x.m - k0 - w;
+            if (rem > 0) np += ceil_div(rem, 64);
+            if (x.n > k0 + 64) {
+                const int TR = ceil_div(x.m - k0 - 64, 64), TC = ceil_div(x.n - k0 - 64, 64);
+                nu += (int64_t)TC * TR - (int64_t)TC * (TC - 1) / 2;
             }
         }
         launch_tiles(OpPotrfDiag{A.d.p, dinfo, k0}, A.size(), nd, s, "potrf_diag");
@@ -307,12 +321,12 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
 struct OpQrPanel {
     const QRItem* q;
     int col0;
-    __device__ int tiles(int b) const { return (q[b].A.n > col0 && q[b].A.m > col0) ? 1 : 0; }
+    __device__ int tiles(int b) const { return (q[b].nfac > col0 && q[b].A.m > col0) ? 1 : 0; }
     __device__ void operator()(int b, int) const {
         __shared__ double red[4 * 33];
         __shared__ double sc[33];
         const DMat A = q[b].A;
-        const int w = min(QR_NB, A.n - col0);
+        const int w = min(QR_NB, q[b].nfac - col0);
         const int mp = A.m - col0;
         double* V = A.p + col0 + (int64_t)col0 * A.ld;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -452,37 +466,82 @@ struct OpBuildT {
     }
 };
 
-// W = op(T) V^T C  (tiles of 64 columns of C). TRANS: op(T) = T^T (apply H^T).
-template <bool TRANS>
-struct OpQrW {
+// W = op(T) V^T C over the columns of C from ccol (geqrf: the columns right
+// of the panel, per item; ormqr: all).  TRANS: op(T) = T^T (apply H^T).
+// Pass 1 splits the long reduction over the rows into chunks of QR_KS rows
+// (partials in Wp), pass 2 sums the chunks in order and applies op(T).
+constexpr int QR_KS = 1024;
+
+__device__ __forceinline__ int qr_ccol(const ORItem& it, int col0, int mode) {
+    return mode ? col0 + min(QR_NB, it.V.n - col0) : 0;
+}
+
+struct OpQrWp {
     const ORItem* o;
+    double* const* Wp;
     int col0;
-    int ccol0;  // first column of C to update (geqrf: col0 + w, ormqr: 0)
-    __device__ int ncols(int b) const { return o[b].C.n - ccol0; }
+    int mode;
+    __device__ int nks(int b) const { return (o[b].V.m - col0 + QR_KS - 1) / QR_KS; }
     __device__ int tiles(int b) const {
         if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
-        const int nc = ncols(b);
-        return nc > 0 ? (nc + 63) / 64 : 0;
+        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
+        return nc > 0 ? ((nc + 63) / 64) * nks(b) : 0;
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
+        const ORItem& it = o[b];
+        const int w = min(QR_NB, it.V.n - col0);
+        const int mp = it.V.m - col0;
+        const int cc0 = qr_ccol(it, col0, mode);
+        const int nc = it.C.n - cc0;
+        const int ntc = (nc + 63) / 64;
+        const int ks = t / ntc, j0 = (t % ntc) * 64;
+        const int r0 = ks * QR_KS;
+        const int kl = min(QR_KS, mp - r0);
+        const double* V = it.V.p + col0 + r0 + (int64_t)col0 * it.V.ld;
+        const double* C = it.C.p + col0 + r0 + (int64_t)cc0 * it.C.ld;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        // unit-lower mask of V is relative to the panel start: shift handled by mode 1 only for ks == 0
+        if (ks == 0) mfma_tile_64<true, false, 1, 0>(V, it.V.ld, C, it.C.ld, w, nc, kl, 0, j0, sm, acc);
+        else mfma_tile_64<true, false, 0, 0>(V, it.V.ld, C, it.C.ld, w, nc, kl, 0, j0, sm, acc);
+        double* P = Wp[b] + (int64_t)ks * QR_NB * it.C.n;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            if (r < 32 && j0 + c < nc) P[r + (int64_t)(j0 + c) * QR_NB] = v;
+        });
+    }
+};
+
+template <bool TRANS>
+struct OpQrWr {
+    const ORItem* o;
+    double* const* Wp;
+    int col0;
+    int mode;
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
+        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
+        return nc > 0 ? (nc + 63) / 64 : 0;
+    }
+    __device__ void operator()(int b, int t) const {
         __shared__ double Ts[32][33];
         __shared__ double P[32][65];
         const ORItem& it = o[b];
         const int w = min(QR_NB, it.V.n - col0);
         const int mp = it.V.m - col0;
-        const double* V = it.V.p + col0 + (int64_t)col0 * it.V.ld;
-        const double* C = it.C.p + col0 + (int64_t)ccol0 * it.C.ld;
-        const int nc = ncols(b);
+        const int nks = (mp + QR_KS - 1) / QR_KS;
+        const int cc0 = qr_ccol(it, col0, mode);
+        const int nc = it.C.n - cc0;
         const int j0 = t * 64;
-        double4_t acc[2][2];
-        acc_zero(acc);
-        mfma_tile_64<true, false, 1, 0>(V, it.V.ld, C, it.C.ld, w, nc, mp, 0, j0, sm, acc);
         const double* Tg = it.T + (int64_t)(col0 / QR_NB) * QR_NB * QR_NB;
         for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) Ts[e & 31][e >> 5] = Tg[e];
-        acc_foreach(acc, [&](int r, int c, double v) {
-            if (r < 32) P[r][c] = v;
-        });
+        for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
+            const int r = e & 31, c = e >> 5;
+            double sum = 0.0;
+            if (j0 + c < nc)
+                for (int ks = 0; ks < nks; ++ks) sum += Wp[b][(int64_t)ks * QR_NB * it.C.n + r + (int64_t)(j0 + c) * QR_NB];
+            P[r][c] = sum;
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
             const int r = e & 31, c = e >> 5;
@@ -503,10 +562,10 @@ struct OpQrW {
 struct OpQrUpd {
     const ORItem* o;
     int col0;
-    int ccol0;
+    int mode;
     __device__ int tiles(int b) const {
         if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
-        const int nc = o[b].C.n - ccol0;
+        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
         const int mp = o[b].V.m - col0;
         return nc > 0 ? ((mp + 63) / 64) * ((nc + 63) / 64) : 0;
     }
@@ -515,11 +574,12 @@ struct OpQrUpd {
         const ORItem& it = o[b];
         const int w = min(QR_NB, it.V.n - col0);
         const int mp = it.V.m - col0;
-        const int nc = it.C.n - ccol0;
+        const int cc0 = qr_ccol(it, col0, mode);
+        const int nc = it.C.n - cc0;
         const int tm = (mp + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
         const double* V = it.V.p + col0 + (int64_t)col0 * it.V.ld;
-        double* C = it.C.p + col0 + (int64_t)ccol0 * it.C.ld;
+        double* C = it.C.p + col0 + (int64_t)cc0 * it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
         mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_NB, mp, nc, w, i0, j0, sm, acc);
@@ -531,18 +591,41 @@ struct OpQrUpd {
     }
 };
 
-static void apply_panel(Batch<ORItem>& o, int col0, int ccol0, bool trans, hipStream_t s) {
-    int64_t nw = 0, nu = 0;
+struct QrScratch {
+    DBuf<double> buf;
+    DBuf<double*> ptr;
+    void alloc(const std::vector<ORItem>& items, hipStream_t s) {
+        std::vector<int64_t> off(items.size() + 1, 0);
+        for (size_t i = 0; i < items.size(); ++i) {
+            const int nks = ceil_div(std::max(1, items[i].V.m), QR_KS);
+            off[i + 1] = off[i] + (int64_t)QR_NB * std::max(1, items[i].C.n) * nks;
+        }
+        buf.alloc(off.back());
+        std::vector<double*> hp(items.size());
+        for (size_t i = 0; i < items.size(); ++i) hp[i] = buf.p + off[i];
+        ptr.alloc(hp.size());
+        h2d(ptr.p, hp.data(), hp.size(), s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+};
+
+static void apply_panel(Batch<ORItem>& o, QrScratch& sc, int col0, int mode, bool trans, hipStream_t s) {
+    int64_t nw = 0, np = 0, nu = 0;
     for (auto& x : o.h) {
         if (x.V.n <= col0 || x.V.m <= col0) continue;
-        const int nc = x.C.n - ccol0;
+        const int cc0 = mode ? col0 + std::min(QR_NB, x.V.n - col0) : 0;
+        const int nc = x.C.n - cc0;
         if (nc <= 0) continue;
-        nw += ceil_div(nc, 64);
-        nu += (int64_t)ceil_div(x.V.m - col0, 64) * ceil_div(nc, 64);
+        const int ntc = ceil_div(nc, 64);
+        nw += ntc;
+        np += (int64_t)ntc * ceil_div(x.V.m - col0, QR_KS);
+        nu += (int64_t)ceil_div(x.V.m - col0, 64) * ntc;
     }
-    if (trans) launch_tiles(OpQrW<true>{o.d.p, col0, ccol0}, o.size(), nw, s, "qr_w");
-    else launch_tiles(OpQrW<false>{o.d.p, col0, ccol0}, o.size(), nw, s, "qr_w");
-    launch_tiles(OpQrUpd{o.d.p, col0, ccol0}, o.size(), nu, s, "qr_upd");
+    if (nw == 0) return;
+    launch_tiles(OpQrWp{o.d.p, sc.ptr.p, col0, mode}, o.size(), np, s, "qr_wp");
+    if (trans) launch_tiles(OpQrWr<true>{o.d.p, sc.ptr.p, col0, mode}, o.size(), nw, s, "qr_wr");
+    else launch_tiles(OpQrWr<false>{o.d.p, sc.ptr.p, col0, mode}, o.size(), nw, s, "qr_wr");
+    launch_tiles(OpQrUpd{o.d.p, col0, mode}, o.size(), nu, s, "qr_upd");
 }
 
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
@@ -550,21 +633,21 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     Batch<ORItem> o;
     std::vector<double*> htau;
     for (auto& x : q.h) {
-        nmax = std::max(nmax, std::min(x.A.n, x.A.m));
-        o.h.push_back(ORItem{x.A, x.T, x.A, x.W});
+        nmax = std::max(nmax, std::min(x.nfac, x.A.m));
+        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W});
         htau.push_back(x.tau);
     }
     o.sync(s);
+    QrScratch sc;
+    sc.alloc(o.h, s);
     DBuf<double*> dtau(htau.size());
     h2d(dtau.p, htau.data(), htau.size(), s);
     for (int col0 = 0; col0 < nmax; col0 += QR_NB) {
         int64_t np = 0;
-        for (auto& x : q.h) np += (x.A.n > col0 && x.A.m > col0) ? 1 : 0;
+        for (auto& x : q.h) np += (x.nfac > col0 && x.A.m > col0) ? 1 : 0;
         launch_tiles(OpQrPanel{q.d.p, col0}, q.size(), np, s, "qr_panel");
         launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "qr_buildT");
-        // trailing columns: C = A, columns col0+w.. ; the ORItem's C.n is A.n
-        // so ccol0 = col0 + QR_NB (w = QR_NB whenever trailing columns exist)
-        apply_panel(o, col0, col0 + QR_NB, true, s);
+        apply_panel(o, sc, col0, 1, true, s);
     }
     DD_HIP(hipStreamSynchronize(s));
 }
@@ -585,11 +668,14 @@ void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t 
 void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s) {
     int kmax = 0;
     for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
+    QrScratch sc;
+    sc.alloc(o.h, s);
     const int np = ceil_div(kmax, QR_NB);
     for (int step = 0; step < np; ++step) {
         const int k = trans ? step : (np - 1 - step);
-        apply_panel(o, k * QR_NB, 0, trans, s);
+        apply_panel(o, sc, k * QR_NB, 0, trans, s);
     }
+    DD_HIP(hipStreamSynchronize(s));
 }
 
 // ===========================================================================
@@ -819,52 +905,63 @@ __device__ unsigned int hash_u32(unsigned int x) {
 // Solve (T - mu I) x = y in place by Gaussian elimination with partial
 // pivoting on the tridiagonal (the working row carries two entries; a row
 // swap gives U a second superdiagonal).  Zero pivots are replaced by `tiny`.
+// Work arrays and x are strided (element i at [i * st]) so that the threads of
+// a wave, each solving its own system, touch consecutive addresses.
 __device__ void tri_solve(const double* d, const double* e, int n, double mu, double* u1, double* u2, double* u3,
-                          double* x, double tiny) {
+                          double* x, int st, double tiny) {
     double a = d[0] - mu;
     double bb = (n > 1) ? e[0] : 0.0;
+    double xi = x[0];
     for (int i = 0; i < n - 1; ++i) {
         const double c = e[i];
         const double dn = d[i + 1] - mu;
         const double en = (i + 1 < n - 1) ? e[i + 1] : 0.0;
+        const double xn = x[(int64_t)(i + 1) * st];
         if (fabs(a) >= fabs(c)) {
             if (a == 0.0) a = tiny;
             const double m = c / a;
-            u1[i] = a; u2[i] = bb; u3[i] = 0.0;
-            x[i + 1] -= m * x[i];
+            u1[(int64_t)i * st] = a; u2[(int64_t)i * st] = bb; u3[(int64_t)i * st] = 0.0;
+            x[(int64_t)i * st] = xi;
+            xi = xn - m * xi;
             a = dn - m * bb;
             bb = en;
         } else {
             const double m = a / c;
-            u1[i] = c; u2[i] = dn; u3[i] = en;
-            const double xi = x[i];
-            x[i] = x[i + 1];
-            x[i + 1] = xi - m * x[i];
+            u1[(int64_t)i * st] = c; u2[(int64_t)i * st] = dn; u3[(int64_t)i * st] = en;
+            x[(int64_t)i * st] = xn;
+            xi = xi - m * xn;
             a = bb - m * dn;
             bb = -m * en;
         }
     }
     if (a == 0.0) a = tiny;
-    u1[n - 1] = a;
-    x[n - 1] /= u1[n - 1];
-    if (n > 1) x[n - 2] = (x[n - 2] - u2[n - 2] * x[n - 1]) / u1[n - 2];
-    for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - u2[i] * x[i + 1] - u3[i] * x[i + 2]) / u1[i];
+    u1[(int64_t)(n - 1) * st] = a;
+    double x1 = xi / a;  // x[n-1]
+    x[(int64_t)(n - 1) * st] = x1;
+    if (n > 1) {
+        double x0 = (x[(int64_t)(n - 2) * st] - u2[(int64_t)(n - 2) * st] * x1) / u1[(int64_t)(n - 2) * st];
+        x[(int64_t)(n - 2) * st] = x0;
+        for (int i = n - 3; i >= 0; --i) {
+            const double v = (x[(int64_t)i * st] - u2[(int64_t)i * st] * x0 - u3[(int64_t)i * st] * x1) / u1[(int64_t)i * st];
+            x[(int64_t)i * st] = v;
+            x1 = x0;
+            x0 = v;
+        }
+    }
 }
 
 __device__ double start_value(int i, int j) {
     return 1.0 + 0.5 * ((hash_u32((unsigned)i * 2654435761u + (unsigned)j * 40503u + 12345u) & 0xffff) / 65536.0 - 0.5);
 }
 
-// Eigenvectors by inverse iteration.  Eigenvalues whose gap to the previous
-// one is below ctol*||T|| form a cluster; members of a cluster are
-// orthogonalised (classical Gram-Schmidt, twice) against the earlier members
-// after every iteration.  Isolated eigenvalues run one per thread.
-struct OpStein {
+// One inverse-iteration round for every eigenvalue of the item (one thread per
+// eigenvalue, the block's 256 threads sweep the list): x_j <- (T - mu_j I)^{-1} x_j,
+// normalised.  first: start from the hashed vector instead of Y.
+struct OpSteinSolve {
     const VecItem* it;
-    double ctol;
+    int first;
     __device__ int tiles(int b) const { return it[b].n > 0 ? 1 : 0; }
     __device__ void operator()(int b, int) const {
-        __shared__ double red[4];
         __shared__ int s_cnt;
         __shared__ double s_tn;
         const VecItem& V = it[b];
@@ -878,67 +975,89 @@ struct OpStein {
         }
         __syncthreads();
         const int p = s_cnt;
-        if (p == 0) return;
-        const double tnorm = s_tn;
-        const double tiny = 2.220446049250313e-16 * tnorm;
-        const double gap = ctol * tnorm;
-        const int stride = 3 * n;
-        // Phase 1: isolated eigenvalues, one thread each.
-        for (int j0 = 0; j0 < p; j0 += blockDim.x) {
-            const int j = j0 + threadIdx.x;
-            if (j < p) {
-                const bool left = (j > 0) && (V.mu[j] - V.mu[j - 1] <= gap);
-                const bool right = (j + 1 < p) && (V.mu[j + 1] - V.mu[j] <= gap);
-                if (!left && !right) {
-                    double* w = V.work + (int64_t)threadIdx.x * stride;
-                    double* x = V.Y + (int64_t)j * V.ldy;
-                    for (int i = 0; i < n; ++i) x[i] = start_value(i, j);
-                    for (int itn = 0; itn < 3; ++itn) {
-                        tri_solve(V.d, V.e, n, V.mu[j], w, w + n, w + 2 * n, x, tiny);
-                        double nr = 0.0;
-                        for (int i = 0; i < n; ++i) nr += x[i] * x[i];
-                        nr = 1.0 / sqrt(nr);
-                        for (int i = 0; i < n; ++i) x[i] *= nr;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // Phase 2: clusters, members in order.
-        int cstart = 0;
-        for (int j = 0; j < p; ++j) {
-            if (j > 0 && V.mu[j] - V.mu[j - 1] > gap) cstart = j;
-            const bool inclu = (j > cstart) || (j + 1 < p && V.mu[j + 1] - V.mu[j] <= gap);
-            if (!inclu) continue;
-            double* x = V.Y + (int64_t)j * V.ldy;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = start_value(i, j);
-            __syncthreads();
-            for (int itn = 0; itn < 3; ++itn) {
-                if (threadIdx.x == 0) tri_solve(V.d, V.e, n, V.mu[j], V.work, V.work + n, V.work + 2 * n, x, tiny);
-                __syncthreads();
-                for (int pass = 0; pass < 2; ++pass) {
-                    for (int r = cstart; r < j; ++r) {
-                        const double* xr = V.Y + (int64_t)r * V.ldy;
-                        double dp = 0.0;
-                        for (int i = threadIdx.x; i < n; i += blockDim.x) dp += xr[i] * x[i];
-                        dp = block_sum(dp, red);
-                        for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] -= dp * xr[i];
-                        __syncthreads();
-                    }
-                    double nr = 0.0;
-                    for (int i = threadIdx.x; i < n; i += blockDim.x) nr += x[i] * x[i];
-                    nr = block_sum(nr, red);
-                    const double sc = 1.0 / sqrt(fmax(nr, 1e-300));
-                    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= sc;
-                    __syncthreads();
-                }
-            }
+        const double tiny = 2.220446049250313e-16 * s_tn;
+        const int t = threadIdx.x;
+        double* u1 = V.work + t;
+        double* u2 = u1 + (int64_t)n * 256;
+        double* u3 = u2 + (int64_t)n * 256;
+        double* x = u3 + (int64_t)n * 256;
+        for (int j = t; j < p; j += 256) {
+            double* y = V.Y + (int64_t)j * V.ldy;
+            for (int i = 0; i < n; ++i) x[(int64_t)i * 256] = first ? start_value(i, j) : y[i];
+            tri_solve(V.d, V.e, n, V.mu[j], u1, u2, u3, x, 256, tiny);
+            double nr = 0.0;
+            for (int i = 0; i < n; ++i) nr += x[(int64_t)i * 256] * x[(int64_t)i * 256];
+            nr = 1.0 / sqrt(nr);
+            for (int i = 0; i < n; ++i) y[i] = x[(int64_t)i * 256] * nr;
         }
     }
 };
 
-void stein_vb(Batch<VecItem>& v, double cluster_tol, hipStream_t s) {
-    launch_tiles(OpStein{v.d.p, cluster_tol}, v.size(), v.size(), s, "stein");
+void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, double cluster_tol, hipStream_t s) {
+    // clusters (size >= 2) become the items of a batched Householder QR
+    Batch<QRItem> qb;
+    Batch<ORItem> ob;
+    std::vector<int64_t> sz_q, sz_T, sz_W, sz_t;
+    struct Cl { int item, c0, c; };
+    std::vector<Cl> cls;
+    for (int b = 0; b < v.size(); ++b) {
+        const auto& mu = hmu[b];
+        const int p = (int)mu.size();
+        double tn = 0.0;
+        for (double m : mu) tn = std::max(tn, std::fabs(m));
+        const double gap = cluster_tol * std::max(1.0, tn);
+        int c0 = 0;
+        for (int j = 1; j <= p; ++j) {
+            if (j == p || mu[j] - mu[j - 1] > gap) {
+                if (j - c0 >= 2) cls.push_back(Cl{b, c0, j - c0});
+                c0 = j;
+            }
+        }
+    }
+    DBuf<double> tq, tT, tW, tQ;
+    std::vector<DMat> hsrc, hdst;
+    if (!cls.empty()) {
+        int64_t a = 0, bT = 0, bW = 0, bQ = 0;
+        for (auto& c : cls) {
+            const int n = v.h[c.item].n;
+            a += c.c;
+            bT += (int64_t)ceil_div(c.c, QR_NB) * QR_NB * QR_NB;
+            bW += (int64_t)QR_NB * c.c;
+            bQ += (int64_t)n * c.c;
+        }
+        tq.alloc(a); tT.alloc(bT); tW.alloc(bW); tQ.alloc(bQ);
+        a = bT = bW = bQ = 0;
+        for (auto& c : cls) {
+            const VecItem& it = v.h[c.item];
+            const int n = it.n;
+            DMat Yc{it.Y + (int64_t)c.c0 * it.ldy, it.ldy, n, c.c};
+            DMat Qc{tQ.p + bQ, n, n, c.c};
+            qb.h.push_back(QRItem{Yc, tq.p + a, tT.p + bT, tW.p + bW, QR_NB, c.c});
+            ob.h.push_back(ORItem{Yc, tT.p + bT, Qc, tW.p + bW});
+            hsrc.push_back(Qc);
+            hdst.push_back(Yc);
+            a += c.c;
+            bT += (int64_t)ceil_div(c.c, QR_NB) * QR_NB * QR_NB;
+            bW += (int64_t)QR_NB * c.c;
+            bQ += (int64_t)n * c.c;
+        }
+        qb.sync(s);
+        ob.sync(s);
+    }
+    Batch<DMat> Qs, Ys;
+    Qs.h = hsrc;
+    Ys.h = hdst;
+    if (!cls.empty()) { Qs.sync(s); Ys.sync(s); }
+    for (int round = 0; round < 3; ++round) {
+        launch_tiles(OpSteinSolve{v.d.p, round == 0}, v.size(), v.size(), s, "stein_solve");
+        if (!cls.empty()) {
+            geqrf_vb(qb, s);
+            set_identity_vb(Qs, 1.0, s);
+            ormqr_vb(ob, false, s);
+            copy_vb(Qs, Ys, false, 1.0, s);
+        }
+    }
+    DD_HIP(hipStreamSynchronize(s));
 }
 
 // ===========================================================================

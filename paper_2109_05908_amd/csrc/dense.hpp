@@ -33,7 +33,8 @@ struct QRItem {
     double* tau;
     double* T;
     double* W;
-    int wld;  // leading dimension of W (>= 32)
+    int wld;   // leading dimension of W (>= 32)
+    int nfac;  // factor only the first nfac columns (<= n); the rest receive Q^T
 };
 
 // Application of the Q stored in V (m x k reflectors, T factors as above) to C
@@ -62,15 +63,17 @@ struct GemmItem {
 
 void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s);
 
-// In-place lower Cholesky A = L L^T (upper triangle untouched).  info[b] =
-// 1-based column of the first non-positive pivot (0 if none).
+// In-place lower Cholesky A = L L^T (upper triangle untouched).  A may be a
+// tall panel (m >= n): the rows below the leading n x n block are solved
+// against L^T (supernodal panel factorisation).  info[b] = 1-based column of
+// the first non-positive pivot (0 if none).
 void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s);
 
 // B := L^{-1} B (trans = false) or L^{-T} B (trans = true), L lower (only the
 // lower triangle of L is read).  Item b: L[b] (n x n), B[b] (n x nrhs).
 void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s);
 
-// Householder QR in place.
+// Householder QR in place (first nfac columns factored, all columns updated).
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
 // C := Q C (trans = false) or Q^T C (trans = true).
 void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s);
@@ -104,8 +107,10 @@ struct EigItem {
 void stebz_vb(Batch<EigItem>& e, hipStream_t s);
 
 // Eigenvectors of the tridiagonal for the eigenvalues mu[0..count) by inverse
-// iteration; vectors clustered within `cluster_tol` (absolute) are
-// orthogonalised against each other.  Y: n x count (ld >= n).
+// iteration (three rounds); after every round the vectors of each cluster
+// (consecutive eigenvalues closer than cluster_tol * ||T||) are
+// orthonormalised together by Householder QR.  Y: n x count (ld >= n).
+// hmu: host copies of the eigenvalues (cluster detection).
 struct VecItem {
     const double* d;
     const double* e;
@@ -114,9 +119,9 @@ struct VecItem {
     const int* count;
     double* Y;
     int ldy;
-    double* work;  // 3 n * 256 doubles
+    double* work;  // 4 n * 256 doubles
 };
-void stein_vb(Batch<VecItem>& v, double cluster_tol, hipStream_t s);
+void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, double cluster_tol, hipStream_t s);
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)
