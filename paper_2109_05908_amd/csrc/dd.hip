@@ -226,19 +226,22 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     info.phase_ms[PH_CHOL] += tm.lap();
 
     // ---- a3 (part 1): Householder QR of Y_i = X_i^T --------------------------------------
-    Arena qtau, qT, qW;
+    Arena qtau, qT, qW, qG;
     {
-        std::vector<int64_t> st(N), sT(N), sW(N);
+        std::vector<int64_t> st(N), sT(N), sW(N), sG(N);
         for (int i = 0; i < N; ++i) {
             st[i] = ni[i];
-            sT[i] = (int64_t)ceil_div(ni[i], QR_NB) * QR_NB * QR_NB;
-            sW[i] = (int64_t)QR_NB * std::max(ni[i], nt[i]);
+            sT[i] = qr_t_size(ni[i]);
+            sW[i] = qr_w_size(std::max(ni[i], nt[i]));
+            sG[i] = qr_g_size(ni[i]);
         }
         qtau.alloc(st);
         qT.alloc(sT);
         qW.alloc(sW);
+        qG.alloc(sG);
         Batch<QRItem> qb;
-        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qtau.ptr[i], qT.ptr[i], qW.ptr[i], QR_NB, ni[i]});
+        for (int i = 0; i < N; ++i)
+            qb.h.push_back(QRItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qtau.ptr[i], qT.ptr[i], qW.ptr[i], QR_NB, ni[i], qG.ptr[i]});
         qb.sync(s);
         geqrf_vb(qb, s);
     }
@@ -319,20 +322,21 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                     axpby_vb(Stop, Stop, d1.p, d2.p, s);
                 }
                 set_identity_vb(Sbot, 1.0, s);
-                Arena tq, tT, tW;
-                std::vector<int64_t> a1(N), a2(N), a3(N);
+                Arena tq, tT, tW, tG;
+                std::vector<int64_t> a1(N), a2(N), a3(N), a4(N);
                 for (int i = 0; i < N; ++i) {
                     a1[i] = actQ[i] ? ni[i] : 1;
-                    a2[i] = actQ[i] ? (int64_t)ceil_div(ni[i], QR_NB) * QR_NB * QR_NB : 1;
-                    a3[i] = actQ[i] ? (int64_t)QR_NB * ni[i] : 1;
+                    a2[i] = actQ[i] ? qr_t_size(ni[i]) : 1;
+                    a3[i] = actQ[i] ? qr_w_size(ni[i]) : 1;
+                    a4[i] = actQ[i] ? qr_g_size(ni[i]) : 1;
                 }
-                tq.alloc(a1); tT.alloc(a2); tW.alloc(a3);
+                tq.alloc(a1); tT.alloc(a2); tW.alloc(a3); tG.alloc(a4);
                 Batch<QRItem> qb;
                 Batch<ORItem> ob;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
-                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i]});
-                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i]});
+                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i], tG.ptr[i]});
+                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i], tG.ptr[i]});
                 }
                 qb.sync(s);
                 ob.sync(s);
@@ -460,7 +464,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Wk.release();
         Batch<ORItem> ob;
         for (int i = 0; i < N; ++i)
-            ob.h.push_back(ORItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qT.ptr[i], DMat{Ft.ptr[i], nt[i], nt[i], nt[i]}, qW.ptr[i]});
+            ob.h.push_back(ORItem{DMat{Y.ptr[i], nt[i], nt[i], ni[i]}, qT.ptr[i], DMat{Ft.ptr[i], nt[i], nt[i], nt[i]}, qW.ptr[i], qG.ptr[i]});
         ob.sync(s);
         ormqr_vb(ob, false, s);  // Ft = Q_full * blkdiag(L_H, sqrt(s) I) = F^T
         DD_HIP(hipStreamSynchronize(s));
@@ -468,6 +472,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         qtau.release();
         qT.release();
         qW.release();
+        qG.release();
         // Fp[:, j] = F[:, perm(j)] = (row perm(j) of F^T)^T, perm = [nI..nt-1, 0..nI-1]
         Fp.alloc(sf);
         std::vector<double*> srcC(N), srcI(N), dstC(N), dstI(N);
@@ -486,16 +491,18 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         copy_vb(sI, dI, true, 1.0, s);
         DD_HIP(hipStreamSynchronize(s));
         Ft.release();
-        Arena ft, fT, fW;
-        std::vector<int64_t> a1(N), a2(N), a3(N);
+        Arena ft, fT, fW, fG;
+        std::vector<int64_t> a1(N), a2(N), a3(N), a4(N);
         for (int i = 0; i < N; ++i) {
             a1[i] = nt[i];
-            a2[i] = (int64_t)ceil_div(nt[i], QR_NB) * QR_NB * QR_NB;
-            a3[i] = (int64_t)QR_NB * nt[i];
+            a2[i] = qr_t_size(std::max(1, nc[i]));
+            a3[i] = qr_w_size(nt[i]);
+            a4[i] = qr_g_size(std::max(1, nc[i]));
         }
-        ft.alloc(a1); fT.alloc(a2); fW.alloc(a3);
+        ft.alloc(a1); fT.alloc(a2); fW.alloc(a3); fG.alloc(a4);
         Batch<QRItem> qb;
-        for (int i = 0; i < N; ++i) qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB, nc[i]});
+        for (int i = 0; i < N; ++i)
+            qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB, nc[i], fG.ptr[i]});
         qb.sync(s);
         geqrf_vb(qb, s);
     }
@@ -572,19 +579,20 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         // back-transform with the tridiagonalisation reflectors (rows 1..nI-1)
         std::vector<int> act(N);
         for (int i = 0; i < N; ++i) act[i] = (Lv.p[i] > 0 && nI[i] > 1);
-        Arena oT, oW;
-        std::vector<int64_t> s1(N), s2(N);
+        Arena oT, oW, oG;
+        std::vector<int64_t> s1(N), s2(N), s3(N);
         for (int i = 0; i < N; ++i) {
-            s1[i] = (int64_t)ceil_div(std::max(1, nI[i] - 1), QR_NB) * QR_NB * QR_NB;
-            s2[i] = (int64_t)QR_NB * std::max(1, Lv.p[i]);
+            s1[i] = qr_t_size(std::max(1, nI[i] - 1));
+            s2[i] = qr_w_size(std::max(1, Lv.p[i]));
+            s3[i] = qr_g_size(std::max(1, nI[i] - 1));
         }
-        oT.alloc(s1); oW.alloc(s2);
+        oT.alloc(s1); oW.alloc(s2); oG.alloc(s3);
         Batch<ORItem> ob;
         std::vector<double*> taus;
         for (int i = 0; i < N; ++i) {
             if (!act[i]) continue;
             ob.h.push_back(ORItem{DMat{Sm.ptr[i] + 1, nI[i], nI[i] - 1, nI[i] - 1}, oT.ptr[i],
-                                  DMat{Yev.ptr[i] + 1, nI[i], nI[i] - 1, Lv.p[i]}, oW.ptr[i]});
+                                  DMat{Yev.ptr[i] + 1, nI[i], nI[i] - 1, Lv.p[i]}, oW.ptr[i], oG.ptr[i]});
             taus.push_back(ttau.ptr[i]);
         }
         if (ob.size()) {
@@ -608,20 +616,21 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Batch<DMat> Yb = mats(Yev.ptr, nI, nI, pp, s, &act);
         if (Yb.size()) {
             trsm_vb(LI, Yb, true, s);
-            Arena zt, zT, zW;
-            std::vector<int64_t> a1(N), a2(N), a3(N);
+            Arena zt, zT, zW, zG;
+            std::vector<int64_t> a1(N), a2(N), a3(N), a4(N);
             for (int i = 0; i < N; ++i) {
                 a1[i] = std::max(1, pp[i]);
-                a2[i] = (int64_t)ceil_div(std::max(1, pp[i]), QR_NB) * QR_NB * QR_NB;
-                a3[i] = (int64_t)QR_NB * std::max(1, pp[i]);
+                a2[i] = qr_t_size(std::max(1, pp[i]));
+                a3[i] = qr_w_size(std::max(1, pp[i]));
+                a4[i] = qr_g_size(std::max(1, pp[i]));
             }
-            zt.alloc(a1); zT.alloc(a2); zW.alloc(a3);
+            zt.alloc(a1); zT.alloc(a2); zW.alloc(a3); zG.alloc(a4);
             Batch<QRItem> qb;
             Batch<ORItem> ob;
             for (int i = 0; i < N; ++i) {
                 if (!act[i]) continue;
-                qb.h.push_back(QRItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zt.ptr[i], zT.ptr[i], zW.ptr[i], QR_NB, pp[i]});
-                ob.h.push_back(ORItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zT.ptr[i], DMat{Lv.Z.ptr[i], nI[i], nI[i], pp[i]}, zW.ptr[i]});
+                qb.h.push_back(QRItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zt.ptr[i], zT.ptr[i], zW.ptr[i], QR_NB, pp[i], zG.ptr[i]});
+                ob.h.push_back(ORItem{DMat{Yev.ptr[i], nI[i], nI[i], pp[i]}, zT.ptr[i], DMat{Lv.Z.ptr[i], nI[i], nI[i], pp[i]}, zW.ptr[i], zG.ptr[i]});
             }
             qb.sync(s);
             ob.sync(s);

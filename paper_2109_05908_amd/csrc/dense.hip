@@ -466,128 +466,250 @@ struct OpBuildT {
     }
 };
 
-// W = op(T) V^T C over the columns of C from ccol (geqrf: the columns right
-// of the panel, per item; ormqr: all).  TRANS: op(T) = T^T (apply H^T).
-// Pass 1 splits the long reduction over the rows into chunks of QR_KS rows
-// (partials in Wp), pass 2 sums the chunks in order and applies op(T).
-constexpr int QR_KS = 1024;
+// ---------------------------------------------------------------------------
+// Block application of reflectors.  A block is up to four consecutive
+// 32-column panels starting at column c0 of V (width wb <= 128).  For C over
+// a column range [cc0, cc1):
+//   P = V_b^T C                     (row chunks of QR_KS rows -> partial sums)
+//   W = recurrence over the panels  (TRANS: W_q = T_q^T (P_q - sum_{j<q} G_qj W_j),
+//                                    else:  W_q = T_q (P_q - sum_{j>q} G_qj W_j))
+//   C -= V_b W
+// which applies H_0^T..H_3^T (TRANS) or H_3..H_0 in turn while reading C twice.
+// ---------------------------------------------------------------------------
+constexpr int QR_KS = 2048;
 
-__device__ __forceinline__ int qr_ccol(const ORItem& it, int col0, int mode) {
-    return mode ? col0 + min(QR_NB, it.V.n - col0) : 0;
+struct BlkRange {  // per-item column range and width of the current block
+    int wb, cc0, cc1;
+};
+// mode 0: ormqr (all columns); mode 1: geqrf trailing [c0+wb, n); mode 2: geqrf
+// inner [c0+wb, min(n, oend, nfac)) (the factored columns of the current outer block)
+__device__ __forceinline__ BlkRange blk_range(const ORItem& it, int c0, int cap, int mode, int oend) {
+    BlkRange r;
+    r.wb = min(cap, it.V.n - c0);
+    if (mode == 0) { r.cc0 = 0; r.cc1 = it.C.n; }
+    else if (mode == 1) { r.cc0 = c0 + r.wb; r.cc1 = it.C.n; }
+    else { r.cc0 = c0 + r.wb; r.cc1 = min(min(it.C.n, oend), it.V.n); }  // inner: factored columns only
+    return r;
 }
 
-struct OpQrWp {
+struct BlkOp {
     const ORItem* o;
-    double* const* Wp;
-    int col0;
-    int mode;
-    __device__ int nks(int b) const { return (o[b].V.m - col0 + QR_KS - 1) / QR_KS; }
+    double* const* Wp;  // per item partial sums: nks x 128 x max(128, C.n)
+    int c0, cap, mode, oend;
+    __device__ bool active(int b, BlkRange& r) const {
+        if (o[b].V.n <= c0 || o[b].V.m <= c0) return false;
+        r = blk_range(o[b], c0, cap, mode, oend);
+        return r.wb > 0 && r.cc1 > r.cc0;
+    }
+    __device__ int nks(int b) const { return (o[b].V.m - c0 + QR_KS - 1) / QR_KS; }
+    __device__ int pstride(int b) const { return QR_OB * max(QR_OB, o[b].C.n); }
+};
+
+// P partials: tile = (row tile of the block 64, column tile 64, row chunk)
+struct OpBlkP : BlkOp {
     __device__ int tiles(int b) const {
-        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
-        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
-        return nc > 0 ? ((nc + 63) / 64) * nks(b) : 0;
+        BlkRange r;
+        if (!active(b, r)) return 0;
+        return ((r.wb + 63) / 64) * ((r.cc1 - r.cc0 + 63) / 64) * nks(b);
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
+        BlkRange R;
+        active(b, R);
         const ORItem& it = o[b];
-        const int w = min(QR_NB, it.V.n - col0);
-        const int mp = it.V.m - col0;
-        const int cc0 = qr_ccol(it, col0, mode);
-        const int nc = it.C.n - cc0;
-        const int ntc = (nc + 63) / 64;
-        const int ks = t / ntc, j0 = (t % ntc) * 64;
+        const int nc = R.cc1 - R.cc0;
+        const int ntc = (nc + 63) / 64, ntr = (R.wb + 63) / 64;
+        const int tr = t % ntr, tc = (t / ntr) % ntc, ks = t / (ntr * ntc);
+        const int mp = it.V.m - c0;
         const int r0 = ks * QR_KS;
         const int kl = min(QR_KS, mp - r0);
-        const double* V = it.V.p + col0 + r0 + (int64_t)col0 * it.V.ld;
-        const double* C = it.C.p + col0 + r0 + (int64_t)cc0 * it.C.ld;
+        const double* V = it.V.p + c0 + r0 + (int64_t)c0 * it.V.ld;
+        const double* C = it.C.p + c0 + r0 + (int64_t)R.cc0 * it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        // unit-lower mask of V is relative to the panel start: shift handled by mode 1 only for ks == 0
-        if (ks == 0) mfma_tile_64<true, false, 1, 0>(V, it.V.ld, C, it.C.ld, w, nc, kl, 0, j0, sm, acc);
-        else mfma_tile_64<true, false, 0, 0>(V, it.V.ld, C, it.C.ld, w, nc, kl, 0, j0, sm, acc);
-        double* P = Wp[b] + (int64_t)ks * QR_NB * it.C.n;
+        if (ks == 0) mfma_tile_64<true, false, 1, 0>(V, it.V.ld, C, it.C.ld, R.wb, nc, kl, tr * 64, tc * 64, sm, acc);
+        else mfma_tile_64<true, false, 0, 0>(V, it.V.ld, C, it.C.ld, R.wb, nc, kl, tr * 64, tc * 64, sm, acc);
+        double* P = Wp[b] + (int64_t)ks * pstride(b);
         acc_foreach(acc, [&](int r, int c, double v) {
-            if (r < 32 && j0 + c < nc) P[r + (int64_t)(j0 + c) * QR_NB] = v;
+            const int gr = tr * 64 + r, gc = tc * 64 + c;
+            if (gr < R.wb && gc < nc) P[gr + (int64_t)gc * QR_OB] = v;
         });
     }
 };
 
+// W from the summed partials, per 64-column tile
 template <bool TRANS>
-struct OpQrWr {
-    const ORItem* o;
-    double* const* Wp;
-    int col0;
-    int mode;
+struct OpBlkW : BlkOp {
     __device__ int tiles(int b) const {
-        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
-        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
-        return nc > 0 ? (nc + 63) / 64 : 0;
+        BlkRange r;
+        if (!active(b, r)) return 0;
+        return (r.cc1 - r.cc0 + 63) / 64;
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ double Ts[32][33];
-        __shared__ double P[32][65];
+        __shared__ double P[QR_OB][65];
+        __shared__ double Ts[4][32][33];
+        __shared__ double LG[6][32][33];  // lower blocks G_qj, j < q: index q*(q-1)/2 + j
+        BlkRange R;
+        active(b, R);
         const ORItem& it = o[b];
-        const int w = min(QR_NB, it.V.n - col0);
-        const int mp = it.V.m - col0;
-        const int nks = (mp + QR_KS - 1) / QR_KS;
-        const int cc0 = qr_ccol(it, col0, mode);
-        const int nc = it.C.n - cc0;
+        const int nc = R.cc1 - R.cc0;
         const int j0 = t * 64;
-        const double* Tg = it.T + (int64_t)(col0 / QR_NB) * QR_NB * QR_NB;
-        for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) Ts[e & 31][e >> 5] = Tg[e];
-        for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
-            const int r = e & 31, c = e >> 5;
+        const int nks_ = nks(b);
+        const int ps = pstride(b);
+        const int nsub = (R.wb + QR_NB - 1) / QR_NB;
+        for (int e = threadIdx.x; e < QR_OB * 64; e += blockDim.x) {
+            const int r = e & (QR_OB - 1), c = e >> 7;
             double sum = 0.0;
-            if (j0 + c < nc)
-                for (int ks = 0; ks < nks; ++ks) sum += Wp[b][(int64_t)ks * QR_NB * it.C.n + r + (int64_t)(j0 + c) * QR_NB];
+            if (r < R.wb && j0 + c < nc)
+                for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + r + (int64_t)(j0 + c) * QR_OB];
             P[r][c] = sum;
         }
+        for (int q = 0; q < nsub; ++q) {
+            const double* Tg = it.T + (int64_t)((c0 / QR_NB) + q) * QR_NB * QR_NB;
+            for (int e = threadIdx.x; e < 1024; e += blockDim.x) Ts[q][e & 31][e >> 5] = Tg[e];
+        }
+        if (nsub > 1) {
+            const double* Gg = it.G + (int64_t)(c0 / QR_OB) * QR_OB * QR_OB;
+            for (int q = 1; q < nsub; ++q)
+                for (int j = 0; j < q; ++j)
+                    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+                        const int l = e & 31, m = e >> 5;
+                        LG[q * (q - 1) / 2 + j][l][m] = Gg[(32 * q + l) + (int64_t)(32 * j + m) * QR_OB];
+                    }
+        }
         __syncthreads();
-        for (int e = threadIdx.x; e < 32 * 64; e += blockDim.x) {
-            const int r = e & 31, c = e >> 5;
-            if (r < w && j0 + c < nc) {
-                double sum = 0.0;
+        for (int step = 0; step < nsub; ++step) {
+            const int q = TRANS ? step : nsub - 1 - step;
+            const int wq = min(QR_NB, R.wb - 32 * q);
+            double u[8];
+            // U_q = P_q - sum over the panels already turned into W of G_qj W_j
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = threadIdx.x + k * 256;
+                const int l = e & 31, c = e >> 5;
+                double v = P[32 * q + l][c];
                 if (TRANS) {
-                    for (int l = 0; l <= r; ++l) sum += Ts[l][r] * P[l][c];
+                    for (int j = 0; j < q; ++j)
+                        for (int m = 0; m < 32; ++m) v -= LG[q * (q - 1) / 2 + j][l][m] * P[32 * j + m][c];
                 } else {
-                    for (int l = r; l < w; ++l) sum += Ts[r][l] * P[l][c];
+                    for (int j = q + 1; j < nsub; ++j)
+                        for (int m = 0; m < 32; ++m) v -= LG[j * (j - 1) / 2 + q][m][l] * P[32 * j + m][c];
                 }
-                it.W[r + (int64_t)(j0 + c) * QR_NB] = sum;
+                u[k] = (l < wq) ? v : 0.0;
             }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = threadIdx.x + k * 256;
+                P[32 * q + (e & 31)][e >> 5] = u[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = threadIdx.x + k * 256;
+                const int r = e & 31, c = e >> 5;
+                double v = 0.0;
+                if (r < wq) {
+                    if (TRANS) {
+                        for (int l = 0; l <= r; ++l) v += Ts[q][l][r] * P[32 * q + l][c];
+                    } else {
+                        for (int l = r; l < wq; ++l) v += Ts[q][r][l] * P[32 * q + l][c];
+                    }
+                }
+                u[k] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int e = threadIdx.x + k * 256;
+                P[32 * q + (e & 31)][e >> 5] = u[k];
+            }
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < QR_OB * 64; e += blockDim.x) {
+            const int r = e & (QR_OB - 1), c = e >> 7;
+            if (r < R.wb && j0 + c < nc) it.W[r + (int64_t)(j0 + c) * QR_OB] = P[r][c];
         }
     }
 };
 
-// C -= V W
-struct OpQrUpd {
-    const ORItem* o;
-    int col0;
-    int mode;
+// C -= V_b W
+struct OpBlkUpd : BlkOp {
     __device__ int tiles(int b) const {
-        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
-        const int nc = o[b].C.n - qr_ccol(o[b], col0, mode);
-        const int mp = o[b].V.m - col0;
-        return nc > 0 ? ((mp + 63) / 64) * ((nc + 63) / 64) : 0;
+        BlkRange r;
+        if (!active(b, r)) return 0;
+        const int mp = o[b].V.m - c0;
+        return ((mp + 63) / 64) * ((r.cc1 - r.cc0 + 63) / 64);
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
+        BlkRange R;
+        active(b, R);
         const ORItem& it = o[b];
-        const int w = min(QR_NB, it.V.n - col0);
-        const int mp = it.V.m - col0;
-        const int cc0 = qr_ccol(it, col0, mode);
-        const int nc = it.C.n - cc0;
+        const int mp = it.V.m - c0;
+        const int nc = R.cc1 - R.cc0;
         const int tm = (mp + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
-        const double* V = it.V.p + col0 + (int64_t)col0 * it.V.ld;
-        double* C = it.C.p + col0 + (int64_t)cc0 * it.C.ld;
+        const double* V = it.V.p + c0 + (int64_t)c0 * it.V.ld;
+        double* C = it.C.p + c0 + (int64_t)R.cc0 * it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_NB, mp, nc, w, i0, j0, sm, acc);
+        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_OB, mp, nc, R.wb, i0, j0, sm, acc);
         const int ld = it.C.ld;
         acc_foreach(acc, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
         });
+    }
+};
+
+// G = V_b^T V_b for the 128-column block at c0 (partials then ordered sum)
+struct OpGramP : BlkOp {
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= c0 || o[b].V.m <= c0) return 0;
+        const int wb = min(QR_OB, o[b].V.n - c0);
+        if (wb <= QR_NB) return 0;
+        const int T = (wb + 63) / 64;
+        return T * T * nks(b);
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const ORItem& it = o[b];
+        const int wb = min(QR_OB, it.V.n - c0);
+        const int T = (wb + 63) / 64;
+        const int tr = t % T, tc = (t / T) % T, ks = t / (T * T);
+        const int mp = it.V.m - c0;
+        const int r0 = ks * QR_KS;
+        const int kl = min(QR_KS, mp - r0);
+        const double* V = it.V.p + c0 + r0 + (int64_t)c0 * it.V.ld;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        if (ks == 0) mfma_tile_64<true, false, 1, 1>(V, it.V.ld, V, it.V.ld, wb, wb, kl, tr * 64, tc * 64, sm, acc);
+        else mfma_tile_64<true, false, 0, 0>(V, it.V.ld, V, it.V.ld, wb, wb, kl, tr * 64, tc * 64, sm, acc);
+        double* P = Wp[b] + (int64_t)ks * pstride(b);
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gr = tr * 64 + r, gc = tc * 64 + c;
+            if (gr < wb && gc < wb) P[gr + (int64_t)gc * QR_OB] = v;
+        });
+    }
+};
+struct OpGramR : BlkOp {
+    __device__ int tiles(int b) const {
+        return (o[b].V.n > c0 && o[b].V.m > c0 && min(QR_OB, o[b].V.n - c0) > QR_NB) ? 1 : 0;
+    }
+    __device__ void operator()(int b, int) const {
+        const ORItem& it = o[b];
+        const int wb = min(QR_OB, it.V.n - c0);
+        const int nks_ = nks(b);
+        const int ps = pstride(b);
+        double* G = it.G + (int64_t)(c0 / QR_OB) * QR_OB * QR_OB;
+        for (int e = threadIdx.x; e < QR_OB * QR_OB; e += blockDim.x) {
+            const int r = e & (QR_OB - 1), c = e >> 7;
+            double sum = 0.0;
+            if (r < wb && c < wb)
+                for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + r + (int64_t)c * QR_OB];
+            G[r + (int64_t)c * QR_OB] = sum;
+        }
     }
 };
 
@@ -598,7 +720,7 @@ struct QrScratch {
         std::vector<int64_t> off(items.size() + 1, 0);
         for (size_t i = 0; i < items.size(); ++i) {
             const int nks = ceil_div(std::max(1, items[i].V.m), QR_KS);
-            off[i + 1] = off[i] + (int64_t)QR_NB * std::max(1, items[i].C.n) * nks;
+            off[i + 1] = off[i] + (int64_t)QR_OB * std::max(QR_OB, items[i].C.n) * nks;
         }
         buf.alloc(off.back());
         std::vector<double*> hp(items.size());
@@ -609,23 +731,45 @@ struct QrScratch {
     }
 };
 
-static void apply_panel(Batch<ORItem>& o, QrScratch& sc, int col0, int mode, bool trans, hipStream_t s) {
-    int64_t nw = 0, np = 0, nu = 0;
+static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mode, int oend, bool trans,
+                        hipStream_t s) {
+    int64_t np = 0, nw = 0, nu = 0;
     for (auto& x : o.h) {
-        if (x.V.n <= col0 || x.V.m <= col0) continue;
-        const int cc0 = mode ? col0 + std::min(QR_NB, x.V.n - col0) : 0;
-        const int nc = x.C.n - cc0;
-        if (nc <= 0) continue;
-        const int ntc = ceil_div(nc, 64);
+        if (x.V.n <= c0 || x.V.m <= c0) continue;
+        const int wb = std::min(cap, x.V.n - c0);
+        int cc0, cc1;
+        if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
+        else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
+        else { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+        if (wb <= 0 || cc1 <= cc0) continue;
+        const int ntc = ceil_div(cc1 - cc0, 64);
+        const int mp = x.V.m - c0;
         nw += ntc;
-        np += (int64_t)ntc * ceil_div(x.V.m - col0, QR_KS);
-        nu += (int64_t)ceil_div(x.V.m - col0, 64) * ntc;
+        np += (int64_t)ceil_div(wb, 64) * ntc * ceil_div(mp, QR_KS);
+        nu += (int64_t)ceil_div(mp, 64) * ntc;
     }
     if (nw == 0) return;
-    launch_tiles(OpQrWp{o.d.p, sc.ptr.p, col0, mode}, o.size(), np, s, "qr_wp");
-    if (trans) launch_tiles(OpQrWr<true>{o.d.p, sc.ptr.p, col0, mode}, o.size(), nw, s, "qr_wr");
-    else launch_tiles(OpQrWr<false>{o.d.p, sc.ptr.p, col0, mode}, o.size(), nw, s, "qr_wr");
-    launch_tiles(OpQrUpd{o.d.p, col0, mode}, o.size(), nu, s, "qr_upd");
+    BlkOp base{o.d.p, sc.ptr.p, c0, cap, mode, oend};
+    launch_tiles(OpBlkP{base}, o.size(), np, s, "qr_blk_p");
+    if (trans) launch_tiles(OpBlkW<true>{base}, o.size(), nw, s, "qr_blk_w");
+    else launch_tiles(OpBlkW<false>{base}, o.size(), nw, s, "qr_blk_w");
+    launch_tiles(OpBlkUpd{base}, o.size(), nu, s, "qr_blk_upd");
+}
+
+static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
+    int64_t np = 0, nr = 0;
+    for (auto& x : o.h) {
+        if (x.V.n <= c0 || x.V.m <= c0) continue;
+        const int wb = std::min(QR_OB, x.V.n - c0);
+        if (wb <= QR_NB) continue;  // a single panel needs no G
+        const int T = ceil_div(wb, 64);
+        np += (int64_t)T * T * ceil_div(x.V.m - c0, QR_KS);
+        ++nr;
+    }
+    if (nr == 0) return;
+    BlkOp base{o.d.p, sc.ptr.p, c0, QR_OB, 0, 0};
+    launch_tiles(OpGramP{base}, o.size(), np, s, "qr_gram_p");
+    launch_tiles(OpGramR{base}, o.size(), nr, s, "qr_gram_r");
 }
 
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
@@ -634,7 +778,7 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     std::vector<double*> htau;
     for (auto& x : q.h) {
         nmax = std::max(nmax, std::min(x.nfac, x.A.m));
-        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W});
+        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W, x.G});
         htau.push_back(x.tau);
     }
     o.sync(s);
@@ -642,12 +786,16 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     sc.alloc(o.h, s);
     DBuf<double*> dtau(htau.size());
     h2d(dtau.p, htau.data(), htau.size(), s);
-    for (int col0 = 0; col0 < nmax; col0 += QR_NB) {
-        int64_t np = 0;
-        for (auto& x : q.h) np += (x.nfac > col0 && x.A.m > col0) ? 1 : 0;
-        launch_tiles(OpQrPanel{q.d.p, col0}, q.size(), np, s, "qr_panel");
-        launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "qr_buildT");
-        apply_panel(o, sc, col0, 1, true, s);
+    for (int col0 = 0; col0 < nmax; col0 += QR_OB) {
+        for (int in0 = col0; in0 < std::min(nmax, col0 + QR_OB); in0 += QR_NB) {
+            int64_t np = 0;
+            for (auto& x : q.h) np += (x.nfac > in0 && x.A.m > in0) ? 1 : 0;
+            launch_tiles(OpQrPanel{q.d.p, in0}, q.size(), np, s, "qr_panel");
+            launch_tiles(OpBuildT{o.d.p, dtau.p, in0}, o.size(), np, s, "qr_buildT");
+            apply_block(o, sc, in0, QR_NB, 2, col0 + QR_OB, true, s);  // rest of this outer block
+        }
+        gram_block(o, sc, col0, s);
+        apply_block(o, sc, col0, QR_OB, 1, 0, true, s);  // trailing matrix
     }
     DD_HIP(hipStreamSynchronize(s));
 }
@@ -657,11 +805,14 @@ void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t 
     for (auto& x : o.h) kmax = std::max(kmax, x.V.n);
     DBuf<double*> dtau(htau.size());
     h2d(dtau.p, htau.data(), htau.size(), s);
+    QrScratch sc;
+    sc.alloc(o.h, s);
     for (int col0 = 0; col0 < kmax; col0 += QR_NB) {
         int64_t np = 0;
         for (auto& x : o.h) np += (x.V.n > col0 && x.V.m > col0) ? 1 : 0;
         launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "buildT");
     }
+    for (int col0 = 0; col0 < kmax; col0 += QR_OB) gram_block(o, sc, col0, s);
     DD_HIP(hipStreamSynchronize(s));
 }
 
@@ -670,10 +821,10 @@ void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s) {
     for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
     QrScratch sc;
     sc.alloc(o.h, s);
-    const int np = ceil_div(kmax, QR_NB);
-    for (int step = 0; step < np; ++step) {
-        const int k = trans ? step : (np - 1 - step);
-        apply_panel(o, sc, k * QR_NB, 0, trans, s);
+    const int nb = ceil_div(kmax, QR_OB);
+    for (int step = 0; step < nb; ++step) {
+        const int k = trans ? step : (nb - 1 - step);
+        apply_block(o, sc, k * QR_OB, QR_OB, 0, 0, trans, s);
     }
     DD_HIP(hipStreamSynchronize(s));
 }
@@ -1014,32 +1165,34 @@ void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, do
             }
         }
     }
-    DBuf<double> tq, tT, tW, tQ;
+    DBuf<double> tq, tT, tW, tQ, tG;
     std::vector<DMat> hsrc, hdst;
     if (!cls.empty()) {
-        int64_t a = 0, bT = 0, bW = 0, bQ = 0;
+        int64_t a = 0, bT = 0, bW = 0, bQ = 0, bG = 0;
         for (auto& c : cls) {
             const int n = v.h[c.item].n;
             a += c.c;
-            bT += (int64_t)ceil_div(c.c, QR_NB) * QR_NB * QR_NB;
-            bW += (int64_t)QR_NB * c.c;
+            bT += qr_t_size(c.c);
+            bW += qr_w_size(c.c);
             bQ += (int64_t)n * c.c;
+            bG += qr_g_size(c.c);
         }
-        tq.alloc(a); tT.alloc(bT); tW.alloc(bW); tQ.alloc(bQ);
-        a = bT = bW = bQ = 0;
+        tq.alloc(a); tT.alloc(bT); tW.alloc(bW); tQ.alloc(bQ); tG.alloc(bG);
+        a = bT = bW = bQ = bG = 0;
         for (auto& c : cls) {
             const VecItem& it = v.h[c.item];
             const int n = it.n;
             DMat Yc{it.Y + (int64_t)c.c0 * it.ldy, it.ldy, n, c.c};
             DMat Qc{tQ.p + bQ, n, n, c.c};
-            qb.h.push_back(QRItem{Yc, tq.p + a, tT.p + bT, tW.p + bW, QR_NB, c.c});
-            ob.h.push_back(ORItem{Yc, tT.p + bT, Qc, tW.p + bW});
+            qb.h.push_back(QRItem{Yc, tq.p + a, tT.p + bT, tW.p + bW, QR_NB, c.c, tG.p + bG});
+            ob.h.push_back(ORItem{Yc, tT.p + bT, Qc, tW.p + bW, tG.p + bG});
             hsrc.push_back(Qc);
             hdst.push_back(Yc);
             a += c.c;
-            bT += (int64_t)ceil_div(c.c, QR_NB) * QR_NB * QR_NB;
-            bW += (int64_t)QR_NB * c.c;
+            bT += qr_t_size(c.c);
+            bW += qr_w_size(c.c);
             bQ += (int64_t)n * c.c;
+            bG += qr_g_size(c.c);
         }
         qb.sync(s);
         ob.sync(s);

@@ -27,27 +27,35 @@ struct Batch {
 
 // QR storage: A (m x n, m >= n) holds R above and the Householder vectors below
 // the diagonal (unit diagonal implicit); tau[n]; T holds one 32x32 upper
-// triangular compact-WY factor per 32-column panel; W is 32 x max(cols) scratch.
+// triangular compact-WY factor per 32-column panel (qr_t_size); G holds the
+// Gram matrix V^T V of every 128-column block of reflectors (qr_g_size); W is
+// scratch of qr_w_size(max columns of the matrices the reflectors touch).
 struct QRItem {
     DMat A;
     double* tau;
     double* T;
     double* W;
-    int wld;   // leading dimension of W (>= 32)
+    int wld;   // unused (kept for layout stability)
     int nfac;  // factor only the first nfac columns (<= n); the rest receive Q^T
+    double* G;
 };
 
-// Application of the Q stored in V (m x k reflectors, T factors as above) to C
+// Application of the Q stored in V (m x k reflectors, T and G as above) to C
 // (m x nc, rows aligned with V's rows).
 struct ORItem {
     DMat V;   // m x k: reflector j in column j, rows j..m-1
     double* T;
     DMat C;
-    double* W;  // 32 x C.n
+    double* W;  // qr_w_size(C.n)
+    double* G;
 };
 
-constexpr int QR_NB = 32;
+constexpr int QR_NB = 32;   // inner panel width
+constexpr int QR_OB = 128;  // outer block (four inner panels)
 constexpr int CH_NB = 64;
+inline int64_t qr_t_size(int k) { return (int64_t)((k + QR_NB - 1) / QR_NB) * QR_NB * QR_NB; }
+inline int64_t qr_g_size(int k) { return (int64_t)((k + QR_OB - 1) / QR_OB) * QR_OB * QR_OB; }
+inline int64_t qr_w_size(int ncols) { return (int64_t)QR_OB * ncols; }
 
 // C := alpha * op(A) op(B) + beta * C for every item (dims from C and A).
 struct GemmItem {
@@ -77,7 +85,7 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s);
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
 // C := Q C (trans = false) or Q^T C (trans = true).
 void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s);
-// T factors for reflectors stored in V with taus (used after sytrd).
+// T and G factors for reflectors stored in V with taus (used after sytrd).
 void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t s);
 
 // Householder tridiagonalisation of symmetric A (full storage, in place).
