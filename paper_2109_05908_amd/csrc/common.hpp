@@ -205,9 +205,11 @@ __device__ __forceinline__ double4_t mfma_f64(double a, double b, double4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+constexpr int KC = 32;  // K depth of one LDS stage
+
 struct TileSmem {
-    double a[16][64 + 1];
-    double b[16][64 + 1];
+    double a[KC][64 + 1];
+    double b[KC][64 + 1];
 };
 
 template <bool TA, int MODEA>
@@ -229,7 +231,9 @@ __device__ __forceinline__ double load_b(const double* __restrict__ B, int64_t l
     return B[r + (int64_t)c * ldb];
 }
 
-// acc += op(A)[i0:i0+64, :] * op(B)[:, j0:j0+64]
+// acc += op(A)[i0:i0+64, :] * op(B)[:, j0:j0+64].  K is consumed in stages of
+// KC; the next stage's operands are loaded into registers while the MFMAs of
+// the current stage run from LDS.
 template <bool TA, bool TB, int MODEA = 0, int MODEB = 0>
 __device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
                                              int64_t ldb, int M, int N, int K, int i0, int j0, TileSmem& sm,
@@ -237,22 +241,37 @@ __device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64
                                              const int* gb = nullptr) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    constexpr int PER = (64 * KC) / 256;  // elements of each operand per thread and stage
+    double ra[PER], rb[PER];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int e = t; e < 1024; e += 256) {
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * 256;
             int ii, kk;
-            if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e & 15; ii = e >> 4; }
-            sm.a[kk][ii] = load_a<TA, MODEA>(A, lda, i0 + ii, k0 + kk, M, K, ga);
+            if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e % KC; ii = e / KC; }
+            ra[q] = load_a<TA, MODEA>(A, lda, i0 + ii, k0 + kk, M, K, ga);
+            int jj, kb;
+            if (!TB) { kb = e % KC; jj = e / KC; } else { jj = e & 63; kb = e >> 6; }
+            rb[q] = load_b<TB, MODEB>(B, ldb, k0 + kb, j0 + jj, K, N, gb);
         }
+    };
+    if (K <= 0) return;
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
 #pragma unroll
-        for (int e = t; e < 1024; e += 256) {
-            int jj, kk;
-            if (!TB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
-            sm.b[kk][jj] = load_b<TB, MODEB>(B, ldb, k0 + kk, j0 + jj, K, N, gb);
+        for (int q = 0; q < PER; ++q) {
+            const int e = t + q * 256;
+            int ii, kk;
+            if (!TA) { ii = e & 63; kk = e >> 6; } else { kk = e % KC; ii = e / KC; }
+            sm.a[kk][ii] = ra[q];
+            int jj, kb;
+            if (!TB) { kb = e % KC; jj = e / KC; } else { jj = e & 63; kb = e >> 6; }
+            sm.b[kb][jj] = rb[q];
         }
         __syncthreads();
+        if (k0 + KC < K) fetch(k0 + KC);
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
+        for (int kq = 0; kq < KC / 4; ++kq) {
             const int kk = kq * 4 + (lane >> 4);
             const double a0 = sm.a[kk][wr + (lane & 15)], a1 = sm.a[kk][wr + 16 + (lane & 15)];
             const double b0 = sm.b[kk][wc + (lane & 15)], b1 = sm.b[kk][wc + 16 + (lane & 15)];

@@ -248,38 +248,39 @@ struct OpTrsmDiag {
     }
 };
 
-// Forward: B[k0+w:, :] -= L[k0+w:, k0:k0+w] B[k0:k0+w, :]
-// Backward: B[0:k0, :] -= L[k0:k0+w, 0:k0]^T B[k0:k0+w, :]
+// Recursive update of a triangular solve over rows [r0, r1) split at mid:
+// forward  B[mid:e, :] -= L[mid:e, r0:mid] B[r0:mid, :]
+// backward B[r0:mid, :] -= L[mid:e, r0:mid]^T B[mid:e, :],  e = min(n, r1)
 template <bool TRANS>
-struct OpTrsmUpd {
+struct OpTrsmGemm {
     const DMat* L;
     const DMat* B;
-    int kb;
-    __device__ int rows(int b) const { return TRANS ? min(kb, L[b].n) : L[b].n - kb - 64; }
+    int r0, mid, r1;
     __device__ int tiles(int b) const {
-        if (L[b].n <= kb) return 0;
-        const int r = rows(b);
-        return r > 0 ? ((r + 63) / 64) * ((B[b].n + 63) / 64) : 0;
+        const int n = L[b].n;
+        if (n <= mid) return 0;
+        const int e = min(n, r1);
+        const int M = TRANS ? mid - r0 : e - mid;
+        return ((M + 63) / 64) * ((B[b].n + 63) / 64);
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
         const DMat Lm = L[b], Bm = B[b];
-        const int w = min(64, Lm.n - kb);
-        const int M = rows(b);
+        const int e = min(Lm.n, r1);
+        const int M = TRANS ? mid - r0 : e - mid;
+        const int K = TRANS ? e - mid : mid - r0;
         const int tm = (M + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
         double4_t acc[2][2];
         acc_zero(acc);
-        const double* Bk = Bm.p + kb;
+        const double* A = Lm.p + mid + (int64_t)r0 * Lm.ld;  // L[mid:e, r0:mid]
         double* Cp;
         if (!TRANS) {
-            const double* A = Lm.p + (kb + w) + (int64_t)kb * Lm.ld;
-            mfma_tile_64<false, false>(A, Lm.ld, Bk, Bm.ld, M, Bm.n, w, i0, j0, sm, acc);
-            Cp = Bm.p + (kb + w);
+            mfma_tile_64<false, false>(A, Lm.ld, Bm.p + r0, Bm.ld, M, Bm.n, K, i0, j0, sm, acc);
+            Cp = Bm.p + mid;
         } else {
-            const double* A = Lm.p + kb;  // rows kb.., cols 0..kb-1, transposed
-            mfma_tile_64<true, false>(A, Lm.ld, Bk, Bm.ld, M, Bm.n, w, i0, j0, sm, acc);
-            Cp = Bm.p;
+            mfma_tile_64<true, false>(A, Lm.ld, Bm.p + mid, Bm.ld, M, Bm.n, K, i0, j0, sm, acc);
+            Cp = Bm.p + r0;
         }
         const int N = Bm.n, ld = Bm.ld;
         acc_foreach(acc, [&](int r, int c, double v) {
@@ -289,112 +290,146 @@ struct OpTrsmUpd {
     }
 };
 
+static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, bool trans, int r0, int r1, hipStream_t s) {
+    if (r1 - r0 <= 64) {
+        int64_t nd = 0;
+        for (int b = 0; b < L.size(); ++b)
+            if (L.h[b].n > r0) nd += ceil_div(B.h[b].n, 64);
+        if (!nd) return;
+        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, r0}, L.size(), nd, s, "trsm_diag");
+        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, r0}, L.size(), nd, s, "trsmT_diag");
+        return;
+    }
+    const int mid = r0 + ceil_div(r1 - r0, 128) * 64;
+    int64_t nu = 0;
+    for (int b = 0; b < L.size(); ++b) {
+        const int n = L.h[b].n;
+        if (n <= mid) continue;
+        const int e = std::min(n, r1);
+        const int M = trans ? mid - r0 : e - mid;
+        nu += (int64_t)ceil_div(M, 64) * ceil_div(B.h[b].n, 64);
+    }
+    if (!trans) {
+        trsm_rec(L, B, trans, r0, mid, s);
+        if (nu) launch_tiles(OpTrsmGemm<false>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsm_gemm");
+        trsm_rec(L, B, trans, mid, r1, s);
+    } else {
+        trsm_rec(L, B, trans, mid, r1, s);
+        if (nu) launch_tiles(OpTrsmGemm<true>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsmT_gemm");
+        trsm_rec(L, B, trans, r0, mid, s);
+    }
+}
+
 void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
     int nmax = 0;
     for (auto& x : L.h) nmax = std::max(nmax, x.n);
-    const int nblk = ceil_div(nmax, 64);
-    for (int step = 0; step < nblk; ++step) {
-        const int kb = trans ? (nblk - 1 - step) * 64 : step * 64;
-        int64_t nd = 0, nu = 0;
-        for (int b = 0; b < L.size(); ++b) {
-            const auto& l = L.h[b];
-            if (l.n <= kb) continue;
-            const int nct = ceil_div(B.h[b].n, 64);
-            nd += nct;
-            const int r = trans ? std::min(kb, l.n) : l.n - kb - 64;
-            if (r > 0) nu += (int64_t)ceil_div(r, 64) * nct;
-        }
-        if (!trans) {
-            launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, kb}, L.size(), nd, s, "trsm_diag");
-            launch_tiles(OpTrsmUpd<false>{L.d.p, B.d.p, kb}, L.size(), nu, s, "trsm_upd");
-        } else {
-            launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, kb}, L.size(), nd, s, "trsmT_diag");
-            launch_tiles(OpTrsmUpd<true>{L.d.p, B.d.p, kb}, L.size(), nu, s, "trsmT_upd");
-        }
-    }
+    if (nmax == 0) return;
+    trsm_rec(L, B, trans, 0, ceil_div(nmax, 64) * 64, s);
 }
 
 // ===========================================================================
 // Householder QR (32-column panels, compact WY)
 // ===========================================================================
-// Unblocked Householder on panel [col0, col0+w) of A, rows col0..m-1.
-struct OpQrPanel {
-    const QRItem* q;
-    int col0;
-    __device__ int tiles(int b) const { return (q[b].nfac > col0 && q[b].A.m > col0) ? 1 : 0; }
-    __device__ void operator()(int b, int) const {
-        __shared__ double red[4 * 33];
-        __shared__ double sc[33];
-        const DMat A = q[b].A;
-        const int w = min(QR_NB, q[b].nfac - col0);
-        const int mp = A.m - col0;
-        double* V = A.p + col0 + (int64_t)col0 * A.ld;
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int j = 0; j < w; ++j) {
-            double* vj = V + (int64_t)j * A.ld;
-            // norm of x[j+1:]
-            double p = 0.0;
-            for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) p += vj[r] * vj[r];
-            p = wave_sum(p);
-            if (lane == 0) red[wv] = p;
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                const double xn2 = red[0] + red[1] + red[2] + red[3];
-                const double alpha = vj[j];
-                double tau = 0.0, beta = alpha, scal = 0.0;
-                if (xn2 > 0.0) {
-                    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                    tau = (beta - alpha) / beta;
-                    scal = 1.0 / (alpha - beta);
-                }
-                sc[0] = tau;
-                sc[1] = scal;
-                sc[2] = beta;
-                q[b].tau[col0 + j] = tau;
-            }
-            __syncthreads();
-            const double tau = sc[0], scal = sc[1];
-            for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) vj[r] *= scal;
-            __syncthreads();
-            if (threadIdx.x == 0) vj[j] = sc[2];
-            // apply H_j to columns j+1..w-1
-            const int nrem = w - j - 1;
-            if (nrem > 0 && tau != 0.0) {
-                double part[QR_NB];
-#pragma unroll
-                for (int c = 0; c < QR_NB; ++c) part[c] = 0.0;
-                for (int r = j + 1 + threadIdx.x; r < mp; r += blockDim.x) {
-                    const double v = vj[r];
-#pragma unroll
-                    for (int c = 0; c < QR_NB; ++c)
-                        if (c < nrem) part[c] += v * V[r + (int64_t)(j + 1 + c) * A.ld];
-                }
-#pragma unroll
-                for (int c = 0; c < QR_NB; ++c) {
-                    if (c < nrem) {
-                        const double sv = wave_sum(part[c]);
-                        if (lane == 0) red[wv * 33 + c] = sv;
-                    }
-                }
-                __syncthreads();
-                if (threadIdx.x < nrem) {
-                    const int c = threadIdx.x;
-                    const double s0 = V[j + (int64_t)(j + 1 + c) * A.ld];  // v_j = 1 term
-                    const double tot = s0 + red[c] + red[33 + c] + red[66 + c] + red[99 + c];
-                    red[c] = tau * tot;  // each thread owns column c of red
+// Unblocked Householder on panel [col0, col0+w) of A, rows col0..m-1, one
+// workgroup of 1024 threads per item.  Each column costs one pass over the
+// remaining panel rows: the pass applies reflector j to columns j+1.. and, on
+// the fly, accumulates the squared norm of the next column below its diagonal
+// and the unscaled products of that column with the later ones; one block
+// reduction then gives every scalar the next reflector needs.
+constexpr int PANEL_THREADS = 1024;
 
-                }
-                __syncthreads();
-                for (int e = threadIdx.x; e < nrem * (mp - j); e += blockDim.x) {
-                    const int c = e / (mp - j), r = j + e % (mp - j);
-                    const double v = (r == j) ? 1.0 : vj[r];
-                    V[r + (int64_t)(j + 1 + c) * A.ld] -= red[c] * v;
-                }
-            }
-            __syncthreads();
+__device__ __forceinline__ void panel_reduce(double (&part)[QR_NB + 1], int nval, double (*red)[QR_NB + 2],
+                                             double* out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c <= QR_NB; ++c) {
+        if (c < nval) {
+            const double v = wave_sum(part[c]);
+            if (lane == 0) red[wv][c] = v;
         }
     }
-};
+    __syncthreads();
+    if ((int)threadIdx.x < nval) {
+        double sum = 0.0;
+        for (int q = 0; q < PANEL_THREADS / 64; ++q) sum += red[q][threadIdx.x];
+        out[threadIdx.x] = sum;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int nitems, int col0) {
+    __shared__ double red[PANEL_THREADS / 64][QR_NB + 2];
+    __shared__ double sh[QR_NB + 2];  // sh[0] = norm^2 below diag of the current column, sh[1+k] = dots
+    __shared__ double coef[QR_NB];
+    __shared__ double s_scal;
+    const int b = blockIdx.x;
+    if (b >= nitems) return;
+    const QRItem it = q[b];
+    if (it.nfac <= col0 || it.A.m <= col0) return;
+    const int w = min(QR_NB, it.nfac - col0);
+    const int mp = it.A.m - col0;
+    const int64_t ld = it.A.ld;
+    double* V = it.A.p + col0 + (int64_t)col0 * ld;
+    double part[QR_NB + 1];
+    // column 0: norm^2 of x[1:] and products x[1:] . a_c[1:], c = 1..w-1
+#pragma unroll
+    for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
+    for (int r = 1 + threadIdx.x; r < mp; r += PANEL_THREADS) {
+        const double x = V[r];
+        part[0] += x * x;
+#pragma unroll
+        for (int c = 1; c < QR_NB; ++c)
+            if (c < w) part[c] += x * V[r + c * ld];
+    }
+    panel_reduce(part, w, red, sh);
+    for (int j = 0; j < w; ++j) {
+        // reflector j from alpha = V[j][j] and ||x[1:]||^2 = sh[0]
+        if (threadIdx.x == 0) {
+            const double alpha = V[j + j * ld];
+            const double xn2 = sh[0];
+            double tau = 0.0, beta = alpha, scal = 0.0;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                scal = 1.0 / (alpha - beta);
+            }
+            it.tau[col0 + j] = tau;
+            s_scal = scal;
+            // coefficient tau * (v . a_c), v = [1; scal * x[1:]]
+            for (int c = j + 1; c < w; ++c) coef[c] = tau * (V[j + c * ld] + scal * sh[1 + (c - j - 1)]);
+            V[j + j * ld] = beta;
+        }
+        __syncthreads();
+        const double scal = s_scal;
+#pragma unroll
+        for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
+        // one pass: scale v, update columns > j, accumulate for column j+1
+        for (int r = j + threadIdx.x; r < mp; r += PANEL_THREADS) {
+            double v = 1.0;
+            if (r > j) {
+                v = V[r + j * ld] * scal;
+                V[r + j * ld] = v;
+            }
+            double xn = 0.0;
+#pragma unroll
+            for (int c = 1; c < QR_NB; ++c) {
+                const int cc = j + c;
+                if (cc < w) {
+                    const double a = V[r + cc * ld] - coef[cc] * v;
+                    if (r != j || true) V[r + cc * ld] = a;
+                    if (c == 1) {
+                        xn = a;
+                        if (r > j + 1) part[0] += a * a;
+                    } else if (r > j + 1) {
+                        part[c - 1] += xn * a;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (j + 1 < w) panel_reduce(part, w - j - 1, red, sh);
+    }
+}
 
 // T factor for the reflectors of panel k: T = upper triangular with
 // H_0 ... H_{w-1} = I - V T V^T.  G = V^T V over rows col0..m-1.
@@ -790,7 +825,10 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
         for (int in0 = col0; in0 < std::min(nmax, col0 + QR_OB); in0 += QR_NB) {
             int64_t np = 0;
             for (auto& x : q.h) np += (x.nfac > in0 && x.A.m > in0) ? 1 : 0;
-            launch_tiles(OpQrPanel{q.d.p, in0}, q.size(), np, s, "qr_panel");
+            if (np) {
+                hipLaunchKernelGGL(k_qr_panel, dim3(q.size()), dim3(PANEL_THREADS), 0, s, q.d.p, q.size(), in0);
+                launch_check("qr_panel");
+            }
             launch_tiles(OpBuildT{o.d.p, dtau.p, in0}, o.size(), np, s, "qr_buildT");
             apply_block(o, sc, in0, QR_NB, 2, col0 + QR_OB, true, s);  // rest of this outer block
         }
