@@ -23,6 +23,21 @@ if ROOT not in sys.path:
 
 METRIC = "setup+solve sec to 1e-8 rel-res: learned/FP32/batched vs plain FP64, 1 MI355X"
 
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# The kernel whose roofline is reported: the trailing update C -= V_b W of the
+# blocked Householder QR (MFMA FP64), the largest single kernel family of the
+# setup.  Its HBM traffic per dispatch comes from two rocprofv3 PMC passes
+# (FETCH_SIZE, WRITE_SIZE) over this same workload, scaled by what the counters
+# read for a plain copy of known size; it is only reported while the kernel
+# sources still hash to what was profiled.
+ROOFLINE_KERNEL = "qr_blk_upd"
+ROOFLINE_SOURCES = ["common.hpp", "dense.hpp", "dense.hip"]
+TRAFFIC = {"sha256": "4beaa33a655d5697", "bytes_per_launch": 8.2334e9,
+           "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6"}
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -33,7 +48,33 @@ def parse():
     p.add_argument("--form", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run a plain device copy of 1 GiB three times (PMC byte-counter calibration) and exit")
     return p.parse_args()
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ROOFLINE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2109_05908_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def calibrate_copy():
+    import torch
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        t0 = time.perf_counter()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] copy 1 GiB -> 1 GiB: {dt * 1e3:.3f} ms, {2 * n * 8 / dt / 1e9:.0f} GB/s", file=sys.stderr,
+              flush=True)
 
 
 def workload(name):
@@ -48,12 +89,19 @@ def workload(name):
                  "lambda_threshold": round(1 / cfg.tau), "tau": cfg.tau, "levels": cfg.levels}
 
 
-def cpu_baseline(cfg, part, budget, pre_sizes):
-    """Oracle (FP64 NumPy/SciPy) on a bounded sample of the same workload,
-    extrapolated to the whole setup + solve: local setups are timed on a
-    size-stratified sample of subdomains and scaled by sum(n_i^3); the dense
-    coarse Cholesky is timed at a smaller size and scaled by n_C^3; the solve
-    is timed per PCG iteration on the sample's local solves and scaled."""
+def cpu_baseline(cfg, part, budget, pre_sizes, its):
+    """The oracle (FP64 NumPy/SciPy, as committed) on a bounded sample of the
+    same workload, extrapolated to the whole setup + solve.
+
+    Setup: the index sets of all subdomains are computed in full; the local
+    setup (extraction, SVD splitting and Schur complement, eigenproblem,
+    Cholesky) runs on a size-stratified sample of subdomains and is scaled by
+    sum(n_i^3); the coarse Cholesky (dense, as in the oracle) is timed at
+    m <= 3000 and scaled by (n_C/m)^3.  Solve: one oracle PCG iteration costs a
+    SpMV (timed in full), the sampled local cho_solve calls scaled by
+    sum(n_i^2), and a dense coarse cho_solve timed at m and scaled by
+    (n_C/m)^2; multiplied by the GPU's iteration count (the oracle's count
+    agrees to +-1 in the parity tests)."""
     import numpy as np
     import scipy.linalg as sla
 
@@ -65,12 +113,12 @@ def cpu_baseline(cfg, part, budget, pre_sizes):
     t_sets = time.perf_counter() - t0
     ni = np.array([s.Omega.size for s in sets], dtype=float)
     order = np.argsort(ni)
-    cost_all = float((ni ** 3).sum())
-    sample, cost_s, t_loc = [], 0.0, 0.0
+    cost3, cost2 = float((ni ** 3).sum()), float((ni ** 2).sum())
+    t_loc, t_sol, c3, c2, nsamp = 0.0, 0.0, 0.0, 0.0, 0
     p_sample = []
-    # stratified: walk the size-sorted list with a stride until the budget is used
     stride = max(1, N // 16)
     idx = list(order[::stride]) + list(order[stride // 2::stride])
+    rng = np.random.default_rng(0)
     for i in idx:
         if t_loc > budget * 0.6:
             break
@@ -79,30 +127,66 @@ def cpu_baseline(cfg, part, budget, pre_sizes):
         Aii, Xi = O.extract(A, s)
         spl = O.local_splitting(Xi, s.I.size, s.Gamma.size)
         _, mk, _ = O.local_eigen(Aii, spl.S_I, s.I.size, cfg.tau)
-        sla.cho_factor(Aii, lower=True)
+        ch = sla.cho_factor(Aii, lower=True)
         t_loc += time.perf_counter() - t1
-        sample.append(int(i))
-        cost_s += ni[i] ** 3
+        r = rng.standard_normal(Aii.shape[0])
+        t1 = time.perf_counter()
+        sla.cho_solve(ch, r)
+        t_sol += time.perf_counter() - t1
+        nsamp += 1
+        c3 += ni[i] ** 3
+        c2 += ni[i] ** 2
         p_sample.append(mk.size)
-    local_est = t_loc * cost_all / cost_s
     nC = int(pre_sizes[:, 3].sum()) if pre_sizes is not None else int(np.mean(p_sample) * N)
     m = min(nC, 3000)
-    M = np.random.default_rng(0).standard_normal((m, m))
+    M = rng.standard_normal((m, m))
     M = M @ M.T + m * np.eye(m)
     t1 = time.perf_counter()
-    sla.cho_factor(M, lower=True)
-    t_c = time.perf_counter() - t1
-    coarse_est = t_c * (nC / m) ** 3
-    used = t_sets + t_loc + t_c
-    est = t_sets + local_est + coarse_est
+    chE = sla.cho_factor(M, lower=True)
+    t_cf = time.perf_counter() - t1
+    y = rng.standard_normal(m)
+    t1 = time.perf_counter()
+    for _ in range(5):
+        sla.cho_solve(chE, y)
+    t_cs = (time.perf_counter() - t1) / 5
+    x = rng.standard_normal(A.shape[0])
+    t1 = time.perf_counter()
+    for _ in range(5):
+        A @ x
+    t_mv = (time.perf_counter() - t1) / 5
+    setup_est = t_sets + t_loc * cost3 / c3 + t_cf * (nC / m) ** 3
+    iter_est = t_mv + t_sol * cost2 / c2 + t_cs * (nC / m) ** 2
+    est = setup_est + its * iter_est
+    used = t_sets + t_loc + t_sol + t_cf + 5 * (t_cs + t_mv)
     threads = os.environ.get("OMP_NUM_THREADS") or str(len(os.sched_getaffinity(0)))
     return {
-        "value": est, "unit": "s (estimated setup, oracle)", "cores": int(threads), "kind": "oracle",
-        "sample": (f"sets for all {N} subdomains ({t_sets:.1f}s); full local setup (SVD, Schur, eigen, Cholesky) "
-                   f"on {len(sample)} size-stratified subdomains ({t_loc:.1f}s) scaled by sum n_i^3; dense coarse "
-                   f"Cholesky at m={m} ({t_c:.2f}s) scaled to n_C={nC} by (n_C/m)^3; solve not included; "
-                   f"{used:.1f}s of CPU work"),
+        "value": est, "unit": "s (setup+solve, extrapolated)", "cores": int(threads), "kind": "oracle",
+        "setup_s": setup_est, "solve_s": its * iter_est,
+        "sample": (f"index sets of all {N} subdomains ({t_sets:.1f}s); oracle local setup (extraction, SVD "
+                   f"splitting + Schur, eigen, Cholesky) on {nsamp} size-stratified subdomains ({t_loc:.1f}s) "
+                   f"scaled by sum n_i^3; dense coarse Cholesky at m={m} ({t_cf:.2f}s) scaled to n_C={nC} by "
+                   f"(n_C/m)^3; per-iteration SpMV + sampled local cho_solve scaled by sum n_i^2 + coarse "
+                   f"cho_solve scaled by (n_C/m)^2, times {its} iterations; {used:.1f}s of CPU work"),
     }
+
+
+def roofline(met, workload_name):
+    """Achieved FP64 MFMA rate of the metered kernel: algorithmic flops per
+    dispatch / average event-timed dispatch duration, against the FP64 peak."""
+    if met["launches"] == 0 or met["total_ms"] <= 0:
+        return None
+    avg_ms = met["total_ms"] / met["launches"]
+    achieved = met["flops"] / (met["total_ms"] * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC and TRAFFIC["sha256"] == source_hash() and TRAFFIC["workload"] == workload_name:
+        traffic = TRAFFIC["bytes_per_launch"]
+    return {"bound": "mfma", "kernel": "k_tiles<OpBlkUpd> (" + ROOFLINE_KERNEL + ")", "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+            "launches": met["launches"], "avg_launch_ms": avg_ms,
+            "flops_per_launch": met["flops"] / met["launches"],
+            "algorithmic_bytes_per_launch": met["bytes"] / met["launches"],
+            "achieved_algorithmic_GBs": met["bytes"] / (met["total_ms"] * 1e-3) / 1e9,
+            "source_sha256": source_hash()}
 
 
 def main():
@@ -115,8 +199,11 @@ def main():
     import torch
 
     import workloads as W
-    from paper_2109_05908_amd import DD_FP32, DD_FP64, DeviceCSR, Preconditioner, partition_ggg
+    from paper_2109_05908_amd import DD_FP32, DD_FP64, DeviceCSR, Preconditioner, meter_read, meter_start, partition_ggg
 
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     cfg, conf = workload(args.workload)
     dev = "cuda:0"
     dA = DeviceCSR.from_workload(cfg.A, device=dev)
@@ -148,6 +235,7 @@ def main():
     times = []
     last = None
     torch.cuda.synchronize()
+    meter_start(ROOFLINE_KERNEL)
     t_all = time.perf_counter()
     for k in range(args.steps):
         pre, ts, tv, its, rr = step()
@@ -160,6 +248,8 @@ def main():
             last = pre
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_all
+    met = meter_read()
+    meter_start(None)
     info = last.info()
     sizes = last.sizes()
     per = [t[0] + t[1] for t in times]
@@ -173,11 +263,11 @@ def main():
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.form == "fp64" else "f64 (f32 local factors)",
-        "data": "synthetic", "config": conf, "roofline": None,
+        "data": "synthetic", "config": conf, "roofline": roofline(met, conf["workload"]),
     }
     if not args.no_cpu_baseline:
         part_h = part.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(cfg, part_h, args.cpu_budget, sizes)
+        out["cpu_baseline"] = cpu_baseline(cfg, part_h, args.cpu_budget, sizes, times[-1][2])
     print(json.dumps(out), flush=True)
 
 

@@ -153,6 +153,25 @@ int dd_subdomain_sigma1(dd_handle h, int32_t level, double* sigma1);
 /* Coarse operator E of `level` (n_C x n_C dense, column-major), only if n_C <= max_n. */
 int dd_coarse_matrix(dd_handle h, int32_t level, double* E, int64_t max_n);
 
+/* ---- kernel meter (measurement) ------------------------------------------
+ * Device-side timing of one kernel family without a profiler.  After
+ * dd_meter_start(name), every dispatch of the kernels launched under `name`
+ * (e.g. "qr_blk_upd": the trailing update C -= V_b W of the blocked
+ * Householder QR; "gemm_nn"/"gemm_nt"/"gemm_tn"/"gemm_tt": batched GEMM) is
+ * bracketed by HIP events recorded on the stream it is launched on, and its
+ * algorithmic flops and bytes (from the item shapes) are accumulated.
+ * dd_meter_read waits for the last recorded event and returns the totals
+ * since the last dd_meter_start; dd_meter_start(NULL) disarms.  Process-wide
+ * state, not thread-safe; arming adds two event records per dispatch. */
+typedef struct {
+    int64_t launches;   /* dispatches recorded */
+    double  total_ms;   /* sum of per-dispatch durations (event pairs) */
+    double  flops;      /* algorithmic floating-point operations */
+    double  bytes;      /* algorithmic HBM bytes (each operand read once, outputs written once) */
+} dd_meter_t;
+int dd_meter_start(const char* kernel);
+int dd_meter_read(dd_meter_t* out);
+
 #ifdef __cplusplus
 }
 #endif

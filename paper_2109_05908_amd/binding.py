@@ -45,6 +45,22 @@ class _Info(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class _Meter(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+def meter_start(kernel: str | None) -> None:
+    """Arm the library's kernel meter for the launches named `kernel` (None disarms)."""
+    _check(lib().dd_meter_start(kernel.encode() if kernel else None), "dd_meter_start")
+
+
+def meter_read() -> dict:
+    """Totals since meter_start: dispatches, summed event-timed ms, algorithmic flops and bytes."""
+    m = _Meter()
+    _check(lib().dd_meter_read(C.byref(m)), "dd_meter_read")
+    return {"launches": m.launches, "total_ms": m.total_ms, "flops": m.flops, "bytes": m.bytes}
+
+
 def library_path() -> str:
     return os.path.join(HERE, "libdd.so")
 
@@ -77,6 +93,8 @@ def lib():
         "dd_subdomain_basis": ([vp, i32, i32, vp], i32),
         "dd_subdomain_sigma1": ([vp, i32, vp], i32),
         "dd_coarse_matrix": ([vp, i32, vp, i64], i32),
+        "dd_meter_start": ([C.c_char_p], i32),
+        "dd_meter_read": ([P(_Meter)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -89,7 +107,8 @@ def lib():
 def exported_symbols() -> list[str]:
     return ["dd_partition_ggg", "dd_setup", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
-            "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix"]
+            "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
+            "dd_meter_start", "dd_meter_read"]
 
 
 def _stream():

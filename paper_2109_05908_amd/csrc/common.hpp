@@ -179,16 +179,51 @@ __global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base) {
     }
 }
 
-// Items are processed in chunks of kMaxItems (one launch per chunk).
-template <class Op>
+// Kernel meter: when armed with a launch name, every dispatch of that name is
+// bracketed by a pair of HIP events on its own stream and its algorithmic
+// work (flops, bytes) is recorded, so that the achieved rate of one kernel
+// family can be read back without a profiler.  Process-wide, not thread-safe.
+struct Meter {
+    std::string name;
+    std::vector<hipEvent_t> ev;     // start/stop pairs, in dispatch order
+    std::vector<hipEvent_t> pool;   // recycled events
+    double flops = 0.0, bytes = 0.0;
+    int64_t launches = 0;
+    bool armed(const char* n) const { return !name.empty() && name == n; }
+    hipEvent_t get();
+    void record_pair(hipEvent_t a, hipEvent_t b) { ev.push_back(a); ev.push_back(b); }
+};
+Meter& meter();
+
+struct NoWork {
+    void operator()(int, int, double&, double&) const {}
+};
+
+// Items are processed in chunks of kMaxItems (one launch per chunk).  work(base,
+// cnt, flops, bytes) adds the algorithmic work of items [base, base+cnt); it is
+// only called while the meter is armed for this launch name.
+template <class Op, class Work = NoWork>
 inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream_t s, const char* name,
-                         int max_grid = 4096) {
+                         int max_grid = 4096, const Work& work = Work()) {
     if (nitems <= 0 || total_hint <= 0) return;
+    const bool m = meter().armed(name);
     for (int base = 0; base < nitems; base += kMaxItems) {
         const int cnt = std::min(kMaxItems, nitems - base);
         int grid = (int)std::min<int64_t>(total_hint, max_grid);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (m) {
+            e0 = meter().get();
+            e1 = meter().get();
+            DD_HIP(hipEventRecord(e0, s));
+        }
         hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base);
         launch_check(name);
+        if (m) {
+            DD_HIP(hipEventRecord(e1, s));
+            meter().record_pair(e0, e1);
+            work(base, cnt, meter().flops, meter().bytes);
+            meter().launches++;
+        }
     }
 }
 

@@ -842,7 +842,55 @@ struct dd_handle_s {
         return DD_ERR_INTERNAL;                                       \
     }
 
+namespace dd {
+Meter& meter() {
+    static Meter m;
+    return m;
+}
+hipEvent_t Meter::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    DD_HIP(hipEventCreate(&e));
+    return e;
+}
+}  // namespace dd
+
 extern "C" {
+
+int dd_meter_start(const char* kernel) {
+    DD_GUARD_BEGIN
+    Meter& m = meter();
+    for (hipEvent_t e : m.ev) m.pool.push_back(e);
+    m.ev.clear();
+    m.flops = m.bytes = 0.0;
+    m.launches = 0;
+    m.name = kernel ? kernel : "";
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_meter_read(dd_meter_t* out) {
+    if (!out) return DD_ERR_INVALID_ARG;
+    DD_GUARD_BEGIN
+    Meter& m = meter();
+    double ms = 0.0;
+    if (!m.ev.empty()) DD_HIP(hipEventSynchronize(m.ev.back()));
+    for (size_t k = 0; k + 1 < m.ev.size(); k += 2) {
+        float t = 0.f;
+        DD_HIP(hipEventElapsedTime(&t, m.ev[k], m.ev[k + 1]));
+        ms += t;
+    }
+    out->launches = m.launches;
+    out->total_ms = ms;
+    out->flops = m.flops;
+    out->bytes = m.bytes;
+    return DD_OK;
+    DD_GUARD_END
+}
 
 const char* dd_strerror(int code) {
     switch (code) {

@@ -40,10 +40,19 @@ struct OpGemm {
 void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
     int64_t total = 0;
     for (auto& x : g.h) total += (int64_t)ceil_div(x.M, 64) * ceil_div(x.N, 64);
-    if (ta && tb) launch_tiles(OpGemm<true, true>{g.d.p}, g.size(), total, s, "gemm_tt");
-    else if (ta) launch_tiles(OpGemm<true, false>{g.d.p}, g.size(), total, s, "gemm_tn");
-    else if (tb) launch_tiles(OpGemm<false, true>{g.d.p}, g.size(), total, s, "gemm_nt");
-    else launch_tiles(OpGemm<false, false>{g.d.p}, g.size(), total, s, "gemm_nn");
+    // 2MNK flops; bytes = read A and B once, write C (and read it when beta != 0)
+    auto work = [&](int b0, int cnt, double& fl, double& by) {
+        for (int i = b0; i < b0 + cnt; ++i) {
+            const GemmItem& x = g.h[i];
+            const double M = x.M, N = x.N, K = x.K;
+            fl += 2.0 * M * N * K;
+            by += 8.0 * (M * K + K * N + M * N * (x.beta != 0.0 ? 2.0 : 1.0));
+        }
+    };
+    if (ta && tb) launch_tiles(OpGemm<true, true>{g.d.p}, g.size(), total, s, "gemm_tt", 4096, work);
+    else if (ta) launch_tiles(OpGemm<true, false>{g.d.p}, g.size(), total, s, "gemm_tn", 4096, work);
+    else if (tb) launch_tiles(OpGemm<false, true>{g.d.p}, g.size(), total, s, "gemm_nt", 4096, work);
+    else launch_tiles(OpGemm<false, false>{g.d.p}, g.size(), total, s, "gemm_nn", 4096, work);
 }
 
 // ===========================================================================
@@ -788,7 +797,26 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
     launch_tiles(OpBlkP{base}, o.size(), np, s, "qr_blk_p");
     if (trans) launch_tiles(OpBlkW<true>{base}, o.size(), nw, s, "qr_blk_w");
     else launch_tiles(OpBlkW<false>{base}, o.size(), nw, s, "qr_blk_w");
-    launch_tiles(OpBlkUpd{base}, o.size(), nu, s, "qr_blk_upd");
+    // Algorithmic work of C -= V_b W: V_b is a unit lower trapezoid with
+    // mp*wb - wb(wb-1)/2 structural entries, so 2*nc flops per entry; bytes =
+    // read the strictly lower part of V_b and W once, read and write C once.
+    auto work = [&](int b0, int cnt, double& fl, double& by) {
+        for (int i = b0; i < b0 + cnt; ++i) {
+            const ORItem& x = o.h[i];
+            if (x.V.n <= c0 || x.V.m <= c0) continue;
+            const int wb = std::min(cap, x.V.n - c0);
+            int cc0, cc1;
+            if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
+            else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
+            else { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+            if (wb <= 0 || cc1 <= cc0) continue;
+            const double mp = x.V.m - c0, nc = cc1 - cc0;
+            const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
+            fl += 2.0 * nc * nzv;
+            by += 8.0 * ((nzv - wb) + (double)wb * nc + 2.0 * mp * nc);
+        }
+    };
+    launch_tiles(OpBlkUpd{base}, o.size(), nu, s, "qr_blk_upd", 4096, work);
 }
 
 static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
