@@ -10,6 +10,7 @@
 #include "bchol.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <set>
 
 namespace dd {
@@ -105,6 +106,13 @@ void BlockChol::symbolic(const std::vector<uint8_t>& adj, const std::vector<int>
     poff[N] = P;
     loff[N] = Lo;
     goff[N] = G;
+    if (std::getenv("DD_VERBOSE")) {
+        fprintf(stderr, "dd: coarse block Cholesky: %d blocks, n_C %lld, %zu tree levels, panel entries %lld, "
+                "flops %.3e\n", na, (long long)nC, by_level.size(), (long long)P, flops);
+        fprintf(stderr, "dd: nodes per level:");
+        for (auto& L : by_level) fprintf(stderr, " %zu", L.size());
+        fprintf(stderr, "\n");
+    }
 }
 
 static int row_offset(const BlockChol& B, int k, int j) {

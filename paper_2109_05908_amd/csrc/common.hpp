@@ -168,11 +168,37 @@ __device__ __forceinline__ int find_item(const int* pre, int nitems, int t) {
     return lo;
 }
 
+// Ops whose neighbouring tiles share operand panels and cost the same can opt
+// in to an XCD-aware order (XcdChunked<Op>::value = true).  Workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2; such ops have
+// their tiles taken in chunks of kXcdChunk consecutive tiles, chunk c on XCD
+// c % 8, so that the tiles of one chunk hit in the same L2.
+constexpr int kXcds = 8;
+constexpr int kXcdChunk = 64;
+template <class Op>
+struct XcdChunked {
+    static constexpr bool value = false;
+};
+
 template <class Op>
 __global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base) {
     __shared__ int pre[kMaxItems + 1];
     const int total = item_prefix(op, nitems, pre, base);
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int G = gridDim.x, g = blockIdx.x;
+    if (!XcdChunked<Op>::value || G % kXcds != 0 || G < kXcds * kXcdChunk) {
+        for (int t = g; t < total; t += G) {
+            const int b = find_item(pre, nitems, t);
+            op(base + b, t - pre[b]);
+            __syncthreads();
+        }
+        return;
+    }
+    const int x = g % kXcds, per = G / kXcds;
+    for (int k = g / kXcds;; k += per) {
+        const int c0 = (x + kXcds * (k / kXcdChunk)) * kXcdChunk;
+        if (c0 >= total) break;  // later k only visit later chunks of this XCD
+        const int t = c0 + k % kXcdChunk;
+        if (t >= total) continue;
         const int b = find_item(pre, nitems, t);
         op(base + b, t - pre[b]);
         __syncthreads();
@@ -324,6 +350,29 @@ __device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = double4_t{0.0, 0.0, 0.0, 0.0};
+}
+
+// Stage the accumulator through LDS and hand it out in column-major order:
+// f(row, col, value) is called with consecutive threads on consecutive rows
+// of one column, so that the caller's global reads and writes of C are
+// coalesced.  Reuses the tile's operand buffers (needs a sync before reuse).
+template <class F>
+__device__ __forceinline__ void acc_store_coalesced(const double4_t (&acc)[2][2], TileSmem& sm, F f) {
+    double* buf = reinterpret_cast<double*>(&sm);  // 64 x 65 doubles: both operand buffers
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                buf[(wc + 16 * y + (lane & 15)) * 65 + wr + 16 * x + 4 * j + (lane >> 4)] = acc[x][y][j];
+    __syncthreads();
+    const int r = threadIdx.x & 63;
+#pragma unroll 4
+    for (int c = threadIdx.x >> 6; c < 64; c += 4) f(r, c, buf[c * 65 + r]);
 }
 
 // Visit the accumulator: f(row, col, value) with tile-relative indices.  The

@@ -76,7 +76,8 @@ struct Level {
     DBuf<int64_t> memb_ptr, memb;
     std::vector<int> ni, nt, nI, nG, nD;
 
-    Arena L;  // local Cholesky factors (n_i x n_i, lower)
+    Arena L;  // local Cholesky factors (n_i x n_i, lower); released after setup
+    Arena W;  // explicit inverses W_i = L_i^{-1} (lower), used by the apply
     std::vector<int> p;
     std::vector<int32_t> status;
     DBuf<int32_t> pcnt;
@@ -91,8 +92,8 @@ struct Level {
     std::vector<double> Ecopy;  // small coarse operators only (inspection)
 
     // apply workspace
-    DBuf<double> rloc, yC;
-    Batch<DMat> Lb, Bb;
+    DBuf<double> rloc, yloc, tpart, yC;
+    Batch<TrmvItem> Tb;
 
     SubInfo sub() const {
         return SubInfo{N, counts.p, offE.p, offO.p, ext.p, part.p, ilocal.p, pcnt.p, offC.p, dZ.p};
@@ -343,7 +344,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 geqrf_vb(qb, s);
                 Batch<DMat> Qb = mats(qp, two_ni, two_ni, ni, s, &actQ);
                 set_identity_vb(Qb, 1.0, s);
-                ormqr_vb(ob, false, s);
+                orgqr_vb(ob, s);
                 Batch<GemmItem> g;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
@@ -637,12 +638,27 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
             geqrf_vb(qb, s);
             Batch<DMat> Zb = mats(Lv.Z.ptr, nI, nI, pp, s, &act);
             set_identity_vb(Zb, 1.0, s);
-            ormqr_vb(ob, false, s);
+            orgqr_vb(ob, s);
             DD_HIP(hipStreamSynchronize(s));
         }
     }
     Yev.release();
     info.phase_ms[PH_BASIS] += tm.lap();
+
+    // ---- W_i = L_i^{-1}: the local solves of the apply become two triangular
+    // matrix-vector products (HBM-bound, fully parallel) ----------------------
+    {
+        std::vector<int64_t> sa(N);
+        for (int i = 0; i < N; ++i) sa[i] = (int64_t)ni[i] * ni[i];
+        Lv.W.alloc(sa);
+        Batch<DMat> Wb = mats(Lv.W.ptr, ni, ni, ni, s);
+        set_identity_vb(Wb, 1.0, s);
+        Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s);
+        trsm_vb(Lb, Wb, false, s);
+        DD_HIP(hipStreamSynchronize(s));
+        Lv.L.release();
+    }
+    info.phase_ms[PH_CHOL] += tm.lap();
 
     // ---- coarse operator E = Z^T A Z (block (i,j) from the rows of Omega_j owned by i) ----------
     Lv.pcnt = upload(std::vector<int32_t>(Lv.p.begin(), Lv.p.end()), s);
@@ -721,18 +737,24 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     // ---- apply workspace ----
     Lv.rloc.alloc(std::max<int64_t>(1, Lv.hoffO[N]));
     Lv.yC.alloc(std::max<int64_t>(1, nC));
-    Lv.Lb = mats(Lv.L.ptr, ni, ni, ni, s);
-    Lv.Bb.h.clear();
-    for (int i = 0; i < N; ++i) Lv.Bb.h.push_back(DMat{Lv.rloc.p + Lv.hoffO[i], ni[i], ni[i], 1});
-    Lv.Bb.sync(s);
+    {
+        std::vector<int64_t> poff(N + 1, 0);
+        for (int i = 0; i < N; ++i) poff[i + 1] = poff[i] + trmv_part_size(ni[i]);
+        Lv.yloc.alloc(std::max<int64_t>(1, Lv.hoffO[N]));
+        Lv.tpart.alloc(std::max<int64_t>(1, poff[N]));
+        Lv.Tb.h.clear();
+        for (int i = 0; i < N; ++i)
+            Lv.Tb.h.push_back(TrmvItem{Lv.W.ptr[i], ni[i], ni[i], Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i],
+                                       Lv.tpart.p + poff[i]});
+        Lv.Tb.sync(s);
+    }
     info.phase_ms[PH_OTHER] += tm.lap();
 }
 
 // z = M^{-1} r, one right-hand side (2.1)
 static void apply1(Level& Lv, const double* r, double* z, hipStream_t s) {
     gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
-    trsm_vb(Lv.Lb, Lv.Bb, false, s);
-    trsm_vb(Lv.Lb, Lv.Bb, true, s);
+    trinv_apply_vb(Lv.Tb, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
     scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
     if (Lv.nC > 0) {
         SubInfo S = Lv.sub();
@@ -998,7 +1020,7 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
     int64_t bytes = 0;
     for (auto& l : H.lv)
-        bytes += l->L.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
+        bytes += l->W.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
     *out = hd.release();
     return (tau >= 1.0) ? DD_WARN_FULL_COARSE : DD_OK;

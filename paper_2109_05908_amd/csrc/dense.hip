@@ -56,6 +56,102 @@ void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
 }
 
 // ===========================================================================
+// x := W^T (W x), W lower triangular (explicit inverse of a Cholesky factor).
+// HBM-bound: each pass streams the lower triangle of W once.
+// ===========================================================================
+// y_part[cc] = W(rb rows, cc columns) x(cc columns): a tile is a 64-row block
+// by a 512-column chunk; lane = row (coalesced 512 B column segments), wave w
+// takes columns w, w+4, ... of the chunk.  Chunks right of the block's
+// diagonal are skipped (W is zero there).
+struct OpTrmvN {
+    const TrmvItem* it;
+    __device__ static int nrb(int n) { return (n + TRMV_RB - 1) / TRMV_RB; }
+    __device__ static int ncc(int n) { return (n + TRMV_CC - 1) / TRMV_CC; }
+    __device__ int tiles(int b) const { return nrb(it[b].n) * ncc(it[b].n); }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double red[4][TRMV_RB];
+        const TrmvItem& I = it[b];
+        const int n = I.n, nc = ncc(n);
+        const int rb = t / nc, cc = t % nc;
+        const int r0 = rb * TRMV_RB, c0 = cc * TRMV_CC;
+        if (c0 > r0 + TRMV_RB - 1) return;  // above the diagonal: no partial (reducer skips it)
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int r = r0 + lane;
+        const int cend = min(min(c0 + TRMV_CC, n), r0 + TRMV_RB);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (r < n) {
+            const double* Wr = I.W + r;
+            int j = c0 + w;
+            for (; j + 12 < cend; j += 16) {
+                a0 += Wr[(int64_t)j * I.ld] * I.x[j];
+                a1 += Wr[(int64_t)(j + 4) * I.ld] * I.x[j + 4];
+                a2 += Wr[(int64_t)(j + 8) * I.ld] * I.x[j + 8];
+                a3 += Wr[(int64_t)(j + 12) * I.ld] * I.x[j + 12];
+            }
+            for (; j < cend; j += 4) a0 += Wr[(int64_t)j * I.ld] * I.x[j];
+        }
+        red[w][lane] = (a0 + a1) + (a2 + a3);
+        __syncthreads();
+        if (w == 0 && r < n)
+            I.part[(int64_t)cc * n + r] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    }
+};
+// y = sum of the partials of the chunks left of (or at) the row's block diagonal
+struct OpTrmvRed {
+    const TrmvItem* it;
+    __device__ int tiles(int b) const { return (it[b].n + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const TrmvItem& I = it[b];
+        const int r = t * 256 + threadIdx.x;
+        if (r >= I.n) return;
+        const int last = ((r / TRMV_RB) * TRMV_RB + TRMV_RB - 1) / TRMV_CC;
+        double v = 0.0;
+        for (int cc = 0; cc <= last; ++cc) v += I.part[(int64_t)cc * I.n + r];
+        I.y[r] = v;
+    }
+};
+// x_j = W(j:n, j)^T y(j:n): a tile is 16 columns, 4 per wave, each a
+// contiguous column segment read by the 64 lanes.
+struct OpTrmvT {
+    const TrmvItem* it;
+    __device__ int tiles(int b) const { return (it[b].n + 15) / 16; }
+    __device__ void operator()(int b, int t) const {
+        const TrmvItem& I = it[b];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int j0 = t * 16 + w * 4;
+        const int n = I.n;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (j0 < n) {
+            const int jn = min(4, n - j0);
+            // rows >= j0 + q for column j0 + q; start at j0 (W is zero above the diagonal)
+            for (int i = j0 + lane; i < n; i += 64) {
+                const double yi = I.y[i];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q < jn) acc[q] += I.W[i + (int64_t)(j0 + q) * I.ld] * yi;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+        if (lane == 0)
+            for (int q = 0; q < 4; ++q)
+                if (j0 + q < n) I.x[j0 + q] = acc[q];
+    }
+};
+
+void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s) {
+    int64_t tn = 0, tr = 0, tt = 0;
+    for (auto& x : t.h) {
+        tn += (int64_t)ceil_div(x.n, TRMV_RB) * ceil_div(x.n, TRMV_CC);
+        tr += ceil_div(x.n, 256);
+        tt += ceil_div(x.n, 16);
+    }
+    launch_tiles(OpTrmvN{t.d.p}, t.size(), tn, s, "trmv_n");
+    launch_tiles(OpTrmvRed{t.d.p}, t.size(), tr, s, "trmv_red");
+    launch_tiles(OpTrmvT{t.d.p}, t.size(), tt, s, "trmv_t");
+}
+
+// ===========================================================================
 // Cholesky (right-looking, 64-column blocks)
 // ===========================================================================
 struct OpPotrfDiag {
@@ -532,7 +628,8 @@ __device__ __forceinline__ BlkRange blk_range(const ORItem& it, int c0, int cap,
     r.wb = min(cap, it.V.n - c0);
     if (mode == 0) { r.cc0 = 0; r.cc1 = it.C.n; }
     else if (mode == 1) { r.cc0 = c0 + r.wb; r.cc1 = it.C.n; }
-    else { r.cc0 = c0 + r.wb; r.cc1 = min(min(it.C.n, oend), it.V.n); }  // inner: factored columns only
+    else if (mode == 2) { r.cc0 = c0 + r.wb; r.cc1 = min(min(it.C.n, oend), it.V.n); }  // inner: factored columns only
+    else { r.cc0 = c0; r.cc1 = it.C.n; }  // explicit Q: columns left of the block are still unit vectors
     return r;
 }
 
@@ -692,19 +789,31 @@ struct OpBlkUpd : BlkOp {
         const ORItem& it = o[b];
         const int mp = it.V.m - c0;
         const int nc = R.cc1 - R.cc0;
-        const int tm = (mp + 63) / 64;
-        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        // 8 x 8 groups of tiles: bands of 8 row tiles, each band swept in
+        // groups of 8 column tiles (column fastest), so that 64 consecutive
+        // tiles read 8 panels of V_b and 8 panels of W
+        const int tm = (mp + 63) / 64, tn = (nc + 63) / 64;
+        const int band = t / (8 * tn), r = t - band * 8 * tn;
+        const int rows = min(8, tm - band * 8);
+        const int cg = r / (rows * 8), q = r - cg * rows * 8;
+        const int cols = min(8, tn - cg * 8);
+        const int i0 = (band * 8 + q / cols) * 64, j0 = (cg * 8 + q % cols) * 64;
         const double* V = it.V.p + c0 + (int64_t)c0 * it.V.ld;
         double* C = it.C.p + c0 + (int64_t)R.cc0 * it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
         mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_OB, mp, nc, R.wb, i0, j0, sm, acc);
         const int ld = it.C.ld;
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
         });
     }
+};
+
+template <>
+struct XcdChunked<OpBlkUpd> {
+    static constexpr bool value = true;
 };
 
 // G = V_b^T V_b for the 128-column block at c0 (partials then ordered sum)
@@ -784,7 +893,8 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
         int cc0, cc1;
         if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
         else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
-        else { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+        else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+        else { cc0 = c0; cc1 = x.C.n; }
         if (wb <= 0 || cc1 <= cc0) continue;
         const int ntc = ceil_div(cc1 - cc0, 64);
         const int mp = x.V.m - c0;
@@ -808,7 +918,8 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
             int cc0, cc1;
             if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
             else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
-            else { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+            else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+            else { cc0 = c0; cc1 = x.C.n; }
             if (wb <= 0 || cc1 <= cc0) continue;
             const double mp = x.V.m - c0, nc = cc1 - cc0;
             const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
@@ -892,6 +1003,20 @@ void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s) {
         const int k = trans ? step : (nb - 1 - step);
         apply_block(o, sc, k * QR_OB, QR_OB, 0, 0, trans, s);
     }
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+// Q [I; 0] (the first C.n columns of Q) for C preset to the identity: the
+// blocks are applied last to first, and each one only to the columns from its
+// own first reflector on (the columns left of it are still unit vectors
+// supported above the block's rows).
+void orgqr_vb(Batch<ORItem>& o, hipStream_t s) {
+    int kmax = 0;
+    for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
+    QrScratch sc;
+    sc.alloc(o.h, s);
+    const int nb = ceil_div(kmax, QR_OB);
+    for (int step = nb - 1; step >= 0; --step) apply_block(o, sc, step * QR_OB, QR_OB, 3, 0, false, s);
     DD_HIP(hipStreamSynchronize(s));
 }
 
@@ -1272,7 +1397,7 @@ void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, do
         if (!cls.empty()) {
             geqrf_vb(qb, s);
             set_identity_vb(Qs, 1.0, s);
-            ormqr_vb(ob, false, s);
+            orgqr_vb(ob, s);
             copy_vb(Qs, Ys, false, 1.0, s);
         }
     }

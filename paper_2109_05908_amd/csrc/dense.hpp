@@ -85,6 +85,8 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s);
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
 // C := Q C (trans = false) or Q^T C (trans = true).
 void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s);
+// C := Q [I; 0] for C preset to the identity (explicit Q, orgqr-style cost)
+void orgqr_vb(Batch<ORItem>& o, hipStream_t s);
 // T and G factors for reflectors stored in V with taus (used after sytrd).
 void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t s);
 
@@ -130,6 +132,22 @@ struct VecItem {
     double* work;  // 4 n * 256 doubles
 };
 void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, double cluster_tol, hipStream_t s);
+
+// Local solves with explicit triangular inverses: x := W^T (W x) for W lower
+// triangular n x n (column-major, exact zeros above the diagonal), one vector
+// per item.  y (n) and part (trmv_part_size(n)) are per-item workspaces.
+struct TrmvItem {
+    const double* W;
+    int ld;
+    int n;
+    double* x;
+    double* y;
+    double* part;
+};
+constexpr int TRMV_RB = 64;    // rows per tile of y = W x
+constexpr int TRMV_CC = 512;   // columns per partial sum of y = W x
+inline int64_t trmv_part_size(int n) { return (int64_t)((n + TRMV_CC - 1) / TRMV_CC) * n; }
+void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s);
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)

@@ -1,0 +1,114 @@
+"""Parity at the full size of the 3-D diffusion workload (64^3, n = 262144,
+256 GGG subdomains, overlap 2, lambda > 50), in the configuration the
+benchmark times.  The oracle cannot run the whole setup in seconds, so:
+
+* index sets of all 256 subdomains: bit-exact (the oracle's set construction
+  is cheap at any size);
+* sigma_1 and the kept eigenvalues on a size-stratified sample of subdomains
+  (smallest, lower quartile, median): oracle per subdomain;
+* the solve: the true relative residual of the returned x, recomputed on the
+  CPU with an FP64 SpMV, is <= 1e-8 (a property that holds at any size), and
+  n_C equals the sum of the per-subdomain counts.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2109_05908_amd import DeviceCSR, Preconditioner, partition_ggg  # noqa: E402
+
+MU_FLOOR = 1e-6
+MU_RTOL = 1e-4
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+_STATE = {}
+
+
+def state():
+    if not _STATE:
+        cfg = W.config_c2()
+        log(f"[fullsize] building diffusion 64^3: n={cfg.A.n} N={cfg.N} delta={cfg.overlap} tau={cfg.tau}")
+        dA = DeviceCSR.from_workload(cfg.A)
+        part = partition_ggg(dA, cfg.N, cfg.ggg_seed)
+        t0 = time.perf_counter()
+        pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau)
+        torch.cuda.synchronize()
+        log(f"[fullsize] setup {time.perf_counter() - t0:.2f}s")
+        part_h = part.cpu().numpy()
+        A = O.as_scipy(cfg.A)
+        sets = O.subdomain_sets(A, part_h, cfg.N, cfg.overlap)
+        _STATE.update(cfg=cfg, dA=dA, part=part_h, pre=pre, A=A, sets=sets)
+    return _STATE
+
+
+def test_fullsize_partition_matches_oracle():
+    st = state()
+    np.testing.assert_array_equal(st["part"], O.ggg_partition(st["cfg"].A, st["cfg"].N, st["cfg"].ggg_seed))
+
+
+def test_fullsize_sets_bit_exact():
+    st = state()
+    pre = st["pre"]
+    for i, s in enumerate(st["sets"]):
+        I, G, D = pre.sets(i)
+        np.testing.assert_array_equal(I, s.I)
+        np.testing.assert_array_equal(G, s.Gamma)
+        np.testing.assert_array_equal(D, s.Delta)
+
+
+def test_fullsize_sampled_eigenvalues():
+    st = state()
+    pre, sets, A, tau = st["pre"], st["sets"], st["A"], st["cfg"].tau
+    ni = np.array([s.Omega.size for s in sets])
+    order = np.argsort(ni, kind="stable")
+    sample = [int(order[0]), int(order[len(order) // 4]), int(order[len(order) // 2])]
+    sizes = pre.sizes()
+    s1 = pre.sigma1()
+    for i in sample:
+        s = sets[i]
+        log(f"[fullsize] oracle subdomain {i}: n_I={s.I.size} n_i={s.Omega.size} n~_i={s.Omega_ext.size}")
+        Aii, Xi = O.extract(A, s)
+        spl = O.local_splitting(Xi, s.I.size, s.Gamma.size)
+        mu_all, mu_keep, _ = O.local_eigen(Aii, spl.S_I, s.I.size, tau)
+        assert abs(s1[i] - spl.sigma1) <= 1e-9 * spl.sigma1
+        near = np.abs(mu_all - tau) <= 1e-6 * tau
+        if not near.any():
+            assert sizes[i, 3] == mu_keep.size, (i, sizes[i, 3], mu_keep.size)
+        mu_g = pre.eigs(i)
+        k = min(mu_g.size, mu_keep.size)
+        big = mu_keep[:k] >= MU_FLOOR
+        if big.any():
+            rel = np.abs(mu_g[:k][big] - mu_keep[:k][big]) / mu_keep[:k][big]
+            log(f"[fullsize] subdomain {i}: p={mu_keep.size}, worst kept-mu rel error {rel.max():.2e}")
+            assert rel.max() <= MU_RTOL
+
+
+def test_fullsize_solve_residual():
+    st = state()
+    pre, A = st["pre"], st["A"]
+    b_h = W.rhs(A.shape[0], 0)
+    b = torch.as_tensor(b_h, device="cuda:0")
+    x, its, rr, code = pre.pcg(b, rtol=1e-8, maxit=1000)
+    assert code == 0
+    x_h = x.cpu().numpy().reshape(-1)
+    true_rr = np.linalg.norm(b_h - A @ x_h) / np.linalg.norm(b_h)
+    log(f"[fullsize] PCG its={its[0]} relres(gpu)={rr[0]:.3e} relres(cpu spmv)={true_rr:.3e}")
+    assert true_rr <= 1e-8
+    assert abs(true_rr - rr[0]) <= 1e-3 * true_rr + 1e-15
+    sizes = pre.sizes()
+    assert pre.info()["n_C"] == int(sizes[:, 3].sum())
