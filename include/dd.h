@@ -108,7 +108,12 @@ int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, h
  *  part    device int32[n], subdomain id of each node in [0, N)  (Omega_Ii = {j : part_j = i})
  *  overlap delta >= 1: Gamma_i = BFS layers 1..delta of Omega_Ii, Delta_i = layer delta+1
  *  tau     the paper's tau > 0 of (3.3): keep eigenpairs with lambda > 1/tau
- *  levels  >= 2; 2 = exact Cholesky of E; >= 3 recursive construction on E (Sec. 3.2, multilevel)
+ *  levels  2..4; 2 = exact (block-sparse) Cholesky of E; >= 3: the construction is repeated on E
+ *          (multilevel remark of Sec. 3.2): the subdomain graph of E (i ~ j iff A(Omega_Ii,
+ *          Omega_Ij) != 0) is partitioned by dd_partition_ggg's rule into ceil(N/coarsen) parts
+ *          (seed 0, empty parts dropped), with the same overlap and tau; E^{-1} in (2.1) becomes
+ *          PCG on E to a relative residual of 1e-4, preconditioned by the next level, and only
+ *          the last level's E is factored.  If a level keeps no coarse mode, recursion stops.
  *  opt     may be NULL (defaults: FP64, threshold selection, no validation)
  *  out     receives the handle (owned by the caller; free with dd_destroy)
  * Errors: DD_ERR_INVALID_ARG, DD_ERR_NOT_SPD, DD_ERR_EIG, DD_ERR_OOM, DD_ERR_HIP.
@@ -116,11 +121,13 @@ int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, h
 int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau,
              int32_t levels, const dd_options* opt, hipStream_t stream, dd_handle* out);
 
-/* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1).
+/* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1); with more than
+ * two levels E^{-1} is the inner PCG described at dd_setup (M then varies slightly with r).
  * r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t stream);
 
-/* Preconditioned CG with M from dd_apply (FP64 dots and residual recurrence).
+/* Preconditioned CG with M from dd_apply (FP64 dots and residual recurrence); with more than
+ * two levels, flexible CG (Polak-Ribiere beta) since M varies between iterations.
  * b: device n x nrhs; x: device n x nrhs, in: initial guess, out: solution.
  * Stops RHS j when ||b_j - A x_j||_2 <= rtol ||b_j||_2 (recurrence residual,
  * true residual recomputed at exit).  iters, relres: host arrays [nrhs]

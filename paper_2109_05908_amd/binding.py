@@ -154,16 +154,18 @@ def partition_ggg(A: DeviceCSR, N: int, seed: int):
 
 
 class Preconditioner:
-    """Handle of dd_setup: the two-level additive Schwarz preconditioner."""
+    """Handle of dd_setup: the additive Schwarz preconditioner with `levels`
+    levels (2 = fine + coarse E; more levels recurse on E, coarsening the
+    subdomain graph by `coarsen`)."""
 
     def __init__(self, A: DeviceCSR, part, N: int, overlap: int, tau: float, levels: int = 2,
                  local_prec: int = DD_FP64, select: int = DD_SEL_THRESHOLD, nev_cap: int = 0,
-                 validate: bool = False):
+                 validate: bool = False, coarsen: int = 0):
         import torch
         self.A = A
         self.n = A.n
         part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device)
-        opts = _Opts(local_prec, select, nev_cap, int(validate), 0, (C.c_int32 * 7)())
+        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), (C.c_int32 * 7)())
         h = C.c_void_p()
         cs = A.cstruct()
         self.setup_status = _check(

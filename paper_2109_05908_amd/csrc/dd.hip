@@ -90,6 +90,10 @@ struct Level {
     int64_t nC = 0;
     BlockChol E;                // block-sparse Cholesky factor of the coarse operator
     std::vector<double> Ecopy;  // small coarse operators only (inspection)
+    std::vector<uint8_t> hadj;  // block graph of E: hadj[i*N+j] = 1 iff A(Omega_Ii, Omega_Ij) != 0, i != j
+
+    // Krylov workspace for systems with this level's matrix
+    DBuf<double> kr, kz, kp, kq, kro, kx;
 
     // apply workspace
     DBuf<double> rloc, yloc, tpart, yC;
@@ -104,8 +108,8 @@ struct Handle {
     std::vector<std::unique_ptr<Level>> lv;
     Opts opt;
     dd_info_t info{};
-    // PCG / apply scratch
-    DBuf<double> r, z, pvec, q, partial, dots;
+    // dot-product scratch
+    DBuf<double> partial, dots;
     double* hpin = nullptr;
     ~Handle() {
         if (hpin) (void)hipHostFree(hpin);
@@ -143,7 +147,11 @@ static Batch<DMat> mats(const std::vector<double*>& p, const std::vector<int>& l
 // ---------------------------------------------------------------------------
 // setup of one level: sets, local splittings, eigenproblems, coarse space
 // ---------------------------------------------------------------------------
-static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s) {
+static void build_e_csr(Level& Lv, Level& next, hipStream_t s);
+
+// `next` (nullable): when given, E is not factored but handed to the next
+// level as its CSR matrix (multilevel recursion).
+static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s, Level* next) {
     Timer tm(s);
     const int N = Lv.N;
     const int delta = Lv.delta;
@@ -677,8 +685,8 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
             DBuf<uint8_t> adj((size_t)N * N);
             DD_HIP(hipMemsetAsync(adj.p, 0, adj.bytes(), s));
             block_adjacency(A, Lv.part.p, N, adj.p, s);
-            auto hadj = to_host(adj.p, (size_t)N * N, s);
-            Lv.E.symbolic(hadj, Lv.p, Lv.hoffC);
+            Lv.hadj = to_host(adj.p, (size_t)N * N, s);
+            Lv.E.symbolic(Lv.hadj, Lv.p, Lv.hoffC);
             Lv.E.allocate(s);
         }
         DBuf<int32_t> cnt((size_t)N * N);
@@ -728,10 +736,13 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
             Lv.Ecopy = to_host(Ed.p, (size_t)nC * nC, s);
         }
         DD_HIP(hipStreamSynchronize(s));
+        if (next) build_e_csr(Lv, *next, s);
         info.phase_ms[PH_E] += tm.lap();
-        const int bad = Lv.E.factor(s);
-        DD_CHECK(bad == 0, DD_ERR_NOT_SPD, "coarse operator E is not positive definite");
-        info.phase_ms[PH_EFACT] += tm.lap();
+        if (!next) {
+            const int bad = Lv.E.factor(s);
+            DD_CHECK(bad == 0, DD_ERR_NOT_SPD, "coarse operator E is not positive definite");
+            info.phase_ms[PH_EFACT] += tm.lap();
+        }
     }
 
     // ---- apply workspace ----
@@ -751,21 +762,144 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     info.phase_ms[PH_OTHER] += tm.lap();
 }
 
-// z = M^{-1} r, one right-hand side (2.1)
-static void apply1(Level& Lv, const double* r, double* z, hipStream_t s) {
-    gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
-    trinv_apply_vb(Lv.Tb, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
-    scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
-    if (Lv.nC > 0) {
-        SubInfo S = Lv.sub();
-        restrict_coarse(S, Lv.nC, r, Lv.yC.p, s);
-        Lv.E.solve(Lv.yC.p, s);
-        prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, z, s);
+// ---------------------------------------------------------------------------
+// multilevel recursion (multilevel remark of Sec. 3.2): E of one level becomes
+// the CSR matrix of the next
+// ---------------------------------------------------------------------------
+struct EcsrItem {
+    const double* src;  // dense block of E inside a factor panel
+    int ld;
+    int trans;          // 0: element (a, b) at src[a + b ld]; 1: at src[b + a ld]; 2: lower triangle mirrored
+    int pi, pj;
+    int64_t row0;       // coarse index of the block's first row
+    int64_t coloff;     // offset of the block's first column within each CSR row
+    int64_t col0;       // coarse index of the block's first column
+};
+struct OpEcsr {
+    const EcsrItem* it;
+    const int32_t* rowptr;
+    int32_t* colind;
+    double* val;
+    __device__ int tiles(int q) const { return ((it[q].pi + 63) / 64) * ((it[q].pj + 63) / 64); }
+    __device__ void operator()(int q, int t) const {
+        const EcsrItem& I = it[q];
+        const int tm = (I.pi + 63) / 64;
+        const int a0 = (t % tm) * 64, b0 = (t / tm) * 64;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int a = a0 + e / 64, b = b0 + e % 64;
+            if (a >= I.pi || b >= I.pj) continue;
+            const int64_t dst = rowptr[I.row0 + a] + I.coloff + b;
+            colind[dst] = (int32_t)(I.col0 + b);
+            int r = a, c = b;
+            if (I.trans == 1 || (I.trans == 2 && b > a)) { r = b; c = a; }  // 2: diagonal block, lower mirrored
+            val[dst] = I.src[r + (int64_t)c * I.ld];
+        }
     }
+};
+
+// E (assembled in the factor panels, not yet factored) -> CSR of `next`:
+// full symmetric storage, row r of block i holds the blocks j in {i} U
+// neighbours(i) with p_j > 0, in increasing j (so columns are sorted).
+static void build_e_csr(Level& Lv, Level& next, hipStream_t s) {
+    const int N = Lv.N;
+    const auto& P = Lv.p;
+    std::vector<std::vector<int>> nb(N);
+    std::vector<int64_t> rowlen(N, 0);
+    for (int i = 0; i < N; ++i) {
+        if (P[i] <= 0) continue;
+        for (int j = 0; j < N; ++j)
+            if (P[j] > 0 && (j == i || Lv.hadj[(size_t)i * N + j])) {
+                nb[i].push_back(j);
+                rowlen[i] += P[j];
+            }
+    }
+    const int64_t nC = Lv.nC;
+    std::vector<int32_t> rp(nC + 1, 0);
+    int64_t nnz = 0;
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < P[i]; ++a) {
+            rp[Lv.hoffC[i] + a] = (int32_t)nnz;
+            nnz += rowlen[i];
+            DD_CHECK(nnz < INT32_MAX, DD_ERR_INVALID_ARG, "coarse operator too large for a 32-bit CSR (use the nev cap)");
+        }
+    rp[nC] = (int32_t)nnz;
+    std::vector<EcsrItem> items;
+    for (int i = 0; i < N; ++i) {
+        int64_t off = 0;
+        for (int j : nb[i]) {
+            int ld = 0;
+            EcsrItem e{};
+            if (i == j) {
+                e.src = Lv.E.block(i, i, &ld);
+                e.trans = 2;
+            } else if (Lv.E.pos[i] >= Lv.E.pos[j]) {
+                e.src = Lv.E.block(i, j, &ld);
+                e.trans = 0;
+            } else {
+                e.src = Lv.E.block(j, i, &ld);
+                e.trans = 1;
+            }
+            DD_CHECK(e.src != nullptr, DD_ERR_INTERNAL, "coarse block missing from the factor structure");
+            e.ld = ld;
+            e.pi = P[i];
+            e.pj = P[j];
+            e.row0 = Lv.hoffC[i];
+            e.coloff = off;
+            e.col0 = Lv.hoffC[j];
+            items.push_back(e);
+            off += P[j];
+        }
+    }
+    next.n = nC;
+    next.nnz = nnz;
+    next.rowptr = upload(rp, s);
+    next.colind.alloc(nnz);
+    next.val.alloc(nnz);
+    DBuf<EcsrItem> dit = upload(items, s);
+    int64_t tiles = 0;
+    for (auto& e : items) tiles += (int64_t)ceil_div(e.pi, 64) * ceil_div(e.pj, 64);
+    launch_tiles(OpEcsr{dit.p, next.rowptr.p, next.colind.p, next.val.p}, (int)items.size(), tiles, s, "e_csr");
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+// Partition of the next level (R8): the nodes of E's block graph are this
+// level's subdomains; seeded greedy graph growing into ceil(N / coarsen) parts
+// (seed 0), expanded to the coarse dofs, empty parts removed.
+static void partition_next(const Level& Lv, Level& next, int coarsen, hipStream_t s) {
+    const int N = Lv.N;
+    std::vector<int32_t> rp(N + 1, 0), ci;
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < N; ++j)
+            if (j != i && Lv.hadj[(size_t)i * N + j]) ci.push_back(j);
+        rp[i + 1] = (int32_t)ci.size();
+    }
+    if (ci.empty()) ci.push_back(0);  // keeps the device arrays non-empty; rp says no edges
+    const int N2 = std::min(N, ceil_div(N, std::max(1, coarsen)));
+    DBuf<int32_t> drp = upload(rp, s), dci = upload(ci, s);
+    DBuf<double> dval(std::max<size_t>(1, ci.size()));
+    CsrDev G{N, (int64_t)rp[N], drp.p, dci.p, dval.p};
+    DBuf<int32_t> dpart(N);
+    ggg_partition(G, N2, 0, dpart.p, s);
+    std::vector<int32_t> pb = to_host(dpart.p, N, s);
+    std::vector<int32_t> used(N2, 0);
+    for (int i = 0; i < N; ++i)
+        if (Lv.p[i] > 0) used[pb[i]] = 1;
+    std::vector<int32_t> remap(N2, -1);
+    int cnt = 0;
+    for (int k = 0; k < N2; ++k)
+        if (used[k]) remap[k] = cnt++;
+    std::vector<int32_t> part2(Lv.nC);
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < Lv.p[i]; ++a) part2[Lv.hoffC[i] + a] = remap[pb[i]];
+    next.part = upload(part2, s);
+    next.N = cnt;
+    next.delta = Lv.delta;
+    next.tau = Lv.tau;
+    DD_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------
-// vector kernels for PCG
+// apply and Krylov solvers
 // ---------------------------------------------------------------------------
 __global__ void k_axpy2(double* x, double* r, const double* p, const double* q, double alpha, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -781,6 +915,10 @@ __global__ void k_sub(const double* b, double* r, int64_t n) {  // r = b - r
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         r[i] = b[i] - r[i];
 }
+__global__ void k_diff(const double* a, const double* b, double* c, int64_t n) {  // c = a - b
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c[i] = a[i] - b[i];
+}
 static int vgrid(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 4096); }
 
 static double dot_host(Handle& H, const double* x, const double* y, int64_t n, hipStream_t s) {
@@ -790,12 +928,63 @@ static double dot_host(Handle& H, const double* x, const double* y, int64_t n, h
     return H.hpin[0];
 }
 
-static int pcg1(Handle& H, const double* b, double* x, double rtol, int maxit, int* iters, double* relres,
-                hipStream_t s) {
-    Level& Lv = *H.lv[0];
+constexpr double kInnerRtol = 1e-4;  // coarse solves by PCG on levels >= 2 (Sec. 4)
+
+static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
+                  bool true_res, int* iters, double* relres, hipStream_t s);
+
+// y := E_m^{-1} y: exact block Cholesky solve on the last level, otherwise PCG
+// on E_m (the next level's matrix) to kInnerRtol, preconditioned by the next
+// level, from x0 = 0.
+static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
+    Level& Lv = *H.lv[m];
+    if (m + 1 >= H.lv.size()) {
+        Lv.E.solve(y, s);
+        return;
+    }
+    Level& Nx = *H.lv[m + 1];
+    int its = 0;
+    double rr = 0.0;
+    fill(Nx.kx.p, Nx.n, 0.0, s);
+    const int rc = krylov(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, &its, &rr, s);
+    DD_CHECK(rc >= 0, rc, "inner coarse solve failed");
+    DD_HIP(hipMemcpyAsync(y, Nx.kx.p, Nx.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+// z = M_m^{-1} r, the additive preconditioner (2.1) of level m
+static void apply_level(Handle& H, size_t m, const double* r, double* z, hipStream_t s) {
+    Level& Lv = *H.lv[m];
+    gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
+    trinv_apply_vb(Lv.Tb, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
+    scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
+    if (Lv.nC > 0) {
+        SubInfo S = Lv.sub();
+        restrict_coarse(S, Lv.nC, r, Lv.yC.p, s);
+        coarse_solve(H, m, Lv.yC.p, s);
+        prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, z, s);
+    }
+}
+
+static void alloc_krylov(Level& Lv) {
+    const int64_t n = std::max<int64_t>(1, Lv.n);
+    Lv.kr.alloc(n);
+    Lv.kz.alloc(n);
+    Lv.kp.alloc(n);
+    Lv.kq.alloc(n);
+    Lv.kro.alloc(n);
+    Lv.kx.alloc(n);
+}
+
+// PCG (R6) on the matrix of level m with the preconditioner of level m; x
+// holds x0 on entry.  Stop when the recurrence residual satisfies
+// ||r_k|| <= rtol ||b||.  flexible: Polak-Ribiere beta for a preconditioner
+// that varies between iterations (inner solves on lower levels, R8).
+static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
+                  bool true_res, int* iters, double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[m];
     const int64_t n = Lv.n;
     const CsrDev A = Lv.A();
-    double *r = H.r.p, *z = H.z.p, *p = H.pvec.p, *q = H.q.p;
+    double *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p, *q = Lv.kq.p, *ro = Lv.kro.p;
     const double bn = std::sqrt(dot_host(H, b, b, n, s));
     DD_CHECK(std::isfinite(bn), DD_ERR_NAN, "right-hand side contains NaN/Inf");
     if (bn == 0.0) {
@@ -810,7 +999,7 @@ static int pcg1(Handle& H, const double* b, double* x, double rtol, int maxit, i
     int its = 0;
     bool conv = rn <= rtol * bn;
     if (!conv) {
-        apply1(Lv, r, z, s);
+        apply_level(H, m, r, z, s);
         DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
         double rz = dot_host(H, r, z, n, s);
         for (its = 1; its <= maxit; ++its) {
@@ -818,24 +1007,34 @@ static int pcg1(Handle& H, const double* b, double* x, double rtol, int maxit, i
             const double pq = dot_host(H, p, q, n, s);
             DD_CHECK(std::isfinite(pq), DD_ERR_NAN, "PCG produced NaN");
             const double alpha = rz / pq;
+            if (flexible) DD_HIP(hipMemcpyAsync(ro, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             hipLaunchKernelGGL(k_axpy2, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, alpha, n);
             rn = std::sqrt(dot_host(H, r, r, n, s));
             if (rn <= rtol * bn) { conv = true; break; }
-            apply1(Lv, r, z, s);
-            const double rzn = dot_host(H, r, z, n, s);
-            const double beta = rzn / rz;
-            rz = rzn;
+            apply_level(H, m, r, z, s);
+            double beta;
+            if (flexible) {
+                hipLaunchKernelGGL(k_diff, dim3(vgrid(n)), dim3(256), 0, s, r, ro, q, n);  // q := r - r_old
+                beta = dot_host(H, z, q, n, s) / rz;
+                rz = dot_host(H, r, z, n, s);
+            } else {
+                const double rzn = dot_host(H, r, z, n, s);
+                beta = rzn / rz;
+                rz = rzn;
+            }
             hipLaunchKernelGGL(k_xpby, dim3(vgrid(n)), dim3(256), 0, s, z, p, beta, n);
         }
         if (its > maxit) its = maxit;
     }
-    // true residual
-    spmv(A, x, r, 1, s);
-    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
-    const double tr = std::sqrt(dot_host(H, r, r, n, s));
+    double rel = rn / bn;
+    if (true_res) {
+        spmv(A, x, r, 1, s);
+        hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+        rel = std::sqrt(dot_host(H, r, r, n, s)) / bn;
+        DD_CHECK(std::isfinite(rel), DD_ERR_NAN, "PCG produced NaN");
+    }
     *iters = its;
-    *relres = tr / bn;
-    DD_CHECK(std::isfinite(tr), DD_ERR_NAN, "PCG produced NaN");
+    *relres = rel;
     return conv ? DD_OK : DD_WARN_MAXIT;
 }
 
@@ -958,7 +1157,6 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     if (A->n <= 0 || A->nnz <= 0 || N < 1 || N > A->n || overlap < 1 || overlap > 200 || !(tau > 0.0) || levels < 2 ||
         levels > DD_MAX_LEVELS)
         return DD_ERR_INVALID_ARG;
-    if (levels > 2) return DD_ERR_INVALID_ARG;  // recursion on E: see dd_info levels
     auto hd = std::make_unique<dd_handle_s>();
     Handle& H = hd->h;
     if (opt) {
@@ -998,23 +1196,34 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
         const int rc = validate_partition(L0.part.p, A->n, N, cnt.p, s);
         if (rc != DD_OK) return rc;
     }
-    build_level(L0, H.opt, H.info, s);
     H.lv.push_back(std::move(lv));
+    // levels - 1 decomposed levels; the coarse operator of the last one is
+    // factored, the others hand E to the next level (R8)
+    for (int l = 0; l + 1 < levels; ++l) {
+        Level& Lv = *H.lv[l];
+        const bool more = l + 2 < levels;
+        std::unique_ptr<Level> nx = more ? std::make_unique<Level>() : nullptr;
+        build_level(Lv, H.opt, H.info, s, more ? nx.get() : nullptr);
+        if (!more || Lv.nC == 0) break;
+        partition_next(Lv, *nx, H.opt.coarsen, s);
+        H.lv.push_back(std::move(nx));
+    }
+    for (auto& l : H.lv) alloc_krylov(*l);
     // diagnostics
     dd_info_t& I = H.info;
-    I.levels = 2;
-    I.N[0] = N;
-    I.n[0] = A->n;
-    I.n[1] = L0.nC;
+    I.levels = (int32_t)H.lv.size() + 1;
+    double gsum = 0.0;
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+        I.N[l] = H.lv[l]->N;
+        I.n[l] = H.lv[l]->n;
+        gsum += (double)H.lv[l]->n;
+    }
+    I.n[H.lv.size()] = H.lv.back()->nC;
+    gsum += (double)H.lv.back()->nC;
     I.n_C = L0.nC;
-    I.grid_complexity = double(A->n + L0.nC) / double(A->n);
+    I.grid_complexity = gsum / double(A->n);
     I.p_min = N ? *std::min_element(L0.p.begin(), L0.p.end()) : 0;
     I.p_max = N ? *std::max_element(L0.p.begin(), L0.p.end()) : 0;
-    // scratch for PCG
-    H.r.alloc(A->n);
-    H.z.alloc(A->n);
-    H.pvec.alloc(A->n);
-    H.q.alloc(A->n);
     H.partial.alloc(512 * 64);
     H.dots.alloc(64);
     DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
@@ -1030,8 +1239,8 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t s) {
     DD_GUARD_BEGIN
     if (!h || !r || !z || nrhs < 1) return DD_ERR_INVALID_ARG;
-    Level& Lv = *h->h.lv[0];
-    for (int k = 0; k < nrhs; ++k) apply1(Lv, r + (int64_t)k * Lv.n, z + (int64_t)k * Lv.n, s);
+    const int64_t n = h->h.lv[0]->n;
+    for (int k = 0; k < nrhs; ++k) apply_level(h->h, 0, r + (int64_t)k * n, z + (int64_t)k * n, s);
     return DD_OK;
     DD_GUARD_END
 }
@@ -1046,7 +1255,7 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
     for (int k = 0; k < nrhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        const int c = pcg1(H, b + k * n, x + k * n, rtol, maxit, &it, &rr, s);
+        const int c = krylov(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, &it, &rr, s);
         if (c < 0) return c;
         if (c > 0) rc = c;
         if (iters) iters[k] = it;

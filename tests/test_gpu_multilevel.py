@@ -1,0 +1,123 @@
+"""Three-level preconditioner (multilevel remark of Sec. 3.2) on the GPU vs the
+oracle, through the C-ABI.
+
+The second level's matrix is E of the first, partitioned over the subdomain
+graph by seeded greedy graph growing into ceil(N / coarsen) parts.  Its sets
+only depend on the subdomain graph and the per-subdomain coarse counts, so
+they must match the oracle bit for bit.  Its kept eigenvalues are invariant
+under the orthogonal change of basis within each subdomain's coarse block
+that separates the GPU's Z_i from the oracle's, so they are compared at the
+usual tolerance.  The outer solve is flexible CG with inner PCG to 1e-4 on E;
+both runs go to rtol 1e-13, which fixes x to 1e-10 relative whatever the
+inner iterations did.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2109_05908_amd import DeviceCSR, Preconditioner  # noqa: E402
+
+MU_FLOOR = 1e-6
+MU_RTOL = 1e-4
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(name):
+    if name == "c1_c4":        # 16 subdomains -> 4 on the second level
+        cfg = W.config_c1()
+        return cfg, cfg.part, 4
+    if name == "c1_c64":       # 16 subdomains -> 1 on the second level (exact second-level solve)
+        cfg = W.config_c1()
+        return cfg, cfg.part, 64
+    if name == "rand_c2":      # irregular graph, 6 subdomains -> 3
+        A = W.random_spd(600, 5, seed=4, positive_offdiag=True)
+        cfg = W.Config("random_spd_600", A, None, 6, 1, 0.1, 2)
+        return cfg, O.ggg_partition(cfg.A, cfg.N, cfg.ggg_seed), 2
+    if name == "small3d_c4":   # 3-D high contrast, 16 -> 4
+        cfg = W.config_small3d(16, 16)
+        return cfg, O.ggg_partition(cfg.A, cfg.N, cfg.ggg_seed), 4
+    raise KeyError(name)
+
+
+_CACHE = {}
+
+
+def built(name):
+    if name not in _CACHE:
+        cfg, part, coarsen = _case(name)
+        log(f"[multilevel] building {name}: n={cfg.A.n} N={cfg.N} delta={cfg.overlap} tau={cfg.tau} "
+            f"coarsen={coarsen}")
+        dA = DeviceCSR.from_workload(cfg.A)
+        pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, levels=3, coarsen=coarsen)
+        torch.cuda.synchronize()
+        ora = O.build(cfg.A, part, cfg.N, cfg.overlap, cfg.tau, levels=3, coarsen=coarsen)
+        _CACHE[name] = (cfg, part, dA, pre, ora)
+    return _CACHE[name]
+
+
+CASES = ["c1_c4", "c1_c64", "rand_c2", "small3d_c4"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_second_level_structure(name):
+    cfg, part, dA, pre, ora = built(name)
+    info = pre.info()
+    inner = ora.inner
+    assert info["levels"] == 3
+    assert info["n_C"] == ora.nC
+    assert pre.count(level=1) == len(inner.locals)
+    for i, L in enumerate(inner.locals):
+        I, G, D = pre.sets(i, level=1)
+        np.testing.assert_array_equal(I, L.sets.I)
+        np.testing.assert_array_equal(G, L.sets.Gamma)
+        np.testing.assert_array_equal(D, L.sets.Delta)
+
+
+@pytest.mark.parametrize("name", ["c1_c4", "c1_c64", "rand_c2"])
+def test_second_level_eigenvalues(name):
+    cfg, part, dA, pre, ora = built(name)
+    sizes = pre.sizes(level=1)
+    worst = 0.0
+    for i, L in enumerate(ora.inner.locals):
+        near = np.abs(L.mu_all - cfg.tau) <= 1e-6 * cfg.tau
+        if not near.any():
+            assert sizes[i, 3] == L.mu_keep.size, (i, sizes[i, 3], L.mu_keep.size)
+        mu_g = pre.eigs(i, level=1)
+        k = min(mu_g.size, L.mu_keep.size)
+        big = L.mu_keep[:k] >= MU_FLOOR
+        if big.any():
+            rel = np.abs(mu_g[:k][big] - L.mu_keep[:k][big]) / L.mu_keep[:k][big]
+            worst = max(worst, float(rel.max()))
+    log(f"[multilevel] {name}: second-level n_C {int(sizes[:, 3].sum())}, worst kept-mu rel error {worst:.2e}")
+    assert worst <= MU_RTOL
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_flexible_pcg_solution(name):
+    cfg, part, dA, pre, ora = built(name)
+    b = W.rhs(cfg.A.n, 0)
+    x, its, rr, code = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-13, maxit=500)
+    xo, itso, rro = O.flexible_pcg(cfg.A, b, ora.apply, rtol=1e-13, maxit=500)
+    xg = x.cpu().numpy()
+    log(f"[multilevel] {name}: flexible CG its gpu {its[0]} oracle {itso}, relres {rr[0]:.2e} / {rro:.2e}")
+    assert code == 0 and rr[0] <= 1e-13
+    assert abs(its[0] - itso) <= 2
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    x8, its8, rr8, code8 = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-8)
+    _, itso8, _ = O.flexible_pcg(cfg.A, b, ora.apply, rtol=1e-8)
+    log(f"[multilevel] {name}: rtol 1e-8 its gpu {its8[0]} oracle {itso8}")
+    assert code8 == 0 and rr8[0] <= 1e-8 and abs(its8[0] - itso8) <= 2
