@@ -546,11 +546,18 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     for (int i = 0; i < N; ++i) { v1[i] = nI[i]; vpart[i] = ceil_div(nI[i], 64) + 1; }
     td.alloc(v1); te.alloc(v1); ttau.alloc(v1); tpart.alloc(vpart); tp.alloc(v1); tmu.alloc(v1);
     {
+        Arena tw, taux;
+        std::vector<int64_t> sw(N), sa(N, 2 * TRD_NB);
+        for (int i = 0; i < N; ++i) sw[i] = (int64_t)nI[i] * TRD_NB;
+        tw.alloc(sw);
+        taux.alloc(sa);
         Batch<TriItem> tb;
         for (int i = 0; i < N; ++i)
-            tb.h.push_back(TriItem{DMat{Sm.ptr[i], nI[i], nI[i], nI[i]}, td.ptr[i], te.ptr[i], ttau.ptr[i], tpart.ptr[i], tp.ptr[i]});
+            tb.h.push_back(TriItem{DMat{Sm.ptr[i], nI[i], nI[i], nI[i]}, td.ptr[i], te.ptr[i], ttau.ptr[i], tpart.ptr[i],
+                                   tp.ptr[i], tw.ptr[i], taux.ptr[i]});
         tb.sync(s);
         sytrd_vb(tb, s);
+        DD_HIP(hipStreamSynchronize(s));
     }
     DBuf<int32_t> dcount(N);
     {

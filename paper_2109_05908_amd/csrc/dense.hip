@@ -304,52 +304,68 @@ void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
 // ===========================================================================
 // Triangular solves with a lower factor, many right-hand sides
 // ===========================================================================
-// Diagonal block: B[k0:k0+w, cols] := L_kk^{-1} (or L_kk^{-T}) B[...].
+// Inverses of the 64 x 64 diagonal blocks of L (lower): block t of item b
+// goes to D[b] + 4096 t (column-major, ld 64), padded with the identity past
+// the matrix edge.  Forward substitution on the identity, 4 threads per
+// column sharing each dot product.
+struct OpTrtri64 {
+    const DMat* L;
+    double* const* D;
+    __device__ int tiles(int b) const { return (L[b].n + 63) / 64; }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double Ls[64][65];
+        __shared__ double X[64][65];
+        __shared__ double red[4][64];
+        const DMat Lm = L[b];
+        const int k0 = t * 64, w = min(64, Lm.n - k0);
+        const double* lb = Lm.p + k0 + (int64_t)k0 * Lm.ld;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6;
+            double v = 0.0;
+            if (r >= c) v = (r < w) ? lb[r + (int64_t)c * Lm.ld] : (r == c ? 1.0 : 0.0);
+            Ls[r][c] = v;
+            X[r][c] = 0.0;
+        }
+        __syncthreads();
+        const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+        for (int i = 0; i < 64; ++i) {
+            double sum = 0.0;
+            for (int l = q; l < i; l += 4) sum += Ls[i][l] * X[l][c];
+            red[q][c] = sum;
+            __syncthreads();
+            if (q == 0) X[i][c] = ((i == c ? 1.0 : 0.0) - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]))) / Ls[i][i];
+            __syncthreads();
+        }
+        double* out = D[b] + (int64_t)t * 4096;
+        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) out[e] = X[e & 63][e >> 6];
+    }
+};
+
+// Diagonal step: B[kb:kb+w, cols] := L_kk^{-1} B (or L_kk^{-T} B) as an MFMA
+// product with the precomputed inverse; each tile owns 64 right-hand-side
+// columns and reads them completely before writing them back.
 template <bool TRANS>
 struct OpTrsmDiag {
     const DMat* L;
     const DMat* B;
+    double* const* D;
     int kb;  // first row of the diagonal block
     __device__ int tiles(int b) const { return (L[b].n > kb) ? (B[b].n + 63) / 64 : 0; }
     __device__ void operator()(int b, int t) const {
-        __shared__ double Ls[64][65];
-        __shared__ double X[64][65];
+        __shared__ TileSmem sm;
         const DMat Lm = L[b], Bm = B[b];
         const int w = min(64, Lm.n - kb);
-        const double* lb = Lm.p + kb + (int64_t)kb * Lm.ld;
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, c = e >> 6;
-            Ls[r][c] = (r < w && c < w && r >= c) ? lb[r + (int64_t)c * Lm.ld] : 0.0;
-        }
         const int c0 = t * 64;
-        const int nc = min(64, Bm.n - c0);
-        double* bb = Bm.p + kb + (int64_t)c0 * Bm.ld;
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, c = e >> 6;
-            X[r][c] = (r < w && c < nc) ? bb[r + (int64_t)c * Bm.ld] : 0.0;
-        }
-        __syncthreads();
-        const int c = threadIdx.x;
-        if (c < nc) {
-            if (!TRANS) {
-                for (int j = 0; j < w; ++j) {
-                    double v = X[j][c];
-                    for (int l = 0; l < j; ++l) v -= Ls[j][l] * X[l][c];
-                    X[j][c] = v / Ls[j][j];
-                }
-            } else {
-                for (int j = w - 1; j >= 0; --j) {
-                    double v = X[j][c];
-                    for (int l = j + 1; l < w; ++l) v -= Ls[l][j] * X[l][c];
-                    X[j][c] = v / Ls[j][j];
-                }
-            }
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, cc = e >> 6;
-            if (r < w && cc < nc) bb[r + (int64_t)cc * Bm.ld] = X[r][cc];
-        }
+        const double* Di = D[b] + (int64_t)(kb / 64) * 4096;
+        double* bb = Bm.p + kb;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<TRANS, false>(Di, 64, bb, Bm.ld, w, Bm.n, w, 0, c0, sm, acc);
+        const int ld = Bm.ld, N = Bm.n;
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
+            const int gj = c0 + c;
+            if (r < w && gj < N) bb[r + (int64_t)gj * ld] = v;
+        });
     }
 };
 
@@ -395,14 +411,14 @@ struct OpTrsmGemm {
     }
 };
 
-static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, bool trans, int r0, int r1, hipStream_t s) {
+static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool trans, int r0, int r1, hipStream_t s) {
     if (r1 - r0 <= 64) {
         int64_t nd = 0;
         for (int b = 0; b < L.size(); ++b)
             if (L.h[b].n > r0) nd += ceil_div(B.h[b].n, 64);
         if (!nd) return;
-        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, r0}, L.size(), nd, s, "trsm_diag");
-        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, r0}, L.size(), nd, s, "trsmT_diag");
+        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, D, r0}, L.size(), nd, s, "trsm_diag");
+        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, D, r0}, L.size(), nd, s, "trsmT_diag");
         return;
     }
     const int mid = r0 + ceil_div(r1 - r0, 128) * 64;
@@ -415,13 +431,13 @@ static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, bool trans, int r0, int r1,
         nu += (int64_t)ceil_div(M, 64) * ceil_div(B.h[b].n, 64);
     }
     if (!trans) {
-        trsm_rec(L, B, trans, r0, mid, s);
+        trsm_rec(L, B, D, trans, r0, mid, s);
         if (nu) launch_tiles(OpTrsmGemm<false>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsm_gemm");
-        trsm_rec(L, B, trans, mid, r1, s);
+        trsm_rec(L, B, D, trans, mid, r1, s);
     } else {
-        trsm_rec(L, B, trans, mid, r1, s);
+        trsm_rec(L, B, D, trans, mid, r1, s);
         if (nu) launch_tiles(OpTrsmGemm<true>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsmT_gemm");
-        trsm_rec(L, B, trans, r0, mid, s);
+        trsm_rec(L, B, D, trans, r0, mid, s);
     }
 }
 
@@ -429,7 +445,22 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
     int nmax = 0;
     for (auto& x : L.h) nmax = std::max(nmax, x.n);
     if (nmax == 0) return;
-    trsm_rec(L, B, trans, 0, ceil_div(nmax, 64) * 64, s);
+    // inverses of the 64 x 64 diagonal blocks
+    std::vector<int64_t> off(L.size() + 1, 0);
+    int64_t nblk = 0;
+    for (int b = 0; b < L.size(); ++b) {
+        const int k = ceil_div(L.h[b].n, 64);
+        off[b + 1] = off[b] + (int64_t)k * 4096;
+        nblk += k;
+    }
+    DBuf<double> dbuf(std::max<int64_t>(1, off.back()));
+    std::vector<double*> hp(L.size());
+    for (int b = 0; b < L.size(); ++b) hp[b] = dbuf.p + off[b];
+    DBuf<double*> dp(std::max<size_t>(1, hp.size()));
+    h2d(dp.p, hp.data(), hp.size(), s);
+    launch_tiles(OpTrtri64{L.d.p, dp.p}, L.size(), nblk, s, "trtri64");
+    trsm_rec(L, B, dp.p, trans, 0, ceil_div(nmax, 64) * 64, s);
+    DD_HIP(hipStreamSynchronize(s));  // dbuf, dp are freed on return
 }
 
 // ===========================================================================
@@ -1021,26 +1052,49 @@ void orgqr_vb(Batch<ORItem>& o, hipStream_t s) {
 }
 
 // ===========================================================================
-// Tridiagonalisation (unblocked, full symmetric storage)
+// Tridiagonalisation Q^T A Q = T (symmetric A, full storage), blocked in
+// panels of TRD_NB columns: within a panel each column first receives the
+// pending rank-2 updates of the panel's earlier columns, then yields its
+// Householder vector v and w = tau (A22 v - V (W^T v) - W (V^T v)),
+// w += -(tau/2)(w.v) v, with A22 not yet updated by the panel; after the
+// panel the trailing matrix takes A22 -= V W^T + W V^T as two MFMA GEMMs.
+// Reflector k is stored in column k, rows k+2.., with an explicit 1 at row k+1.
 // ===========================================================================
-struct OpSytrdHouse {
+struct OpTrdCol {
     const TriItem* t;
-    int k;
-    __device__ int tiles(int b) const { return t[b].A.n > k ? 1 : 0; }
+    int k0, i;
+    __device__ int tiles(int b) const { return t[b].A.n > k0 + i ? 1 : 0; }
     __device__ void operator()(int b, int) const {
+        __shared__ double vk[TRD_NB], wk[TRD_NB];
         __shared__ double red[4];
+        __shared__ double sc;
         const TriItem& T = t[b];
-        const int n = T.A.n, ld = T.A.ld;
-        double* col = T.A.p + (int64_t)k * ld;
+        const int n = T.A.n, ld = T.A.ld, k = k0 + i;
+        double* A = T.A.p;
+        if ((int)threadIdx.x < i) {
+            const int j = threadIdx.x, c = k0 + j;
+            vk[j] = (k == c + 1) ? 1.0 : A[k + (int64_t)c * ld];
+            wk[j] = T.W[k + (int64_t)j * n];
+        }
+        __syncthreads();
+        double* col = A + (int64_t)k * ld;
+        for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
+            double a = col[r];
+            for (int j = 0; j < i; ++j) {
+                const int c = k0 + j;
+                const double vr = (r == c + 1) ? 1.0 : A[r + (int64_t)c * ld];
+                a -= vr * wk[j] + T.W[r + (int64_t)j * n] * vk[j];
+            }
+            col[r] = a;
+        }
+        __syncthreads();
         if (k == n - 1) {
             if (threadIdx.x == 0) T.d[k] = col[k];
             return;
         }
-        // x = A[k+1:, k]
         double p = 0.0;
         for (int r = k + 2 + threadIdx.x; r < n; r += blockDim.x) p += col[r] * col[r];
         const double xn2 = block_sum(p, red);
-        __shared__ double sc[3];
         if (threadIdx.x == 0) {
             const double alpha = col[k + 1];
             double tau = 0.0, beta = alpha, scal = 0.0;
@@ -1052,103 +1106,139 @@ struct OpSytrdHouse {
             T.d[k] = col[k];
             T.e[k] = beta;
             T.tau[k] = tau;
-            sc[0] = scal;
+            col[k + 1] = 1.0;
+            sc = scal;
         }
         __syncthreads();
-        const double scal = sc[0];
+        const double scal = sc;
         for (int r = k + 2 + threadIdx.x; r < n; r += blockDim.x) col[r] *= scal;
     }
 };
 
-// p = tau * A22 v over 64-column tiles (A22 symmetric: p_r = tau * A22[:, r] . v).
-struct OpSytrdSymv {
+// y = A22 v (column dots over 64-column tiles, A22 symmetric), and the
+// corrections t1_j = W(:, j)^T v, t2_j = V(:, j)^T v (one extra tile per j).
+struct OpTrdSymv {
     const TriItem* t;
-    int k;
+    int k0, i;
     __device__ int tiles(int b) const {
-        const int L = t[b].A.n - k - 1;
-        return (L >= 2) ? (L + 63) / 64 : 0;
+        const int L = t[b].A.n - (k0 + i) - 1;
+        return (L >= 1) ? (L + 63) / 64 + i : 0;
     }
     __device__ void operator()(int b, int tile) const {
-        __shared__ double vs[4096 + 64];
-        __shared__ double red[4];
+        __shared__ double vs[4096];
+        __shared__ double red[2][4];
         const TriItem& T = t[b];
-        const int n = T.A.n, ld = T.A.ld;
+        const int n = T.A.n, ld = T.A.ld, k = k0 + i;
         const int L = n - k - 1;
-        const double tau = T.tau[k];
-        const double* vsrc = T.A.p + (k + 1) + (int64_t)k * ld;  // v_0 = 1 implicit
-        double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
+        const double* v = T.A.p + (k + 1) + (int64_t)k * ld;  // v[0] = 1 stored
         const bool inl = L <= 4096;
         if (inl)
-            for (int r = threadIdx.x; r < L; r += blockDim.x) vs[r] = (r == 0) ? 1.0 : vsrc[r];
+            for (int r = threadIdx.x; r < L; r += blockDim.x) vs[r] = v[r];
         __syncthreads();
+        const int nct = (L + 63) / 64;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        double pv_part = 0.0;
-        for (int cc = wv; cc < 64; cc += 4) {
-            const int c = tile * 64 + cc;
-            if (c >= L) break;
-            const double* a = A22 + (int64_t)c * ld;
-            double sum = 0.0;
-            for (int r = lane; r < L; r += 64) sum += a[r] * (inl ? vs[r] : (r == 0 ? 1.0 : vsrc[r]));
-            sum = wave_sum(sum) * tau;
-            if (lane == 0) {
-                T.p[c] = sum;
-                pv_part += sum * (inl ? vs[c] : (c == 0 ? 1.0 : vsrc[c]));
+        if (tile < nct) {
+            // two columns per wave at a time, four row blocks per step: eight
+            // independent 512 B loads in flight per wave
+            const double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
+            for (int cc = 2 * wv; cc < 64; cc += 8) {
+                const int c = tile * 64 + cc;
+                if (c >= L) break;
+                const bool two = c + 1 < L;
+                const double* a0 = A22 + (int64_t)c * ld;
+                const double* a1 = two ? a0 + ld : a0;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+                int r = lane;
+                for (; r + 192 < L; r += 256) {
+                    const double v0 = inl ? vs[r] : v[r], v1 = inl ? vs[r + 64] : v[r + 64];
+                    const double v2 = inl ? vs[r + 128] : v[r + 128], v3 = inl ? vs[r + 192] : v[r + 192];
+                    s0 += a0[r] * v0; s1 += a0[r + 64] * v1; s2 += a0[r + 128] * v2; s3 += a0[r + 192] * v3;
+                    u0 += a1[r] * v0; u1 += a1[r + 64] * v1; u2 += a1[r + 128] * v2; u3 += a1[r + 192] * v3;
+                }
+                for (; r < L; r += 64) {
+                    const double vr = inl ? vs[r] : v[r];
+                    s0 += a0[r] * vr;
+                    u0 += a1[r] * vr;
+                }
+                const double y0 = wave_sum((s0 + s1) + (s2 + s3));
+                const double y1 = wave_sum((u0 + u1) + (u2 + u3));
+                if (lane == 0) {
+                    T.p[c] = y0;
+                    if (two) T.p[c + 1] = y1;
+                }
             }
+            return;
         }
-        if (lane == 0) red[wv] = pv_part;
+        const int j = tile - nct;
+        const double* wc = T.W + (k + 1) + (int64_t)j * n;
+        const double* vc = T.A.p + (k + 1) + (int64_t)(k0 + j) * ld;  // rows > k0+j+1: stored values
+        double s1 = 0.0, s2 = 0.0;
+        for (int r = threadIdx.x; r < L; r += blockDim.x) {
+            const double vr = inl ? vs[r] : v[r];
+            s1 += wc[r] * vr;
+            s2 += vc[r] * vr;
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0) { red[0][wv] = s1; red[1][wv] = s2; }
         __syncthreads();
-        if (threadIdx.x == 0) T.part[tile] = red[0] + red[1] + red[2] + red[3];
+        if (threadIdx.x == 0) {
+            T.aux[j] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+            T.aux[TRD_NB + j] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        }
     }
 };
 
-// A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v, 64x64 tiles (full square).
-struct OpSytrdRank2 {
+// w = tau (y - V t1 - W t2) into column i of W; partial sums of w.v
+struct OpTrdW {
     const TriItem* t;
-    int k;
+    int k0, i;
     __device__ int tiles(int b) const {
-        const int L = t[b].A.n - k - 1;
-        if (L < 2) return 0;
-        const int T = (L + 63) / 64;
-        return T * T;
+        const int L = t[b].A.n - (k0 + i) - 1;
+        return (L >= 1) ? (L + 255) / 256 : 0;
     }
     __device__ void operator()(int b, int tile) const {
-        __shared__ double gam;
-        __shared__ double vr[64], wr[64], vc[64], wc[64];
+        __shared__ double red[4];
         const TriItem& T = t[b];
-        const int n = T.A.n, ld = T.A.ld;
+        const int n = T.A.n, ld = T.A.ld, k = k0 + i;
         const int L = n - k - 1;
-        const int nt = (L + 63) / 64;
         const double tau = T.tau[k];
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int i = 0; i < nt; ++i) s += T.part[i];
-            gam = 0.5 * tau * s;
+        const int r = tile * 256 + threadIdx.x;
+        double pv = 0.0;
+        if (r < L) {
+            const int g = k + 1 + r;
+            double w = T.p[r];
+            for (int j = 0; j < i; ++j)
+                w -= T.A.p[g + (int64_t)(k0 + j) * ld] * T.aux[j] + T.W[g + (int64_t)j * n] * T.aux[TRD_NB + j];
+            w *= tau;
+            T.W[g + (int64_t)i * n] = w;
+            pv = w * T.A.p[g + (int64_t)k * ld];
         }
-        __syncthreads();
-        const int ti = tile % nt, tj = tile / nt;
-        const double* vsrc = T.A.p + (k + 1) + (int64_t)k * ld;
-        if (threadIdx.x < 64) {
-            const int r = ti * 64 + threadIdx.x;
-            if (r < L) {
-                const double v = (r == 0) ? 1.0 : vsrc[r];
-                vr[threadIdx.x] = v;
-                wr[threadIdx.x] = T.p[r] - gam * v;
-            }
-        } else if (threadIdx.x < 128) {
-            const int c = tj * 64 + threadIdx.x - 64;
-            if (c < L) {
-                const double v = (c == 0) ? 1.0 : vsrc[c];
-                vc[threadIdx.x - 64] = v;
-                wc[threadIdx.x - 64] = T.p[c] - gam * v;
-            }
-        }
-        __syncthreads();
-        if (tau == 0.0) return;
-        double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, c = e >> 6;
-            const int gr = ti * 64 + r, gc = tj * 64 + c;
-            if (gr < L && gc < L) A22[gr + (int64_t)gc * ld] -= vr[r] * wc[c] + wr[r] * vc[c];
+        pv = block_sum(pv, red);
+        if (threadIdx.x == 0) T.part[tile] = pv;
+    }
+};
+
+// w += -(tau/2)(w.v) v
+struct OpTrdAlpha {
+    const TriItem* t;
+    int k0, i;
+    __device__ int tiles(int b) const {
+        const int L = t[b].A.n - (k0 + i) - 1;
+        return (L >= 1) ? (L + 255) / 256 : 0;
+    }
+    __device__ void operator()(int b, int tile) const {
+        const TriItem& T = t[b];
+        const int n = T.A.n, ld = T.A.ld, k = k0 + i;
+        const int L = n - k - 1;
+        const int nt = (L + 255) / 256;
+        double s = 0.0;
+        for (int q = 0; q < nt; ++q) s += T.part[q];
+        const double alpha = -0.5 * T.tau[k] * s;
+        const int r = tile * 256 + threadIdx.x;
+        if (r < L) {
+            const int g = k + 1 + r;
+            T.W[g + (int64_t)i * n] += alpha * T.A.p[g + (int64_t)k * ld];
         }
     }
 };
@@ -1156,21 +1246,44 @@ struct OpSytrdRank2 {
 void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
     int nmax = 0;
     for (auto& x : t.h) nmax = std::max(nmax, x.A.n);
-    for (int k = 0; k < nmax; ++k) {
-        int64_t nh = 0, ns = 0, nr = 0;
-        for (auto& x : t.h) {
-            if (x.A.n <= k) continue;
-            ++nh;
-            const int L = x.A.n - k - 1;
-            if (L >= 2) {
-                ns += ceil_div(L, 64);
-                nr += (int64_t)ceil_div(L, 64) * ceil_div(L, 64);
+    for (int k0 = 0; k0 < nmax; k0 += TRD_NB) {
+        for (int i = 0; i < TRD_NB && k0 + i < nmax; ++i) {
+            const int k = k0 + i;
+            int64_t nc = 0, ns = 0, nw = 0;
+            for (auto& x : t.h) {
+                if (x.A.n <= k) continue;
+                ++nc;
+                const int L = x.A.n - k - 1;
+                if (L >= 1) {
+                    ns += ceil_div(L, 64) + i;
+                    nw += ceil_div(L, 256);
+                }
+            }
+            launch_tiles(OpTrdCol{t.d.p, k0, i}, t.size(), nc, s, "trd_col");
+            if (ns) {
+                launch_tiles(OpTrdSymv{t.d.p, k0, i}, t.size(), ns, s, "trd_symv");
+                launch_tiles(OpTrdW{t.d.p, k0, i}, t.size(), nw, s, "trd_w");
+                launch_tiles(OpTrdAlpha{t.d.p, k0, i}, t.size(), nw, s, "trd_alpha");
             }
         }
-        launch_tiles(OpSytrdHouse{t.d.p, k}, t.size(), nh, s, "sytrd_house");
-        if (ns) {
-            launch_tiles(OpSytrdSymv{t.d.p, k}, t.size(), ns, s, "sytrd_symv");
-            launch_tiles(OpSytrdRank2{t.d.p, k}, t.size(), nr, s, "sytrd_rank2");
+        // trailing update A22 -= V W^T + W V^T (rows/columns from k0 + TRD_NB)
+        const int k1 = k0 + TRD_NB;
+        Batch<GemmItem> g1, g2;
+        for (auto& x : t.h) {
+            const int m = x.A.n - k1;
+            if (m <= 0) continue;
+            double* C = x.A.p + k1 + (int64_t)k1 * x.A.ld;
+            const double* V = x.A.p + k1 + (int64_t)k0 * x.A.ld;
+            const double* Wm = x.W + k1;
+            g1.h.push_back(GemmItem{V, x.A.ld, Wm, x.A.n, C, x.A.ld, m, m, TRD_NB, -1.0, 1.0});
+            g2.h.push_back(GemmItem{Wm, x.A.n, V, x.A.ld, C, x.A.ld, m, m, TRD_NB, -1.0, 1.0});
+        }
+        if (!g1.h.empty()) {
+            g1.sync(s);
+            g2.sync(s);
+            gemm_vb(g1, false, true, s);
+            gemm_vb(g2, false, true, s);
+            DD_HIP(hipStreamSynchronize(s));  // the host batches are freed at scope exit
         }
     }
 }

@@ -93,13 +93,16 @@ void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t 
 // Householder tridiagonalisation of symmetric A (full storage, in place).
 // d[n], e[n-1] (off-diagonal), tau[n-1]; reflector k stored in A[k+2:, k]
 // (implicit 1 at row k+1).  part: scratch of >= ceil(n/64) doubles per item.
+constexpr int TRD_NB = 32;  // panel width of the blocked tridiagonalisation
 struct TriItem {
     DMat A;
     double* d;
     double* e;
     double* tau;
-    double* part;
-    double* p;  // scratch vector of n doubles
+    double* part;  // >= ceil(n / 256) doubles
+    double* p;     // n doubles
+    double* W;     // n x TRD_NB (ld n)
+    double* aux;   // 2 * TRD_NB doubles
 };
 void sytrd_vb(Batch<TriItem>& t, hipStream_t s);
 
