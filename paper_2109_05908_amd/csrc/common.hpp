@@ -266,7 +266,7 @@ __device__ __forceinline__ double4_t mfma_f64(double a, double b, double4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int KC = 32;  // K depth of one LDS stage
+constexpr int KC = 16;  // K depth of one LDS stage
 
 struct TileSmem {
     double a[KC][64 + 1];
@@ -331,7 +331,7 @@ __device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64
         }
         __syncthreads();
         if (k0 + KC < K) fetch(k0 + KC);
-#pragma unroll
+#pragma unroll 1
         for (int kq = 0; kq < KC / 4; ++kq) {
             const int kk = kq * 4 + (lane >> 4);
             const double a0 = sm.a[kk][wr + (lane & 15)], a1 = sm.a[kk][wr + 16 + (lane & 15)];
@@ -356,9 +356,17 @@ __device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
 // f(row, col, value) is called with consecutive threads on consecutive rows
 // of one column, so that the caller's global reads and writes of C are
 // coalesced.  Reuses the tile's operand buffers (needs a sync before reuse).
-template <class F>
-__device__ __forceinline__ void acc_store_coalesced(const double4_t (&acc)[2][2], TileSmem& sm, F f) {
-    double* buf = reinterpret_cast<double*>(&sm);  // 64 x 65 doubles: both operand buffers
+// Operand buffers of the MFMA tile shared with a 64 x 65 staging area for
+// the accumulator (epilogues that write C coalesced).
+union TileSmemC {
+    TileSmem t;
+    double c[64 * 65];
+};
+
+// acc -> LDS as a 64 x 64 column-major tile with ld 65; returns the buffer
+// (synchronised: every thread may read any element).
+__device__ __forceinline__ const double* acc_stage(const double4_t (&acc)[2][2], TileSmemC& sm) {
+    double* buf = sm.c;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     __syncthreads();
@@ -370,6 +378,12 @@ __device__ __forceinline__ void acc_store_coalesced(const double4_t (&acc)[2][2]
             for (int j = 0; j < 4; ++j)
                 buf[(wc + 16 * y + (lane & 15)) * 65 + wr + 16 * x + 4 * j + (lane >> 4)] = acc[x][y][j];
     __syncthreads();
+    return buf;
+}
+
+template <class F>
+__device__ __forceinline__ void acc_store_coalesced(const double4_t (&acc)[2][2], TileSmemC& sm, F f) {
+    const double* buf = acc_stage(acc, sm);
     const int r = threadIdx.x & 63;
 #pragma unroll 4
     for (int c = threadIdx.x >> 6; c < 64; c += 4) f(r, c, buf[c * 65 + r]);

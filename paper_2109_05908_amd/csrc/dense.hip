@@ -352,7 +352,7 @@ struct OpTrsmDiag {
     int kb;  // first row of the diagonal block
     __device__ int tiles(int b) const { return (L[b].n > kb) ? (B[b].n + 63) / 64 : 0; }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const DMat Lm = L[b], Bm = B[b];
         const int w = min(64, Lm.n - kb);
         const int c0 = t * 64;
@@ -360,7 +360,7 @@ struct OpTrsmDiag {
         double* bb = Bm.p + kb;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<TRANS, false>(Di, 64, bb, Bm.ld, w, Bm.n, w, 0, c0, sm, acc);
+        mfma_tile_64<TRANS, false>(Di, 64, bb, Bm.ld, w, Bm.n, w, 0, c0, sm.t, acc);
         const int ld = Bm.ld, N = Bm.n;
         acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gj = c0 + c;
@@ -814,7 +814,7 @@ struct OpBlkUpd : BlkOp {
         return ((mp + 63) / 64) * ((r.cc1 - r.cc0 + 63) / 64);
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         BlkRange R;
         active(b, R);
         const ORItem& it = o[b];
@@ -831,10 +831,10 @@ struct OpBlkUpd : BlkOp {
         const int i0 = (band * 8 + q / cols) * 64, j0 = (cg * 8 + q % cols) * 64;
         const double* V = it.V.p + c0 + (int64_t)c0 * it.V.ld;
         double* C = it.C.p + c0 + (int64_t)R.cc0 * it.C.ld;
+        const int ld = it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_OB, mp, nc, R.wb, i0, j0, sm, acc);
-        const int ld = it.C.ld;
+        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_OB, mp, nc, R.wb, i0, j0, sm.t, acc);
         acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
