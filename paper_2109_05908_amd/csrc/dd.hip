@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -296,6 +297,12 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         DBuf<double> da = upload(inv_alpha, s), dz0 = upload(zero, s);
         axpby_vb(Xb, Xb, da.p, dz0.p, s);  // Xt := Xt / alpha
 
+        const bool verbose = std::getenv("DD_VERBOSE") != nullptr;
+        if (verbose) {
+            std::vector<double> e2(ell);
+            std::sort(e2.begin(), e2.end());
+            fprintf(stderr, "dd: qdwh l0 min %.3e median %.3e max %.3e\n", e2.front(), e2[N / 2], e2.back());
+        }
         std::vector<int> done(N, 0);
         for (int it = 0; it < 20; ++it) {
             std::vector<int> actQ(N, 0), actC(N, 0);
@@ -311,6 +318,11 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 else { actC[i] = 1; anyC = 1; coefC[i] = a - b / c; }
             }
             if (!anyQ && !anyC) break;
+            if (verbose) {
+                int nq = 0, nch = 0;
+                for (int i = 0; i < N; ++i) { nq += actQ[i]; nch += actC[i]; }
+                fprintf(stderr, "dd: qdwh iteration %d: %d QR-based, %d Cholesky-based\n", it, nq, nch);
+            }
             if (anyQ) {
                 // S = [sqrt(c) Xt^T ; I]  (2 ni x ni), QR, explicit Q = [Q1; Q2]; Xt := b/c Xt + coef Q2 Q1^T
                 std::vector<double*> sp(N), qp(N), scr(N);
@@ -344,8 +356,9 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 Batch<ORItem> ob;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
-                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i], tG.ptr[i]});
-                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i], tG.ptr[i]});
+                    // [sqrt(c) Xt^T; I]: column j is zero below row ni + j
+                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i], tG.ptr[i], ni[i]});
+                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i], tG.ptr[i], ni[i]});
                 }
                 qb.sync(s);
                 ob.sync(s);

@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
     const QRItem it = q[b];
     if (it.nfac <= col0 || it.A.m <= col0) return;
     const int w = min(QR_NB, it.nfac - col0);
-    const int mp = it.A.m - col0;
+    const int mp = qr_rows(it.A.m, it.zrow, col0, QR_NB) - col0;
     const int64_t ld = it.A.ld;
     double* V = it.A.p + col0 + (int64_t)col0 * ld;
     double part[QR_NB + 1];
@@ -580,7 +580,7 @@ struct OpBuildT {
         __shared__ double T[32][33];
         const DMat Vm = o[b].V;
         const int w = min(QR_NB, Vm.n - col0);
-        const int mp = Vm.m - col0;
+        const int mp = qr_rows(Vm.m, o[b].zrow, col0, QR_NB) - col0;
         const double* V = Vm.p + col0 + (int64_t)col0 * Vm.ld;
         // pairs (a,c) with a <= c owned by threads
         double accv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -673,7 +673,8 @@ struct BlkOp {
         r = blk_range(o[b], c0, cap, mode, oend);
         return r.wb > 0 && r.cc1 > r.cc0;
     }
-    __device__ int nks(int b) const { return (o[b].V.m - c0 + QR_KS - 1) / QR_KS; }
+    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, c0, cap) - c0; }
+    __device__ int nks(int b) const { return (mrows(b) + QR_KS - 1) / QR_KS; }
     __device__ int pstride(int b) const { return QR_OB * max(QR_OB, o[b].C.n); }
 };
 
@@ -692,7 +693,7 @@ struct OpBlkP : BlkOp {
         const int nc = R.cc1 - R.cc0;
         const int ntc = (nc + 63) / 64, ntr = (R.wb + 63) / 64;
         const int tr = t % ntr, tc = (t / ntr) % ntc, ks = t / (ntr * ntc);
-        const int mp = it.V.m - c0;
+        const int mp = mrows(b);
         const int r0 = ks * QR_KS;
         const int kl = min(QR_KS, mp - r0);
         const double* V = it.V.p + c0 + r0 + (int64_t)c0 * it.V.ld;
@@ -810,7 +811,7 @@ struct OpBlkUpd : BlkOp {
     __device__ int tiles(int b) const {
         BlkRange r;
         if (!active(b, r)) return 0;
-        const int mp = o[b].V.m - c0;
+        const int mp = mrows(b);
         return ((mp + 63) / 64) * ((r.cc1 - r.cc0 + 63) / 64);
     }
     __device__ void operator()(int b, int t) const {
@@ -818,7 +819,7 @@ struct OpBlkUpd : BlkOp {
         BlkRange R;
         active(b, R);
         const ORItem& it = o[b];
-        const int mp = it.V.m - c0;
+        const int mp = mrows(b);
         const int nc = R.cc1 - R.cc0;
         // 8 x 8 groups of tiles: bands of 8 row tiles, each band swept in
         // groups of 8 column tiles (column fastest), so that 64 consecutive
@@ -862,7 +863,7 @@ struct OpGramP : BlkOp {
         const int wb = min(QR_OB, it.V.n - c0);
         const int T = (wb + 63) / 64;
         const int tr = t % T, tc = (t / T) % T, ks = t / (T * T);
-        const int mp = it.V.m - c0;
+        const int mp = mrows(b);
         const int r0 = ks * QR_KS;
         const int kl = min(QR_KS, mp - r0);
         const double* V = it.V.p + c0 + r0 + (int64_t)c0 * it.V.ld;
@@ -928,7 +929,7 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
         else { cc0 = c0; cc1 = x.C.n; }
         if (wb <= 0 || cc1 <= cc0) continue;
         const int ntc = ceil_div(cc1 - cc0, 64);
-        const int mp = x.V.m - c0;
+        const int mp = qr_rows(x.V.m, x.zrow, c0, cap) - c0;
         nw += ntc;
         np += (int64_t)ceil_div(wb, 64) * ntc * ceil_div(mp, QR_KS);
         nu += (int64_t)ceil_div(mp, 64) * ntc;
@@ -952,7 +953,7 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
             else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
             else { cc0 = c0; cc1 = x.C.n; }
             if (wb <= 0 || cc1 <= cc0) continue;
-            const double mp = x.V.m - c0, nc = cc1 - cc0;
+            const double mp = qr_rows(x.V.m, x.zrow, c0, cap) - c0, nc = cc1 - cc0;
             const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
             fl += 2.0 * nc * nzv;
             by += 8.0 * ((nzv - wb) + (double)wb * nc + 2.0 * mp * nc);
@@ -968,7 +969,7 @@ static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
         const int wb = std::min(QR_OB, x.V.n - c0);
         if (wb <= QR_NB) continue;  // a single panel needs no G
         const int T = ceil_div(wb, 64);
-        np += (int64_t)T * T * ceil_div(x.V.m - c0, QR_KS);
+        np += (int64_t)T * T * ceil_div(qr_rows(x.V.m, x.zrow, c0, QR_OB) - c0, QR_KS);
         ++nr;
     }
     if (nr == 0) return;
@@ -983,7 +984,7 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     std::vector<double*> htau;
     for (auto& x : q.h) {
         nmax = std::max(nmax, std::min(x.nfac, x.A.m));
-        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W, x.G});
+        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W, x.G, x.zrow});
         htau.push_back(x.tau);
     }
     o.sync(s);

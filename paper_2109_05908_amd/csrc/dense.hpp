@@ -30,6 +30,10 @@ struct Batch {
 // triangular compact-WY factor per 32-column panel (qr_t_size); G holds the
 // Gram matrix V^T V of every 128-column block of reflectors (qr_g_size); W is
 // scratch of qr_w_size(max columns of the matrices the reflectors touch).
+// zrow (optional structure): column j of A has zeros in rows > zrow + j, as
+// for a stack [X; I] with zrow = rows of X.  Reflector j then vanishes below
+// row zrow + j too, so every step only touches rows < zrow + (block end).
+constexpr int QR_NOZ = 1 << 29;
 struct QRItem {
     DMat A;
     double* tau;
@@ -38,6 +42,7 @@ struct QRItem {
     int wld;   // unused (kept for layout stability)
     int nfac;  // factor only the first nfac columns (<= n); the rest receive Q^T
     double* G;
+    int zrow = QR_NOZ;
 };
 
 // Application of the Q stored in V (m x k reflectors, T and G as above) to C
@@ -48,7 +53,10 @@ struct ORItem {
     DMat C;
     double* W;  // qr_w_size(C.n)
     double* G;
+    int zrow = QR_NOZ;  // reflector j is zero below row zrow + j
 };
+// rows touched by the reflectors in columns [c0, c0 + w) of an m-row matrix
+__host__ __device__ inline int qr_rows(int m, int zrow, int c0, int w) { return m < zrow + c0 + w ? m : zrow + c0 + w; }
 
 constexpr int QR_NB = 32;   // inner panel width
 constexpr int QR_OB = 128;  // outer block (four inner panels)
