@@ -1,22 +1,29 @@
-// Block-sparse (supernodal) Cholesky of the coarse operator and its solves.
+// Block-sparse supernodal Cholesky of the coarse operator and its solves.
 //
 // Symbolic phase (host, from sizes and the block graph only): weighted
-// minimum-degree ordering of the subdomain blocks, elimination structure
-// struct(k) (the blocks below the diagonal in block column k of L), the
-// elimination-tree levels, and the panel layout.  Numeric phase (device):
-// per level, a deterministic left-looking block update of every panel of the
-// level followed by a batched tall Cholesky of those panels; explicit
-// inverses of the diagonal blocks serve the triangular solves.
+// minimum-degree ordering of the subdomain blocks and the elimination
+// structure struct(k) of every block; blocks along a chain of the
+// elimination tree whose structures nest (struct(k) = {next} U struct(next))
+// are grouped into supernodes of at most kSnMax columns, so that a dense
+// clique (the top of the tree) becomes a few wide panels instead of a long
+// sequence of narrow ones.  Numeric phase (device): per tree level, a
+// deterministic left-looking update of every panel from its descendants,
+// then a batched tall Cholesky of the level's panels; explicit inverses of
+// the diagonal blocks turn the triangular solves into matrix-vector products.
+// The solves run on the coarse vector permuted to elimination order, where
+// every supernode is a contiguous range.
 #include "bchol.hpp"
 
 #include <algorithm>
 #include <cstdlib>
+#include <map>
 #include <set>
 
 namespace dd {
 
-constexpr int kSolCh = 256;   // forward: columns per partial sum
+constexpr int kSolCh = 256;   // forward: source columns per partial sum
 constexpr int kSolRow = 512;  // backward: panel rows per partial sum
+constexpr int kSnMax = 4096;  // widest supernode
 
 void BlockChol::symbolic(const std::vector<uint8_t>& adj, const std::vector<int>& p_,
                          const std::vector<int64_t>& yoff_) {
@@ -35,7 +42,7 @@ void BlockChol::symbolic(const std::vector<uint8_t>& adj, const std::vector<int>
     // weighted minimum (external) degree, ties -> lowest id
     pos.assign(N, -1);
     order.clear();
-    strct.assign(N, {});
+    bstruct.assign(N, {});
     std::vector<char> gone(N, 0);
     const int na = (int)active.size();
     for (int step = 0; step < na; ++step) {
@@ -43,16 +50,16 @@ void BlockChol::symbolic(const std::vector<uint8_t>& adj, const std::vector<int>
         int64_t bw = INT64_MAX;
         for (int i : active) {
             if (gone[i]) continue;
-            int64_t w = 0;
-            for (int j : g[i]) w += p[j];
-            if (w < bw) { bw = w; best = i; }
+            int64_t wgt = 0;
+            for (int j : g[i]) wgt += p[j];
+            if (wgt < bw) { bw = wgt; best = i; }
         }
         const int k = best;
         gone[k] = 1;
         pos[k] = step;
         order.push_back(k);
         std::vector<int> S(g[k].begin(), g[k].end());
-        strct[k] = S;
+        bstruct[k] = S;
         for (int a : S) {
             g[a].erase(k);
             for (int b : S)
@@ -60,168 +67,243 @@ void BlockChol::symbolic(const std::vector<uint8_t>& adj, const std::vector<int>
         }
         g[k].clear();
     }
-    // sort struct by elimination position; row offsets; heights
-    rowoff.assign(N, {});
-    h.assign(N, 0);
-    for (int k : order) {
-        std::sort(strct[k].begin(), strct[k].end(), [&](int a, int b) { return pos[a] < pos[b]; });
-        int off = p[k];
-        rowoff[k].resize(strct[k].size());
-        for (size_t q = 0; q < strct[k].size(); ++q) {
-            rowoff[k][q] = off;
-            off += p[strct[k][q]];
+    for (int k : order) std::sort(bstruct[k].begin(), bstruct[k].end(), [&](int a, int b) { return pos[a] < pos[b]; });
+    // supernodes (fundamental, width-capped)
+    sn.assign(N, -1);
+    cof.assign(N, 0);
+    members.clear();
+    w.clear();
+    for (size_t idx = 0; idx < order.size(); ++idx) {
+        const int b = order[idx];
+        bool merged = false;
+        if (idx > 0) {
+            const int prev = order[idx - 1];
+            const int K = sn[prev];
+            const auto& Sp = bstruct[prev];
+            const auto& Sb = bstruct[b];
+            if (!Sp.empty() && Sp[0] == b && w[K] + p[b] <= kSnMax && Sp.size() == Sb.size() + 1 &&
+                std::equal(Sb.begin(), Sb.end(), Sp.begin() + 1)) {
+                sn[b] = K;
+                cof[b] = w[K];
+                w[K] += p[b];
+                members[K].push_back(b);
+                merged = true;
+            }
         }
-        h[k] = off;
+        if (!merged) {
+            sn[b] = (int)members.size();
+            cof[b] = 0;
+            members.push_back({b});
+            w.push_back(p[b]);
+        }
     }
-    // elimination tree levels: parent = first block of struct(k)
-    lev.assign(N, 0);
+    NS = (int)members.size();
+    srows.assign(NS, {});
+    srowoff.assign(NS, {});
+    h.assign(NS, 0);
+    start.assign(NS + 1, 0);
+    bstart.assign(N, 0);
+    for (int K = 0; K < NS; ++K) {
+        srows[K] = bstruct[members[K].back()];
+        int off = w[K];
+        for (int j : srows[K]) {
+            srowoff[K].push_back(off);
+            off += p[j];
+        }
+        h[K] = off;
+        start[K + 1] = start[K] + w[K];
+        for (int b : members[K]) bstart[b] = start[K] + cof[b];
+    }
+    // elimination-tree levels of the supernodes (children precede parents)
+    lev.assign(NS, 0);
     int maxlev = 0;
-    for (int k : order) {
-        if (!strct[k].empty()) {
-            const int par = strct[k][0];
-            lev[par] = std::max(lev[par], lev[k] + 1);
+    for (int K = 0; K < NS; ++K) {
+        if (!srows[K].empty()) {
+            const int par = sn[srows[K][0]];
+            lev[par] = std::max(lev[par], lev[K] + 1);
         }
-        maxlev = std::max(maxlev, lev[k]);
+        maxlev = std::max(maxlev, lev[K]);
     }
-    by_level.assign(na ? maxlev + 1 : 0, {});
-    for (int k : order) by_level[lev[k]].push_back(k);
-    // offsets
-    poff.assign(N + 1, 0);
-    loff.assign(N + 1, 0);
-    goff.assign(N + 1, 0);
-    int64_t P = 0, Lo = 0, G = 0;
+    by_level.assign(NS ? maxlev + 1 : 0, {});
+    for (int K = 0; K < NS; ++K) by_level[lev[K]].push_back(K);
+    poff.assign(NS + 1, 0);
+    loff.assign(NS + 1, 0);
+    goff.assign(NS + 1, 0);
     flops = 0.0;
-    for (int i = 0; i < N; ++i) {
-        poff[i] = P;
-        loff[i] = Lo;
-        goff[i] = G;
-        if (p[i] > 0) {
-            P += (int64_t)h[i] * p[i];
-            Lo += (int64_t)p[i] * p[i];
-            G += h[i] - p[i];
-            const double pk = p[i], hk = h[i];
-            flops += pk * pk * pk / 3.0 + (hk - pk) * pk * pk + (hk - pk) * (hk - pk) * pk;
-        }
+    for (int K = 0; K < NS; ++K) {
+        poff[K + 1] = poff[K] + (int64_t)h[K] * w[K];
+        loff[K + 1] = loff[K] + (int64_t)w[K] * w[K];
+        goff[K + 1] = goff[K] + (h[K] - w[K]);
+        const double wk = w[K], r = h[K] - w[K];
+        flops += wk * wk * wk / 3.0 + r * wk * wk + r * r * wk;
     }
-    poff[N] = P;
-    loff[N] = Lo;
-    goff[N] = G;
     if (std::getenv("DD_VERBOSE")) {
-        fprintf(stderr, "dd: coarse block Cholesky: %d blocks, n_C %lld, %zu tree levels, panel entries %lld, "
-                "flops %.3e\n", na, (long long)nC, by_level.size(), (long long)P, flops);
-        fprintf(stderr, "dd: nodes per level:");
-        for (auto& L : by_level) fprintf(stderr, " %zu", L.size());
+        fprintf(stderr, "dd: coarse block Cholesky: %d blocks in %d supernodes, n_C %lld, %zu tree levels, panel "
+                "entries %lld, flops %.3e\n", na, NS, (long long)nC, by_level.size(), (long long)poff[NS], flops);
+        fprintf(stderr, "dd: supernodes per level:");
+        for (auto& Lv : by_level) fprintf(stderr, " %zu", Lv.size());
         fprintf(stderr, "\n");
     }
 }
 
-static int row_offset(const BlockChol& B, int k, int j) {
-    if (j == k) return 0;
-    const auto& S = B.strct[k];
-    for (size_t q = 0; q < S.size(); ++q)
-        if (S[q] == j) return B.rowoff[k][q];
-    return -1;
-}
-
 double* BlockChol::block(int i, int j, int* ld) const {
-    const int r = row_offset(*this, j, i);
-    if (r < 0) return nullptr;
-    *ld = h[j];
-    return panels.p + poff[j] + r;
+    if (p[i] <= 0 || p[j] <= 0 || pos[i] < pos[j]) return nullptr;
+    const int K = sn[j];
+    int r = -1;
+    if (sn[i] == K) {
+        r = cof[i];
+    } else {
+        const auto& S = srows[K];
+        for (size_t q = 0; q < S.size(); ++q)
+            if (S[q] == i) { r = srowoff[K][q]; break; }
+        if (r < 0) return nullptr;
+    }
+    *ld = h[K];
+    return panels.p + poff[K] + r + (int64_t)cof[j] * h[K];
 }
 
 void BlockChol::allocate(hipStream_t s) {
-    panels.alloc(std::max<int64_t>(1, poff[N]));
-    linv.alloc(std::max<int64_t>(1, loff[N]));
+    panels.alloc(std::max<int64_t>(1, poff[NS]));
+    linv.alloc(std::max<int64_t>(1, loff[NS]));
     fill(panels.p, panels.n, 0.0, s);
     tbuf.alloc(std::max<int64_t>(1, nC));
-    // backward gather indices: panel row q >= p_k of node k -> coarse index
-    std::vector<int64_t> g(std::max<int64_t>(1, goff[N]));
-    for (int k = 0; k < N; ++k) {
-        if (p[k] <= 0) continue;
-        int64_t q = goff[k];
-        for (int j : strct[k])
-            for (int r = 0; r < p[j]; ++r) g[q++] = yoff[j] + r;
+    ybuf.alloc(std::max<int64_t>(1, nC));
+    {
+        std::vector<int64_t> hp(std::max<int64_t>(1, nC), 0);
+        for (int b = 0; b < N; ++b)
+            for (int r = 0; r < p[b]; ++r) hp[yoff[b] + r] = bstart[b] + r;
+        perm = upload(hp, s);
     }
-    gidx.alloc(g.size());
-    h2d(gidx.p, g.data(), g.size(), s);
-    // factorization update jobs: for node k and block row j in {k} U struct(k),
-    // sources are the descendants d with k, j in struct(d)
+    {
+        std::vector<int64_t> g(std::max<int64_t>(1, goff[NS]));
+        for (int K = 0; K < NS; ++K) {
+            int64_t q = goff[K];
+            for (int j : srows[K])
+                for (int r = 0; r < p[j]; ++r) g[q++] = bstart[j] + r;
+        }
+        gidx = upload(g, s);
+    }
     const int L = (int)by_level.size();
-    std::vector<std::vector<std::vector<int>>> srcs(N);  // srcs[k][q]: q = 0 diag, q >= 1 struct index
-    for (int k = 0; k < N; ++k)
-        if (p[k] > 0) srcs[k].assign(strct[k].size() + 1, {});
-    for (int d : order) {
-        const auto& S = strct[d];
-        for (size_t a = 0; a < S.size(); ++a) {
-            const int k = S[a];
-            srcs[k][0].push_back(d);
-            for (size_t b = a + 1; b < S.size(); ++b) {
-                const int j = S[b];
-                // j in struct(k) (elimination-tree property); find its index
-                const auto& Sk = strct[k];
-                const int q = (int)(std::find(Sk.begin(), Sk.end(), j) - Sk.begin());
-                srcs[k][q + 1].push_back(d);
+    // factorization update jobs: target (row block b, column block a), a in a
+    // supernode K; sources = the descendant supernodes D with a, b in struct(D)
+    {
+        std::map<std::pair<int, int>, std::vector<std::pair<int, std::pair<int, int>>>> jobs;
+        for (int D = 0; D < NS; ++D) {
+            const auto& S = srows[D];
+            for (size_t ia = 0; ia < S.size(); ++ia)
+                for (size_t ib = ia; ib < S.size(); ++ib) jobs[{S[ia], S[ib]}].push_back({D, {(int)ia, (int)ib}});
+        }
+        upd.clear();
+        upd.resize(L);
+        upd_src.clear();
+        upd_src.resize(L);
+        std::vector<std::vector<UpdSrc>> us(L);
+        for (auto& kv : jobs) {
+            const int a = kv.first.first, b = kv.first.second;
+            int ld = 0;
+            double* out = block(b, a, &ld);
+            if (!out) throw Error(DD_ERR_INTERNAL, "coarse factor: update target outside the structure");
+            const int l = lev[sn[a]];
+            upd[l].h.push_back(UpdJob{out, ld, p[b], p[a], (int)us[l].size(), (int)kv.second.size()});
+            for (auto& src : kv.second) {
+                const int D = src.first;
+                us[l].push_back(UpdSrc{panels.p + poff[D] + srowoff[D][src.second.second],
+                                       panels.p + poff[D] + srowoff[D][src.second.first], h[D], w[D]});
             }
         }
+        for (int l = 0; l < L; ++l) {
+            if (!upd[l].h.empty()) upd[l].sync(s);
+            upd_src[l].alloc(std::max<size_t>(1, us[l].size()));
+            h2d(upd_src[l].p, us[l].data(), us[l].size(), s);
+        }
+        DD_HIP(hipStreamSynchronize(s));  // the host source arrays go out of scope
     }
-    upd.clear();
-    upd.resize(L);
-    upd_src.clear();
-    upd_src.resize(L);
+    // forward sources: for supernode K, the descendants D whose struct meets K
+    // (a contiguous run of struct(D), since K's blocks are consecutive in pos)
+    std::vector<std::vector<std::pair<int, std::pair<int, int>>>> fsrc(NS);  // K -> (D, (q0, q1))
+    for (int D = 0; D < NS; ++D) {
+        const auto& S = srows[D];
+        size_t q = 0;
+        while (q < S.size()) {
+            const int K = sn[S[q]];
+            size_t q1 = q;
+            while (q1 + 1 < S.size() && sn[S[q1 + 1]] == K) ++q1;
+            fsrc[K].push_back({D, {(int)q, (int)q1}});
+            q = q1 + 1;
+        }
+    }
     sol.clear();
     sol.resize(L);
     sol_src.clear();
     sol_src.resize(L);
     sol_ch.clear();
     sol_ch.resize(L);
+    sol_trf.clear();
+    sol_trf.resize(L);
+    sol_trb.clear();
+    sol_trb.resize(L);
     fwd_tiles.assign(L, 0);
     bwd_tiles.assign(L, 0);
-    int64_t pmax = 1;
+    part_len.assign(L, 0);
+    std::vector<int32_t> hr;                       // row maps of all forward sources
+    std::vector<std::vector<SolSrc>> ss(L);
+    std::vector<std::vector<int64_t>> ssroff(L);   // offset of each source's row map in hr
+    int64_t pmax = 1, tpmax = 1;
     for (int l = 0; l < L; ++l) {
-        std::vector<UpdSrc> us;
-        std::vector<SolSrc> ss;
-        int64_t part = 0;
-        for (int k : by_level[l]) {
-            const int nq = (int)strct[k].size() + 1;
-            for (int q = 0; q < nq; ++q) {
-                const int j = (q == 0) ? k : strct[k][q - 1];
-                const auto& D = srcs[k][q];
-                if (D.empty()) continue;
-                UpdJob job{panels.p + poff[k] + (q == 0 ? 0 : rowoff[k][q - 1]), h[k], p[j], p[k], (int)us.size(),
-                           (int)D.size()};
-                for (int d : D) {
-                    const int rj = row_offset(*this, d, j), rk = row_offset(*this, d, k);
-                    us.push_back(UpdSrc{panels.p + poff[d] + rj, panels.p + poff[d] + rk, h[d], p[d]});
-                }
-                upd[l].h.push_back(job);
-            }
+        int64_t part = 0, tpart = 0;
+        for (int K : by_level[l]) {
             const int node = (int)sol[l].h.size();
-            SolNode sn{panels.p + poff[k], h[k], p[k], linv.p + loff[k], yoff[k], (int)ss.size(),
-                       (int)srcs[k][0].size(), gidx.p + goff[k], (int)sol_ch[l].h.size(), 0, 0, part};
-            for (int d : srcs[k][0]) {
-                const int qi = (int)ss.size();
-                ss.push_back(SolSrc{panels.p + poff[d] + row_offset(*this, d, k), h[d], p[d], yoff[d]});
-                for (int c0 = 0; c0 < p[d]; c0 += kSolCh) sol_ch[l].h.push_back(SolChunk{node, qi, c0, std::min(p[d], c0 + kSolCh)});
+            SolNode nd{panels.p + poff[K], h[K], w[K], start[K], nullptr, (int)sol_ch[l].h.size(), 0,
+                       ceil_div(h[K] - w[K], kSolRow), part};
+            for (auto& fs : fsrc[K]) {
+                const int D = fs.first, q0 = fs.second.first, q1 = fs.second.second;
+                const int64_t roff = (int64_t)hr.size();
+                int rows = 0;
+                for (int q = q0; q <= q1; ++q) {
+                    const int b = srows[D][q];
+                    for (int r = 0; r < p[b]; ++r) hr.push_back(cof[b] + r);
+                    rows += p[b];
+                }
+                const int lsrc = (int)ss[l].size();
+                ss[l].push_back(SolSrc{panels.p + poff[D] + srowoff[D][q0], h[D], w[D], rows, start[D], nullptr});
+                ssroff[l].push_back(roff);
+                for (int c0 = 0; c0 < w[D]; c0 += kSolCh) {
+                    sol_ch[l].h.push_back(SolChunk{node, lsrc, c0, std::min(w[D], c0 + kSolCh)});
+                    fwd_tiles[l] += ceil_div(rows, 64);
+                }
             }
-            sn.nfch = (int)sol_ch[l].h.size() - sn.fch0;
-            sn.nbch = ceil_div(h[k] - p[k], kSolRow);
-            part += (int64_t)p[k] * std::max(sn.nfch, sn.nbch);
-            fwd_tiles[l] += (int64_t)sn.nfch * ceil_div(p[k], 64);
-            bwd_tiles[l] += (int64_t)sn.nbch * ceil_div(p[k], 64);
-            sol[l].h.push_back(sn);
+            nd.nfch = (int)sol_ch[l].h.size() - nd.fch0;
+            nd.gidx = gidx.p + goff[K];
+            part += (int64_t)w[K] * std::max(nd.nfch, nd.nbch);
+            bwd_tiles[l] += (int64_t)nd.nbch * ceil_div(w[K], 64);
+            sol[l].h.push_back(nd);
+            tpart += trmv_part_size(w[K]);
         }
+        part_len[l] = part;
         pmax = std::max(pmax, part);
-        if (!upd[l].h.empty()) upd[l].sync(s);
-        upd_src[l].alloc(std::max<size_t>(1, us.size()));
-        h2d(upd_src[l].p, us.data(), us.size(), s);
+        tpmax = std::max(tpmax, tpart);
+    }
+    if (hr.empty()) hr.push_back(0);
+    ridx = upload(hr, s);
+    pbuf.alloc(pmax);
+    trpart.alloc(tpmax);
+    for (int l = 0; l < L; ++l) {
+        for (size_t q = 0; q < ss[l].size(); ++q) ss[l][q].ridx = ridx.p + ssroff[l][q];
+        int64_t tp = 0;
+        for (int K : by_level[l]) {
+            // forward: y_K = L_KK^{-1} t_K;  backward: y_K = L_KK^{-T} t_K
+            sol_trf[l].h.push_back(TrmvItem{linv.p + loff[K], w[K], w[K], tbuf.p + start[K], ybuf.p + start[K], trpart.p + tp});
+            sol_trb[l].h.push_back(TrmvItem{linv.p + loff[K], w[K], w[K], ybuf.p + start[K], tbuf.p + start[K], trpart.p + tp});
+            tp += trmv_part_size(w[K]);
+        }
         sol[l].sync(s);
-        sol_src[l].alloc(std::max<size_t>(1, ss.size()));
-        h2d(sol_src[l].p, ss.data(), ss.size(), s);
+        sol_trf[l].sync(s);
+        sol_trb[l].sync(s);
+        sol_src[l].alloc(std::max<size_t>(1, ss[l].size()));
+        h2d(sol_src[l].p, ss[l].data(), ss[l].size(), s);
         if (sol_ch[l].h.empty()) sol_ch[l].h.push_back(SolChunk{0, 0, 0, 0});
         sol_ch[l].sync(s);
     }
-    pbuf.alloc(pmax);
     DD_HIP(hipStreamSynchronize(s));
 }
 
@@ -249,8 +331,6 @@ struct OpBUpd {
 };
 
 int BlockChol::factor(hipStream_t s) {
-    DBuf<int32_t> info(std::max(1, N));
-    DD_HIP(hipMemsetAsync(info.p, 0, std::max(1, N) * sizeof(int32_t), s));
     const int L = (int)by_level.size();
     for (int l = 0; l < L; ++l) {
         if (!upd[l].h.empty()) {
@@ -259,41 +339,50 @@ int BlockChol::factor(hipStream_t s) {
             launch_tiles(OpBUpd{upd[l].d.p, upd_src[l].p}, upd[l].size(), tot, s, "bchol_update");
         }
         Batch<DMat> pn, dg, iv;
-        for (int k : by_level[l]) {
-            pn.h.push_back(DMat{panels.p + poff[k], h[k], h[k], p[k]});
-            dg.h.push_back(DMat{panels.p + poff[k], h[k], p[k], p[k]});
-            iv.h.push_back(DMat{linv.p + loff[k], p[k], p[k], p[k]});
+        for (int K : by_level[l]) {
+            pn.h.push_back(DMat{panels.p + poff[K], h[K], h[K], w[K]});
+            dg.h.push_back(DMat{panels.p + poff[K], h[K], w[K], w[K]});
+            iv.h.push_back(DMat{linv.p + loff[K], w[K], w[K], w[K]});
         }
         pn.sync(s);
         dg.sync(s);
         iv.sync(s);
-        // info index: position within the level; remapped below on failure
         DBuf<int32_t> li(pn.size());
         DD_HIP(hipMemsetAsync(li.p, 0, pn.size() * sizeof(int32_t), s));
         potrf_vb(pn, li.p, s);
         set_identity_vb(iv, 1.0, s);
-        trsm_vb(dg, iv, false, s);  // L_kk^{-1}
+        trsm_vb(dg, iv, false, s);  // L_KK^{-1}
         std::vector<int32_t> hl(pn.size());
         DD_HIP(hipMemcpyAsync(hl.data(), li.p, pn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DD_HIP(hipStreamSynchronize(s));
         for (size_t q = 0; q < hl.size(); ++q)
-            if (hl[q]) return by_level[l][q] + 1;
+            if (hl[q]) return members[by_level[l][q]][0] + 1;
     }
     return 0;
 }
 
 // ---------------------------------------------------------------------------
-// solves
+// solves (on the permuted coarse vector ybuf)
 // ---------------------------------------------------------------------------
-// forward, pass 1: partial sums of L_{k,d} y_d over one column chunk of one
-// descendant d (rows of block k inside panel d), 64 rows per workgroup.
+__global__ void k_perm_gather(const double* y, const int64_t* perm, int64_t n, double* yp) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        yp[perm[q]] = y[q];
+}
+__global__ void k_perm_scatter(const double* yp, const int64_t* perm, int64_t n, double* y) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        y[q] = yp[perm[q]];
+}
+
+// forward, pass 1: partial sums of L_{K,D} x_D over one column chunk of one
+// descendant D (its rows that fall in K), 64 rows per workgroup, written to
+// the rows of K they belong to (the other rows of the chunk's slice stay 0).
 struct OpFwdPart {
     const SolNode* nodes;
     const SolSrc* src;
     const SolChunk* ch;
-    const double* y;
+    const double* x;
     double* part;
-    __device__ int tiles(int g) const { return (nodes[ch[g].node].p + 63) / 64 * (ch[g].c1 > ch[g].c0); }
+    __device__ int tiles(int g) const { return (ch[g].c1 > ch[g].c0) ? (src[ch[g].src].rows + 63) / 64 : 0; }
     __device__ void operator()(int g, int tile) const {
         __shared__ double red[4][64];
         const SolChunk C = ch[g];
@@ -302,132 +391,84 @@ struct OpFwdPart {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int r = tile * 64 + lane;
         double acc = 0.0;
-        if (r < nd.p)
-            for (int c = C.c0 + wv; c < C.c1; c += 4) acc += S.L[r + (int64_t)c * S.ld] * y[S.yoff + c];
+        if (r < S.rows)
+            for (int c = C.c0 + wv; c < C.c1; c += 4) acc += S.L[r + (int64_t)c * S.ld] * x[S.xoff + c];
         red[wv][lane] = acc;
         __syncthreads();
-        if (wv == 0 && r < nd.p)
-            part[nd.part0 + (int64_t)(g - nd.fch0) * nd.p + r] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        if (wv == 0 && r < S.rows)
+            part[nd.part0 + (int64_t)(g - nd.fch0) * nd.w + S.ridx[r]] =
+                (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     }
 };
-// forward, pass 2: t_k = y_k - sum of the partials (in chunk order)
-struct OpFwdRed {
+// pass 2 (both directions): t_K = y_K - sum of the node's partials (in chunk order)
+struct OpSolRed {
     const SolNode* nodes;
     const double* part;
     const double* y;
     double* t;
-    __device__ int tiles(int b) const { return (nodes[b].p + 255) / 256; }
+    int backward;
+    __device__ int tiles(int b) const { return (nodes[b].w + 255) / 256; }
     __device__ void operator()(int b, int tile) const {
         const SolNode nd = nodes[b];
         const int r = tile * 256 + threadIdx.x;
-        if (r >= nd.p) return;
+        if (r >= nd.w) return;
+        const int nch = backward ? nd.nbch : nd.nfch;
         double acc = 0.0;
-        for (int q = 0; q < nd.nfch; ++q) acc += part[nd.part0 + (int64_t)q * nd.p + r];
-        t[nd.yoff + r] = y[nd.yoff + r] - acc;
+        for (int q = 0; q < nch; ++q) acc += part[nd.part0 + (int64_t)q * nd.w + r];
+        t[nd.start + r] = y[nd.start + r] - acc;
     }
 };
-// forward, pass 3: y_k = L_kk^{-1} t_k
-struct OpFwdY {
-    const SolNode* nodes;
-    const double* t;
-    double* y;
-    __device__ int tiles(int b) const { return (nodes[b].p + 63) / 64; }
-    __device__ void operator()(int b, int tile) const {
-        __shared__ double red[4][64];
-        const SolNode nd = nodes[b];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int r = tile * 64 + lane;
-        double acc = 0.0;
-        if (r < nd.p)
-            for (int c = wv; c <= r; c += 4) acc += nd.linv[r + (int64_t)c * nd.p] * t[nd.yoff + c];
-        red[wv][lane] = acc;
-        __syncthreads();
-        if (wv == 0 && r < nd.p) y[nd.yoff + r] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    }
-};
-// backward, pass 1: partial column dots of panel k over one chunk of rows below the diagonal block
+// backward, pass 1: partial column dots of panel K over one chunk of rows below the diagonal block
 struct OpBwdPart {
     const SolNode* nodes;
     const double* x;
     double* part;
-    __device__ int tiles(int b) const { return nodes[b].nbch * ((nodes[b].p + 63) / 64); }
+    __device__ int tiles(int b) const { return nodes[b].nbch * ((nodes[b].w + 63) / 64); }
     __device__ void operator()(int b, int tile) const {
         const SolNode nd = nodes[b];
-        const int nct = (nd.p + 63) / 64;
+        const int nct = (nd.w + 63) / 64;
         const int rc = tile / nct, ct = tile % nct;
-        const int q0 = nd.p + rc * kSolRow, q1 = min(nd.h, q0 + kSolRow);
+        const int q0 = nd.w + rc * kSolRow, q1 = min(nd.h, q0 + kSolRow);
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int cc = wv; cc < 64; cc += 4) {
             const int c = ct * 64 + cc;
-            if (c >= nd.p) break;
+            if (c >= nd.w) break;
             const double* col = nd.panel + (int64_t)c * nd.h;
             double acc = 0.0;
-            for (int q = q0 + lane; q < q1; q += 64) acc += col[q] * x[nd.gidx[q - nd.p]];
+            for (int q = q0 + lane; q < q1; q += 64) acc += col[q] * x[nd.gidx[q - nd.w]];
             acc = wave_sum(acc);
-            if (lane == 0) part[nd.part0 + (int64_t)rc * nd.p + c] = acc;
-        }
-    }
-};
-struct OpBwdRed {
-    const SolNode* nodes;
-    const double* part;
-    const double* x;
-    double* t;
-    __device__ int tiles(int b) const { return (nodes[b].p + 255) / 256; }
-    __device__ void operator()(int b, int tile) const {
-        const SolNode nd = nodes[b];
-        const int c = tile * 256 + threadIdx.x;
-        if (c >= nd.p) return;
-        double acc = 0.0;
-        for (int q = 0; q < nd.nbch; ++q) acc += part[nd.part0 + (int64_t)q * nd.p + c];
-        t[nd.yoff + c] = x[nd.yoff + c] - acc;
-    }
-};
-// backward, pass 3: x_k = L_kk^{-T} t_k (column dots of the inverse)
-struct OpBwdX {
-    const SolNode* nodes;
-    const double* t;
-    double* x;
-    __device__ int tiles(int b) const { return (nodes[b].p + 63) / 64; }
-    __device__ void operator()(int b, int tile) const {
-        const SolNode nd = nodes[b];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int cc = wv; cc < 64; cc += 4) {
-            const int c = tile * 64 + cc;
-            if (c >= nd.p) break;
-            const double* col = nd.linv + (int64_t)c * nd.p;
-            double acc = 0.0;
-            for (int r = c + lane; r < nd.p; r += 64) acc += col[r] * t[nd.yoff + r];
-            acc = wave_sum(acc);
-            if (lane == 0) x[nd.yoff + c] = acc;
+            if (lane == 0) part[nd.part0 + (int64_t)rc * nd.w + c] = acc;
         }
     }
 };
 
 void BlockChol::solve(double* y, hipStream_t s) {
+    if (nC <= 0) return;
+    const int grid = (int)std::min<int64_t>((nC + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_perm_gather, dim3(grid), dim3(256), 0, s, y, perm.p, nC, ybuf.p);
+    launch_check("bchol_perm");
     const int L = (int)by_level.size();
     for (int l = 0; l < L; ++l) {
-        int64_t tot = 0, tot4 = 0;
-        for (auto& nd : sol[l].h) {
-            tot += ceil_div(nd.p, 64);
-            tot4 += ceil_div(nd.p, 256);
+        int64_t tot4 = 0;
+        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 256);
+        if (fwd_tiles[l] > 0) {
+            fill(pbuf.p, part_len[l], 0.0, s);
+            launch_tiles(OpFwdPart{sol[l].d.p, sol_src[l].p, sol_ch[l].d.p, ybuf.p, pbuf.p}, sol_ch[l].size(),
+                         fwd_tiles[l], s, "bchol_fwd_part");
         }
-        if (fwd_tiles[l] > 0)
-            launch_tiles(OpFwdPart{sol[l].d.p, sol_src[l].p, sol_ch[l].d.p, y, pbuf.p}, sol_ch[l].size(), fwd_tiles[l], s,
-                         "bchol_fwd_part");
-        launch_tiles(OpFwdRed{sol[l].d.p, pbuf.p, y, tbuf.p}, sol[l].size(), tot4, s, "bchol_fwd_red");
-        launch_tiles(OpFwdY{sol[l].d.p, tbuf.p, y}, sol[l].size(), tot, s, "bchol_fwd_y");
+        launch_tiles(OpSolRed{sol[l].d.p, pbuf.p, ybuf.p, tbuf.p, 0}, sol[l].size(), tot4, s, "bchol_fwd_red");
+        trmv_n_vb(sol_trf[l], s);  // y_K = L_KK^{-1} t_K
     }
     for (int l = L - 1; l >= 0; --l) {
-        int64_t tot = 0, tot4 = 0;
-        for (auto& nd : sol[l].h) {
-            tot += ceil_div(nd.p, 64);
-            tot4 += ceil_div(nd.p, 256);
-        }
-        if (bwd_tiles[l] > 0) launch_tiles(OpBwdPart{sol[l].d.p, y, pbuf.p}, sol[l].size(), bwd_tiles[l], s, "bchol_bwd_part");
-        launch_tiles(OpBwdRed{sol[l].d.p, pbuf.p, y, tbuf.p}, sol[l].size(), tot4, s, "bchol_bwd_red");
-        launch_tiles(OpBwdX{sol[l].d.p, tbuf.p, y}, sol[l].size(), tot, s, "bchol_bwd_x");
+        int64_t tot4 = 0;
+        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 256);
+        if (bwd_tiles[l] > 0)
+            launch_tiles(OpBwdPart{sol[l].d.p, ybuf.p, pbuf.p}, sol[l].size(), bwd_tiles[l], s, "bchol_bwd_part");
+        launch_tiles(OpSolRed{sol[l].d.p, pbuf.p, ybuf.p, tbuf.p, 1}, sol[l].size(), tot4, s, "bchol_bwd_red");
+        trmv_t_vb(sol_trb[l], s);  // y_K = L_KK^{-T} t_K
     }
+    hipLaunchKernelGGL(k_perm_scatter, dim3(grid), dim3(256), 0, s, ybuf.p, perm.p, nC, y);
+    launch_check("bchol_perm");
 }
 
 }  // namespace dd

@@ -139,16 +139,25 @@ struct OpTrmvT {
     }
 };
 
-void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s) {
-    int64_t tn = 0, tr = 0, tt = 0;
+void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s) {
+    int64_t tn = 0, tr = 0;
     for (auto& x : t.h) {
         tn += (int64_t)ceil_div(x.n, TRMV_RB) * ceil_div(x.n, TRMV_CC);
         tr += ceil_div(x.n, 256);
-        tt += ceil_div(x.n, 16);
     }
     launch_tiles(OpTrmvN{t.d.p}, t.size(), tn, s, "trmv_n");
     launch_tiles(OpTrmvRed{t.d.p}, t.size(), tr, s, "trmv_red");
+}
+
+void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s) {
+    int64_t tt = 0;
+    for (auto& x : t.h) tt += ceil_div(x.n, 16);
     launch_tiles(OpTrmvT{t.d.p}, t.size(), tt, s, "trmv_t");
+}
+
+void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s) {
+    trmv_n_vb(t, s);
+    trmv_t_vb(t, s);
 }
 
 // ===========================================================================

@@ -159,6 +159,8 @@ constexpr int TRMV_RB = 64;    // rows per tile of y = W x
 constexpr int TRMV_CC = 512;   // columns per partial sum of y = W x
 inline int64_t trmv_part_size(int n) { return (int64_t)((n + TRMV_CC - 1) / TRMV_CC) * n; }
 void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s);
+void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s);  // y := W x   (uses part)
+void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s);  // x := W^T y
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)
