@@ -162,7 +162,8 @@ void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s) {
 
 // ===========================================================================
 // Cholesky (right-looking, 64-column blocks)
-// ===========================================================================
+// Cholesky of the 64 x 64 diagonal block at k0 in LDS, written back.  A
+// non-positive pivot records info = its 1-based column and continues with 1.
 struct OpPotrfDiag {
     const DMat* A;
     int* info;
@@ -205,8 +206,8 @@ struct OpPotrfDiag {
     }
 };
 
-// A21 := A21 * L11^{-T} for the rows below the diagonal block (tall panels:
-// rows up to m), 64-row tiles, one thread per row.
+// A21 := A21 L11^{-T} for the rows below the diagonal block (down to m) by
+// forward substitution, one row per thread, 256 rows per workgroup.
 struct OpPotrfPanel {
     const DMat* A;
     int k0;
@@ -214,7 +215,7 @@ struct OpPotrfPanel {
         if (A[b].n <= k0) return 0;
         const int w = min(64, A[b].n - k0);
         const int rem = A[b].m - k0 - w;
-        return rem > 0 ? (rem + 63) / 64 : 0;
+        return rem > 0 ? (rem + 255) / 256 : 0;
     }
     __device__ void operator()(int b, int t) const {
         __shared__ double L[64][65];
@@ -226,8 +227,8 @@ struct OpPotrfPanel {
             L[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : 0.0;
         }
         __syncthreads();
-        const int row = k0 + w + t * 64 + (int)threadIdx.x;
-        if (threadIdx.x < 64 && row < M.m) {
+        const int row = k0 + w + t * 256 + (int)threadIdx.x;
+        if (row < M.m) {
             double x[64];
             double* a = M.p + row + (int64_t)k0 * M.ld;
 #pragma unroll
@@ -248,39 +249,40 @@ struct OpPotrfPanel {
     }
 };
 
-// Trailing update A22 -= A21 A21^T: columns k0+64..n-1, rows down to m-1,
-// lower part only inside the square block.
+// Left-looking block update of the recursion: columns [mid, c1) and rows
+// [mid, m) take -= A[mid:m, c0:mid] A[mid:c1, c0:mid]^T (lower part only
+// inside the square block).
 struct OpPotrfUpdate {
     const DMat* A;
-    int k0;
-    __device__ static void dims(const DMat& M, int k0, int& TR, int& TC) {
-        const int rows = M.m - k0 - 64, cols = M.n - k0 - 64;
+    int c0, mid, c1;
+    __device__ void dims(const DMat& M, int& TR, int& TC) const {
+        const int rows = M.m - mid, cols = min(c1, M.n) - mid;
         TR = rows > 0 ? (rows + 63) / 64 : 0;
         TC = cols > 0 ? (cols + 63) / 64 : 0;
     }
     __device__ int tiles(int b) const {
-        if (A[b].n <= k0 + 64) return 0;
+        if (A[b].n <= mid) return 0;
         int TR, TC;
-        dims(A[b], k0, TR, TC);
+        dims(A[b], TR, TC);
         return TC * TR - TC * (TC - 1) / 2;
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
         const DMat M = A[b];
         int TR, TC;
-        dims(M, k0, TR, TC);
+        dims(M, TR, TC);
         int tj = 0, rem_t = t;
         while (rem_t >= TR - tj) {
             rem_t -= TR - tj;
             ++tj;
         }
         const int ti = tj + rem_t;
-        const int rows = M.m - k0 - 64, cols = M.n - k0 - 64;
-        const double* A21 = M.p + (k0 + 64) + (int64_t)k0 * M.ld;
+        const int rows = M.m - mid, cols = min(c1, M.n) - mid;
+        const double* A21 = M.p + mid + (int64_t)c0 * M.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, 64, ti * 64, tj * 64, sm, acc);
-        double* C = M.p + (k0 + 64) + (int64_t)(k0 + 64) * M.ld;
+        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, mid - c0, ti * 64, tj * 64, sm, acc);
+        double* C = M.p + mid + (int64_t)mid * M.ld;
         acc_foreach(acc, [&](int r, int c, double v) {
             const int gi = ti * 64 + r, gj = tj * 64 + c;
             if (gi < rows && gj < cols && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
@@ -288,26 +290,38 @@ struct OpPotrfUpdate {
     }
 };
 
+// Recursive (left half, update, right half) Cholesky of columns [c0, c1).
+static void potrf_rec(Batch<DMat>& A, int* dinfo, int c0, int c1, hipStream_t s) {
+    if (c1 - c0 <= 64) {
+        int64_t nd = 0, np = 0;
+        for (auto& x : A.h) {
+            if (x.n <= c0) continue;
+            ++nd;
+            const int rem = x.m - c0 - std::min(64, x.n - c0);
+            if (rem > 0) np += ceil_div(rem, 256);
+        }
+        if (!nd) return;
+        launch_tiles(OpPotrfDiag{A.d.p, dinfo, c0}, A.size(), nd, s, "potrf_diag");
+        if (np) launch_tiles(OpPotrfPanel{A.d.p, c0}, A.size(), np, s, "potrf_panel");
+        return;
+    }
+    const int mid = c0 + ceil_div(c1 - c0, 128) * 64;
+    potrf_rec(A, dinfo, c0, mid, s);
+    int64_t nu = 0;
+    for (auto& x : A.h) {
+        if (x.n <= mid) continue;
+        const int TR = ceil_div(x.m - mid, 64), TC = ceil_div(std::min(c1, x.n) - mid, 64);
+        nu += (int64_t)TC * TR - (int64_t)TC * (TC - 1) / 2;
+    }
+    if (nu) launch_tiles(OpPotrfUpdate{A.d.p, c0, mid, c1}, A.size(), nu, s, "potrf_update");
+    potrf_rec(A, dinfo, mid, c1, s);
+}
+
 void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
     int nmax = 0;
     for (auto& x : A.h) nmax = std::max(nmax, x.n);
-    for (int k0 = 0; k0 < nmax; k0 += 64) {
-        int64_t nd = 0, np = 0, nu = 0;
-        for (auto& x : A.h) {
-            if (x.n <= k0) continue;
-            ++nd;
-            const int w = std::min(64, x.n - k0);
-            const int rem = x.m - k0 - w;
-            if (rem > 0) np += ceil_div(rem, 64);
-            if (x.n > k0 + 64) {
-                const int TR = ceil_div(x.m - k0 - 64, 64), TC = ceil_div(x.n - k0 - 64, 64);
-                nu += (int64_t)TC * TR - (int64_t)TC * (TC - 1) / 2;
-            }
-        }
-        launch_tiles(OpPotrfDiag{A.d.p, dinfo, k0}, A.size(), nd, s, "potrf_diag");
-        launch_tiles(OpPotrfPanel{A.d.p, k0}, A.size(), np, s, "potrf_panel");
-        launch_tiles(OpPotrfUpdate{A.d.p, k0}, A.size(), nu, s, "potrf_update");
-    }
+    if (nmax == 0) return;
+    potrf_rec(A, dinfo, 0, ceil_div(nmax, 64) * 64, s);
 }
 
 // ===========================================================================
@@ -1691,25 +1705,47 @@ void axpby_vb(Batch<DMat>& X, Batch<DMat>& Y, const double* dalpha, const double
     launch_tiles(OpAxpby{X.d.p, Y.d.p, dalpha, dbeta}, Y.size(), tot, s, "axpby");
 }
 
-struct OpFrob {
+// ||A||_F: partial sums over 16-column slabs, then an ordered sum per item
+struct OpFrobPart {
     const DMat* A;
-    double* out;
-    __device__ int tiles(int b) const { return 1; }
-    __device__ void operator()(int b, int) const {
+    double* const* part;
+    __device__ int tiles(int b) const { return (A[b].n + 15) / 16; }
+    __device__ void operator()(int b, int t) const {
         __shared__ double red[4];
         const DMat M = A[b];
         double s = 0.0;
-        for (int c = 0; c < M.n; ++c)
+        for (int c = t * 16; c < min(M.n, t * 16 + 16); ++c)
             for (int r = threadIdx.x; r < M.m; r += blockDim.x) {
                 const double v = M.p[r + (int64_t)c * M.ld];
                 s += v * v;
             }
         s = block_sum(s, red);
-        if (threadIdx.x == 0) out[b] = sqrt(s);
+        if (threadIdx.x == 0) part[b][t] = s;
+    }
+};
+struct OpFrob {
+    const DMat* A;
+    double* const* part;
+    double* out;
+    __device__ int tiles(int b) const { return 1; }
+    __device__ void operator()(int b, int) const {
+        if (threadIdx.x != 0) return;
+        double s = 0.0;
+        for (int t = 0; t < (A[b].n + 15) / 16; ++t) s += part[b][t];
+        out[b] = sqrt(s);
     }
 };
 void frob_vb(Batch<DMat>& A, double* dout, hipStream_t s) {
-    launch_tiles(OpFrob{A.d.p, dout}, A.size(), A.size(), s, "frob");
+    std::vector<int64_t> off(A.size() + 1, 0);
+    for (int b = 0; b < A.size(); ++b) off[b + 1] = off[b] + ceil_div(std::max(1, A.h[b].n), 16);
+    DBuf<double> pbuf(std::max<int64_t>(1, off.back()));
+    std::vector<double*> hp(A.size());
+    for (int b = 0; b < A.size(); ++b) hp[b] = pbuf.p + off[b];
+    DBuf<double*> dp(std::max<size_t>(1, hp.size()));
+    h2d(dp.p, hp.data(), hp.size(), s);
+    launch_tiles(OpFrobPart{A.d.p, dp.p}, A.size(), off.back(), s, "frob_part");
+    launch_tiles(OpFrob{A.d.p, dp.p, dout}, A.size(), A.size(), s, "frob");
+    DD_HIP(hipStreamSynchronize(s));
 }
 
 // Largest eigenvalue of the symmetric tridiagonal (a, b) of size m by bisection.
