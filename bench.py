@@ -47,6 +47,8 @@ def parse():
     p.add_argument("--workload", choices=["diffusion3d_64", "poisson2d_64"], default="diffusion3d_64")
     p.add_argument("--form", choices=["fp64", "fp32"], default="fp64")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-compare-forms", action="store_true",
+                   help="skip timing the other local-solve precision form (after the timed steps)")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of 1 GiB three times (PMC byte-counter calibration) and exit")
@@ -215,7 +217,7 @@ def main():
     prec = DD_FP32 if args.form == "fp32" else DD_FP64
     torch.cuda.synchronize()
 
-    def step():
+    def step(prec=prec):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, levels=cfg.levels, local_prec=prec)
@@ -262,9 +264,24 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.form == "fp64" else "f64 (f32 local factors)",
+        "vs_baseline": None, "dtype": "f64" if args.form == "fp64" else "f64 (f32 local solves)",
         "data": "synthetic", "config": conf, "roofline": roofline(met, conf["workload"]),
     }
+    forms = {args.form: {"setup_plus_solve_s": value, "pcg_iterations": times[-1][2], "final_relres": times[-1][3]}}
+    if not args.no_compare_forms:
+        other = "fp32" if args.form == "fp64" else "fp64"
+        oprec = DD_FP32 if other == "fp32" else DD_FP64
+        del last
+        ot = []
+        for k in range(1 + args.steps):
+            pre, ts, tv, its, rr = step(oprec)
+            del pre
+            if k > 0:
+                ot.append((ts + tv, its, rr))
+            print(f"[bench] form {other} step {k}: {ts + tv:.3f}s its {its} relres {rr:.2e}", file=sys.stderr, flush=True)
+        forms[other] = {"setup_plus_solve_s": float(np.median([t[0] for t in ot])), "pcg_iterations": ot[-1][1],
+                        "final_relres": ot[-1][2]}
+    conf["forms"] = forms
     if not args.no_cpu_baseline:
         part_h = part.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(cfg, part_h, args.cpu_budget, sizes, times[-1][2])

@@ -79,6 +79,8 @@ struct Level {
 
     Arena L;  // local Cholesky factors (n_i x n_i, lower); released after setup
     Arena W;  // explicit inverses W_i = L_i^{-1} (lower), used by the apply
+    DBuf<float> W32;  // FP32 copy of W (FP32 local-solve form); W is released then
+    bool fp32 = false;
     std::vector<int> p;
     std::vector<int32_t> status;
     DBuf<int32_t> pcnt;
@@ -99,6 +101,7 @@ struct Level {
     // apply workspace
     DBuf<double> rloc, yloc, tpart, yC;
     Batch<TrmvItem> Tb;
+    Batch<TrmvItem32> Tb32;
 
     SubInfo sub() const {
         return SubInfo{N, counts.p, offE.p, offO.p, ext.p, part.p, ilocal.p, pcnt.p, offC.p, dZ.p};
@@ -685,6 +688,20 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         trsm_vb(Lb, Wb, false, s);
         DD_HIP(hipStreamSynchronize(s));
         Lv.L.release();
+        if (opt.local_prec == DD_FP32) {
+            // FP32 local-solve form: W rounded once; kept in FP64 if that overflows
+            Lv.W32.alloc(Lv.W.buf.n);
+            DBuf<int32_t> bad(1);
+            DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+            to_fp32(Lv.W.buf.p, Lv.W32.p, Lv.W.buf.n, bad.p, s);
+            const auto hb = to_host(bad.p, 1, s);
+            if (hb[0] == 0) {
+                Lv.fp32 = true;
+            } else {
+                Lv.W32.release();
+                info.fp32_fallbacks += 1;
+            }
+        }
     }
     info.phase_ms[PH_CHOL] += tm.lap();
 
@@ -774,10 +791,22 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Lv.yloc.alloc(std::max<int64_t>(1, Lv.hoffO[N]));
         Lv.tpart.alloc(std::max<int64_t>(1, poff[N]));
         Lv.Tb.h.clear();
-        for (int i = 0; i < N; ++i)
-            Lv.Tb.h.push_back(TrmvItem{Lv.W.ptr[i], ni[i], ni[i], Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i],
-                                       Lv.tpart.p + poff[i]});
-        Lv.Tb.sync(s);
+        Lv.Tb32.h.clear();
+        for (int i = 0; i < N; ++i) {
+            if (Lv.fp32)
+                Lv.Tb32.h.push_back(TrmvItem32{Lv.W32.p + (Lv.W.ptr[i] - Lv.W.buf.p), ni[i], ni[i],
+                                               Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i], Lv.tpart.p + poff[i]});
+            else
+                Lv.Tb.h.push_back(TrmvItem{Lv.W.ptr[i], ni[i], ni[i], Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i],
+                                           Lv.tpart.p + poff[i]});
+        }
+        if (Lv.fp32) {
+            Lv.Tb32.sync(s);
+            DD_HIP(hipStreamSynchronize(s));
+            Lv.W.release();  // the apply reads the FP32 copy only
+        } else {
+            Lv.Tb.sync(s);
+        }
     }
     info.phase_ms[PH_OTHER] += tm.lap();
 }
@@ -975,7 +1004,8 @@ static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
 static void apply_level(Handle& H, size_t m, const double* r, double* z, hipStream_t s) {
     Level& Lv = *H.lv[m];
     gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
-    trinv_apply_vb(Lv.Tb, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
+    if (Lv.fp32) trinv_apply_vb(Lv.Tb32, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
+    else trinv_apply_vb(Lv.Tb, s);
     scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
     if (Lv.nC > 0) {
         SubInfo S = Lv.sub();
@@ -1180,6 +1210,7 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     auto hd = std::make_unique<dd_handle_s>();
     Handle& H = hd->h;
     if (opt) {
+        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
         H.opt.local_prec = opt->local_prec;
         H.opt.select = opt->select;
         H.opt.nev_cap = opt->nev_cap;
@@ -1249,10 +1280,11 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
     int64_t bytes = 0;
     for (auto& l : H.lv)
-        bytes += l->W.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
+        bytes += l->W.buf.bytes() + l->W32.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
     *out = hd.release();
-    return (tau >= 1.0) ? DD_WARN_FULL_COARSE : DD_OK;
+    if (tau >= 1.0) return DD_WARN_FULL_COARSE;
+    return I.fp32_fallbacks > 0 ? DD_WARN_FP32_FALLBACK : DD_OK;
     DD_GUARD_END
 }
 

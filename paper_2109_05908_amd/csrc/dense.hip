@@ -63,14 +63,15 @@ void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
 // by a 512-column chunk; lane = row (coalesced 512 B column segments), wave w
 // takes columns w, w+4, ... of the chunk.  Chunks right of the block's
 // diagonal are skipped (W is zero there).
+template <class TW>
 struct OpTrmvN {
-    const TrmvItem* it;
+    const TrmvItemT<TW>* it;
     __device__ static int nrb(int n) { return (n + TRMV_RB - 1) / TRMV_RB; }
     __device__ static int ncc(int n) { return (n + TRMV_CC - 1) / TRMV_CC; }
     __device__ int tiles(int b) const { return nrb(it[b].n) * ncc(it[b].n); }
     __device__ void operator()(int b, int t) const {
         __shared__ double red[4][TRMV_RB];
-        const TrmvItem& I = it[b];
+        const TrmvItemT<TW>& I = it[b];
         const int n = I.n, nc = ncc(n);
         const int rb = t / nc, cc = t % nc;
         const int r0 = rb * TRMV_RB, c0 = cc * TRMV_CC;
@@ -78,30 +79,31 @@ struct OpTrmvN {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const int r = r0 + lane;
         const int cend = min(min(c0 + TRMV_CC, n), r0 + TRMV_RB);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        TW a0 = 0, a1 = 0, a2 = 0, a3 = 0;  // arithmetic in the factor's precision
         if (r < n) {
-            const double* Wr = I.W + r;
+            const TW* Wr = I.W + r;
             int j = c0 + w;
             for (; j + 12 < cend; j += 16) {
-                a0 += Wr[(int64_t)j * I.ld] * I.x[j];
-                a1 += Wr[(int64_t)(j + 4) * I.ld] * I.x[j + 4];
-                a2 += Wr[(int64_t)(j + 8) * I.ld] * I.x[j + 8];
-                a3 += Wr[(int64_t)(j + 12) * I.ld] * I.x[j + 12];
+                a0 += Wr[(int64_t)j * I.ld] * (TW)I.x[j];
+                a1 += Wr[(int64_t)(j + 4) * I.ld] * (TW)I.x[j + 4];
+                a2 += Wr[(int64_t)(j + 8) * I.ld] * (TW)I.x[j + 8];
+                a3 += Wr[(int64_t)(j + 12) * I.ld] * (TW)I.x[j + 12];
             }
-            for (; j < cend; j += 4) a0 += Wr[(int64_t)j * I.ld] * I.x[j];
+            for (; j < cend; j += 4) a0 += Wr[(int64_t)j * I.ld] * (TW)I.x[j];
         }
-        red[w][lane] = (a0 + a1) + (a2 + a3);
+        red[w][lane] = (double)((a0 + a1) + (a2 + a3));
         __syncthreads();
         if (w == 0 && r < n)
             I.part[(int64_t)cc * n + r] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     }
 };
 // y = sum of the partials of the chunks left of (or at) the row's block diagonal
+template <class TW>
 struct OpTrmvRed {
-    const TrmvItem* it;
+    const TrmvItemT<TW>* it;
     __device__ int tiles(int b) const { return (it[b].n + 255) / 256; }
     __device__ void operator()(int b, int t) const {
-        const TrmvItem& I = it[b];
+        const TrmvItemT<TW>& I = it[b];
         const int r = t * 256 + threadIdx.x;
         if (r >= I.n) return;
         const int last = ((r / TRMV_RB) * TRMV_RB + TRMV_RB - 1) / TRMV_CC;
@@ -112,52 +114,75 @@ struct OpTrmvRed {
 };
 // x_j = W(j:n, j)^T y(j:n): a tile is 16 columns, 4 per wave, each a
 // contiguous column segment read by the 64 lanes.
+template <class TW>
 struct OpTrmvT {
-    const TrmvItem* it;
+    const TrmvItemT<TW>* it;
     __device__ int tiles(int b) const { return (it[b].n + 15) / 16; }
     __device__ void operator()(int b, int t) const {
-        const TrmvItem& I = it[b];
+        const TrmvItemT<TW>& I = it[b];
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const int j0 = t * 16 + w * 4;
         const int n = I.n;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        TW accw[4] = {0, 0, 0, 0};
         if (j0 < n) {
             const int jn = min(4, n - j0);
             // rows >= j0 + q for column j0 + q; start at j0 (W is zero above the diagonal)
             for (int i = j0 + lane; i < n; i += 64) {
-                const double yi = I.y[i];
+                const TW yi = (TW)I.y[i];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (q < jn) acc[q] += I.W[i + (int64_t)(j0 + q) * I.ld] * yi;
+                    if (q < jn) accw[q] += I.W[i + (int64_t)(j0 + q) * I.ld] * yi;
             }
         }
+        double acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+        for (int q = 0; q < 4; ++q) acc[q] = wave_sum((double)accw[q]);
         if (lane == 0)
             for (int q = 0; q < 4; ++q)
                 if (j0 + q < n) I.x[j0 + q] = acc[q];
     }
 };
 
-void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s) {
+template <class TW>
+static void trmv_n_t(Batch<TrmvItemT<TW>>& t, hipStream_t s) {
     int64_t tn = 0, tr = 0;
     for (auto& x : t.h) {
         tn += (int64_t)ceil_div(x.n, TRMV_RB) * ceil_div(x.n, TRMV_CC);
         tr += ceil_div(x.n, 256);
     }
-    launch_tiles(OpTrmvN{t.d.p}, t.size(), tn, s, "trmv_n");
-    launch_tiles(OpTrmvRed{t.d.p}, t.size(), tr, s, "trmv_red");
+    launch_tiles(OpTrmvN<TW>{t.d.p}, t.size(), tn, s, "trmv_n");
+    launch_tiles(OpTrmvRed<TW>{t.d.p}, t.size(), tr, s, "trmv_red");
 }
-
-void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s) {
+template <class TW>
+static void trmv_t_t(Batch<TrmvItemT<TW>>& t, hipStream_t s) {
     int64_t tt = 0;
     for (auto& x : t.h) tt += ceil_div(x.n, 16);
-    launch_tiles(OpTrmvT{t.d.p}, t.size(), tt, s, "trmv_t");
+    launch_tiles(OpTrmvT<TW>{t.d.p}, t.size(), tt, s, "trmv_t");
 }
 
+void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s) { trmv_n_t(t, s); }
+void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s) { trmv_t_t(t, s); }
 void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s) {
-    trmv_n_vb(t, s);
-    trmv_t_vb(t, s);
+    trmv_n_t(t, s);
+    trmv_t_t(t, s);
+}
+void trinv_apply_vb(Batch<TrmvItem32>& t, hipStream_t s) {
+    trmv_n_t(t, s);
+    trmv_t_t(t, s);
+}
+
+__global__ void k_to_fp32(const double* src, float* dst, int64_t n, int* bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = (float)src[i];
+        dst[i] = v;
+        if (!isfinite(v)) *bad = 1;  // every writer stores the same value
+    }
+}
+void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_fp32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0, s, src, dst,
+                       n, bad);
+    launch_check("to_fp32");
 }
 
 // ===========================================================================

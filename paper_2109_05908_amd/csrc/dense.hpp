@@ -147,20 +147,26 @@ void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, do
 // Local solves with explicit triangular inverses: x := W^T (W x) for W lower
 // triangular n x n (column-major, exact zeros above the diagonal), one vector
 // per item.  y (n) and part (trmv_part_size(n)) are per-item workspaces.
-struct TrmvItem {
-    const double* W;
+template <class TW>
+struct TrmvItemT {
+    const TW* W;
     int ld;
     int n;
     double* x;
     double* y;
     double* part;
 };
+using TrmvItem = TrmvItemT<double>;
+using TrmvItem32 = TrmvItemT<float>;  // FP32 factor, FP32 arithmetic, FP64 vectors
 constexpr int TRMV_RB = 64;    // rows per tile of y = W x
 constexpr int TRMV_CC = 512;   // columns per partial sum of y = W x
 inline int64_t trmv_part_size(int n) { return (int64_t)((n + TRMV_CC - 1) / TRMV_CC) * n; }
 void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s);
+void trinv_apply_vb(Batch<TrmvItem32>& t, hipStream_t s);
 void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s);  // y := W x   (uses part)
 void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s);  // x := W^T y
+// FP64 -> FP32 copy of n elements; *bad is set to 1 if a rounded value is not finite
+void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s);
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)

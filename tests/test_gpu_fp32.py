@@ -1,0 +1,65 @@
+"""FP32 local-solve form: the explicit local inverses W_i = L_i^{-1} are rounded
+to FP32 and the two triangular matrix-vector products of every local solve
+run in FP32, while PCG (dots, residual recurrence), the coarse factorization
+and solve and the whole splitting / eigen setup stay in FP64.  The outer
+solve must still reach FP64 accuracy: the same x as the FP64 oracle to 1e-10
+relative at rtol 1e-13.  The error of the FP32 apply against the FP64 apply
+is logged per case (it scales with eps_32 * cond(A_ii)).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2109_05908_amd import DD_FP32, DD_FP64, DeviceCSR, Preconditioner  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(name):
+    if name == "c1":
+        cfg = W.config_c1()
+        return cfg, cfg.part
+    cfg = W.config_small3d(16, 16)
+    return cfg, O.ggg_partition(cfg.A, cfg.N, cfg.ggg_seed)
+
+
+@pytest.mark.parametrize("name", ["c1", "small3d"])
+def test_fp32_local_solves_reach_fp64_accuracy(name):
+    cfg, part = _case(name)
+    log(f"[fp32] {name}: n={cfg.A.n} N={cfg.N}")
+    dA = DeviceCSR.from_workload(cfg.A)
+    p64 = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, local_prec=DD_FP64)
+    p32 = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, local_prec=DD_FP32)
+    assert p32.info()["fp32_fallbacks"] == 0
+    assert p32.info()["n_C"] == p64.info()["n_C"]
+    r = torch.as_tensor(W.rhs(cfg.A.n, 3), device="cuda")
+    z64 = p64.apply(r).cpu().numpy()
+    z32 = p32.apply(r).cpu().numpy()
+    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    log(f"[fp32] {name}: FP32 vs FP64 apply, relative difference {rel:.3e}")
+    assert np.isfinite(rel) and rel < 1e-2
+    b = W.rhs(cfg.A.n, 0)
+    ora = O.build(cfg.A, part, cfg.N, cfg.overlap, cfg.tau)
+    xo, itso, _ = O.pcg(cfg.A, b, ora.apply, rtol=1e-13, maxit=500)
+    x, its, rr, code = p32.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-13, maxit=500)
+    xg = x.cpu().numpy()
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    log(f"[fp32] {name}: PCG its fp32-local {its[0]} oracle {itso}, relres {rr[0]:.2e}, x error vs oracle {err:.2e}")
+    assert code == 0 and rr[0] <= 1e-13
+    assert err <= 1e-10
+    assert its[0] <= 2 * itso + 5
+    x8, its8, rr8, code8 = p32.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-8)
+    assert code8 == 0 and rr8[0] <= 1e-8
