@@ -281,7 +281,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         copy_vb(Ysrc, Rb, false, 1.0, s);
         zero_lower_vb(Rb, s);
         copy_vb(Rb, Xb, true, 1.0, s);  // Xt = R^T (lower)
-        // alpha = ||R||_F, lower bound of sigma_min via ||R^{-1}||_F
+        // alpha >= ||R||_2 and l0 <= sigma_min(R) / alpha from norm bounds of R and R^{-1}
         DBuf<double> dnorm(N), dnorm2(N);
         frob_vb(Rb, dnorm.p, s);
         std::vector<double*> wfirst(Wk.ptr);
@@ -291,6 +291,33 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         frob_vb(Ib, dnorm2.p, s);
         auto alpha = to_host(dnorm.p, N, s);
         auto rinv = to_host(dnorm2.p, N, s);
+        // tighter guaranteed bounds: ||M||_2 <= sqrt(||M||_1 ||M||_inf) for M = R and R^{-1}
+        // (a larger l0 saves QR-based iterations; it must stay <= sigma_min / alpha)
+        {
+            Arena cs, rs;
+            std::vector<int64_t> sz(ni.begin(), ni.end());
+            cs.alloc(sz);
+            rs.alloc(sz);
+            DBuf<double*> dcs(N), drs(N);
+            h2d(dcs.p, cs.ptr.data(), N, s);
+            h2d(drs.p, rs.ptr.data(), N, s);
+            auto norm_1inf = [&](Batch<DMat>& M, std::vector<double>& out) {
+                abs_sums_vb(M, dcs.p, drs.p, s);
+                const auto hc = to_host(cs.buf.p, cs.buf.n, s);
+                const auto hr = to_host(rs.buf.p, rs.buf.n, s);
+                for (int i = 0; i < N; ++i) {
+                    const int64_t o = cs.ptr[i] - cs.buf.p;
+                    double m1 = 0.0, mi = 0.0;
+                    for (int k = 0; k < ni[i]; ++k) {
+                        m1 = std::max(m1, hc[o + k]);
+                        mi = std::max(mi, hr[o + k]);
+                    }
+                    out[i] = std::min(out[i], std::sqrt(m1 * mi));
+                }
+            };
+            norm_1inf(Rb, alpha);
+            norm_1inf(Ib, rinv);
+        }
         std::vector<double> ell(N), inv_alpha(N), zero(N, 0.0);
         for (int i = 0; i < N; ++i) {
             DD_CHECK(alpha[i] > 0 && std::isfinite(rinv[i]), DD_ERR_NOT_SPD, "singular local block row X_i");

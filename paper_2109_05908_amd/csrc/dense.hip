@@ -171,6 +171,48 @@ void trinv_apply_vb(Batch<TrmvItem32>& t, hipStream_t s) {
     trmv_t_t(t, s);
 }
 
+// column sums: a wave per column (contiguous); row sums: a thread per row,
+// columns in order (coalesced across the rows of a 256-row tile)
+struct OpAbsCol {
+    const DMat* A;
+    double* const* out;
+    __device__ int tiles(int b) const { return (A[b].n + 15) / 16; }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int q = 0; q < 4; ++q) {
+            const int c = t * 16 + w * 4 + q;
+            if (c >= M.n) break;
+            double s = 0.0;
+            for (int r = lane; r < M.m; r += 64) s += fabs(M.p[r + (int64_t)c * M.ld]);
+            s = wave_sum(s);
+            if (lane == 0) out[b][c] = s;
+        }
+    }
+};
+struct OpAbsRow {
+    const DMat* A;
+    double* const* out;
+    __device__ int tiles(int b) const { return (A[b].m + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const DMat M = A[b];
+        const int r = t * 256 + threadIdx.x;
+        if (r >= M.m) return;
+        double s = 0.0;
+        for (int c = 0; c < M.n; ++c) s += fabs(M.p[r + (int64_t)c * M.ld]);
+        out[b][r] = s;
+    }
+};
+void abs_sums_vb(Batch<DMat>& A, double* const* colsum, double* const* rowsum, hipStream_t s) {
+    int64_t tc = 0, tr = 0;
+    for (auto& x : A.h) {
+        tc += ceil_div(x.n, 16);
+        tr += ceil_div(x.m, 256);
+    }
+    launch_tiles(OpAbsCol{A.d.p, colsum}, A.size(), tc, s, "abs_col");
+    launch_tiles(OpAbsRow{A.d.p, rowsum}, A.size(), tr, s, "abs_row");
+}
+
 __global__ void k_to_fp32(const double* src, float* dst, int64_t n, int* bad) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float v = (float)src[i];

@@ -165,6 +165,9 @@ void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s);
 void trinv_apply_vb(Batch<TrmvItem32>& t, hipStream_t s);
 void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s);  // y := W x   (uses part)
 void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s);  // x := W^T y
+// Absolute column sums colsum[b][j] = sum_i |A_ij| and row sums rowsum[b][i]
+// (for ||A||_1, ||A||_inf, hence the bound ||A||_2 <= sqrt(||A||_1 ||A||_inf))
+void abs_sums_vb(Batch<DMat>& A, double* const* colsum, double* const* rowsum, hipStream_t s);
 // FP64 -> FP32 copy of n elements; *bad is set to 1 if a rounded value is not finite
 void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s);
 
