@@ -351,7 +351,7 @@ int BlockChol::factor(hipStream_t s) {
         DD_HIP(hipMemsetAsync(li.p, 0, pn.size() * sizeof(int32_t), s));
         potrf_vb(pn, li.p, s);
         set_identity_vb(iv, 1.0, s);
-        trsm_vb(dg, iv, false, s);  // L_KK^{-1}
+        trsm_vb(dg, iv, false, s, true);  // L_KK^{-1}
         std::vector<int32_t> hl(pn.size());
         DD_HIP(hipMemcpyAsync(hl.data(), li.p, pn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DD_HIP(hipStreamSynchronize(s));

@@ -287,7 +287,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         std::vector<double*> wfirst(Wk.ptr);
         Batch<DMat> Ib = mats(wfirst, ni, ni, ni, s);
         set_identity_vb(Ib, 1.0, s);
-        trsm_vb(Xb, Ib, false, s);  // R^{-T}
+        trsm_vb(Xb, Ib, false, s, true);  // R^{-T}
         frob_vb(Ib, dnorm2.p, s);
         auto alpha = to_host(dnorm.p, N, s);
         auto rinv = to_host(dnorm2.p, N, s);
@@ -420,7 +420,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                     g.h.push_back(GemmItem{Xt.ptr[i], ni[i], Xt.ptr[i], ni[i], zp[i], ni[i], ni[i], ni[i], ni[i], cc[i], 1.0});
                 }
                 g.sync(s);
-                gemm_vb(g, false, true, s);
+                syrk_vb(g, s);  // lower triangle of Zc: all potrf reads
                 DBuf<int32_t> dinfo(Zb.size());
                 DD_HIP(hipMemsetAsync(dinfo.p, 0, Zb.size() * sizeof(int32_t), s));
                 potrf_vb(Zb, dinfo.p, s);
@@ -447,7 +447,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         for (int i = 0; i < N; ++i)
             g.h.push_back(GemmItem{Rm.ptr[i], ni[i], Xt.ptr[i], ni[i], Wk.ptr[i], ni[i], ni[i], ni[i], ni[i], 1.0, 0.0});
         g.sync(s);
-        gemm_vb(g, false, false, s);
+        gemm_upper_a_vb(g, s);  // R is upper triangular
         Batch<DMat> Hb = mats(Wk.ptr, ni, ni, ni, s);
         symmetrize_vb(Hb, s);
         DD_HIP(hipStreamSynchronize(s));
@@ -712,7 +712,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Batch<DMat> Wb = mats(Lv.W.ptr, ni, ni, ni, s);
         set_identity_vb(Wb, 1.0, s);
         Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s);
-        trsm_vb(Lb, Wb, false, s);
+        trsm_vb(Lb, Wb, false, s, true);
         DD_HIP(hipStreamSynchronize(s));
         Lv.L.release();
         if (opt.local_prec == DD_FP32) {

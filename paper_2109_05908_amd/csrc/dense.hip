@@ -55,6 +55,78 @@ void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
     else launch_tiles(OpGemm<false, false>{g.d.p}, g.size(), total, s, "gemm_nn", 4096, work);
 }
 
+// lower-triangle tiles (ti >= tj) of C = alpha A A^T + beta C
+struct OpSyrk {
+    const GemmItem* g;
+    __device__ int tiles(int b) const {
+        const int T = (g[b].M + 63) / 64;
+        return T * (T + 1) / 2;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const GemmItem& G = g[b];
+        int tj = 0, r = t;
+        const int T = (G.M + 63) / 64;
+        while (r >= T - tj) {
+            r -= T - tj;
+            ++tj;
+        }
+        const int ti = tj + r;
+        const int i0 = ti * 64, j0 = tj * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<false, true>(G.A, G.lda, G.A, G.lda, G.M, G.M, G.K, i0, j0, sm, acc);
+        double* C = G.C;
+        const int ldc = G.ldc, M = G.M;
+        const double al = G.alpha, be = G.beta;
+        acc_foreach(acc, [&](int rr, int c, double v) {
+            const int gi = i0 + rr, gj = j0 + c;
+            if (gi < M && gj < M) {
+                double* p = C + gi + (int64_t)gj * ldc;
+                *p = (be == 0.0) ? al * v : al * v + be * *p;
+            }
+        });
+    }
+};
+void syrk_vb(Batch<GemmItem>& g, hipStream_t s) {
+    int64_t total = 0;
+    for (auto& x : g.h) {
+        const int64_t T = ceil_div(x.M, 64);
+        total += T * (T + 1) / 2;
+    }
+    launch_tiles(OpSyrk{g.d.p}, g.size(), total, s, "syrk");
+}
+
+// C = alpha A B + beta C, A upper triangular: row tile i0 only needs k >= i0
+struct OpGemmUpperA {
+    const GemmItem* g;
+    __device__ int tiles(int b) const { return ((g[b].M + 63) / 64) * ((g[b].N + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const GemmItem& G = g[b];
+        const int tm = (G.M + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<false, false>(G.A + (int64_t)i0 * G.lda, G.lda, G.B + i0, G.ldb, G.M, G.N, G.K - i0, i0, j0, sm, acc);
+        double* C = G.C;
+        const int ldc = G.ldc, M = G.M, N = G.N;
+        const double al = G.alpha, be = G.beta;
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = i0 + r, gj = j0 + c;
+            if (gi < M && gj < N) {
+                double* p = C + gi + (int64_t)gj * ldc;
+                *p = (be == 0.0) ? al * v : al * v + be * *p;
+            }
+        });
+    }
+};
+void gemm_upper_a_vb(Batch<GemmItem>& g, hipStream_t s) {
+    int64_t total = 0;
+    for (auto& x : g.h) total += (int64_t)ceil_div(x.M, 64) * ceil_div(x.N, 64);
+    launch_tiles(OpGemmUpperA{g.d.p}, g.size(), total, s, "gemm_upper_a");
+}
+
 // ===========================================================================
 // x := W^T (W x), W lower triangular (explicit inverse of a Cholesky factor).
 // HBM-bound: each pass streams the lower triangle of W once.
@@ -439,8 +511,9 @@ struct OpTrsmDiag {
     const DMat* L;
     const DMat* B;
     double* const* D;
-    int kb;  // first row of the diagonal block
-    __device__ int tiles(int b) const { return (L[b].n > kb) ? (B[b].n + 63) / 64 : 0; }
+    int kb;   // first row of the diagonal block
+    int ncap; // column tiles that can be nonzero (lower-triangular right-hand side), or a large value
+    __device__ int tiles(int b) const { return (L[b].n > kb) ? min((B[b].n + 63) / 64, ncap) : 0; }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmemC sm;
         const DMat Lm = L[b], Bm = B[b];
@@ -467,12 +540,13 @@ struct OpTrsmGemm {
     const DMat* L;
     const DMat* B;
     int r0, mid, r1;
+    int ncap;  // column tiles that can be nonzero (lower-triangular right-hand side), or a large value
     __device__ int tiles(int b) const {
         const int n = L[b].n;
         if (n <= mid) return 0;
         const int e = min(n, r1);
         const int M = TRANS ? mid - r0 : e - mid;
-        return ((M + 63) / 64) * ((B[b].n + 63) / 64);
+        return ((M + 63) / 64) * min((B[b].n + 63) / 64, ncap);
     }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmem sm;
@@ -501,37 +575,44 @@ struct OpTrsmGemm {
     }
 };
 
-static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool trans, int r0, int r1, hipStream_t s) {
+// lower_rhs (forward solves only): B is lower triangular on entry (e.g. the
+// identity), so column j stays zero in rows < j and column tiles right of the
+// rows being solved are skipped.
+static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool trans, bool lower_rhs, int r0, int r1,
+                     hipStream_t s) {
+    constexpr int kAll = 1 << 30;
     if (r1 - r0 <= 64) {
+        const int cap = lower_rhs ? r0 / 64 + 1 : kAll;
         int64_t nd = 0;
         for (int b = 0; b < L.size(); ++b)
-            if (L.h[b].n > r0) nd += ceil_div(B.h[b].n, 64);
+            if (L.h[b].n > r0) nd += std::min(ceil_div(B.h[b].n, 64), cap);
         if (!nd) return;
-        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, D, r0}, L.size(), nd, s, "trsm_diag");
-        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, D, r0}, L.size(), nd, s, "trsmT_diag");
+        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, "trsm_diag");
+        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, "trsmT_diag");
         return;
     }
     const int mid = r0 + ceil_div(r1 - r0, 128) * 64;
+    const int cap = lower_rhs ? mid / 64 : kAll;
     int64_t nu = 0;
     for (int b = 0; b < L.size(); ++b) {
         const int n = L.h[b].n;
         if (n <= mid) continue;
         const int e = std::min(n, r1);
         const int M = trans ? mid - r0 : e - mid;
-        nu += (int64_t)ceil_div(M, 64) * ceil_div(B.h[b].n, 64);
+        nu += (int64_t)ceil_div(M, 64) * std::min(ceil_div(B.h[b].n, 64), cap);
     }
     if (!trans) {
-        trsm_rec(L, B, D, trans, r0, mid, s);
-        if (nu) launch_tiles(OpTrsmGemm<false>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsm_gemm");
-        trsm_rec(L, B, D, trans, mid, r1, s);
+        trsm_rec(L, B, D, trans, lower_rhs, r0, mid, s);
+        if (nu) launch_tiles(OpTrsmGemm<false>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, "trsm_gemm");
+        trsm_rec(L, B, D, trans, lower_rhs, mid, r1, s);
     } else {
-        trsm_rec(L, B, D, trans, mid, r1, s);
-        if (nu) launch_tiles(OpTrsmGemm<true>{L.d.p, B.d.p, r0, mid, r1}, L.size(), nu, s, "trsmT_gemm");
-        trsm_rec(L, B, D, trans, r0, mid, s);
+        trsm_rec(L, B, D, trans, lower_rhs, mid, r1, s);
+        if (nu) launch_tiles(OpTrsmGemm<true>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, "trsmT_gemm");
+        trsm_rec(L, B, D, trans, lower_rhs, r0, mid, s);
     }
 }
 
-void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
+void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool lower_rhs) {
     int nmax = 0;
     for (auto& x : L.h) nmax = std::max(nmax, x.n);
     if (nmax == 0) return;
@@ -549,7 +630,7 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s) {
     DBuf<double*> dp(std::max<size_t>(1, hp.size()));
     h2d(dp.p, hp.data(), hp.size(), s);
     launch_tiles(OpTrtri64{L.d.p, dp.p}, L.size(), nblk, s, "trtri64");
-    trsm_rec(L, B, dp.p, trans, 0, ceil_div(nmax, 64) * 64, s);
+    trsm_rec(L, B, dp.p, trans, lower_rhs && !trans, 0, ceil_div(nmax, 64) * 64, s);
     DD_HIP(hipStreamSynchronize(s));  // dbuf, dp are freed on return
 }
 

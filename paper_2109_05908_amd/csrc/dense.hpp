@@ -78,6 +78,10 @@ struct GemmItem {
 };
 
 void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s);
+// C := alpha A A^T + beta C, lower-triangle tiles only (A = M x K, B unused)
+void syrk_vb(Batch<GemmItem>& g, hipStream_t s);
+// C := alpha A B + beta C with A upper triangular (M = K, zeros stored below)
+void gemm_upper_a_vb(Batch<GemmItem>& g, hipStream_t s);
 
 // In-place lower Cholesky A = L L^T (upper triangle untouched).  A may be a
 // tall panel (m >= n): the rows below the leading n x n block are solved
@@ -87,7 +91,7 @@ void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s);
 
 // B := L^{-1} B (trans = false) or L^{-T} B (trans = true), L lower (only the
 // lower triangle of L is read).  Item b: L[b] (n x n), B[b] (n x nrhs).
-void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s);
+void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool lower_rhs = false);
 
 // Householder QR in place (first nfac columns factored, all columns updated).
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
