@@ -1,0 +1,169 @@
+"""Degenerate and edge cases of the method on the GPU, against the oracle and
+closed forms, through the C-ABI:
+
+* one subdomain: Omega = everything, Gamma = Delta = empty, all lambda ~ 1 so
+  nothing is kept for tau < 1, M^{-1} = A^{-1} and PCG stops after one step;
+* tau below every mu: no coarse space, the one-level additive Schwarz method;
+* tau >= 1 with the Boolean partition of unity: every mode is kept (lambda >= 1),
+  the coarse space is the whole space and dd_setup warns;
+* a graph of two disconnected components: the seeded graph growing hands the
+  unreached component to the smallest part;
+* the threshold-with-cap selection (nev smallest mu below tau);
+* invalid arguments are rejected before any kernel runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2109_05908_amd import (  # noqa: E402
+    DD_SEL_THRESHOLD_CAP, DDError, DeviceCSR, Preconditioner, partition_ggg,
+)
+
+MU_FLOOR = 1e-6
+MU_RTOL = 1e-4
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(A):
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    return DeviceCSR(A.shape[0], A.indptr, A.indices, A.data)
+
+
+def test_single_subdomain_is_exact_solve():
+    A = W.poisson2d(32).to_scipy()
+    n = A.shape[0]
+    part = np.zeros(n, dtype=np.int32)
+    log(f"[edge] N=1: n={n}")
+    pre = Preconditioner(dev(A), part, 1, 1, 0.1)
+    I, G, D = pre.sets(0)
+    assert I.size == n and G.size == 0 and D.size == 0
+    assert pre.info()["n_C"] == 0
+    r = W.rhs(n, 5)
+    z = pre.apply(torch.as_tensor(r, device="cuda")).cpu().numpy()
+    zx = spla.spsolve(A.tocsc(), r)
+    assert np.linalg.norm(z - zx) <= 1e-10 * np.linalg.norm(zx)
+    x, its, rr, code = pre.pcg(torch.as_tensor(r, device="cuda"), rtol=1e-10)
+    assert code == 0 and its[0] == 1 and rr[0] <= 1e-10
+
+
+def test_tiny_tau_is_one_level_asm():
+    cfg = W.config_c1()
+    tau = 1e-30
+    pre = Preconditioner(DeviceCSR.from_workload(cfg.A), cfg.part, cfg.N, cfg.overlap, tau)
+    assert pre.info()["n_C"] == 0
+    ora = O.build(cfg.A, cfg.part, cfg.N, cfg.overlap, tau)
+    assert ora.nC == 0
+    b = W.rhs(cfg.A.n, 0)
+    x, its, rr, code = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-8)
+    _, itso, _ = O.pcg(cfg.A, b, ora.apply, rtol=1e-8)
+    log(f"[edge] one-level ASM: its gpu {its[0]} oracle {itso}")
+    assert code == 0 and abs(its[0] - itso) <= 1
+
+
+def test_tau_at_least_one_keeps_everything():
+    A = W.random_spd(300, 5, seed=7, positive_offdiag=True)
+    N = 4
+    part = O.ggg_partition(A, N, 0)
+    pre = Preconditioner(DeviceCSR.from_workload(A), part, N, 1, 1.5)
+    assert pre.setup_status == 2  # DD_WARN_FULL_COARSE
+    assert pre.info()["n_C"] == A.n
+    ora = O.build(A, part, N, 1, 1.5)
+    assert ora.nC == A.n
+    b = W.rhs(A.n, 1)
+    # Z spans R^n, so Z E^{-1} Z^T = A^{-1} and M^{-1} A = I + sum_i R_i^T A_ii^{-1} R_i A:
+    # eigenvalues in [1, k_c + 2], iteration counts as the oracle's
+    x, its, rr, code = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-12)
+    _, itso, _ = O.pcg(A, b, ora.apply, rtol=1e-12)
+    xo = spla.spsolve(A.to_scipy().tocsc(), b)
+    log(f"[edge] full coarse space: its gpu {its[0]} oracle {itso}")
+    assert code == 0 and abs(its[0] - itso) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_disconnected_graph():
+    A1 = W.diffusion3d(8, seed=2).to_scipy()
+    A2 = W.diffusion3d(6, seed=3).to_scipy()
+    A = sp.block_diag([A1, A2]).tocsr()
+    N = 5
+    d = dev(A)
+    for seed in range(4):
+        got = partition_ggg(d, N, seed).cpu().numpy()
+        np.testing.assert_array_equal(got, O.ggg_partition(A, N, seed))
+    part = O.ggg_partition(A, N, 1)
+    counts = np.bincount(part, minlength=N)
+    assert counts.min() > 0
+    pre = Preconditioner(d, part, N, 1, 0.05)
+    ora = O.build(A, part, N, 1, 0.05)
+    assert pre.info()["n_C"] == ora.nC
+    b = W.rhs(A.shape[0], 2)
+    x, its, rr, code = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-13, maxit=500)
+    xo, itso, _ = O.pcg(A, b, ora.apply, rtol=1e-13, maxit=500)
+    log(f"[edge] disconnected: part sizes {counts.tolist()}, its gpu {its[0]} oracle {itso}")
+    assert code == 0 and abs(its[0] - itso) <= 1
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_nev_cap_selection():
+    cfg = W.config_small3d(16, 16)
+    part = O.ggg_partition(cfg.A, cfg.N, cfg.ggg_seed)
+    nev = 8
+    pre = Preconditioner(DeviceCSR.from_workload(cfg.A), part, cfg.N, cfg.overlap, cfg.tau,
+                         select=DD_SEL_THRESHOLD_CAP, nev_cap=nev)
+    ora = O.build(cfg.A, part, cfg.N, cfg.overlap, cfg.tau, nev=nev)
+    sizes = pre.sizes()
+    worst = 0.0
+    for i, L in enumerate(ora.locals):
+        assert sizes[i, 3] == L.mu_keep.size <= nev
+        mu_g = pre.eigs(i)
+        big = L.mu_keep >= MU_FLOOR
+        if big.any():
+            worst = max(worst, float(np.max(np.abs(mu_g[big] - L.mu_keep[big]) / L.mu_keep[big])))
+    assert worst <= MU_RTOL
+    b = W.rhs(cfg.A.n, 0)
+    x, its, rr, code = pre.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-13, maxit=1000)
+    xo, itso, _ = O.pcg(cfg.A, b, ora.apply, rtol=1e-13, maxit=1000)
+    log(f"[edge] nev cap {nev}: n_C {int(sizes[:, 3].sum())}, its gpu {its[0]} oracle {itso}")
+    # which vectors of the near-kernel cluster the cap keeps is not fixed by the
+    # method, so iteration counts may differ a little; the solution may not
+    assert code == 0 and abs(its[0] - itso) <= max(3, itso // 10)
+    assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_invalid_arguments_rejected():
+    cfg = W.config_c1()
+    d = DeviceCSR.from_workload(cfg.A)
+    bad = [
+        dict(N=cfg.N, overlap=0, tau=0.1, levels=2),
+        dict(N=cfg.N, overlap=1, tau=0.0, levels=2),
+        dict(N=cfg.N, overlap=1, tau=-1.0, levels=2),
+        dict(N=cfg.N, overlap=1, tau=0.1, levels=1),
+        dict(N=cfg.N, overlap=1, tau=0.1, levels=9),
+        dict(N=0, overlap=1, tau=0.1, levels=2),
+    ]
+    for kw in bad:
+        with pytest.raises(DDError) as e:
+            Preconditioner(d, cfg.part, kw["N"], kw["overlap"], kw["tau"], levels=kw["levels"])
+        assert e.value.code == -1, kw
+    nanval = cfg.A.val.copy()
+    nanval[7] = np.nan
+    dn = DeviceCSR(cfg.A.n, cfg.A.rowptr, cfg.A.colind, nanval)
+    with pytest.raises(DDError) as e:
+        Preconditioner(dn, cfg.part, cfg.N, 1, 0.1)
+    assert e.value.code == -4
