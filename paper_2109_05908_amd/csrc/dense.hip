@@ -835,10 +835,15 @@ __device__ __forceinline__ BlkRange blk_range(const ORItem& it, int c0, int cap,
     return r;
 }
 
+// P partial sums (nks slabs) and W use leading dimension QR_PAIR: a 256-column
+// pair of reflector blocks is applied to C in one pass (see apply_pair).
+constexpr int PLD = QR_PAIR;
+
 struct BlkOp {
     const ORItem* o;
-    double* const* Wp;  // per item partial sums: nks x 128 x max(128, C.n)
+    double* const* Wp;  // per item partial sums: nks x PLD x max(PLD, C.n)
     int c0, cap, mode, oend;
+    int half = 0;       // OpBlkW / OpBlkCorr: which 128-block of a pair
     __device__ bool active(int b, BlkRange& r) const {
         if (o[b].V.n <= c0 || o[b].V.m <= c0) return false;
         r = blk_range(o[b], c0, cap, mode, oend);
@@ -846,7 +851,7 @@ struct BlkOp {
     }
     __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, c0, cap) - c0; }
     __device__ int nks(int b) const { return (mrows(b) + QR_KS - 1) / QR_KS; }
-    __device__ int pstride(int b) const { return QR_OB * max(QR_OB, o[b].C.n); }
+    __device__ int pstride(int b) const { return PLD * max(PLD, o[b].C.n); }
 };
 
 // P partials: tile = (row tile of the block 64, column tile 64, row chunk)
@@ -876,17 +881,20 @@ struct OpBlkP : BlkOp {
         double* P = Wp[b] + (int64_t)ks * pstride(b);
         acc_foreach(acc, [&](int r, int c, double v) {
             const int gr = tr * 64 + r, gc = tc * 64 + c;
-            if (gr < R.wb && gc < nc) P[gr + (int64_t)gc * QR_OB] = v;
+            if (gr < R.wb && gc < nc) P[gr + (int64_t)gc * PLD] = v;
         });
     }
 };
 
-// W from the summed partials, per 64-column tile
+// W from the summed partials for one 128-block (half of the range), per
+// 64-column tile: W_q = T_q^T (P_q - sum_j G_qj W_j) over its 32-column panels
+// (T_q (P_q - ...) for Q C)
 template <bool TRANS>
 struct OpBlkW : BlkOp {
     __device__ int tiles(int b) const {
         BlkRange r;
         if (!active(b, r)) return 0;
+        if (r.wb - QR_OB * half <= 0) return 0;
         return (r.cc1 - r.cc0 + 63) / 64;
     }
     __device__ void operator()(int b, int t) const {
@@ -900,20 +908,22 @@ struct OpBlkW : BlkOp {
         const int j0 = t * 64;
         const int nks_ = nks(b);
         const int ps = pstride(b);
-        const int nsub = (R.wb + QR_NB - 1) / QR_NB;
+        const int roff = QR_OB * half, c0h = c0 + roff;
+        const int wbh = min(QR_OB, R.wb - roff);
+        const int nsub = (wbh + QR_NB - 1) / QR_NB;
         for (int e = threadIdx.x; e < QR_OB * 64; e += blockDim.x) {
             const int r = e & (QR_OB - 1), c = e >> 7;
             double sum = 0.0;
-            if (r < R.wb && j0 + c < nc)
-                for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + r + (int64_t)(j0 + c) * QR_OB];
+            if (r < wbh && j0 + c < nc)
+                for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + (roff + r) + (int64_t)(j0 + c) * PLD];
             P[r][c] = sum;
         }
         for (int q = 0; q < nsub; ++q) {
-            const double* Tg = it.T + (int64_t)((c0 / QR_NB) + q) * QR_NB * QR_NB;
+            const double* Tg = it.T + (int64_t)((c0h / QR_NB) + q) * QR_NB * QR_NB;
             for (int e = threadIdx.x; e < 1024; e += blockDim.x) Ts[q][e & 31][e >> 5] = Tg[e];
         }
         if (nsub > 1) {
-            const double* Gg = it.G + (int64_t)(c0 / QR_OB) * QR_OB * QR_OB;
+            const double* Gg = it.G + (int64_t)(c0h / QR_OB) * QR_OB * QR_OB;
             for (int q = 1; q < nsub; ++q)
                 for (int j = 0; j < q; ++j)
                     for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
@@ -924,7 +934,7 @@ struct OpBlkW : BlkOp {
         __syncthreads();
         for (int step = 0; step < nsub; ++step) {
             const int q = TRANS ? step : nsub - 1 - step;
-            const int wq = min(QR_NB, R.wb - 32 * q);
+            const int wq = min(QR_NB, wbh - 32 * q);
             double u[8];
             // U_q = P_q - sum over the panels already turned into W of G_qj W_j
 #pragma unroll
@@ -972,8 +982,43 @@ struct OpBlkW : BlkOp {
         }
         for (int e = threadIdx.x; e < QR_OB * 64; e += blockDim.x) {
             const int r = e & (QR_OB - 1), c = e >> 7;
-            if (r < R.wb && j0 + c < nc) it.W[r + (int64_t)(j0 + c) * QR_OB] = P[r][c];
+            if (r < wbh && j0 + c < nc) it.W[(roff + r) + (int64_t)(j0 + c) * PLD] = P[r][c];
         }
+    }
+};
+
+// Coupling of the two blocks of a pair before the second W: with the cross
+// Gram Gx = V_b^T V_a, C <- Q^T C needs P_b -= Gx W_a (W_a first), and
+// C <- Q C needs P_a -= Gx^T W_b (W_b first).  Applied to partial slab 0.
+template <bool TRANS>
+struct OpBlkCorr : BlkOp {
+    __device__ int tiles(int b) const {
+        BlkRange r;
+        if (!active(b, r) || r.wb <= QR_OB) return 0;
+        const int wt = TRANS ? r.wb - QR_OB : QR_OB;
+        return ((wt + 63) / 64) * ((r.cc1 - r.cc0 + 63) / 64);
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        BlkRange R;
+        active(b, R);
+        const ORItem& it = o[b];
+        const int nc = R.cc1 - R.cc0;
+        const int wa = QR_OB, wbb = R.wb - QR_OB;
+        const int wt = TRANS ? wbb : wa, ws = TRANS ? wa : wbb;    // target / source widths
+        const int rt = TRANS ? QR_OB : 0, rs = TRANS ? 0 : QR_OB;  // their row offsets in P and W
+        const int tm = (wt + 63) / 64;
+        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        const int nblk = (it.V.n + QR_OB - 1) / QR_OB;
+        const double* Gx = it.G + (int64_t)(nblk + c0 / QR_PAIR) * QR_OB * QR_OB;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<!TRANS, false>(Gx, QR_OB, it.W + rs, PLD, wt, nc, ws, i0, j0, sm, acc);
+        double* P0 = Wp[b];
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gi = i0 + r, gj = j0 + c;
+            if (gi < wt && gj < nc) P0[(rt + gi) + (int64_t)gj * PLD] -= v;
+        });
     }
 };
 
@@ -1006,7 +1051,7 @@ struct OpBlkUpd : BlkOp {
         const int ld = it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, QR_OB, mp, nc, R.wb, i0, j0, sm.t, acc);
+        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, PLD, mp, nc, R.wb, i0, j0, sm.t, acc);
         acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
@@ -1076,7 +1121,7 @@ struct QrScratch {
         std::vector<int64_t> off(items.size() + 1, 0);
         for (size_t i = 0; i < items.size(); ++i) {
             const int nks = ceil_div(std::max(1, items[i].V.m), QR_KS);
-            off[i + 1] = off[i] + (int64_t)QR_OB * std::max(QR_OB, items[i].C.n) * nks;
+            off[i + 1] = off[i] + (int64_t)PLD * std::max(PLD, items[i].C.n) * nks;
         }
         buf.alloc(off.back());
         std::vector<double*> hp(items.size());
@@ -1149,6 +1194,130 @@ static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
     launch_tiles(OpGramR{base}, o.size(), nr, s, "qr_gram_r");
 }
 
+// Cross Gram Gx = V_b^T V_a of the pair (a at c0, b at c0 + 128): both vanish
+// above row c0 + 128 except V_a, whose rows there are all below its diagonal.
+// Partials over row chunks, then an ordered sum (rows of Gx past V_b's width are 0).
+struct OpGramXP : BlkOp {
+    __device__ int wbb(int b) const { return min(QR_OB, o[b].V.n - c0 - QR_OB); }
+    __device__ int mx(int b) const { return qr_rows(o[b].V.m, o[b].zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB); }
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= c0 + QR_OB || mx(b) <= 0) return 0;
+        return ((wbb(b) + 63) / 64) * 2 * ((mx(b) + QR_KS - 1) / QR_KS);
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem sm;
+        const ORItem& it = o[b];
+        const int wb = wbb(b), m = mx(b);
+        const int tr = t % ((wb + 63) / 64), rest = t / ((wb + 63) / 64);
+        const int tc = rest % 2, ks = rest / 2;
+        const int r0 = ks * QR_KS, kl = min(QR_KS, m - r0);
+        const int cb = c0 + QR_OB;
+        const double* Vb = it.V.p + cb + r0 + (int64_t)cb * it.V.ld;
+        const double* Va = it.V.p + cb + r0 + (int64_t)c0 * it.V.ld;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        if (ks == 0) mfma_tile_64<true, false, 1, 0>(Vb, it.V.ld, Va, it.V.ld, wb, QR_OB, kl, tr * 64, tc * 64, sm, acc);
+        else mfma_tile_64<true, false, 0, 0>(Vb, it.V.ld, Va, it.V.ld, wb, QR_OB, kl, tr * 64, tc * 64, sm, acc);
+        double* P = Wp[b] + (int64_t)ks * pstride(b);
+        acc_foreach(acc, [&](int r, int c, double v) {
+            const int gr = tr * 64 + r, gc = tc * 64 + c;
+            if (gr < wb && gc < QR_OB) P[gr + (int64_t)gc * QR_OB] = v;
+        });
+    }
+};
+struct OpGramXR : BlkOp {
+    __device__ int tiles(int b) const { return o[b].V.n > c0 + QR_OB ? 1 : 0; }
+    __device__ void operator()(int b, int) const {
+        const ORItem& it = o[b];
+        const int wb = min(QR_OB, it.V.n - c0 - QR_OB);
+        const int m = qr_rows(it.V.m, it.zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
+        const int nks_ = m > 0 ? (m + QR_KS - 1) / QR_KS : 0;
+        const int ps = pstride(b);
+        const int nblk = (it.V.n + QR_OB - 1) / QR_OB;
+        double* Gx = it.G + (int64_t)(nblk + c0 / QR_PAIR) * QR_OB * QR_OB;
+        for (int e = threadIdx.x; e < QR_OB * QR_OB; e += blockDim.x) {
+            const int r = e & (QR_OB - 1), c = e >> 7;
+            double sum = 0.0;
+            if (r < wb)
+                for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + r + (int64_t)c * QR_OB];
+            Gx[r + (int64_t)c * QR_OB] = sum;
+        }
+    }
+};
+
+static void gram_cross(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
+    int64_t np = 0, nr = 0;
+    for (auto& x : o.h) {
+        if (x.V.n <= c0 + QR_OB) continue;
+        const int wbb = std::min(QR_OB, x.V.n - c0 - QR_OB);
+        const int m = qr_rows(x.V.m, x.zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
+        ++nr;
+        if (m > 0) np += (int64_t)ceil_div(wbb, 64) * 2 * ceil_div(m, QR_KS);
+    }
+    if (nr == 0) return;
+    BlkOp base{o.d.p, sc.ptr.p, c0, QR_PAIR, 0, 0};
+    if (np) launch_tiles(OpGramXP{base}, o.size(), np, s, "qr_gramx_p");
+    launch_tiles(OpGramXR{base}, o.size(), nr, s, "qr_gramx_r");
+}
+
+// Q^T C (trans) or Q C for the pair of reflector blocks at c0 and c0 + 128 in
+// one pass over C: P = [V_a V_b]^T C, the two W from the 128-block recurrence
+// coupled through the cross Gram, then C -= [V_a V_b] [W_a; W_b] with K = 256.
+static void apply_pair(Batch<ORItem>& o, QrScratch& sc, int c0, int mode, int oend, bool trans, hipStream_t s) {
+    int64_t np = 0, nwa = 0, nwb = 0, ncr = 0, nu = 0;
+    for (auto& x : o.h) {
+        if (x.V.n <= c0 || x.V.m <= c0) continue;
+        const int wb = std::min(QR_PAIR, x.V.n - c0);
+        int cc0, cc1;
+        if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
+        else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
+        else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+        else { cc0 = c0; cc1 = x.C.n; }
+        if (wb <= 0 || cc1 <= cc0) continue;
+        const int ntc = ceil_div(cc1 - cc0, 64);
+        const int mp = qr_rows(x.V.m, x.zrow, c0, QR_PAIR) - c0;
+        np += (int64_t)ceil_div(wb, 64) * ntc * ceil_div(mp, QR_KS);
+        nwa += ntc;
+        if (wb > QR_OB) {
+            nwb += ntc;
+            ncr += (int64_t)ceil_div(trans ? wb - QR_OB : QR_OB, 64) * ntc;
+        }
+        nu += (int64_t)ceil_div(mp, 64) * ntc;
+    }
+    if (nwa == 0) return;
+    BlkOp base{o.d.p, sc.ptr.p, c0, QR_PAIR, mode, oend};
+    BlkOp ha = base, hb = base;
+    hb.half = 1;
+    launch_tiles(OpBlkP{base}, o.size(), np, s, "qr_blk_p");
+    if (trans) {
+        launch_tiles(OpBlkW<true>{ha}, o.size(), nwa, s, "qr_blk_w");
+        if (ncr) launch_tiles(OpBlkCorr<true>{base}, o.size(), ncr, s, "qr_blk_corr");
+        if (nwb) launch_tiles(OpBlkW<true>{hb}, o.size(), nwb, s, "qr_blk_w");
+    } else {
+        if (nwb) launch_tiles(OpBlkW<false>{hb}, o.size(), nwb, s, "qr_blk_w");
+        if (ncr) launch_tiles(OpBlkCorr<false>{base}, o.size(), ncr, s, "qr_blk_corr");
+        launch_tiles(OpBlkW<false>{ha}, o.size(), nwa, s, "qr_blk_w");
+    }
+    auto work = [&](int b0, int cnt, double& fl, double& by) {
+        for (int i = b0; i < b0 + cnt; ++i) {
+            const ORItem& x = o.h[i];
+            if (x.V.n <= c0 || x.V.m <= c0) continue;
+            const int wb = std::min(QR_PAIR, x.V.n - c0);
+            int cc0, cc1;
+            if (mode == 0) { cc0 = 0; cc1 = x.C.n; }
+            else if (mode == 1) { cc0 = c0 + wb; cc1 = x.C.n; }
+            else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
+            else { cc0 = c0; cc1 = x.C.n; }
+            if (wb <= 0 || cc1 <= cc0) continue;
+            const double mp = qr_rows(x.V.m, x.zrow, c0, QR_PAIR) - c0, nc = cc1 - cc0;
+            const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
+            fl += 2.0 * nc * nzv;
+            by += 8.0 * ((nzv - wb) + (double)wb * nc + 2.0 * mp * nc);
+        }
+    };
+    launch_tiles(OpBlkUpd{base}, o.size(), nu, s, "qr_blk_upd", 4096, work);
+}
+
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     int nmax = 0;
     Batch<ORItem> o;
@@ -1163,19 +1332,25 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     sc.alloc(o.h, s);
     DBuf<double*> dtau(htau.size());
     h2d(dtau.p, htau.data(), htau.size(), s);
-    for (int col0 = 0; col0 < nmax; col0 += QR_OB) {
-        for (int in0 = col0; in0 < std::min(nmax, col0 + QR_OB); in0 += QR_NB) {
-            int64_t np = 0;
-            for (auto& x : q.h) np += (x.nfac > in0 && x.A.m > in0) ? 1 : 0;
-            if (np) {
-                hipLaunchKernelGGL(k_qr_panel, dim3(q.size()), dim3(PANEL_THREADS), 0, s, q.d.p, q.size(), in0);
-                launch_check("qr_panel");
+    for (int col0 = 0; col0 < nmax; col0 += QR_PAIR) {
+        for (int sub = 0; sub < 2; ++sub) {
+            const int cb = col0 + sub * QR_OB;
+            if (cb >= nmax) break;
+            for (int in0 = cb; in0 < std::min(nmax, cb + QR_OB); in0 += QR_NB) {
+                int64_t np = 0;
+                for (auto& x : q.h) np += (x.nfac > in0 && x.A.m > in0) ? 1 : 0;
+                if (np) {
+                    hipLaunchKernelGGL(k_qr_panel, dim3(q.size()), dim3(PANEL_THREADS), 0, s, q.d.p, q.size(), in0);
+                    launch_check("qr_panel");
+                }
+                launch_tiles(OpBuildT{o.d.p, dtau.p, in0}, o.size(), np, s, "qr_buildT");
+                apply_block(o, sc, in0, QR_NB, 2, cb + QR_OB, true, s);  // rest of this 128-block
             }
-            launch_tiles(OpBuildT{o.d.p, dtau.p, in0}, o.size(), np, s, "qr_buildT");
-            apply_block(o, sc, in0, QR_NB, 2, col0 + QR_OB, true, s);  // rest of this outer block
+            gram_block(o, sc, cb, s);
+            if (sub == 0) apply_block(o, sc, cb, QR_OB, 2, col0 + QR_PAIR, true, s);  // the pair's second block
         }
-        gram_block(o, sc, col0, s);
-        apply_block(o, sc, col0, QR_OB, 1, 0, true, s);  // trailing matrix
+        gram_cross(o, sc, col0, s);
+        apply_pair(o, sc, col0, 1, 0, true, s);  // trailing matrix
     }
     DD_HIP(hipStreamSynchronize(s));
 }
@@ -1193,6 +1368,7 @@ void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t 
         launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "buildT");
     }
     for (int col0 = 0; col0 < kmax; col0 += QR_OB) gram_block(o, sc, col0, s);
+    for (int col0 = 0; col0 < kmax; col0 += QR_PAIR) gram_cross(o, sc, col0, s);
     DD_HIP(hipStreamSynchronize(s));
 }
 
@@ -1201,10 +1377,10 @@ void ormqr_vb(Batch<ORItem>& o, bool trans, hipStream_t s) {
     for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
     QrScratch sc;
     sc.alloc(o.h, s);
-    const int nb = ceil_div(kmax, QR_OB);
+    const int nb = ceil_div(kmax, QR_PAIR);
     for (int step = 0; step < nb; ++step) {
         const int k = trans ? step : (nb - 1 - step);
-        apply_block(o, sc, k * QR_OB, QR_OB, 0, 0, trans, s);
+        apply_pair(o, sc, k * QR_PAIR, 0, 0, trans, s);
     }
     DD_HIP(hipStreamSynchronize(s));
 }
@@ -1218,8 +1394,8 @@ void orgqr_vb(Batch<ORItem>& o, hipStream_t s) {
     for (auto& x : o.h) kmax = std::max(kmax, std::min(x.V.n, x.V.m));
     QrScratch sc;
     sc.alloc(o.h, s);
-    const int nb = ceil_div(kmax, QR_OB);
-    for (int step = nb - 1; step >= 0; --step) apply_block(o, sc, step * QR_OB, QR_OB, 3, 0, false, s);
+    const int nb = ceil_div(kmax, QR_PAIR);
+    for (int step = nb - 1; step >= 0; --step) apply_pair(o, sc, step * QR_PAIR, 3, 0, false, s);
     DD_HIP(hipStreamSynchronize(s));
 }
 

@@ -62,8 +62,13 @@ constexpr int QR_NB = 32;   // inner panel width
 constexpr int QR_OB = 128;  // outer block (four inner panels)
 constexpr int CH_NB = 64;
 inline int64_t qr_t_size(int k) { return (int64_t)((k + QR_NB - 1) / QR_NB) * QR_NB * QR_NB; }
-inline int64_t qr_g_size(int k) { return (int64_t)((k + QR_OB - 1) / QR_OB) * QR_OB * QR_OB; }
-inline int64_t qr_w_size(int ncols) { return (int64_t)QR_OB * ncols; }
+constexpr int QR_PAIR = 256; // two outer blocks applied to C in one pass
+// G: the Gram matrix of every 128-column block, then the cross Gram V_b^T V_a
+// of every 256-column pair (a, b) of blocks
+inline int64_t qr_g_size(int k) {
+    return ((int64_t)(k + QR_OB - 1) / QR_OB + (k + QR_PAIR - 1) / QR_PAIR) * QR_OB * QR_OB;
+}
+inline int64_t qr_w_size(int ncols) { return (int64_t)QR_PAIR * ncols; }
 
 // C := alpha * op(A) op(B) + beta * C for every item (dims from C and A).
 struct GemmItem {
