@@ -576,11 +576,11 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Batch<DMat> LI = mats(Lv.L.ptr, ni, nI, nI, s);
         trsm_vb(LI, Bb, false, s);
         Sm.alloc(sI2);
-        Batch<GemmItem> g;
+        Batch<GemmItem> g;  // lower triangle of S~ (the tridiagonalisation reads no more)
         for (int i = 0; i < N; ++i)
-            g.h.push_back(GemmItem{B2.ptr[i], nI[i], B2.ptr[i], nI[i], Sm.ptr[i], nI[i], nI[i], nI[i], nI[i], 1.0, 0.0});
+            g.h.push_back(GemmItem{B2.ptr[i], nI[i], nullptr, 0, Sm.ptr[i], nI[i], nI[i], nI[i], nI[i], 1.0, 0.0});
         g.sync(s);
-        gemm_vb(g, false, true, s);
+        syrk_vb(g, s);
         DD_HIP(hipStreamSynchronize(s));
     }
     B2.release();
@@ -589,15 +589,19 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     for (int i = 0; i < N; ++i) { v1[i] = nI[i]; vpart[i] = ceil_div(nI[i], 64) + 1; }
     td.alloc(v1); te.alloc(v1); ttau.alloc(v1); tpart.alloc(vpart); tp.alloc(v1); tmu.alloc(v1);
     {
-        Arena tw, taux;
-        std::vector<int64_t> sw(N), sa(N, 2 * TRD_NB);
-        for (int i = 0; i < N; ++i) sw[i] = (int64_t)nI[i] * TRD_NB;
+        Arena tw, taux, typ;
+        std::vector<int64_t> sw(N), sa(N, 2 * TRD_NB), syp(N);
+        for (int i = 0; i < N; ++i) {
+            sw[i] = (int64_t)nI[i] * TRD_NB;
+            syp[i] = trd_part_size(nI[i]);
+        }
         tw.alloc(sw);
         taux.alloc(sa);
+        typ.alloc(syp);
         Batch<TriItem> tb;
         for (int i = 0; i < N; ++i)
             tb.h.push_back(TriItem{DMat{Sm.ptr[i], nI[i], nI[i], nI[i]}, td.ptr[i], te.ptr[i], ttau.ptr[i], tpart.ptr[i],
-                                   tp.ptr[i], tw.ptr[i], taux.ptr[i]});
+                                   tp.ptr[i], tw.ptr[i], taux.ptr[i], typ.ptr[i]});
         tb.sync(s);
         sytrd_vb(tb, s);
         DD_HIP(hipStreamSynchronize(s));

@@ -1400,12 +1400,13 @@ void orgqr_vb(Batch<ORItem>& o, hipStream_t s) {
 }
 
 // ===========================================================================
-// Tridiagonalisation Q^T A Q = T (symmetric A, full storage), blocked in
+// Tridiagonalisation Q^T A Q = T (symmetric A, lower triangle), blocked in
 // panels of TRD_NB columns: within a panel each column first receives the
 // pending rank-2 updates of the panel's earlier columns, then yields its
 // Householder vector v and w = tau (A22 v - V (W^T v) - W (V^T v)),
 // w += -(tau/2)(w.v) v, with A22 not yet updated by the panel; after the
-// panel the trailing matrix takes A22 -= V W^T + W V^T as two MFMA GEMMs.
+// panel the lower tiles of the trailing matrix take A22 -= V W^T + W V^T in
+// one MFMA pass (K = 2 TRD_NB).  Every step reads the lower triangle only.
 // Reflector k is stored in column k, rows k+2.., with an explicit 1 at row k+1.
 // ===========================================================================
 struct OpTrdCol {
@@ -1463,76 +1464,114 @@ struct OpTrdCol {
     }
 };
 
-// y = A22 v (column dots over 64-column tiles, A22 symmetric), and the
-// corrections t1_j = W(:, j)^T v, t2_j = V(:, j)^T v (one extra tile per j).
+// y = A22 v from the lower triangle of A22.  A tile is a 64-column block J
+// and a chunk of up to TRD_RB 64-row blocks I >= J below it; each 64 x 64
+// block is staged in LDS (the next one's loads are in flight meanwhile) and
+// adds A_IJ v_J to the rows of block I (row partial yp[J n + r]) and A_IJ^T
+// v_I to the columns of block J, summed over the chunk (column partial
+// yp[T n + (J T + chunk) 64 + c]); on diagonal blocks the stored diagonal
+// counts once.  Extra tiles give the corrections t1_j = W(:, j)^T v,
+// t2_j = V(:, j)^T v.
+__host__ __device__ inline int trd_symv_tiles(int TL) {
+    int n = 0;
+    for (int J = 0; J < TL; ++J) n += (TL - J + TRD_RB - 1) / TRD_RB;
+    return n;
+}
 struct OpTrdSymv {
     const TriItem* t;
     int k0, i;
     __device__ int tiles(int b) const {
         const int L = t[b].A.n - (k0 + i) - 1;
-        return (L >= 1) ? (L + 63) / 64 + i : 0;
+        return (L >= 1) ? trd_symv_tiles((L + 63) / 64) + i : 0;
     }
     __device__ void operator()(int b, int tile) const {
-        __shared__ double vs[4096];
-        __shared__ double red[2][4];
+        __shared__ double As[64][65];
+        __shared__ double vi[64], vj[64];
+        __shared__ double red[2][4][64];
         const TriItem& T = t[b];
         const int n = T.A.n, ld = T.A.ld, k = k0 + i;
         const int L = n - k - 1;
         const double* v = T.A.p + (k + 1) + (int64_t)k * ld;  // v[0] = 1 stored
-        const bool inl = L <= 4096;
-        if (inl)
-            for (int r = threadIdx.x; r < L; r += blockDim.x) vs[r] = v[r];
-        __syncthreads();
-        const int nct = (L + 63) / 64;
+        const int TL = (L + 63) / 64;
+        const int nsym = trd_symv_tiles(TL);
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (tile < nct) {
-            // two columns per wave at a time, four row blocks per step: eight
-            // independent 512 B loads in flight per wave
+        if (tile < nsym) {
+            int J = 0, ch = tile;
+            for (;;) {
+                const int c = (TL - J + TRD_RB - 1) / TRD_RB;
+                if (ch < c) break;
+                ch -= c;
+                ++J;
+            }
+            const int Ib = J + ch * TRD_RB, Ie = min(TL, Ib + TRD_RB);
+            const int j0 = J * 64;
             const double* A22 = T.A.p + (k + 1) + (int64_t)(k + 1) * ld;
-            for (int cc = 2 * wv; cc < 64; cc += 8) {
-                const int c = tile * 64 + cc;
-                if (c >= L) break;
-                const bool two = c + 1 < L;
-                const double* a0 = A22 + (int64_t)c * ld;
-                const double* a1 = two ? a0 + ld : a0;
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
-                int r = lane;
-                for (; r + 192 < L; r += 256) {
-                    const double v0 = inl ? vs[r] : v[r], v1 = inl ? vs[r + 64] : v[r + 64];
-                    const double v2 = inl ? vs[r + 128] : v[r + 128], v3 = inl ? vs[r + 192] : v[r + 192];
-                    s0 += a0[r] * v0; s1 += a0[r + 64] * v1; s2 += a0[r + 128] * v2; s3 += a0[r + 192] * v3;
-                    u0 += a1[r] * v0; u1 += a1[r + 64] * v1; u2 += a1[r + 128] * v2; u3 += a1[r + 192] * v3;
+            double cur[16];
+            const int64_t ld4 = 4 * (int64_t)ld;
+            auto fetch = [&](int I) {
+                const int gr = I * 64 + lane;
+                // columns gc = j0 + wv + 4 q < min(L, gr + 1)
+                const int cend = (gr < L) ? gr + 1 - (j0 + wv) : 0;
+                const double* p = A22 + gr + (int64_t)(j0 + wv) * ld;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    cur[q] = (4 * q < cend) ? *p : 0.0;
+                    p += ld4;
                 }
-                for (; r < L; r += 64) {
-                    const double vr = inl ? vs[r] : v[r];
-                    s0 += a0[r] * vr;
-                    u0 += a1[r] * vr;
+            };
+            fetch(Ib);
+            if (threadIdx.x < 64) vj[lane] = (j0 + lane < L) ? v[j0 + lane] : 0.0;
+            double sc = 0.0;
+            for (int I = Ib; I < Ie; ++I) {
+                const int gr = I * 64 + lane;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) As[wv + 4 * q][lane] = cur[q];
+                if (threadIdx.x >= 64 && threadIdx.x < 128) vi[lane] = (gr < L) ? v[gr] : 0.0;
+                __syncthreads();
+                if (I + 1 < Ie) fetch(I + 1);
+                // rows: lane = row, wave wv takes columns 16 wv .. 16 wv + 15
+                double sr = 0.0;
+#pragma unroll 4
+                for (int q = 0; q < 16; ++q) sr += As[16 * wv + q][lane] * vj[16 * wv + q];
+                // columns: lane = column, wave wv takes rows 16 wv .. 16 wv + 15
+                // (the diagonal of a diagonal block is already in the row sums)
+#pragma unroll 4
+                for (int q = 0; q < 16; ++q) {
+                    const int r = 16 * wv + q;
+                    const double a = (I == J && r == lane) ? 0.0 : As[lane][r];
+                    sc += a * vi[r];
                 }
-                const double y0 = wave_sum((s0 + s1) + (s2 + s3));
-                const double y1 = wave_sum((u0 + u1) + (u2 + u3));
-                if (lane == 0) {
-                    T.p[c] = y0;
-                    if (two) T.p[c + 1] = y1;
-                }
+                red[0][wv][lane] = sr;
+                __syncthreads();
+                if (threadIdx.x < 64 && gr < L)
+                    T.yp[(int64_t)J * n + gr] = (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]);
+            }
+            red[1][wv][lane] = sc;
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                const int64_t Tn = (n + 63) / 64;
+                T.yp[Tn * n + ((int64_t)J * Tn + ch) * 64 + lane] =
+                    (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]);
             }
             return;
         }
-        const int j = tile - nct;
+        const int j = tile - nsym;
         const double* wc = T.W + (k + 1) + (int64_t)j * n;
         const double* vc = T.A.p + (k + 1) + (int64_t)(k0 + j) * ld;  // rows > k0+j+1: stored values
         double s1 = 0.0, s2 = 0.0;
         for (int r = threadIdx.x; r < L; r += blockDim.x) {
-            const double vr = inl ? vs[r] : v[r];
+            const double vr = v[r];
             s1 += wc[r] * vr;
             s2 += vc[r] * vr;
         }
         s1 = wave_sum(s1);
         s2 = wave_sum(s2);
-        if (lane == 0) { red[0][wv] = s1; red[1][wv] = s2; }
+        double (*r2)[4] = reinterpret_cast<double (*)[4]>(&red[0][0][0]);
+        if (lane == 0) { r2[0][wv] = s1; r2[1][wv] = s2; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            T.aux[j] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-            T.aux[TRD_NB + j] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+            T.aux[j] = (r2[0][0] + r2[0][1]) + (r2[0][2] + r2[0][3]);
+            T.aux[TRD_NB + j] = (r2[1][0] + r2[1][1]) + (r2[1][2] + r2[1][3]);
         }
     }
 };
@@ -1555,7 +1594,16 @@ struct OpTrdW {
         double pv = 0.0;
         if (r < L) {
             const int g = k + 1 + r;
-            double w = T.p[r];
+            // y_r: row partials of blocks J <= r/64, column partials of the
+            // row chunks below column block r/64
+            const int64_t Tn = (n + 63) / 64;
+            const int Jr = r >> 6, TL = (L + 63) / 64;
+            const int nch = (TL - Jr + TRD_RB - 1) / TRD_RB;
+            double y0 = 0.0, y1 = 0.0;
+            for (int J = 0; J <= Jr; ++J) y0 += T.yp[(int64_t)J * n + r];
+            const double* pc = T.yp + Tn * n + (int64_t)Jr * Tn * 64 + (r & 63);
+            for (int c = 0; c < nch; ++c) y1 += pc[(int64_t)c * 64];
+            double w = y0 + y1;
             for (int j = 0; j < i; ++j)
                 w -= T.A.p[g + (int64_t)(k0 + j) * ld] * T.aux[j] + T.W[g + (int64_t)j * n] * T.aux[TRD_NB + j];
             w *= tau;
@@ -1591,6 +1639,39 @@ struct OpTrdAlpha {
     }
 };
 
+// lower tiles of C += alpha (A B^T + B A^T), A and B M x K (column-major):
+// both products accumulate in one tile, then one read-modify-write of C
+struct OpSyr2kLower {
+    const GemmItem* g;
+    __device__ int tiles(int b) const {
+        const int T = (g[b].M + 63) / 64;
+        return T * (T + 1) / 2;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmemC sm;
+        const GemmItem& G = g[b];
+        int tj = 0, r = t;
+        const int T = (G.M + 63) / 64;
+        while (r >= T - tj) {
+            r -= T - tj;
+            ++tj;
+        }
+        const int ti = tj + r;
+        const int i0 = ti * 64, j0 = tj * 64;
+        double4_t acc[2][2];
+        acc_zero(acc);
+        mfma_tile_64<false, true>(G.A, G.lda, G.B, G.ldb, G.M, G.M, G.K, i0, j0, sm.t, acc);
+        mfma_tile_64<false, true>(G.B, G.ldb, G.A, G.lda, G.M, G.M, G.K, i0, j0, sm.t, acc);
+        double* C = G.C;
+        const int ldc = G.ldc, M = G.M;
+        const double al = G.alpha;
+        acc_store_coalesced(acc, sm, [&](int rr, int c, double v) {
+            const int gi = i0 + rr, gj = j0 + c;
+            if (gi < M && gj < M) C[gi + (int64_t)gj * ldc] += al * v;
+        });
+    }
+};
+
 void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
     int nmax = 0;
     for (auto& x : t.h) nmax = std::max(nmax, x.A.n);
@@ -1603,7 +1684,7 @@ void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
                 ++nc;
                 const int L = x.A.n - k - 1;
                 if (L >= 1) {
-                    ns += ceil_div(L, 64) + i;
+                    ns += trd_symv_tiles(ceil_div(L, 64)) + i;
                     nw += ceil_div(L, 256);
                 }
             }
@@ -1614,9 +1695,10 @@ void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
                 launch_tiles(OpTrdAlpha{t.d.p, k0, i}, t.size(), nw, s, "trd_alpha");
             }
         }
-        // trailing update A22 -= V W^T + W V^T (rows/columns from k0 + TRD_NB)
+        // trailing update A22 -= V W^T + W V^T, lower tiles (rows/columns from k0 + TRD_NB)
         const int k1 = k0 + TRD_NB;
-        Batch<GemmItem> g1, g2;
+        Batch<GemmItem> g1;
+        int64_t nt = 0;
         for (auto& x : t.h) {
             const int m = x.A.n - k1;
             if (m <= 0) continue;
@@ -1624,14 +1706,13 @@ void sytrd_vb(Batch<TriItem>& t, hipStream_t s) {
             const double* V = x.A.p + k1 + (int64_t)k0 * x.A.ld;
             const double* Wm = x.W + k1;
             g1.h.push_back(GemmItem{V, x.A.ld, Wm, x.A.n, C, x.A.ld, m, m, TRD_NB, -1.0, 1.0});
-            g2.h.push_back(GemmItem{Wm, x.A.n, V, x.A.ld, C, x.A.ld, m, m, TRD_NB, -1.0, 1.0});
+            const int64_t T = ceil_div(m, 64);
+            nt += T * (T + 1) / 2;
         }
         if (!g1.h.empty()) {
             g1.sync(s);
-            g2.sync(s);
-            gemm_vb(g1, false, true, s);
-            gemm_vb(g2, false, true, s);
-            DD_HIP(hipStreamSynchronize(s));  // the host batches are freed at scope exit
+            launch_tiles(OpSyr2kLower{g1.d.p}, g1.size(), nt, s, "trd_syr2k");
+            DD_HIP(hipStreamSynchronize(s));  // the host batch is freed at scope exit
         }
     }
 }

@@ -107,10 +107,19 @@ void orgqr_vb(Batch<ORItem>& o, hipStream_t s);
 // T and G factors for reflectors stored in V with taus (used after sytrd).
 void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t s);
 
-// Householder tridiagonalisation of symmetric A (full storage, in place).
-// d[n], e[n-1] (off-diagonal), tau[n-1]; reflector k stored in A[k+2:, k]
-// (implicit 1 at row k+1).  part: scratch of >= ceil(n/64) doubles per item.
+// Householder tridiagonalisation of symmetric A, in place.  Only the lower
+// triangle of A is read (the strict upper triangle may hold anything and is
+// overwritten with garbage).  d[n], e[n-1] (off-diagonal), tau[n-1];
+// reflector k stored in A[k+1:, k] with an explicit 1 at row k+1.
 constexpr int TRD_NB = 32;  // panel width of the blocked tridiagonalisation
+// partial sums of the lower-triangle matrix-vector product: row partials of
+// every 64-column block (T x n), then column partials of every chunk of
+// TRD_RB row blocks below each column block (at most T x T x 64), T = ceil(n / 64)
+constexpr int TRD_RB = 4;
+__host__ __device__ inline int64_t trd_part_size(int n) {
+    const int64_t T = (n + 63) / 64;
+    return T * n + T * T * 64;
+}
 struct TriItem {
     DMat A;
     double* d;
@@ -120,6 +129,7 @@ struct TriItem {
     double* p;     // n doubles
     double* W;     // n x TRD_NB (ld n)
     double* aux;   // 2 * TRD_NB doubles
+    double* yp;    // trd_part_size(n) doubles
 };
 void sytrd_vb(Batch<TriItem>& t, hipStream_t s);
 
