@@ -739,52 +739,82 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
 }
 
 // T factor for the reflectors of panel k: T = upper triangular with
-// H_0 ... H_{w-1} = I - V T V^T.  G = V^T V over rows col0..m-1.
+// H_0 ... H_{w-1} = I - V T V^T, from G = V^T V over rows col0..m-1.  G is
+// summed from partials over chunks of QR_GKS rows (MFMA, many workgroups per
+// item), then one workgroup per item runs the recurrence
+// T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j), T(j, j) = tau_j.
+constexpr int QR_GKS = 256;
+
+struct OpPanelGram {
+    const ORItem* o;
+    double* const* Wp;  // per item: ceil(mp / QR_GKS) partials of 32 x 32
+    int col0;
+    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, col0, QR_NB) - col0; }
+    __device__ int tiles(int b) const {
+        if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
+        return (mrows(b) + QR_GKS - 1) / QR_GKS;
+    }
+    __device__ void operator()(int b, int ks) const {
+        __shared__ double Vs[4][64][QR_NB + 1];
+        const ORItem& it = o[b];
+        const int w = min(QR_NB, it.V.n - col0);
+        const int mp = mrows(b);
+        const int64_t ld = it.V.ld;
+        const double* V = it.V.p + col0 + (int64_t)col0 * ld;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        // wave wv stages rows ks*QR_GKS + 64 wv + lane (unit lower trapezoid)
+        const int gr = ks * QR_GKS + wv * 64 + lane;
+#pragma unroll 8
+        for (int c = 0; c < QR_NB; ++c) {
+            double v = 0.0;
+            if (gr < mp && c < w) v = (gr < c) ? 0.0 : (gr == c ? 1.0 : V[gr + (int64_t)c * ld]);
+            Vs[wv][lane][c] = v;
+        }
+        __syncthreads();
+        double4_t acc[2][2];
+        acc_zero(acc);
+#pragma unroll 4
+        for (int kq = 0; kq < 16; ++kq) {
+            const int kk = kq * 4 + (lane >> 4);
+            const double a0 = Vs[wv][kk][lane & 15], a1 = Vs[wv][kk][16 + (lane & 15)];
+            acc[0][0] = mfma_f64(a0, a0, acc[0][0]);
+            acc[0][1] = mfma_f64(a0, a1, acc[0][1]);
+            acc[1][0] = mfma_f64(a1, a0, acc[1][0]);
+            acc[1][1] = mfma_f64(a1, a1, acc[1][1]);
+        }
+        __syncthreads();
+        double* red = &Vs[0][0][0];  // 4 x 1024 doubles
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[wv * 1024 + (16 * x + 4 * e + (lane >> 4)) + 32 * (16 * y + (lane & 15))] = acc[x][y][e];
+        __syncthreads();
+        double* P = Wp[b] + (int64_t)ks * 1024;
+        for (int e = threadIdx.x; e < 1024; e += 256) P[e] = (red[e] + red[1024 + e]) + (red[2048 + e] + red[3072 + e]);
+    }
+};
+
 struct OpBuildT {
     const ORItem* o;
     const double* const* tau;  // per item tau array (reflector j's tau at tau[b][j])
+    double* const* Wp;         // Gram partials from OpPanelGram
     int col0;
     __device__ int tiles(int b) const { return (o[b].V.n > col0 && o[b].V.m > col0) ? 1 : 0; }
     __device__ void operator()(int b, int) const {
-        __shared__ double Vs[64][33];
         __shared__ double G[32][33];
         __shared__ double T[32][33];
         const DMat Vm = o[b].V;
         const int w = min(QR_NB, Vm.n - col0);
         const int mp = qr_rows(Vm.m, o[b].zrow, col0, QR_NB) - col0;
-        const double* V = Vm.p + col0 + (int64_t)col0 * Vm.ld;
-        // pairs (a,c) with a <= c owned by threads
-        double accv[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int r0 = 0; r0 < mp; r0 += 64) {
-            for (int e = threadIdx.x; e < 64 * 32; e += blockDim.x) {
-                const int r = e & 63, c = e >> 6;
-                const int gr = r0 + r;
-                double v = 0.0;
-                if (gr < mp && c < w) v = (gr < c) ? 0.0 : (gr == c ? 1.0 : V[gr + (int64_t)c * Vm.ld]);
-                Vs[r][c] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int pidx = threadIdx.x + q * 256;
-                if (pidx < 32 * 32) {
-                    const int a = pidx & 31, c = pidx >> 5;
-                    if (a <= c) {
-                        double sum = 0.0;
-                        for (int r = 0; r < 64; ++r) sum += Vs[r][a] * Vs[r][c];
-                        accv[q] += sum;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int pidx = threadIdx.x + q * 256;
-            if (pidx < 32 * 32) {
-                const int a = pidx & 31, c = pidx >> 5;
-                if (a <= c) G[a][c] = accv[q];
-            }
+        const int nks = (mp + QR_GKS - 1) / QR_GKS;
+        const double* P = Wp[b];
+        for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
+            double sum = 0.0;
+            for (int ks = 0; ks < nks; ++ks) sum += P[(int64_t)ks * 1024 + e];
+            G[e & 31][e >> 5] = sum;
         }
         for (int e = threadIdx.x; e < 32 * 33; e += blockDim.x) (&T[0][0])[e] = 0.0;
         __syncthreads();
@@ -1132,6 +1162,19 @@ struct QrScratch {
     }
 };
 
+// T factor of the 32-column panel at col0 (Gram partials in the scratch)
+static void build_t_panel(Batch<ORItem>& o, QrScratch& sc, const double* const* dtau, int col0, hipStream_t s) {
+    int64_t ng = 0, nt = 0;
+    for (auto& x : o.h) {
+        if (x.V.n <= col0 || x.V.m <= col0) continue;
+        ++nt;
+        ng += ceil_div(qr_rows(x.V.m, x.zrow, col0, QR_NB) - col0, QR_GKS);
+    }
+    if (nt == 0) return;
+    launch_tiles(OpPanelGram{o.d.p, sc.ptr.p, col0}, o.size(), ng, s, "qr_panel_gram");
+    launch_tiles(OpBuildT{o.d.p, dtau, sc.ptr.p, col0}, o.size(), nt, s, "qr_buildT");
+}
+
 static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mode, int oend, bool trans,
                         hipStream_t s) {
     int64_t np = 0, nw = 0, nu = 0;
@@ -1343,7 +1386,7 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
                     hipLaunchKernelGGL(k_qr_panel, dim3(q.size()), dim3(PANEL_THREADS), 0, s, q.d.p, q.size(), in0);
                     launch_check("qr_panel");
                 }
-                launch_tiles(OpBuildT{o.d.p, dtau.p, in0}, o.size(), np, s, "qr_buildT");
+                build_t_panel(o, sc, dtau.p, in0, s);
                 apply_block(o, sc, in0, QR_NB, 2, cb + QR_OB, true, s);  // rest of this 128-block
             }
             gram_block(o, sc, cb, s);
@@ -1362,11 +1405,7 @@ void build_t_vb(Batch<ORItem>& o, const std::vector<double*>& htau, hipStream_t 
     h2d(dtau.p, htau.data(), htau.size(), s);
     QrScratch sc;
     sc.alloc(o.h, s);
-    for (int col0 = 0; col0 < kmax; col0 += QR_NB) {
-        int64_t np = 0;
-        for (auto& x : o.h) np += (x.V.n > col0 && x.V.m > col0) ? 1 : 0;
-        launch_tiles(OpBuildT{o.d.p, dtau.p, col0}, o.size(), np, s, "buildT");
-    }
+    for (int col0 = 0; col0 < kmax; col0 += QR_NB) build_t_panel(o, sc, dtau.p, col0, s);
     for (int col0 = 0; col0 < kmax; col0 += QR_OB) gram_block(o, sc, col0, s);
     for (int col0 = 0; col0 < kmax; col0 += QR_PAIR) gram_cross(o, sc, col0, s);
     DD_HIP(hipStreamSynchronize(s));
