@@ -929,8 +929,6 @@ struct OpBlkW : BlkOp {
     }
     __device__ void operator()(int b, int t) const {
         __shared__ double P[QR_OB][65];
-        __shared__ double Ts[4][32][33];
-        __shared__ double LG[6][32][33];  // lower blocks G_qj, j < q: index q*(q-1)/2 + j
         BlkRange R;
         active(b, R);
         const ORItem& it = o[b];
@@ -948,66 +946,59 @@ struct OpBlkW : BlkOp {
                 for (int ks = 0; ks < nks_; ++ks) sum += Wp[b][(int64_t)ks * ps + (roff + r) + (int64_t)(j0 + c) * PLD];
             P[r][c] = sum;
         }
-        for (int q = 0; q < nsub; ++q) {
-            const double* Tg = it.T + (int64_t)((c0h / QR_NB) + q) * QR_NB * QR_NB;
-            for (int e = threadIdx.x; e < 1024; e += blockDim.x) Ts[q][e & 31][e >> 5] = Tg[e];
-        }
-        if (nsub > 1) {
-            const double* Gg = it.G + (int64_t)(c0h / QR_OB) * QR_OB * QR_OB;
-            for (int q = 1; q < nsub; ++q)
-                for (int j = 0; j < q; ++j)
-                    for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
-                        const int l = e & 31, m = e >> 5;
-                        LG[q * (q - 1) / 2 + j][l][m] = Gg[(32 * q + l) + (int64_t)(32 * j + m) * QR_OB];
-                    }
-        }
         __syncthreads();
+        // MFMA 16x16x4: wave wv owns rows 16 (wv & 1) .. +15 of the current
+        // panel and the column blocks 2 (wv >> 1), 2 (wv >> 1) + 1 of the tile
+        const double* Tg0 = it.T + (int64_t)(c0h / QR_NB) * QR_NB * QR_NB;
+        const double* Gg = it.G + (int64_t)(c0h / QR_OB) * QR_OB * QR_OB;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int rb = wv & 1, cb0 = (wv >> 1) * 2;
+        const int li = lane & 15, lk = lane >> 4;
         for (int step = 0; step < nsub; ++step) {
             const int q = TRANS ? step : nsub - 1 - step;
             const int wq = min(QR_NB, wbh - 32 * q);
-            double u[8];
+            double4_t acc[2];
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[y][e] = P[32 * q + 16 * rb + 4 * e + lk][16 * (cb0 + y) + li];
             // U_q = P_q - sum over the panels already turned into W of G_qj W_j
+            // (the lower blocks of the Gram: G(32q + i, 32j + k) for j < q, or
+            // G(32j + k, 32q + i) for j > q)
+            const int jb = TRANS ? 0 : q + 1, je = TRANS ? q : nsub;
+            for (int j = jb; j < je; ++j) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = threadIdx.x + k * 256;
-                const int l = e & 31, c = e >> 5;
-                double v = P[32 * q + l][c];
-                if (TRANS) {
-                    for (int j = 0; j < q; ++j)
-                        for (int m = 0; m < 32; ++m) v -= LG[q * (q - 1) / 2 + j][l][m] * P[32 * j + m][c];
-                } else {
-                    for (int j = q + 1; j < nsub; ++j)
-                        for (int m = 0; m < 32; ++m) v -= LG[j * (j - 1) / 2 + q][m][l] * P[32 * j + m][c];
+                for (int kk = 0; kk < 8; ++kk) {
+                    const int gi = 32 * q + 16 * rb + li, gk = 32 * j + 4 * kk + lk;
+                    double a = 0.0;
+                    if (gi < wbh && gk < wbh) a = -(TRANS ? Gg[gi + (int64_t)gk * QR_OB] : Gg[gk + (int64_t)gi * QR_OB]);
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) acc[y] = mfma_f64(a, P[gk][16 * (cb0 + y) + li], acc[y]);
                 }
-                u[k] = (l < wq) ? v : 0.0;
             }
-            __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = threadIdx.x + k * 256;
-                P[32 * q + (e & 31)][e >> 5] = u[k];
-            }
-            __syncthreads();
+            for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = threadIdx.x + k * 256;
-                const int r = e & 31, c = e >> 5;
-                double v = 0.0;
-                if (r < wq) {
-                    if (TRANS) {
-                        for (int l = 0; l <= r; ++l) v += Ts[q][l][r] * P[32 * q + l][c];
-                    } else {
-                        for (int l = r; l < wq; ++l) v += Ts[q][r][l] * P[32 * q + l][c];
-                    }
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * rb + 4 * e + lk;
+                    P[32 * q + r][16 * (cb0 + y) + li] = (r < wq) ? acc[y][e] : 0.0;
                 }
-                u[k] = v;
+            __syncthreads();
+            // W_q = T_q^T U_q (T_q U_q for Q C); T_q is zero outside its wq x wq corner
+            double4_t acc2[2] = {double4_t{0.0, 0.0, 0.0, 0.0}, double4_t{0.0, 0.0, 0.0, 0.0}};
+            const double* Tq = Tg0 + (int64_t)q * QR_NB * QR_NB;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const int i_ = 16 * rb + li, k_ = 4 * kk + lk;
+                const double a = TRANS ? Tq[k_ + 32 * i_] : Tq[i_ + 32 * k_];
+#pragma unroll
+                for (int y = 0; y < 2; ++y) acc2[y] = mfma_f64(a, P[32 * q + k_][16 * (cb0 + y) + li], acc2[y]);
             }
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int e = threadIdx.x + k * 256;
-                P[32 * q + (e & 31)][e >> 5] = u[k];
-            }
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) P[32 * q + 16 * rb + 4 * e + lk][16 * (cb0 + y) + li] = acc2[y][e];
             __syncthreads();
         }
         for (int e = threadIdx.x; e < QR_OB * 64; e += blockDim.x) {
