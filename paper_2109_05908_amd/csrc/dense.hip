@@ -301,7 +301,9 @@ void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s) 
 
 // ===========================================================================
 // Cholesky (right-looking, 64-column blocks)
-// Cholesky of the 64 x 64 diagonal block at k0 in LDS, written back.  A
+// Cholesky of the 64 x 64 diagonal block at k0 by one wave: lane i holds
+// row i in registers; column j's pivot and entries reach the other lanes by
+// cross-lane shuffles, so no step waits on a workgroup barrier.  A
 // non-positive pivot records info = its 1-based column and continues with 1.
 struct OpPotrfDiag {
     const DMat* A;
@@ -309,39 +311,35 @@ struct OpPotrfDiag {
     int k0;
     __device__ int tiles(int b) const { return A[b].n > k0 ? 1 : 0; }
     __device__ void operator()(int b, int) const {
-        __shared__ double s[64][65];
+        if (threadIdx.x >= 64) return;  // one wave; no workgroup barrier below
         const DMat M = A[b];
         const int w = min(64, M.n - k0);
-        double* base = M.p + k0 + (int64_t)k0 * M.ld;
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, c = e >> 6;
-            s[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : 0.0;
-        }
-        __syncthreads();
-        for (int j = 0; j < w; ++j) {
-            if (threadIdx.x == 0) {
-                double d = s[j][j];
+        const int64_t ld = M.ld;
+        double* base = M.p + k0 + (int64_t)k0 * ld;
+        const int i = threadIdx.x;
+        double a[64];
+#pragma unroll
+        for (int c = 0; c < 64; ++c) a[c] = (i < w && c < w && i >= c) ? base[i + c * ld] : 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int j = 0; j < 64; ++j) {
+            if (j < w) {
+                double d = readlane_d(a[j], j);
                 if (!(d > 0.0)) {
-                    if (info[b] == 0) info[b] = k0 + j + 1;
+                    if (!bad) bad = j + 1;
                     d = 1.0;
                 }
-                s[j][j] = sqrt(d);
+                const double piv = sqrt(d);
+                const double l = (i > j) ? a[j] / piv : (i == j ? piv : 0.0);
+                if (i < w && i >= j) base[i + j * ld] = l;  // column j is final
+#pragma unroll
+                for (int c = j + 1; c < 64; ++c) {
+                    const double lc = readlane_d(l, c);
+                    if (i >= c) a[c] -= l * lc;
+                }
             }
-            __syncthreads();
-            const double piv = s[j][j];
-            for (int r = j + 1 + threadIdx.x; r < w; r += blockDim.x) s[r][j] /= piv;
-            __syncthreads();
-            const int rem = w - j - 1;
-            for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-                const int r = j + 1 + e % rem, c = j + 1 + e / rem;
-                if (r >= c) s[r][c] -= s[r][j] * s[c][j];
-            }
-            __syncthreads();
         }
-        for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
-            const int r = e & 63, c = e >> 6;
-            if (r < w && c < w && r >= c) base[r + (int64_t)c * M.ld] = s[r][c];
-        }
+        if (bad && i == 0 && info[b] == 0) info[b] = k0 + bad;
     }
 };
 
@@ -638,12 +636,12 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool low
 // Householder QR (32-column panels, compact WY)
 // ===========================================================================
 // Unblocked Householder on panel [col0, col0+w) of A, rows col0..m-1, one
-// workgroup of 1024 threads per item.  Each column costs one pass over the
+// workgroup of 512 threads per item.  Each column costs one pass over the
 // remaining panel rows: the pass applies reflector j to columns j+1.. and, on
 // the fly, accumulates the squared norm of the next column below its diagonal
 // and the unscaled products of that column with the later ones; one block
 // reduction then gives every scalar the next reflector needs.
-constexpr int PANEL_THREADS = 1024;
+constexpr int PANEL_THREADS = 512;
 
 __device__ __forceinline__ void panel_reduce(double (&part)[QR_NB + 1], int nval, double (*red)[QR_NB + 2],
                                              double* out) {
@@ -668,7 +666,6 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
     __shared__ double red[PANEL_THREADS / 64][QR_NB + 2];
     __shared__ double sh[QR_NB + 2];  // sh[0] = norm^2 below diag of the current column, sh[1+k] = dots
     __shared__ double coef[QR_NB];
-    __shared__ double s_scal;
     const int b = blockIdx.x;
     if (b >= nitems) return;
     const QRItem it = q[b];
@@ -690,31 +687,39 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
     }
     panel_reduce(part, w, red, sh);
     for (int j = 0; j < w; ++j) {
-        // reflector j from alpha = V[j][j] and ||x[1:]||^2 = sh[0]
-        if (threadIdx.x == 0) {
-            const double alpha = V[j + j * ld];
-            const double xn2 = sh[0];
-            double tau = 0.0, beta = alpha, scal = 0.0;
-            if (xn2 > 0.0) {
-                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                tau = (beta - alpha) / beta;
-                scal = 1.0 / (alpha - beta);
-            }
-            it.tau[col0 + j] = tau;
-            s_scal = scal;
+        // reflector j from alpha = V[j][j] and ||x[1:]||^2 = sh[0], formed by
+        // every thread alike; thread c - j - 1 forms the coefficient of column c
+        const double alpha = V[j + j * ld];
+        const double xn2 = sh[0];
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        {
             // coefficient tau * (v . a_c), v = [1; scal * x[1:]]
-            for (int c = j + 1; c < w; ++c) coef[c] = tau * (V[j + c * ld] + scal * sh[1 + (c - j - 1)]);
-            V[j + j * ld] = beta;
+            const int c = j + 1 + (int)threadIdx.x;
+            if (c < w) coef[c] = tau * (V[j + c * ld] + scal * sh[1 + threadIdx.x]);
         }
         __syncthreads();
-        const double scal = s_scal;
+        if (threadIdx.x == 0) {
+            it.tau[col0 + j] = tau;
+            V[j + j * ld] = beta;
+        }
 #pragma unroll
         for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
-        // one pass: scale v, update columns > j, accumulate for column j+1
+        // one pass: scale v, update columns > j, accumulate for column j+1.
+        // All of a row's loads are issued before its first store, so they
+        // are in flight together.
         for (int r = j + threadIdx.x; r < mp; r += PANEL_THREADS) {
+            double x[QR_NB];
+            const double* row = V + r + (int64_t)j * ld;
+#pragma unroll
+            for (int c = 0; c < QR_NB; ++c) x[c] = (j + c < w) ? row[(int64_t)c * ld] : 0.0;
             double v = 1.0;
             if (r > j) {
-                v = V[r + j * ld] * scal;
+                v = x[0] * scal;
                 V[r + j * ld] = v;
             }
             double xn = 0.0;
@@ -722,8 +727,8 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
             for (int c = 1; c < QR_NB; ++c) {
                 const int cc = j + c;
                 if (cc < w) {
-                    const double a = V[r + cc * ld] - coef[cc] * v;
-                    if (r != j || true) V[r + cc * ld] = a;
+                    const double a = x[c] - coef[cc] * v;
+                    V[r + cc * ld] = a;
                     if (c == 1) {
                         xn = a;
                         if (r > j + 1) part[0] += a * a;
