@@ -662,31 +662,13 @@ __device__ __forceinline__ void panel_reduce(double (&part)[QR_NB + 1], int nval
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int nitems, int col0) {
-    __shared__ double red[PANEL_THREADS / 64][QR_NB + 2];
-    __shared__ double sh[QR_NB + 2];  // sh[0] = norm^2 below diag of the current column, sh[1+k] = dots
-    __shared__ double coef[QR_NB];
-    const int b = blockIdx.x;
-    if (b >= nitems) return;
-    const QRItem it = q[b];
-    if (it.nfac <= col0 || it.A.m <= col0) return;
-    const int w = min(QR_NB, it.nfac - col0);
-    const int mp = qr_rows(it.A.m, it.zrow, col0, QR_NB) - col0;
-    const int64_t ld = it.A.ld;
-    double* V = it.A.p + col0 + (int64_t)col0 * ld;
+// Columns [jb, je) of the panel, one pass each, updating columns < wl.  On
+// entry sh[0] is the squared norm of column jb below its diagonal and
+// sh[1 + k] its product with column jb + 1 + k (rows below the diagonal).
+__device__ __forceinline__ void panel_cols(const QRItem& it, int col0, double* V, int64_t ld, int mp, int jb,
+                                           int je, int wl, double (*red)[QR_NB + 2], double* sh, double* coef) {
     double part[QR_NB + 1];
-    // column 0: norm^2 of x[1:] and products x[1:] . a_c[1:], c = 1..w-1
-#pragma unroll
-    for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
-    for (int r = 1 + threadIdx.x; r < mp; r += PANEL_THREADS) {
-        const double x = V[r];
-        part[0] += x * x;
-#pragma unroll
-        for (int c = 1; c < QR_NB; ++c)
-            if (c < w) part[c] += x * V[r + c * ld];
-    }
-    panel_reduce(part, w, red, sh);
-    for (int j = 0; j < w; ++j) {
+    for (int j = jb; j < je; ++j) {
         // reflector j from alpha = V[j][j] and ||x[1:]||^2 = sh[0], formed by
         // every thread alike; thread c - j - 1 forms the coefficient of column c
         const double alpha = V[j + j * ld];
@@ -700,7 +682,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
         {
             // coefficient tau * (v . a_c), v = [1; scal * x[1:]]
             const int c = j + 1 + (int)threadIdx.x;
-            if (c < w) coef[c] = tau * (V[j + c * ld] + scal * sh[1 + threadIdx.x]);
+            if (c < wl) coef[c] = tau * (V[j + c * ld] + scal * sh[1 + threadIdx.x]);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -709,14 +691,14 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
         }
 #pragma unroll
         for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
-        // one pass: scale v, update columns > j, accumulate for column j+1.
-        // All of a row's loads are issued before its first store, so they
-        // are in flight together.
+        // one pass: scale v, update columns j+1..wl-1, accumulate for column
+        // j+1.  All of a row's loads are issued before its first store, so
+        // they are in flight together.
         for (int r = j + threadIdx.x; r < mp; r += PANEL_THREADS) {
             double x[QR_NB];
             const double* row = V + r + (int64_t)j * ld;
 #pragma unroll
-            for (int c = 0; c < QR_NB; ++c) x[c] = (j + c < w) ? row[(int64_t)c * ld] : 0.0;
+            for (int c = 0; c < QR_NB; ++c) x[c] = (j + c < wl) ? row[(int64_t)c * ld] : 0.0;
             double v = 1.0;
             if (r > j) {
                 v = x[0] * scal;
@@ -726,7 +708,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
 #pragma unroll
             for (int c = 1; c < QR_NB; ++c) {
                 const int cc = j + c;
-                if (cc < w) {
+                if (cc < wl) {
                     const double a = x[c] - coef[cc] * v;
                     V[r + cc * ld] = a;
                     if (c == 1) {
@@ -739,8 +721,147 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
             }
         }
         __syncthreads();
-        if (j + 1 < w) panel_reduce(part, w - j - 1, red, sh);
+        if (j + 1 < je) panel_reduce(part, wl - j - 1, red, sh);
     }
+}
+
+// The panel is factored in two halves of QR_HB columns: the first half by
+// the column passes above (touching only its own columns), then one pass
+// applies its reflectors to the second half in compact WY form,
+// A2 -= V1 T1^T (V1^T A2) (G1 = V1^T V1 and V1^T A2 by MFMA), and the second
+// half is factored.  Each pass over the panel thus moves about a third fewer
+// bytes than column passes over all 32 columns.
+constexpr int QR_HB = 16;
+
+__global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int nitems, int col0) {
+    __shared__ double red[PANEL_THREADS / 64][QR_NB + 2];
+    __shared__ double sh[QR_NB + 2];  // sh[0] = norm^2 below diag of the current column, sh[1+k] = dots
+    __shared__ double coef[QR_NB];
+    __shared__ double gz[2][PANEL_THREADS / 64][QR_HB * QR_HB];
+    __shared__ double G1[QR_HB][QR_HB + 1], Z1[QR_HB][QR_HB + 1], T1[QR_HB][QR_HB + 1], M1[QR_HB][QR_HB + 1];
+    const int b = blockIdx.x;
+    if (b >= nitems) return;
+    const QRItem it = q[b];
+    if (it.nfac <= col0 || it.A.m <= col0) return;
+    const int w = min(QR_NB, it.nfac - col0);
+    const int mp = qr_rows(it.A.m, it.zrow, col0, QR_NB) - col0;
+    const int64_t ld = it.A.ld;
+    double* V = it.A.p + col0 + (int64_t)col0 * ld;
+    const int w1 = (w > QR_HB) ? QR_HB : w;  // first half
+    double part[QR_NB + 1];
+    // column 0: norm^2 of x[1:] and products x[1:] . a_c[1:], c = 1..w1-1
+#pragma unroll
+    for (int c = 0; c <= QR_NB; ++c) part[c] = 0.0;
+    for (int r = 1 + threadIdx.x; r < mp; r += PANEL_THREADS) {
+        const double x = V[r];
+        part[0] += x * x;
+#pragma unroll
+        for (int c = 1; c < QR_HB; ++c)
+            if (c < w1) part[c] += x * V[r + c * ld];
+    }
+    panel_reduce(part, w1, red, sh);
+    panel_cols(it, col0, V, ld, mp, 0, w1, w1, red, sh, coef);
+    if (w <= QR_HB) return;
+
+    // second half: G1 = V1^T V1, Z1 = V1^T A2 (V1 unit lower trapezoid)
+    const int w2 = w - QR_HB;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    {
+        double4_t ag = {0.0, 0.0, 0.0, 0.0}, az = {0.0, 0.0, 0.0, 0.0};
+        const int k = lane & 15;
+#pragma unroll 4
+        for (int r0 = 4 * wv; r0 < mp; r0 += 4 * (PANEL_THREADS / 64)) {
+            const int r = r0 + (lane >> 4);
+            double v = 0.0, a2 = 0.0;
+            if (r < mp) {
+                v = (r < k) ? 0.0 : (r == k ? 1.0 : V[r + k * ld]);
+                if (k < w2) a2 = V[r + (QR_HB + k) * ld];
+            }
+            ag = mfma_f64(v, v, ag);
+            az = mfma_f64(v, a2, az);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ij = (4 * e + (lane >> 4)) * QR_HB + (lane & 15);
+            gz[0][wv][ij] = ag[e];
+            gz[1][wv][ij] = az[e];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < QR_HB * QR_HB) {
+        const int e = threadIdx.x;
+        double g = 0.0, z = 0.0;
+        for (int q2 = 0; q2 < PANEL_THREADS / 64; ++q2) {
+            g += gz[0][q2][e];
+            z += gz[1][q2][e];
+        }
+        G1[e / QR_HB][e % QR_HB] = g;
+        Z1[e / QR_HB][e % QR_HB] = z;
+        T1[e / QR_HB][e % QR_HB] = 0.0;
+    }
+    __syncthreads();
+    // T1(0:j, j) = -tau_j T1(0:j, 0:j) G1(0:j, j), T1(j, j) = tau_j
+    for (int j = 0; j < QR_HB; ++j) {
+        const double tj = it.tau[col0 + j];
+        if ((int)threadIdx.x < j) {
+            const int i = threadIdx.x;
+            double sum = 0.0;
+            for (int l = i; l < j; ++l) sum += T1[i][l] * G1[l][j];
+            T1[i][j] = -tj * sum;
+        }
+        if (threadIdx.x == 0) T1[j][j] = tj;
+        __syncthreads();
+    }
+    // M1 = T1^T Z1
+    if (threadIdx.x < QR_HB * QR_HB) {
+        const int kk = threadIdx.x / QR_HB, c = threadIdx.x % QR_HB;
+        double sum = 0.0;
+        for (int i = 0; i <= kk; ++i) sum += T1[i][kk] * Z1[i][c];
+        M1[kk][c] = sum;
+    }
+    __syncthreads();
+    // A2 -= V1 M1 on MFMA (a wave takes 16-row blocks; lane l ends with
+    // A2(r0 + 4e + l/16, l%16)), and the sums that start the second half:
+    // each lane accumulates column QR_HB times its own column
+    {
+        const int li = lane & 15, lq = lane >> 4;
+        double bm[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) bm[s4] = M1[4 * s4 + lq][li];
+        double pc = 0.0;
+        for (int r0 = 16 * wv; r0 < mp; r0 += 16 * (PANEL_THREADS / 64)) {
+            double4_t acc = {0.0, 0.0, 0.0, 0.0};
+            double a2[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + 4 * e + lq;
+                a2[e] = (r < mp && li < w2) ? V[r + (int64_t)(QR_HB + li) * ld] : 0.0;
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int r = r0 + li, k = 4 * s4 + lq;
+                double v = 0.0;
+                if (r < mp) v = (r < k) ? 0.0 : (r == k ? 1.0 : V[r + (int64_t)k * ld]);
+                acc = mfma_f64(v, bm[s4], acc);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + 4 * e + lq;
+                double a = 0.0;
+                if (r < mp && li < w2) {
+                    a = a2[e] - acc[e];
+                    V[r + (int64_t)(QR_HB + li) * ld] = a;
+                }
+                const double a0 = __shfl(a, lane & 0x30, 64);  // column QR_HB of the same row
+                if (r > QR_HB) pc += a0 * a;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c <= QR_NB; ++c) part[c] = (c == li) ? pc : 0.0;
+    }
+    __syncthreads();
+    panel_reduce(part, w2, red, sh);
+    panel_cols(it, col0, V, ld, mp, QR_HB, w, w, red, sh, coef);
 }
 
 // T factor for the reflectors of panel k: T = upper triangular with
