@@ -313,7 +313,7 @@ struct OpBUpd {
     const UpdSrc* src;
     __device__ int tiles(int b) const { return ((jobs[b].M + 63) / 64) * ((jobs[b].N + 63) / 64); }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const UpdJob J = jobs[b];
         const int tm = (J.M + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
@@ -321,9 +321,9 @@ struct OpBUpd {
         acc_zero(acc);
         for (int q = 0; q < J.nsrc; ++q) {
             const UpdSrc S = src[J.src0 + q];
-            mfma_tile_64<false, true>(S.A, S.ld, S.B, S.ld, J.M, J.N, S.K, i0, j0, sm, acc);
+            mfma_tile_64<false, true>(S.A, S.ld, S.B, S.ld, J.M, J.N, S.K, i0, j0, sm.t, acc);
         }
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < J.M && gj < J.N) J.out[gi + (int64_t)gj * J.ldo] -= v;
         });

@@ -17,17 +17,17 @@ struct OpGemm {
     __device__ int tiles(int b) const { return ceil_div_d(g[b].M, 64) * ceil_div_d(g[b].N, 64); }
     __device__ static int ceil_div_d(int a, int c) { return a > 0 ? (a + c - 1) / c : 0; }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const GemmItem& G = g[b];
         const int tm = ceil_div_d(G.M, 64);
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<TA, TB>(G.A, G.lda, G.B, G.ldb, G.M, G.N, G.K, i0, j0, sm, acc);
+        mfma_tile_64<TA, TB>(G.A, G.lda, G.B, G.ldb, G.M, G.N, G.K, i0, j0, sm.t, acc);
         double* C = G.C;
         const int ldc = G.ldc, M = G.M, N = G.N;
         const double al = G.alpha, be = G.beta;
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < M && gj < N) {
                 double* p = C + gi + (int64_t)gj * ldc;
@@ -63,7 +63,7 @@ struct OpSyrk {
         return T * (T + 1) / 2;
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const GemmItem& G = g[b];
         int tj = 0, r = t;
         const int T = (G.M + 63) / 64;
@@ -75,11 +75,11 @@ struct OpSyrk {
         const int i0 = ti * 64, j0 = tj * 64;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, true>(G.A, G.lda, G.A, G.lda, G.M, G.M, G.K, i0, j0, sm, acc);
+        mfma_tile_64<false, true>(G.A, G.lda, G.A, G.lda, G.M, G.M, G.K, i0, j0, sm.t, acc);
         double* C = G.C;
         const int ldc = G.ldc, M = G.M;
         const double al = G.alpha, be = G.beta;
-        acc_foreach(acc, [&](int rr, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int rr, int c, double v) {
             const int gi = i0 + rr, gj = j0 + c;
             if (gi < M && gj < M) {
                 double* p = C + gi + (int64_t)gj * ldc;
@@ -102,17 +102,17 @@ struct OpGemmUpperA {
     const GemmItem* g;
     __device__ int tiles(int b) const { return ((g[b].M + 63) / 64) * ((g[b].N + 63) / 64); }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const GemmItem& G = g[b];
         const int tm = (G.M + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, false>(G.A + (int64_t)i0 * G.lda, G.lda, G.B + i0, G.ldb, G.M, G.N, G.K - i0, i0, j0, sm, acc);
+        mfma_tile_64<false, false>(G.A + (int64_t)i0 * G.lda, G.lda, G.B + i0, G.ldb, G.M, G.N, G.K - i0, i0, j0, sm.t, acc);
         double* C = G.C;
         const int ldc = G.ldc, M = G.M, N = G.N;
         const double al = G.alpha, be = G.beta;
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < M && gj < N) {
                 double* p = C + gi + (int64_t)gj * ldc;
@@ -404,7 +404,7 @@ struct OpPotrfUpdate {
         return TC * TR - TC * (TC - 1) / 2;
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const DMat M = A[b];
         int TR, TC;
         dims(M, TR, TC);
@@ -418,9 +418,9 @@ struct OpPotrfUpdate {
         const double* A21 = M.p + mid + (int64_t)c0 * M.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, mid - c0, ti * 64, tj * 64, sm, acc);
+        mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, mid - c0, ti * 64, tj * 64, sm.t, acc);
         double* C = M.p + mid + (int64_t)mid * M.ld;
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = ti * 64 + r, gj = tj * 64 + c;
             if (gi < rows && gj < cols && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
         });
@@ -547,7 +547,7 @@ struct OpTrsmGemm {
         return ((M + 63) / 64) * min((B[b].n + 63) / 64, ncap);
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmem sm;
+        __shared__ TileSmemC sm;
         const DMat Lm = L[b], Bm = B[b];
         const int e = min(Lm.n, r1);
         const int M = TRANS ? mid - r0 : e - mid;
@@ -559,14 +559,14 @@ struct OpTrsmGemm {
         const double* A = Lm.p + mid + (int64_t)r0 * Lm.ld;  // L[mid:e, r0:mid]
         double* Cp;
         if (!TRANS) {
-            mfma_tile_64<false, false>(A, Lm.ld, Bm.p + r0, Bm.ld, M, Bm.n, K, i0, j0, sm, acc);
+            mfma_tile_64<false, false>(A, Lm.ld, Bm.p + r0, Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
             Cp = Bm.p + mid;
         } else {
-            mfma_tile_64<true, false>(A, Lm.ld, Bm.p + mid, Bm.ld, M, Bm.n, K, i0, j0, sm, acc);
+            mfma_tile_64<true, false>(A, Lm.ld, Bm.p + mid, Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
             Cp = Bm.p + r0;
         }
         const int N = Bm.n, ld = Bm.ld;
-        acc_foreach(acc, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < M && gj < N) Cp[gi + (int64_t)gj * ld] -= v;
         });
