@@ -1889,48 +1889,117 @@ __device__ int sturm_count(const double* d, const double* e, int n, double x, do
     return cnt;
 }
 
-struct OpStebz {
+// Gershgorin interval, pivmin and the number of eigenvalues below the
+// threshold (capped), one thread per item: aux[3b..3b+2] = (gl, gu, pivmin).
+struct OpStebzCount {
     const EigItem* it;
-    __device__ int tiles(int b) const { return it[b].n > 0 ? 1 : 0; }
+    double* aux;
+    __device__ int tiles(int b) const { return 1; }
     __device__ void operator()(int b, int) const {
-        __shared__ double gl, gu, pivmin;
-        __shared__ int cnt;
         const EigItem& E = it[b];
         const int n = E.n;
-        if (threadIdx.x == 0) {
-            double lo = 1e300, hi = -1e300, emax = 0.0;
-            for (int i = 0; i < n; ++i) {
-                const double r = (i > 0 ? fabs(E.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(E.e[i]) : 0.0);
-                lo = fmin(lo, E.d[i] - r);
-                hi = fmax(hi, E.d[i] + r);
-                if (i < n - 1) emax = fmax(emax, E.e[i] * E.e[i]);
+        if (threadIdx.x != 0) return;
+        if (n <= 0) {
+            *E.count = 0;
+            return;
+        }
+        double lo = 1e300, hi = -1e300, emax = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double r = (i > 0 ? fabs(E.e[i - 1]) : 0.0) + (i < n - 1 ? fabs(E.e[i]) : 0.0);
+            lo = fmin(lo, E.d[i] - r);
+            hi = fmax(hi, E.d[i] + r);
+            if (i < n - 1) emax = fmax(emax, E.e[i] * E.e[i]);
+        }
+        const double nrm = fmax(fabs(lo), fabs(hi));
+        const double pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax) * 4.0;
+        aux[3 * b] = lo - 2.0 * nrm * 2.220446049250313e-16 * n - pivmin;
+        aux[3 * b + 1] = hi + 2.0 * nrm * 2.220446049250313e-16 * n + pivmin;
+        aux[3 * b + 2] = pivmin;
+        *E.count = min(sturm_count(E.d, E.e, n, E.thr, pivmin), E.cap);
+    }
+};
+
+// j-th smallest eigenvalue = smallest x with count(x) >= j + 1, by 4-point
+// multisection: four lanes evaluate the Sturm count at the interior points
+// of a 5-way split of [lo, hi] and the interval shrinks to the sub-interval
+// where the count first reaches j + 1.  The stopping test is that of plain
+// bisection (width <= 2 eps max(|lo|, |hi|) + pivmin).  A tile is 64
+// eigenvalues; d and e^2 are staged in LDS when they fit.
+constexpr int STEBZ_LDS = 4096;  // doubles per array staged in LDS
+struct OpStebzBisect {
+    const EigItem* it;
+    const double* aux;
+    __device__ int tiles(int b) const { return (min(it[b].n, it[b].cap) + 63) / 64; }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double ds[STEBZ_LDS], e2s[STEBZ_LDS];
+        const EigItem& E = it[b];
+        const int n = E.n;
+        const int cnt = *E.count;
+        if (t * 64 >= cnt) return;
+        const bool inl = n <= STEBZ_LDS;
+        if (inl) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                ds[i] = E.d[i];
+                e2s[i] = (i < n - 1) ? E.e[i] * E.e[i] : 0.0;
             }
-            const double nrm = fmax(fabs(lo), fabs(hi));
-            pivmin = fmax(2.2250738585072014e-308, 2.2250738585072014e-308 * emax) * 4.0;
-            gl = lo - 2.0 * nrm * 2.220446049250313e-16 * n - pivmin;
-            gu = hi + 2.0 * nrm * 2.220446049250313e-16 * n + pivmin;
-            int c = sturm_count(E.d, E.e, n, E.thr, pivmin);
-            cnt = min(c, E.cap);
-            *E.count = cnt;
         }
         __syncthreads();
+        const double* d = inl ? ds : E.d;
+        const double gl = aux[3 * b], gu = aux[3 * b + 1], pivmin = aux[3 * b + 2];
         const double eps = 2.220446049250313e-16;
-        for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
-            // j-th smallest eigenvalue: smallest x with count(x) >= j+1
-            double lo = gl, hi = fmin(gu, E.thr);
-            for (int itn = 0; itn < 200; ++itn) {
-                const double mid = 0.5 * (lo + hi);
-                if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-                if (sturm_count(E.d, E.e, n, mid, pivmin) >= j + 1) hi = mid;
-                else lo = mid;
+        const int lane = threadIdx.x & 63, sub = lane & 3;
+        const int j = t * 64 + (int)(threadIdx.x >> 2);
+        const bool active = j < cnt;  // uniform over the 4 lanes of an eigenvalue
+        double lo = gl, hi = fmin(gu, E.thr);
+        for (int itn = 0; itn < 200; ++itn) {
+            const bool done = !active || (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin);
+            if (__all(done)) break;
+            const double h = (hi - lo) * 0.2;
+            const double x = lo + (sub + 1) * h;
+            int c = 0;
+            if (!done) {
+                double q = d[0] - x;
+                if (fabs(q) < pivmin) q = -pivmin;
+                if (q < 0) ++c;
+                if (inl) {
+                    for (int i = 1; i < n; ++i) {
+                        q = d[i] - x - e2s[i - 1] / q;
+                        if (fabs(q) < pivmin) q = -pivmin;
+                        if (q < 0) ++c;
+                    }
+                } else {
+                    for (int i = 1; i < n; ++i) {
+                        q = d[i] - x - E.e[i - 1] * E.e[i - 1] / q;
+                        if (fabs(q) < pivmin) q = -pivmin;
+                        if (q < 0) ++c;
+                    }
+                }
             }
-            E.mu[j] = 0.5 * (lo + hi);
+            // flags of the 4 points of this eigenvalue: bit k = count(x_k) >= j + 1
+            const int f = (c >= j + 1) ? 1 : 0;
+            const int base = lane & ~3;
+            const int f0 = __shfl(f, base, 64), f1 = __shfl(f, base + 1, 64);
+            const int f2 = __shfl(f, base + 2, 64), f3 = __shfl(f, base + 3, 64);
+            if (!done) {
+                // first point whose count reaches j + 1 (4 if none)
+                const int k = f0 ? 0 : (f1 ? 1 : (f2 ? 2 : (f3 ? 3 : 4)));
+                const double nlo = (k == 0) ? lo : lo + k * h;
+                const double nhi = (k == 4) ? hi : lo + (k + 1) * h;
+                lo = nlo;
+                hi = nhi;
+            }
         }
+        if (active && sub == 0) E.mu[j] = 0.5 * (lo + hi);
     }
 };
 
 void stebz_vb(Batch<EigItem>& e, hipStream_t s) {
-    launch_tiles(OpStebz{e.d.p}, e.size(), e.size(), s, "stebz");
+    DBuf<double> aux(3 * std::max(1, e.size()));
+    int64_t nt = 0;
+    for (auto& x : e.h) nt += ceil_div(std::min(x.n, x.cap), 64);
+    launch_tiles(OpStebzCount{e.d.p, aux.p}, e.size(), e.size(), s, "stebz_count");
+    if (nt) launch_tiles(OpStebzBisect{e.d.p, aux.p}, e.size(), nt, s, "stebz");
+    DD_HIP(hipStreamSynchronize(s));  // aux is freed on return
 }
 
 // ===========================================================================
