@@ -629,7 +629,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         std::vector<int64_t> sy(N), sw(N);
         for (int i = 0; i < N; ++i) {
             sy[i] = (int64_t)nI[i] * std::max(1, Lv.p[i]);
-            sw[i] = (int64_t)4 * nI[i] * 256;
+            sw[i] = stein_work_size(nI[i], Lv.p[i]);
         }
         Yev.alloc(sy);
         Arena wk;

@@ -184,22 +184,40 @@ struct OpTrmvRed {
         I.y[r] = v;
     }
 };
-// x_j = W(j:n, j)^T y(j:n): a tile is 16 columns, 4 per wave, each a
-// contiguous column segment read by the 64 lanes.
+// x_j = W(j:n, j)^T y(j:n): a tile is 16 columns (4 per wave, each a
+// contiguous column segment read by the 64 lanes) by a chunk of TRMV_CC rows
+// at or below the columns' diagonal block; its dots go to part[chunk n + j]
+// and OpTrmvTRed sums them.  Short chunks keep every wave's chain of
+// dependent loads short.
+__host__ __device__ inline int trmv_t_tiles(int n) {
+    const int ng = (n + 15) / 16, nch = (n + TRMV_CC - 1) / TRMV_CC;
+    int t = 0;
+    for (int c = 0; c < nch; ++c) t += min(ng, (TRMV_CC / 16) * (c + 1));
+    return t;
+}
 template <class TW>
 struct OpTrmvT {
     const TrmvItemT<TW>* it;
-    __device__ int tiles(int b) const { return (it[b].n + 15) / 16; }
+    __device__ int tiles(int b) const { return trmv_t_tiles(it[b].n); }
     __device__ void operator()(int b, int t) const {
         const TrmvItemT<TW>& I = it[b];
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int j0 = t * 16 + w * 4;
         const int n = I.n;
+        const int ng = (n + 15) / 16;
+        int c = 0, g = t;
+        for (;;) {
+            const int k = min(ng, (TRMV_CC / 16) * (c + 1));
+            if (g < k) break;
+            g -= k;
+            ++c;
+        }
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int j0 = g * 16 + w * 4;
+        const int rb = max(c * TRMV_CC, g * 16), re = min(n, (c + 1) * TRMV_CC);
         TW accw[4] = {0, 0, 0, 0};
         if (j0 < n) {
             const int jn = min(4, n - j0);
-            // rows >= j0 + q for column j0 + q; start at j0 (W is zero above the diagonal)
-            for (int i = j0 + lane; i < n; i += 64) {
+            // W is zero above the diagonal, so rows from the block's first column on
+            for (int i = rb + lane; i < re; i += 64) {
                 const TW yi = (TW)I.y[i];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -211,7 +229,22 @@ struct OpTrmvT {
         for (int q = 0; q < 4; ++q) acc[q] = wave_sum((double)accw[q]);
         if (lane == 0)
             for (int q = 0; q < 4; ++q)
-                if (j0 + q < n) I.x[j0 + q] = acc[q];
+                if (j0 + q < n) I.part[(int64_t)c * n + j0 + q] = acc[q];
+    }
+};
+// x_j = sum of the partials of the chunks from the one holding j on
+template <class TW>
+struct OpTrmvTRed {
+    const TrmvItemT<TW>* it;
+    __device__ int tiles(int b) const { return (it[b].n + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const TrmvItemT<TW>& I = it[b];
+        const int j = t * 256 + threadIdx.x;
+        if (j >= I.n) return;
+        const int nch = (I.n + TRMV_CC - 1) / TRMV_CC;
+        double v = 0.0;
+        for (int c = j / TRMV_CC; c < nch; ++c) v += I.part[(int64_t)c * I.n + j];
+        I.x[j] = v;
     }
 };
 
@@ -227,9 +260,13 @@ static void trmv_n_t(Batch<TrmvItemT<TW>>& t, hipStream_t s) {
 }
 template <class TW>
 static void trmv_t_t(Batch<TrmvItemT<TW>>& t, hipStream_t s) {
-    int64_t tt = 0;
-    for (auto& x : t.h) tt += ceil_div(x.n, 16);
+    int64_t tt = 0, tr = 0;
+    for (auto& x : t.h) {
+        tt += trmv_t_tiles(x.n);
+        tr += ceil_div(x.n, 256);
+    }
     launch_tiles(OpTrmvT<TW>{t.d.p}, t.size(), tt, s, "trmv_t");
+    launch_tiles(OpTrmvTRed<TW>{t.d.p}, t.size(), tr, s, "trmv_t_red");
 }
 
 void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s) { trmv_n_t(t, s); }
@@ -2069,8 +2106,9 @@ __device__ double start_value(int i, int j) {
 struct OpSteinSolve {
     const VecItem* it;
     int first;
-    __device__ int tiles(int b) const { return it[b].n > 0 ? 1 : 0; }
-    __device__ void operator()(int b, int) const {
+    // 256 eigenvectors per workgroup, each workgroup with its own work arrays
+    __device__ int tiles(int b) const { return it[b].n > 0 ? (*it[b].count + 255) / 256 : 0; }
+    __device__ void operator()(int b, int tile) const {
         __shared__ int s_cnt;
         __shared__ double s_tn;
         const VecItem& V = it[b];
@@ -2086,11 +2124,13 @@ struct OpSteinSolve {
         const int p = s_cnt;
         const double tiny = 2.220446049250313e-16 * s_tn;
         const int t = threadIdx.x;
-        double* u1 = V.work + t;
+        double* u1 = V.work + (int64_t)tile * 4 * n * 256 + t;
         double* u2 = u1 + (int64_t)n * 256;
         double* u3 = u2 + (int64_t)n * 256;
         double* x = u3 + (int64_t)n * 256;
-        for (int j = t; j < p; j += 256) {
+        {
+            const int j = tile * 256 + t;
+            if (j >= p) return;
             double* y = V.Y + (int64_t)j * V.ldy;
             for (int i = 0; i < n; ++i) x[(int64_t)i * 256] = first ? start_value(i, j) : y[i];
             tri_solve(V.d, V.e, n, V.mu[j], u1, u2, u3, x, 256, tiny);
@@ -2159,8 +2199,10 @@ void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, do
     Qs.h = hsrc;
     Ys.h = hdst;
     if (!cls.empty()) { Qs.sync(s); Ys.sync(s); }
+    int64_t nst = 0;
+    for (int b = 0; b < v.size(); ++b) nst += ceil_div((int64_t)hmu[b].size(), 256);
     for (int round = 0; round < 3; ++round) {
-        launch_tiles(OpSteinSolve{v.d.p, round == 0}, v.size(), v.size(), s, "stein_solve");
+        launch_tiles(OpSteinSolve{v.d.p, round == 0}, v.size(), nst, s, "stein_solve");
         if (!cls.empty()) {
             geqrf_vb(qb, s);
             set_identity_vb(Qs, 1.0, s);

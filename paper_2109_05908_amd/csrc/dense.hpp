@@ -159,8 +159,11 @@ struct VecItem {
     const int* count;
     double* Y;
     int ldy;
-    double* work;  // 4 n * 256 doubles
+    double* work;  // stein_work_size(n, number of eigenvalues) doubles
 };
+inline int64_t stein_work_size(int n, int count) {
+    return (int64_t)4 * n * 256 * std::max<int64_t>(1, (count + 255) / 256);
+}
 void stein_vb(Batch<VecItem>& v, const std::vector<std::vector<double>>& hmu, double cluster_tol, hipStream_t s);
 
 // Local solves with explicit triangular inverses: x := W^T (W x) for W lower
