@@ -390,32 +390,56 @@ struct OpFwdPart {
         const SolSrc S = src[C.src];
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         const int r = tile * 64 + lane;
-        double acc = 0.0;
-        if (r < S.rows)
-            for (int c = C.c0 + wv; c < C.c1; c += 4) acc += S.L[r + (int64_t)c * S.ld] * x[S.xoff + c];
-        red[wv][lane] = acc;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;  // four loads in flight per lane
+        if (r < S.rows) {
+            const double* Lr = S.L + r;
+            const double* xs = x + S.xoff;
+            int c = C.c0 + wv;
+            for (; c + 12 < C.c1; c += 16) {
+                a0 += Lr[(int64_t)c * S.ld] * xs[c];
+                a1 += Lr[(int64_t)(c + 4) * S.ld] * xs[c + 4];
+                a2 += Lr[(int64_t)(c + 8) * S.ld] * xs[c + 8];
+                a3 += Lr[(int64_t)(c + 12) * S.ld] * xs[c + 12];
+            }
+            for (; c < C.c1; c += 4) a0 += Lr[(int64_t)c * S.ld] * xs[c];
+        }
+        red[wv][lane] = (a0 + a1) + (a2 + a3);
         __syncthreads();
         if (wv == 0 && r < S.rows)
             part[nd.part0 + (int64_t)(g - nd.fch0) * nd.w + S.ridx[r]] =
                 (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     }
 };
-// pass 2 (both directions): t_K = y_K - sum of the node's partials (in chunk order)
+// pass 2 (both directions): t_K = y_K - sum of the node's partials.  A tile
+// is 64 rows (lane = row); wave wv sums the partials q = wv, wv + 4, ... with
+// two accumulators, and the four wave sums are added in a fixed order.
 struct OpSolRed {
     const SolNode* nodes;
     const double* part;
     const double* y;
     double* t;
     int backward;
-    __device__ int tiles(int b) const { return (nodes[b].w + 255) / 256; }
+    __device__ int tiles(int b) const { return (nodes[b].w + 63) / 64; }
     __device__ void operator()(int b, int tile) const {
+        __shared__ double red[4][64];
         const SolNode nd = nodes[b];
-        const int r = tile * 256 + threadIdx.x;
-        if (r >= nd.w) return;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int r = tile * 64 + lane;
         const int nch = backward ? nd.nbch : nd.nfch;
-        double acc = 0.0;
-        for (int q = 0; q < nch; ++q) acc += part[nd.part0 + (int64_t)q * nd.w + r];
-        t[nd.start + r] = y[nd.start + r] - acc;
+        double a0 = 0.0, a1 = 0.0;
+        if (r < nd.w) {
+            const double* p = part + nd.part0 + r;
+            int q = wv;
+            for (; q + 4 < nch; q += 8) {
+                a0 += p[(int64_t)q * nd.w];
+                a1 += p[(int64_t)(q + 4) * nd.w];
+            }
+            for (; q < nch; q += 4) a0 += p[(int64_t)q * nd.w];
+        }
+        red[wv][lane] = a0 + a1;
+        __syncthreads();
+        if (wv == 0 && r < nd.w)
+            t[nd.start + r] = y[nd.start + r] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
     }
 };
 // backward, pass 1: partial column dots of panel K over one chunk of rows below the diagonal block
@@ -425,19 +449,32 @@ struct OpBwdPart {
     double* part;
     __device__ int tiles(int b) const { return nodes[b].nbch * ((nodes[b].w + 63) / 64); }
     __device__ void operator()(int b, int tile) const {
+        __shared__ double xs[kSolRow];  // x at the chunk's rows, gathered once
         const SolNode nd = nodes[b];
         const int nct = (nd.w + 63) / 64;
         const int rc = tile / nct, ct = tile % nct;
         const int q0 = nd.w + rc * kSolRow, q1 = min(nd.h, q0 + kSolRow);
+        for (int q = q0 + (int)threadIdx.x; q < q1; q += blockDim.x) xs[q - q0] = x[nd.gidx[q - nd.w]];
+        __syncthreads();
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int cc = wv; cc < 64; cc += 4) {
-            const int c = ct * 64 + cc;
-            if (c >= nd.w) break;
-            const double* col = nd.panel + (int64_t)c * nd.h;
-            double acc = 0.0;
-            for (int q = q0 + lane; q < q1; q += 64) acc += col[q] * x[nd.gidx[q - nd.w]];
-            acc = wave_sum(acc);
-            if (lane == 0) part[nd.part0 + (int64_t)rc * nd.w + c] = acc;
+        // wave wv: columns ct*64 + 16 wv + k, k < 16, all sixteen in flight together
+        const int c0 = ct * 64 + 16 * wv;
+        const int nk = min(16, nd.w - c0);
+        if (nk <= 0) return;
+        const double* col = nd.panel + (int64_t)c0 * nd.h;
+        double acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+        for (int q = q0 + lane; q < q1; q += 64) {
+            const double xv = xs[q - q0];
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < nk) acc[k] += col[q + (int64_t)k * nd.h] * xv;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double v = wave_sum(acc[k]);
+            if (lane == 0 && k < nk) part[nd.part0 + (int64_t)rc * nd.w + c0 + k] = v;
         }
     }
 };
@@ -450,7 +487,7 @@ void BlockChol::solve(double* y, hipStream_t s) {
     const int L = (int)by_level.size();
     for (int l = 0; l < L; ++l) {
         int64_t tot4 = 0;
-        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 256);
+        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 64);
         if (fwd_tiles[l] > 0) {
             fill(pbuf.p, part_len[l], 0.0, s);
             launch_tiles(OpFwdPart{sol[l].d.p, sol_src[l].p, sol_ch[l].d.p, ybuf.p, pbuf.p}, sol_ch[l].size(),
@@ -461,7 +498,7 @@ void BlockChol::solve(double* y, hipStream_t s) {
     }
     for (int l = L - 1; l >= 0; --l) {
         int64_t tot4 = 0;
-        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 256);
+        for (auto& nd : sol[l].h) tot4 += ceil_div(nd.w, 64);
         if (bwd_tiles[l] > 0)
             launch_tiles(OpBwdPart{sol[l].d.p, ybuf.p, pbuf.p}, sol[l].size(), bwd_tiles[l], s, "bchol_bwd_part");
         launch_tiles(OpSolRed{sol[l].d.p, pbuf.p, ybuf.p, tbuf.p, 1}, sol[l].size(), tot4, s, "bchol_bwd_red");
