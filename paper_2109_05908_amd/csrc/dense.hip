@@ -2471,12 +2471,64 @@ struct OpLzMatvec {
     }
 };
 
-// alpha_j, full reorthogonalisation (twice), beta_j, v_{j+1}; convergence test
-// on the largest Ritz value every 4 steps.
-struct OpLzOrth {
+// Full reorthogonalisation of w against v_0..v_j by classical Gram-Schmidt
+// applied twice: h = V^T w (OpLzDots, 16 columns per workgroup), then
+// w -= V h (OpLzUpd, 256 rows per workgroup); hp holds 2 (K+1) doubles per
+// item, the dots of the two passes.
+struct OpLzDots {
     const LzItem* it;
-    int j;
-    int K;
+    double* const* hp;
+    int j, K, pass;
+    __device__ int tiles(int b) const { return (*it[b].done || j >= it[b].H.n) ? 0 : (j + 16) / 16; }
+    __device__ void operator()(int b, int t) const {
+        const LzItem& L = it[b];
+        const int n = L.H.n;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int i0 = t * 16 + wv * 4;
+        if (i0 > j) return;
+        const int ni = min(4, j + 1 - i0);
+        const double* V = L.V + (int64_t)i0 * n;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = lane; r < n; r += 64) {
+            const double wr = L.w[r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < ni) a[q] += V[r + (int64_t)q * n] * wr;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = wave_sum(a[q]);
+            if (lane == 0 && q < ni) hp[b][pass * (K + 1) + i0 + q] = v;
+        }
+    }
+};
+struct OpLzUpd {
+    const LzItem* it;
+    double* const* hp;
+    int j, K, pass;
+    __device__ int tiles(int b) const { return (*it[b].done || j >= it[b].H.n) ? 0 : (it[b].H.n + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const LzItem& L = it[b];
+        const int n = L.H.n;
+        const int r = t * 256 + threadIdx.x;
+        if (r >= n) return;
+        const double* h = hp[b] + pass * (K + 1);
+        double a0 = 0.0, a1 = 0.0;
+        int i = 0;
+        for (; i + 1 <= j; i += 2) {
+            a0 += L.V[r + (int64_t)i * n] * h[i];
+            a1 += L.V[r + (int64_t)(i + 1) * n] * h[i + 1];
+        }
+        for (; i <= j; ++i) a0 += L.V[r + (int64_t)i * n] * h[i];
+        L.w[r] -= a0 + a1;
+    }
+};
+// alpha_j (both passes), beta_j = ||w||, v_{j+1} = w / beta_j, and the
+// convergence test on the largest Ritz value every 4 steps.
+struct OpLzFinish {
+    const LzItem* it;
+    double* const* hp;
+    int j, K;
     __device__ int tiles(int b) const { return (*it[b].done || j >= it[b].H.n) ? 0 : 1; }
     __device__ void operator()(int b, int) const {
         __shared__ double red[4];
@@ -2484,27 +2536,17 @@ struct OpLzOrth {
         const LzItem& L = it[b];
         const int n = L.H.n;
         double* w = L.w;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int i = 0; i <= j; ++i) {
-                const double* vi = L.V + (int64_t)i * n;
-                double d = 0.0;
-                for (int r = threadIdx.x; r < n; r += blockDim.x) d += vi[r] * w[r];
-                d = block_sum(d, red);
-                if (i == j && threadIdx.x == 0) L.al[j] = (pass == 0) ? d : L.al[j] + d;
-                for (int r = threadIdx.x; r < n; r += blockDim.x) w[r] -= d * vi[r];
-                __syncthreads();
-            }
-        }
         double nr = 0.0;
         for (int r = threadIdx.x; r < n; r += blockDim.x) nr += w[r] * w[r];
         nr = sqrt(block_sum(nr, red));
         if (threadIdx.x == 0) {
+            L.al[j] = hp[b][j] + hp[b][(K + 1) + j];
             L.be[j] = nr;
             s_stop = 0;
             const bool last = (j + 1 >= min(K, n)) || nr == 0.0;
             if ((j % 4 == 3) || last) {
                 const double th = tri_max_eig(L.al, L.be, j + 1);
-                if (last || fabs(th - *L.theta) <= 1e-15 * fabs(th) || nr <= 1e-14 * fabs(th)) s_stop = 1;
+                if (last || fabs(th - *L.theta) <= 1e-13 * fabs(th) || nr <= 1e-14 * fabs(th)) s_stop = 1;
                 *L.theta = th;
             }
             if (s_stop) *L.done = 1;
@@ -2515,7 +2557,6 @@ struct OpLzOrth {
         for (int r = threadIdx.x; r < n; r += blockDim.x) vn[r] = w[r] / nr;
     }
 };
-
 __global__ void k_lz_init(LzItem* it, int nitems) {
     const int b = blockIdx.x;
     if (b >= nitems) return;
@@ -2548,17 +2589,31 @@ void lanczos_max_vb(Batch<DMat>& H, double* const* work, int K, double* dout, in
         lz.h.push_back(LzItem{H.h[b], V, w, al, be, dsteps + b, dout + b});
     }
     lz.sync(s);
+    DBuf<double> hbuf((int64_t)std::max(1, N) * 2 * (K + 1));
+    std::vector<double*> hh(N);
+    for (int b = 0; b < N; ++b) hh[b] = hbuf.p + (int64_t)b * 2 * (K + 1);
+    DBuf<double*> hp(std::max(1, N));
+    h2d(hp.p, hh.data(), N, s);
     hipLaunchKernelGGL(k_lz_init, dim3(N), dim3(256), 0, s, lz.d.p, N);
     launch_check("lz_init");
     std::vector<int> hdone(N);
     const int Kmax = std::min(K, nmax);
     for (int j = 0; j < Kmax; ++j) {
-        int64_t nt = 0;
+        int64_t nt = 0, nd = 0, nu = 0, nf = 0;
         for (int b = 0; b < N; ++b)
-            if (!hdone[b] && j < H.h[b].n) nt += ceil_div(H.h[b].n, 64);
+            if (!hdone[b] && j < H.h[b].n) {
+                nt += ceil_div(H.h[b].n, 64);
+                nd += (j + 16) / 16;
+                nu += ceil_div(H.h[b].n, 256);
+                ++nf;
+            }
         if (nt == 0) break;
         launch_tiles(OpLzMatvec{lz.d.p, j}, N, nt, s, "lz_matvec");
-        launch_tiles(OpLzOrth{lz.d.p, j, K}, N, N, s, "lz_orth");
+        for (int pass = 0; pass < 2; ++pass) {
+            launch_tiles(OpLzDots{lz.d.p, hp.p, j, K, pass}, N, nd, s, "lz_dots");
+            launch_tiles(OpLzUpd{lz.d.p, hp.p, j, K, pass}, N, nu, s, "lz_upd");
+        }
+        launch_tiles(OpLzFinish{lz.d.p, hp.p, j, K}, N, nf, s, "lz_finish");
         if (j % 8 == 7) {
             DD_HIP(hipMemcpyAsync(hdone.data(), dsteps, N * sizeof(int), hipMemcpyDeviceToHost, s));
             DD_HIP(hipStreamSynchronize(s));
