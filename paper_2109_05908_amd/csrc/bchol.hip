@@ -204,7 +204,7 @@ void BlockChol::allocate(hipStream_t s) {
             double* out = block(b, a, &ld);
             if (!out) throw Error(DD_ERR_INTERNAL, "coarse factor: update target outside the structure");
             const int l = lev[sn[a]];
-            upd[l].h.push_back(UpdJob{out, ld, p[b], p[a], (int)us[l].size(), (int)kv.second.size()});
+            upd[l].h.push_back(UpdJob{out, ld, p[b], p[a], (int)us[l].size(), (int)kv.second.size(), a == b ? 1 : 0});
             for (auto& src : kv.second) {
                 const int D = src.first;
                 us[l].push_back(UpdSrc{panels.p + poff[D] + srowoff[D][src.second.second],
@@ -311,12 +311,27 @@ void BlockChol::allocate(hipStream_t s) {
 struct OpBUpd {
     const UpdJob* jobs;
     const UpdSrc* src;
-    __device__ int tiles(int b) const { return ((jobs[b].M + 63) / 64) * ((jobs[b].N + 63) / 64); }
+    __device__ int tiles(int b) const {
+        const int tm = (jobs[b].M + 63) / 64, tn = (jobs[b].N + 63) / 64;
+        return jobs[b].lower ? tm * (tm + 1) / 2 : tm * tn;
+    }
     __device__ void operator()(int b, int t) const {
         __shared__ TileSmemC sm;
         const UpdJob J = jobs[b];
         const int tm = (J.M + 63) / 64;
-        const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
+        int i0, j0;
+        if (J.lower) {  // tile (ti, tj), ti >= tj, column by column
+            int tj = 0, r = t;
+            while (r >= tm - tj) {
+                r -= tm - tj;
+                ++tj;
+            }
+            i0 = (tj + r) * 64;
+            j0 = tj * 64;
+        } else {
+            i0 = (t % tm) * 64;
+            j0 = (t / tm) * 64;
+        }
         double4_t acc[2][2];
         acc_zero(acc);
         for (int q = 0; q < J.nsrc; ++q) {
@@ -335,7 +350,10 @@ int BlockChol::factor(hipStream_t s) {
     for (int l = 0; l < L; ++l) {
         if (!upd[l].h.empty()) {
             int64_t tot = 0;
-            for (auto& j : upd[l].h) tot += (int64_t)ceil_div(j.M, 64) * ceil_div(j.N, 64);
+            for (auto& j : upd[l].h) {
+                const int64_t tm = ceil_div(j.M, 64), tn = ceil_div(j.N, 64);
+                tot += j.lower ? tm * (tm + 1) / 2 : tm * tn;
+            }
             launch_tiles(OpBUpd{upd[l].d.p, upd_src[l].p}, upd[l].size(), tot, s, "bchol_update");
         }
         Batch<DMat> pn, dg, iv;

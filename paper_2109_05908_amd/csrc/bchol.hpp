@@ -18,6 +18,7 @@ struct UpdJob {
     int ldo;
     int M, N;
     int src0, nsrc;
+    int lower;  // diagonal block (A == B in every source): lower tiles only
 };
 // Forward-solve source: rows of a descendant supernode's panel that belong to
 // the target supernode (a contiguous row range of the panel), and where each
