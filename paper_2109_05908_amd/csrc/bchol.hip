@@ -211,6 +211,24 @@ void BlockChol::allocate(hipStream_t s) {
                                        panels.p + poff[D] + srowoff[D][src.second.first], h[D], w[D]});
             }
         }
+        if (std::getenv("DD_VERBOSE")) {
+            for (int l = 0; l < L; ++l) {
+                double fl = 0.0, ksum = 0.0;
+                int64_t tiles = 0;
+                for (auto& j : upd[l].h) {
+                    const int64_t tm = ceil_div(j.M, 64), tn = ceil_div(j.N, 64);
+                    tiles += j.lower ? tm * (tm + 1) / 2 : tm * tn;
+                    for (int q = 0; q < j.nsrc; ++q) {
+                        const double K = us[l][j.src0 + q].K;
+                        ksum += K;
+                        fl += 2.0 * j.M * j.N * K * (j.lower ? 0.5 : 1.0);
+                    }
+                }
+                if (!upd[l].h.empty())
+                    fprintf(stderr, "dd: coarse update level %d: %zu jobs, %zu sources (mean K %.0f), %lld tiles, %.3e flops\n",
+                            l, upd[l].h.size(), us[l].size(), ksum / std::max<size_t>(1, us[l].size()), (long long)tiles, fl);
+            }
+        }
         for (int l = 0; l < L; ++l) {
             if (!upd[l].h.empty()) upd[l].sync(s);
             upd_src[l].alloc(std::max<size_t>(1, us[l].size()));
