@@ -193,6 +193,108 @@ def diffusion3d(m: int, seed: int, sigma: float = 2.0, channels: int = 8,
 
 
 # --------------------------------------------------------------------------
+# 3-D linear elasticity, trilinear hexahedra (Q1), 3 dofs per node
+# --------------------------------------------------------------------------
+def elasticity_element(young: float, poisson: float, h: float) -> np.ndarray:
+    """24 x 24 stiffness of a cube of side h with trilinear shape functions,
+    isotropic material, 2x2x2 Gauss quadrature (exact for this element).
+
+    Local node a = dx + 2 dy + 4 dz sits at (dx, dy, dz) h; local dof 3a + c
+    is displacement component c (x, y, z).  Strains in Voigt order
+    (xx, yy, zz, yz, xz, xy) with engineering shears; lambda and mu from
+    (E, nu).
+    """
+    lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson))
+    mu = young / (2.0 * (1.0 + poisson))
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[0, 0] += 2.0 * mu
+    C[1, 1] += 2.0 * mu
+    C[2, 2] += 2.0 * mu
+    C[3, 3] = C[4, 4] = C[5, 5] = mu
+    sgn = np.array([[(a & 1), (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], dtype=float) * 2.0 - 1.0
+    g = 1.0 / math.sqrt(3.0)
+    K = np.zeros((24, 24))
+    for xi in (-g, g):
+        for eta in (-g, g):
+            for zeta in (-g, g):
+                q = np.array([xi, eta, zeta])
+                f = 1.0 + sgn * q                      # (8, 3) factors (1 + s_k q_k)
+                dN = np.empty((8, 3))                  # dN_a / d(xi, eta, zeta)
+                dN[:, 0] = sgn[:, 0] * f[:, 1] * f[:, 2] / 8.0
+                dN[:, 1] = f[:, 0] * sgn[:, 1] * f[:, 2] / 8.0
+                dN[:, 2] = f[:, 0] * f[:, 1] * sgn[:, 2] / 8.0
+                dx = dN * (2.0 / h)                    # the map is x = (h/2)(xi + 1)
+                B = np.zeros((6, 24))
+                for a in range(8):
+                    gx, gy, gz = dx[a]
+                    B[0, 3 * a] = gx
+                    B[1, 3 * a + 1] = gy
+                    B[2, 3 * a + 2] = gz
+                    B[3, 3 * a + 1] = gz
+                    B[3, 3 * a + 2] = gy
+                    B[4, 3 * a] = gz
+                    B[4, 3 * a + 2] = gx
+                    B[5, 3 * a] = gy
+                    B[5, 3 * a + 1] = gx
+                K += B.T @ C @ B * (h / 2.0) ** 3
+    return K
+
+
+def elasticity3d_stiffness(m: int, layer: int = 6, young=(1.0, 1e5), poisson=(0.3, 0.45)):
+    """Assembled stiffness (scipy CSR, 3 m^3 dofs, no boundary conditions) of
+    the unit cube meshed by (m-1)^3 trilinear hexahedra, node k =
+    (iz*m+iy)*m+ix, dof 3k + component.  Elements are layered along z,
+    ``layer`` elements thick, alternating between material 0 (young[0],
+    poisson[0]) and material 1.  Every element coupling is kept in the pattern
+    (the 3 x 3 blocks of all node pairs that share an element)."""
+    import scipy.sparse as sp
+    h = 1.0 / (m - 1)
+    Ke = np.stack([elasticity_element(young[t], poisson[t], h) for t in range(2)])
+    ne = m - 1
+    e = np.arange(ne ** 3, dtype=np.int64)
+    ez, rem = np.divmod(e, ne * ne)
+    ey, ex = np.divmod(rem, ne)
+    mat = (ez // layer) % 2
+    nodes = np.stack([((ez + ((a >> 2) & 1)) * m + (ey + ((a >> 1) & 1))) * m + (ex + (a & 1)) for a in range(8)],
+                     axis=1)
+    dofs = (3 * nodes[:, :, None] + np.arange(3)).reshape(-1, 24)
+    rows = np.repeat(dofs, 24, axis=1).reshape(-1)
+    cols = np.tile(dofs, (1, 24)).reshape(-1)
+    vals = Ke[mat].reshape(-1)
+    nd = 3 * m ** 3
+    K = sp.coo_matrix((vals, (rows, cols)), shape=(nd, nd)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    return K
+
+
+def elasticity3d(m: int, layer: int = 6, young=(1.0, 1e5), poisson=(0.3, 0.45)) -> CSR:
+    """3-D linear elasticity on an m^3-node grid (see ``elasticity3d_stiffness``)
+    with the face x = 0 clamped: its dofs are removed, leaving n = 3 m^2 (m-1)
+    unknowns in the original order."""
+    K = elasticity3d_stiffness(m, layer, young, poisson)
+    nd = 3 * m ** 3
+    keep = np.nonzero((np.arange(nd) // 3) % m > 0)[0]
+    A = K[keep][:, keep].tocsr()
+    A.sort_indices()
+    if A.nnz >= 2 ** 31:
+        raise ValueError("nnz exceeds int32 range")
+    return CSR(A.shape[0], A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64))
+
+
+def elasticity3d_partition(m: int, p: int) -> np.ndarray:
+    """Geometric p x p x p partition by node (all three dofs of a node in one
+    part) for ``elasticity3d(m)``: part = (bz p + by) p + bx with b = i p // m."""
+    nd = 3 * m ** 3
+    node = np.arange(nd) // 3
+    iz, rem = np.divmod(node, m * m)
+    iy, ix = np.divmod(rem, m)
+    part = ((iz * p // m) * p + (iy * p // m)) * p + (ix * p // m)
+    return part[ix > 0].astype(np.int32)
+
+
+# --------------------------------------------------------------------------
 # Right-hand sides and configuration helpers
 # --------------------------------------------------------------------------
 def rhs(n: int, seed: int, nrhs: int = 1) -> np.ndarray:
@@ -213,6 +315,7 @@ class Config:
     tau: float                # the paper's tau: keep lambda > 1/tau
     levels: int
     ggg_seed: int = 0
+    nev_cap: int = 0          # > 0: keep at most the nev_cap smallest mu below tau per subdomain
 
 
 def config_c1() -> Config:
@@ -229,6 +332,21 @@ def config_c2(m: int = 64, N: int = 256, seed: int = 0) -> Config:
 def config_small3d(m: int = 16, N: int = 16, seed: int = 0) -> Config:
     """Down-scaled version of the 3-D diffusion workload (oracle-sized)."""
     return Config(f"diffusion3d_{m}^3_N{N}", diffusion3d(m, seed), None, N, 2, 0.02, 2, ggg_seed=0)
+
+
+def config_c3(m: int = 48, p: int = 8, nev_cap: int = 20) -> Config:
+    """3-D layered linear elasticity (E 1 / 1e5, nu 0.3 / 0.45, layers 6
+    elements thick), 48^3 nodes, face x = 0 clamped (n = 324864), 8x8x8
+    geometric parts, overlap 1, lambda > 10, 3 levels, at most nev_cap kept
+    modes per subdomain."""
+    return Config(f"elasticity3d_{m}^3_N{p ** 3}", elasticity3d(m), elasticity3d_partition(m, p), p ** 3, 1, 0.1, 3,
+                  nev_cap=nev_cap)
+
+
+def config_small_elasticity(m: int = 10, p: int = 2, levels: int = 2, nev_cap: int = 0) -> Config:
+    """Down-scaled layered elasticity (oracle-sized): 10^3 nodes, 2x2x2 parts."""
+    return Config(f"elasticity3d_{m}^3_N{p ** 3}", elasticity3d(m, layer=3), elasticity3d_partition(m, p), p ** 3, 1,
+                  0.1, levels, nev_cap=nev_cap)
 
 
 def log_uniform_sizes(count: int, lo: float, hi: float, seed: int) -> np.ndarray:
