@@ -121,6 +121,16 @@ int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, h
 int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau,
              int32_t levels, const dd_options* opt, hipStream_t stream, dd_handle* out);
 
+/* New values for the matrix the handle was built on, same pattern and same partition (a family
+ * of matrices that differ only in coefficients, as in a parametric study): the whole setup
+ * (Secs. 2-3, every level) is redone for the new values with the handle's overlap, tau,
+ * levels and options, and replaces the old preconditioner only on success.
+ *  val   device, nnz values in the handle's CSR order (full symmetric storage)
+ * The caller keeps ownership of val (it is copied).  On any error the handle keeps its
+ * previous values and preconditioner.  Errors and warnings as for dd_setup
+ * (DD_ERR_NAN for non-finite values). */
+int dd_update_values(dd_handle h, const double* val, hipStream_t stream);
+
 /* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1); with more than
  * two levels E^{-1} is the inner PCG described at dd_setup (M then varies slightly with r).
  * r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */

@@ -79,6 +79,7 @@ def lib():
     sig = {
         "dd_partition_ggg": ([P(_Csr), i32, C.c_uint64, vp, vp], i32),
         "dd_setup": ([P(_Csr), vp, i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
+        "dd_update_values": ([vp, vp, vp], i32),
         "dd_apply": ([vp, vp, vp, i32, vp], i32),
         "dd_pcg": ([vp, vp, vp, i32, f64, i32, P(i32), P(f64), vp], i32),
         "dd_spmv": ([vp, vp, vp, vp], i32),
@@ -105,7 +106,7 @@ def lib():
 
 
 def exported_symbols() -> list[str]:
-    return ["dd_partition_ggg", "dd_setup", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
+    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
             "dd_meter_start", "dd_meter_read"]
@@ -183,6 +184,18 @@ class Preconditioner:
             self.close()
         except Exception:
             pass
+
+    def update_values(self, val):
+        """dd_update_values: new matrix values (same pattern, CSR order), whole setup redone."""
+        import torch
+        val = torch.as_tensor(val, dtype=torch.float64).to(self.A.val.device).contiguous()
+        if val.numel() != self.A.val.numel():
+            raise ValueError("update_values: expected nnz values")
+        self.setup_status = _check(lib().dd_update_values(self._h, _ptr(val), _stream()), "dd_update_values")
+        A = DeviceCSR.__new__(DeviceCSR)
+        A.n, A.rowptr, A.colind, A.val, A.nnz = self.A.n, self.A.rowptr, self.A.colind, val, self.A.nnz
+        self.A = A
+        return self.setup_status
 
     # ---- solve phase ----
     def apply(self, r):

@@ -110,6 +110,7 @@ struct Level {
 
 struct Handle {
     std::vector<std::unique_ptr<Level>> lv;
+    int32_t levels_req = 2;  // levels asked for at setup
     Opts opt;
     dd_info_t info{};
     // dot-product scratch
@@ -1230,35 +1231,26 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* bad) {
         if (!isfinite(v[i])) atomicOr(bad, 1);
 }
 
-int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau, int32_t levels,
-             const dd_options* opt, hipStream_t s, dd_handle* out) {
-    DD_GUARD_BEGIN
-    if (!A || !part || !out) return DD_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (A->n <= 0 || A->nnz <= 0 || N < 1 || N > A->n || overlap < 1 || overlap > 200 || !(tau > 0.0) || levels < 2 ||
-        levels > DD_MAX_LEVELS)
-        return DD_ERR_INVALID_ARG;
-    auto hd = std::make_unique<dd_handle_s>();
-    Handle& H = hd->h;
-    if (opt) {
-        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
-        H.opt.local_prec = opt->local_prec;
-        H.opt.select = opt->select;
-        H.opt.nev_cap = opt->nev_cap;
-        H.opt.validate = opt->validate;
-        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
-        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
-    }
+}  // extern "C"
+
+namespace dd {
+// Level 0 from device CSR arrays and a partition (copied), then every level of
+// the hierarchy (R8) and the diagnostics.  Returns DD_OK, a warning, or an
+// error with H unusable.
+static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                        const double* val, const int32_t* part, int32_t N, int32_t overlap, double tau, int32_t levels,
+                        hipStream_t s) {
+    H.levels_req = levels;
     auto lv = std::make_unique<Level>();
     Level& L0 = *lv;
-    L0.n = A->n;
-    L0.nnz = A->nnz;
-    L0.rowptr.alloc(A->n + 1);
-    L0.colind.alloc(A->nnz);
-    L0.val.alloc(A->nnz);
-    DD_HIP(hipMemcpyAsync(L0.rowptr.p, A->rowptr, (A->n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    DD_HIP(hipMemcpyAsync(L0.colind.p, A->colind, A->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    DD_HIP(hipMemcpyAsync(L0.val.p, A->val, A->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    L0.n = n;
+    L0.nnz = nnz;
+    L0.rowptr.alloc(n + 1);
+    L0.colind.alloc(nnz);
+    L0.val.alloc(nnz);
+    DD_HIP(hipMemcpyAsync(L0.rowptr.p, rowptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L0.colind.p, colind, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L0.val.p, val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
     {
         DBuf<int32_t> bad(1);
         DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
@@ -1271,11 +1263,11 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     L0.N = N;
     L0.delta = overlap;
     L0.tau = tau;
-    L0.part.alloc(A->n);
-    DD_HIP(hipMemcpyAsync(L0.part.p, part, A->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    L0.part.alloc(n);
+    DD_HIP(hipMemcpyAsync(L0.part.p, part, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     {
         DBuf<int32_t> cnt(N);
-        const int rc = validate_partition(L0.part.p, A->n, N, cnt.p, s);
+        const int rc = validate_partition(L0.part.p, n, N, cnt.p, s);
         if (rc != DD_OK) return rc;
     }
     H.lv.push_back(std::move(lv));
@@ -1303,19 +1295,66 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     I.n[H.lv.size()] = H.lv.back()->nC;
     gsum += (double)H.lv.back()->nC;
     I.n_C = L0.nC;
-    I.grid_complexity = gsum / double(A->n);
+    I.grid_complexity = gsum / double(n);
     I.p_min = N ? *std::min_element(L0.p.begin(), L0.p.end()) : 0;
     I.p_max = N ? *std::max_element(L0.p.begin(), L0.p.end()) : 0;
-    H.partial.alloc(512 * 64);
-    H.dots.alloc(64);
-    DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
+    if (!H.partial.p) {
+        H.partial.alloc(512 * 64);
+        H.dots.alloc(64);
+        DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
+    }
     int64_t bytes = 0;
     for (auto& l : H.lv)
         bytes += l->W.buf.bytes() + l->W32.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
-    *out = hd.release();
     if (tau >= 1.0) return DD_WARN_FULL_COARSE;
     return I.fp32_fallbacks > 0 ? DD_WARN_FP32_FALLBACK : DD_OK;
+}
+}  // namespace dd
+
+extern "C" {
+
+int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, double tau, int32_t levels,
+             const dd_options* opt, hipStream_t s, dd_handle* out) {
+    DD_GUARD_BEGIN
+    if (!A || !part || !out) return DD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (A->n <= 0 || A->nnz <= 0 || N < 1 || N > A->n || overlap < 1 || overlap > 200 || !(tau > 0.0) || levels < 2 ||
+        levels > DD_MAX_LEVELS)
+        return DD_ERR_INVALID_ARG;
+    auto hd = std::make_unique<dd_handle_s>();
+    Handle& H = hd->h;
+    if (opt) {
+        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
+        H.opt.local_prec = opt->local_prec;
+        H.opt.select = opt->select;
+        H.opt.nev_cap = opt->nev_cap;
+        H.opt.validate = opt->validate;
+        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
+        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
+    }
+    const int rc = build_handle(H, A->n, A->nnz, A->rowptr, A->colind, A->val, part, N, overlap, tau, levels, s);
+    if (rc < 0) return rc;
+    *out = hd.release();
+    return rc;
+    DD_GUARD_END
+}
+
+int dd_update_values(dd_handle h, const double* val, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!h || !val || h->h.lv.empty()) return DD_ERR_INVALID_ARG;
+    const Level& L0 = *h->h.lv[0];
+    // the new hierarchy is built beside the old one and replaces it only on success
+    auto fresh = std::make_unique<dd_handle_s>();
+    Handle& F = fresh->h;
+    F.opt = h->h.opt;
+    const int rc = build_handle(F, L0.n, L0.nnz, L0.rowptr.p, L0.colind.p, val, L0.part.p, L0.N, L0.delta, L0.tau,
+                                h->h.levels_req, s);
+    if (rc < 0) return rc;
+    DD_HIP(hipStreamSynchronize(s));
+    std::swap(h->h.lv, F.lv);
+    h->h.info = F.info;
+    return rc;
     DD_GUARD_END
 }
 
