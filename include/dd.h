@@ -131,6 +131,24 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
  * (DD_ERR_NAN for non-finite values). */
 int dd_update_values(dd_handle h, const double* val, hipStream_t stream);
 
+/* Several independent systems in one handle: As[j] (device CSR, n_j unknowns) with partition
+ * parts[j] (device, n_j entries in [0, Ns[j])), all with the same overlap, tau, levels and
+ * options.  The handle holds the block-diagonal union of the systems (unknowns and parts
+ * numbered system after system), so every setup phase runs all subdomains of all systems in
+ * the same batched launches; with two levels the result for each system is that of its own
+ * dd_setup (its subdomains and coarse blocks never touch another system).
+ *  nsys    number of systems (>= 1); As, parts, Ns: host arrays of nsys entries
+ * Vectors passed to dd_apply and dd_pcg are the systems' vectors concatenated (sum n_j per RHS).
+ * dd_pcg on such a handle runs one PCG per system in lockstep (per-system dot products, alpha
+ * and beta; each system stops on its own residual) and writes nsys entries of iters and relres
+ * per RHS (system j of RHS k at k*nsys + j).  With more than two levels the systems share the
+ * inner coarse solves of the union.  The caller keeps ownership of all inputs (copied).
+ * Errors and warnings as for dd_setup; DD_ERR_INVALID_ARG also for n or nnz of the union
+ * beyond int32. */
+int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t* Ns, int32_t nsys,
+                   int32_t overlap, double tau, int32_t levels, const dd_options* opt,
+                   hipStream_t stream, dd_handle* out);
+
 /* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1); with more than
  * two levels E^{-1} is the inner PCG described at dd_setup (M then varies slightly with r).
  * r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */

@@ -80,6 +80,7 @@ def lib():
         "dd_partition_ggg": ([P(_Csr), i32, C.c_uint64, vp, vp], i32),
         "dd_setup": ([P(_Csr), vp, i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
         "dd_update_values": ([vp, vp, vp], i32),
+        "dd_setup_batch": ([P(_Csr), P(vp), P(i32), i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
         "dd_apply": ([vp, vp, vp, i32, vp], i32),
         "dd_pcg": ([vp, vp, vp, i32, f64, i32, P(i32), P(f64), vp], i32),
         "dd_spmv": ([vp, vp, vp, vp], i32),
@@ -106,7 +107,7 @@ def lib():
 
 
 def exported_symbols() -> list[str]:
-    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
+    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
             "dd_meter_start", "dd_meter_read"]
@@ -173,6 +174,34 @@ class Preconditioner:
             lib().dd_setup(C.byref(cs), _ptr(part), N, overlap, float(tau), levels, C.byref(opts), _stream(),
                            C.byref(h)), "dd_setup")
         self._h = h
+        self.nsys = 1
+
+    @classmethod
+    def batch(cls, As, parts, Ns, overlap: int, tau: float, levels: int = 2, local_prec: int = DD_FP64,
+              select: int = DD_SEL_THRESHOLD, nev_cap: int = 0, validate: bool = False, coarsen: int = 0):
+        """dd_setup_batch: independent systems As[j] (DeviceCSR) with partitions
+        parts[j] into Ns[j] parts, one handle over their block-diagonal union.
+        Vectors are the systems concatenated; pcg returns per-system counts."""
+        import torch
+        k = len(As)
+        dev = As[0].val.device
+        tparts = [torch.as_tensor(p, dtype=torch.int32).to(dev).contiguous() for p in parts]
+        csrs = (_Csr * k)(*[A.cstruct() for A in As])
+        pp = (C.c_void_p * k)(*[t.data_ptr() for t in tparts])
+        ns = (C.c_int32 * k)(*[int(x) for x in Ns])
+        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), (C.c_int32 * 7)())
+        h = C.c_void_p()
+        self = cls.__new__(cls)
+        self.setup_status = _check(
+            lib().dd_setup_batch(csrs, pp, ns, k, overlap, float(tau), levels, C.byref(opts), _stream(), C.byref(h)),
+            "dd_setup_batch")
+        self._h = h
+        self.nsys = k
+        self.sys_n = [A.n for A in As]
+        self.n = sum(self.sys_n)
+        self.A = None
+        self._keep = tparts
+        return self
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -188,6 +217,8 @@ class Preconditioner:
     def update_values(self, val):
         """dd_update_values: new matrix values (same pattern, CSR order), whole setup redone."""
         import torch
+        if self.A is None:
+            raise ValueError("update_values: use the C-ABI for a batch handle (values of the union in order)")
         val = torch.as_tensor(val, dtype=torch.float64).to(self.A.val.device).contiguous()
         if val.numel() != self.A.val.numel():
             raise ValueError("update_values: expected nnz values")
@@ -211,8 +242,8 @@ class Preconditioner:
         b = b.contiguous()
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         nrhs = 1 if b.dim() == 1 else b.shape[1]
-        its = (C.c_int32 * nrhs)()
-        rr = (C.c_double * nrhs)()
+        its = (C.c_int32 * (nrhs * self.nsys))()
+        rr = (C.c_double * (nrhs * self.nsys))()
         code = _check(lib().dd_pcg(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, its, rr, _stream()), "dd_pcg")
         return x, list(its), list(rr), code
 

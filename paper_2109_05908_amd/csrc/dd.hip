@@ -116,8 +116,18 @@ struct Handle {
     // dot-product scratch
     DBuf<double> partial, dots;
     double* hpin = nullptr;
+    // batch of independent systems (dd_setup_batch): dof offsets of the
+    // systems in the block-diagonal union, the system of every dof, and the
+    // per-system Krylov scalars (pinned host, device)
+    std::vector<int64_t> sys_off;
+    DBuf<int64_t> dsys_off;
+    DBuf<int32_t> sys_id;
+    DBuf<double> dscal;
+    double* hscal = nullptr;
+    int nsys() const { return sys_off.size() > 1 ? (int)sys_off.size() - 1 : 1; }
     ~Handle() {
         if (hpin) (void)hipHostFree(hpin);
+        if (hscal) (void)hipHostFree(hscal);
     }
 };
 
@@ -1120,6 +1130,131 @@ static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, 
     return conv ? DD_OK : DD_WARN_MAXIT;
 }
 
+// ---------------------------------------------------------------------------
+// One PCG per system of a batch (dd_setup_batch), run in lockstep on the
+// union vector: every dot product is per system (segmented reduction), alpha
+// and beta are per system, and a system that has converged takes alpha = 0 so
+// its iterate stays put while the others go on.  The preconditioner of the
+// union is block diagonal over the systems, so each system sees its own PCG.
+// ---------------------------------------------------------------------------
+__global__ void k_axpy2_seg(double* x, double* r, const double* p, const double* q, const double* alpha,
+                            const int32_t* sid, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = alpha[sid[i]];
+        x[i] += a * p[i];
+        r[i] -= a * q[i];
+    }
+}
+__global__ void k_xpby_seg(const double* z, double* p, const double* beta, const int32_t* sid, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta[sid[i]] * p[i];
+}
+
+static std::vector<double> dot_sys(Handle& H, const double* x, const double* y, hipStream_t s) {
+    const int ns = H.nsys();
+    dot_seg(x, y, H.dsys_off.p, ns, H.partial.p, H.dots.p, s);
+    DD_HIP(hipMemcpyAsync(H.hpin, H.dots.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    DD_HIP(hipStreamSynchronize(s));
+    return std::vector<double>(H.hpin, H.hpin + ns);
+}
+// per-system scalars to the device (slot 0: alpha, slot 1: beta); the pinned
+// slot is not rewritten before a later stream synchronisation
+static const double* put_sys(Handle& H, const std::vector<double>& v, int slot, hipStream_t s) {
+    const int ns = H.nsys();
+    double* h = H.hscal + (size_t)slot * ns;
+    std::copy(v.begin(), v.end(), h);
+    double* d = H.dscal.p + (size_t)slot * ns;
+    DD_HIP(hipMemcpyAsync(d, h, ns * sizeof(double), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+static int krylov_seg(Handle& H, const double* b, double* x, double rtol, int maxit, bool flexible, int* iters,
+                      double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const int ns = H.nsys();
+    const CsrDev A = Lv.A();
+    double *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p, *q = Lv.kq.p, *ro = Lv.kro.p;
+    std::vector<double> bn = dot_sys(H, b, b, s);
+    for (int k = 0; k < ns; ++k) {
+        DD_CHECK(std::isfinite(bn[k]), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+        bn[k] = std::sqrt(bn[k]);
+        if (bn[k] == 0.0) DD_HIP(hipMemsetAsync(x + H.sys_off[k], 0, (H.sys_off[k + 1] - H.sys_off[k]) * sizeof(double), s));
+    }
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    std::vector<double> rn = dot_sys(H, r, r, s);
+    std::vector<int> its(ns, 0);
+    std::vector<char> conv(ns, 0);
+    int left = 0;
+    for (int k = 0; k < ns; ++k) {
+        rn[k] = std::sqrt(rn[k]);
+        conv[k] = (bn[k] == 0.0 || rn[k] <= rtol * bn[k]) ? 1 : 0;
+        left += conv[k] ? 0 : 1;
+    }
+    if (left) {
+        apply_level(H, 0, r, z, s);
+        DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        std::vector<double> rz = dot_sys(H, r, z, s);
+        std::vector<double> alpha(ns), beta(ns);
+        for (int it = 1; it <= maxit && left; ++it) {
+            spmv(A, p, q, 1, s);
+            const std::vector<double> pq = dot_sys(H, p, q, s);
+            for (int k = 0; k < ns; ++k) {
+                alpha[k] = conv[k] ? 0.0 : rz[k] / pq[k];
+                DD_CHECK(std::isfinite(alpha[k]), DD_ERR_NAN, "PCG produced NaN");
+            }
+            if (flexible) DD_HIP(hipMemcpyAsync(ro, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_axpy2_seg, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, put_sys(H, alpha, 0, s),
+                               H.sys_id.p, n);
+            rn = dot_sys(H, r, r, s);
+            for (int k = 0; k < ns; ++k) {
+                if (conv[k]) continue;
+                its[k] = it;
+                if (std::sqrt(rn[k]) <= rtol * bn[k]) {
+                    conv[k] = 1;
+                    --left;
+                }
+            }
+            if (!left) break;
+            apply_level(H, 0, r, z, s);
+            if (flexible) {
+                hipLaunchKernelGGL(k_diff, dim3(vgrid(n)), dim3(256), 0, s, r, ro, q, n);  // q := r - r_old
+                const std::vector<double> zq = dot_sys(H, z, q, s);
+                for (int k = 0; k < ns; ++k) beta[k] = conv[k] ? 0.0 : zq[k] / rz[k];
+                rz = dot_sys(H, r, z, s);
+            } else {
+                const std::vector<double> rzn = dot_sys(H, r, z, s);
+                for (int k = 0; k < ns; ++k) beta[k] = conv[k] ? 0.0 : rzn[k] / rz[k];
+                rz = rzn;
+            }
+            hipLaunchKernelGGL(k_xpby_seg, dim3(vgrid(n)), dim3(256), 0, s, z, p, put_sys(H, beta, 1, s), H.sys_id.p,
+                               n);
+        }
+    }
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    const std::vector<double> tr = dot_sys(H, r, r, s);
+    bool all = true;
+    for (int k = 0; k < ns; ++k) {
+        const double rel = bn[k] > 0.0 ? std::sqrt(tr[k]) / bn[k] : 0.0;
+        DD_CHECK(std::isfinite(rel), DD_ERR_NAN, "PCG produced NaN");
+        if (iters) iters[k] = its[k];
+        if (relres) relres[k] = rel;
+        all = all && conv[k];
+    }
+    return all ? DD_OK : DD_WARN_MAXIT;
+}
+
+__global__ void k_copy_add_i32(const int32_t* src, int32_t* dst, int64_t n, int64_t add) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (int32_t)(src[i] + add);
+}
+__global__ void k_set_i32(int32_t* dst, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = v;
+}
+
 }  // namespace dd
 
 // ===========================================================================
@@ -1299,9 +1434,10 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
     I.p_min = N ? *std::min_element(L0.p.begin(), L0.p.end()) : 0;
     I.p_max = N ? *std::max_element(L0.p.begin(), L0.p.end()) : 0;
     if (!H.partial.p) {
-        H.partial.alloc(512 * 64);
-        H.dots.alloc(64);
-        DD_HIP(hipHostMalloc(&H.hpin, 64 * sizeof(double)));
+        const int w = std::max(64, H.nsys());
+        H.partial.alloc((int64_t)512 * w);
+        H.dots.alloc(w);
+        DD_HIP(hipHostMalloc(&H.hpin, w * sizeof(double)));
     }
     int64_t bytes = 0;
     for (auto& l : H.lv)
@@ -1358,6 +1494,62 @@ int dd_update_values(dd_handle h, const double* val, hipStream_t s) {
     DD_GUARD_END
 }
 
+int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t* Ns, int32_t nsys, int32_t overlap,
+                   double tau, int32_t levels, const dd_options* opt, hipStream_t s, dd_handle* out) {
+    DD_GUARD_BEGIN
+    if (!As || !parts || !Ns || !out || nsys < 1) return DD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (overlap < 1 || overlap > 200 || !(tau > 0.0) || levels < 2 || levels > DD_MAX_LEVELS) return DD_ERR_INVALID_ARG;
+    std::vector<int64_t> noff(nsys + 1, 0), zoff(nsys + 1, 0), poff(nsys + 1, 0);
+    for (int j = 0; j < nsys; ++j) {
+        const dd_csr& A = As[j];
+        if (A.n <= 0 || A.nnz <= 0 || !A.rowptr || !A.colind || !A.val || !parts[j] || Ns[j] < 1 || Ns[j] > A.n)
+            return DD_ERR_INVALID_ARG;
+        noff[j + 1] = noff[j] + A.n;
+        zoff[j + 1] = zoff[j] + A.nnz;
+        poff[j + 1] = poff[j] + Ns[j];
+    }
+    if (noff[nsys] >= ((int64_t)1 << 31) || zoff[nsys] >= ((int64_t)1 << 31) || poff[nsys] > noff[nsys])
+        return DD_ERR_INVALID_ARG;
+    auto hd = std::make_unique<dd_handle_s>();
+    Handle& H = hd->h;
+    if (opt) {
+        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
+        H.opt.local_prec = opt->local_prec;
+        H.opt.select = opt->select;
+        H.opt.nev_cap = opt->nev_cap;
+        H.opt.validate = opt->validate;
+        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
+        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
+    }
+    // the block-diagonal union of the systems, its partition and the system of every dof
+    const int64_t n = noff[nsys], nnz = zoff[nsys];
+    DBuf<int32_t> rowptr(n + 1), colind(nnz), part(n);
+    DBuf<double> val(nnz);
+    H.sys_id.alloc(n);
+    for (int j = 0; j < nsys; ++j) {
+        const dd_csr& A = As[j];
+        const int g1 = vgrid(A.n + 1), g2 = vgrid(A.nnz);
+        hipLaunchKernelGGL(k_copy_add_i32, dim3(g1), dim3(256), 0, s, A.rowptr, rowptr.p + noff[j], A.n + 1, zoff[j]);
+        hipLaunchKernelGGL(k_copy_add_i32, dim3(g2), dim3(256), 0, s, A.colind, colind.p + zoff[j], A.nnz, noff[j]);
+        hipLaunchKernelGGL(k_copy_add_i32, dim3(g1), dim3(256), 0, s, parts[j], part.p + noff[j], A.n, poff[j]);
+        hipLaunchKernelGGL(k_set_i32, dim3(g1), dim3(256), 0, s, H.sys_id.p + noff[j], A.n, j);
+        DD_HIP(hipMemcpyAsync(val.p + zoff[j], A.val, A.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+        launch_check("batch_union");
+    }
+    H.sys_off = noff;
+    H.dsys_off = upload(noff, s);
+    H.dscal.alloc(2 * nsys);
+    DD_HIP(hipHostMalloc(&H.hscal, 2 * nsys * sizeof(double)));
+    const int rc = build_handle(H, n, nnz, rowptr.p, colind.p, val.p, part.p, (int32_t)poff[nsys], overlap, tau,
+                                levels, s);
+    if (rc < 0) return rc;
+    DD_HIP(hipStreamSynchronize(s));
+    *out = hd.release();
+    return rc;
+    DD_GUARD_END
+}
+
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t s) {
     DD_GUARD_BEGIN
     if (!h || !r || !z || nrhs < 1) return DD_ERR_INVALID_ARG;
@@ -1374,6 +1566,25 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
     Handle& H = h->h;
     const int64_t n = H.lv[0]->n;
     int rc = DD_OK;
+    if (H.nsys() > 1) {  // batch: one PCG per system, nsys results per right-hand side
+        const int ns = H.nsys();
+        std::vector<int> it(ns);
+        std::vector<double> rr(ns);
+        for (int k = 0; k < nrhs; ++k) {
+            const int c = krylov_seg(H, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, it.data(), rr.data(), s);
+            if (c < 0) return c;
+            if (c > 0) rc = c;
+            for (int j = 0; j < ns; ++j) {
+                if (iters) iters[(int64_t)k * ns + j] = it[j];
+                if (relres) relres[(int64_t)k * ns + j] = rr[j];
+            }
+            if (k == 0) {
+                H.info.last_iters = *std::max_element(it.begin(), it.end());
+                H.info.last_relres = *std::max_element(rr.begin(), rr.end());
+            }
+        }
+        return rc;
+    }
     for (int k = 0; k < nrhs; ++k) {
         int it = 0;
         double rr = 0.0;

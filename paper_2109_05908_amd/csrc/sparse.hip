@@ -432,6 +432,22 @@ __global__ void k_dot_final(const double* partial, double* out) {
     s = block_sum(s, red);
     if (threadIdx.x == 0) out[k] = s;
 }
+__global__ void k_dot_seg_part(const double* x, const double* y, const int64_t* off, double* partial) {
+    __shared__ double red[4];
+    const int k = blockIdx.y;
+    const int64_t b = off[k], e = off[k + 1];
+    double s = 0.0;
+    for (int64_t i = b + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < e; i += (int64_t)gridDim.x * blockDim.x)
+        s += x[i] * y[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[k * kDotBlocks + blockIdx.x] = s;
+}
+void dot_seg(const double* x, const double* y, const int64_t* off, int nseg, double* partial, double* out,
+             hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_seg_part, dim3(kDotBlocks, nseg), dim3(256), 0, s, x, y, off, partial);
+    hipLaunchKernelGGL(k_dot_final, dim3(nseg), dim3(256), 0, s, partial, out);
+    launch_check("dot_seg");
+}
 void dot(const double* x, const double* y, int64_t n, int nrhs, double* partial, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_dot_part, dim3(kDotBlocks, nrhs), dim3(256), 0, s, x, y, n, partial);
     hipLaunchKernelGGL(k_dot_final, dim3(nrhs), dim3(256), 0, s, partial, out);

@@ -51,6 +51,10 @@ void spmv(const CsrDev& A, const double* x, double* y, int nrhs, hipStream_t s);
 void fill(double* p, int64_t n, double v, hipStream_t s);
 // out[k] = sum of blocks; deterministic two-pass; out device (nrhs values)
 void dot(const double* x, const double* y, int64_t n, int nrhs, double* partial, double* out, hipStream_t s);
+// out[k] = x[off[k]:off[k+1]] . y[off[k]:off[k+1]] for k < nseg (off on the
+// device); partial holds 512 * nseg doubles.  Deterministic order.
+void dot_seg(const double* x, const double* y, const int64_t* off, int nseg, double* partial, double* out,
+             hipStream_t s);
 void gather(const double* x, const int32_t* idx, int64_t m, double* out, hipStream_t s);
 void scatter_sum(const double* loc, const int64_t* memb_ptr, const int64_t* memb, int64_t n, double* z,
                  bool accumulate, hipStream_t s);
