@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 # sources still hash to what was profiled.
 ROOFLINE_KERNEL = "qr_blk_upd"
 ROOFLINE_SOURCES = ["common.hpp", "dense.hpp", "dense.hip"]
-TRAFFIC = {"sha256": "5b41b24f76a17f66", "bytes_per_launch": 3.7166e9,
+TRAFFIC = {"sha256": "6302077c154661cd", "bytes_per_launch": 3.7012e9,
            "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6"}
 
 
