@@ -35,6 +35,15 @@ design notes):
       synchronous BFS with minimum-id conflict resolution).
 * R8  Levels >= 3: coarse graph blocks = fine subdomains, N_2 = ceil(N/64),
       inner PCG on E to 1e-4, outer flexible CG.
+* R12 The deflated variant of Sec. 4, M_deflated = R_0^T E^{-1} R_0 +
+      M_RAS (I - A R_0^T E^{-1} R_0), with the one-level restricted additive
+      Schwarz M_RAS = sum_i R_i^T D_i A_ii^{-1} R_i and the Boolean D_i of R1,
+      under right-preconditioned GMRES(30) from x0 = 0, Arnoldi by modified
+      Gram-Schmidt, stopping when the Arnoldi estimate of the unpreconditioned
+      residual reaches rtol ||b||_2 (the true residual is recomputed at every
+      restart).  With levels >= 3 the coarse systems are solved by right-
+      preconditioned GMRES(30) to 1e-4 with the next level's M_deflated, and
+      the outer solver is flexible GMRES(30).
 
 Parity for the finite-precision near-kernel cluster (lambda >~ 1e6) is only
 meaningful as a subspace; its individual values are parity unpinned.
@@ -53,7 +62,7 @@ EPS = 2.0 ** -52
 __all__ = [
     "EPS", "splitmix64", "ggg_partition", "Sets", "subdomain_sets", "extract",
     "Splitting", "local_splitting", "schur_via_qr", "local_eigen", "LocalResult",
-    "TwoLevel", "build", "pcg", "flexible_pcg", "coloring_kc", "diagnostics",
+    "TwoLevel", "build", "pcg", "flexible_pcg", "gmres", "coloring_kc", "diagnostics",
     "coarse_partition", "as_scipy",
 ]
 
@@ -306,9 +315,13 @@ def local_eigen(Aii: np.ndarray, S_I: np.ndarray, nI: int, tau: float, nev: int 
 # ---------------------------------------------------------------------------
 class TwoLevel:
     """M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1),
-    R_0^T = [R_1^T D_1 Z_1, ..., R_N^T D_N Z_N], E = R_0 A R_0^T."""
+    R_0^T = [R_1^T D_1 Z_1, ..., R_N^T D_N Z_N], E = R_0 A R_0^T.
+    variant "deflated": M_deflated of Sec. 4 (R12) from the same parts."""
 
-    def __init__(self, A, locals_: list[LocalResult], coarse_solver=None):
+    def __init__(self, A, locals_: list[LocalResult], coarse_solver=None, variant="additive"):
+        if variant not in ("additive", "deflated"):
+            raise ValueError("variant is 'additive' or 'deflated'")
+        self.variant = variant
         self.A = as_scipy(A)
         self.n = self.A.shape[0]
         self.locals = locals_
@@ -356,7 +369,24 @@ class TwoLevel:
             y = sla.cho_solve(self.E_chol, y)
         return self.Z @ y
 
+    def apply_ras(self, r: np.ndarray) -> np.ndarray:
+        """M_RAS r = sum_i R_i^T D_i A_ii^{-1} R_i r (Sec. 4), Boolean D_i (R1):
+        of each local solution on Omega_i = [Omega_Ii, Gamma_i] only the
+        Omega_Ii part is kept, so every dof takes the value of its own part."""
+        z = np.zeros_like(r)
+        for L, Om, c in zip(self.locals, self.omega, self.chol):
+            zi = sla.cho_solve(c, r[Om])
+            z[L.sets.I] = zi[:L.sets.I.size]
+        return z
+
+    def apply_deflated(self, r: np.ndarray) -> np.ndarray:
+        """M_deflated r = y + M_RAS (r - A y), y = R_0^T E^{-1} R_0 r (Sec. 4)."""
+        y = self.apply_coarse(r)
+        return y + self.apply_ras(r - self.A @ y)
+
     def apply(self, r: np.ndarray) -> np.ndarray:
+        if self.variant == "deflated":
+            return self.apply_deflated(r)
         return self.apply_coarse(r) + self.apply_local(r)
 
     @property
@@ -398,14 +428,16 @@ def _subdomain_graph(A, locals_: list[LocalResult]) -> sp.csr_matrix:
     return G
 
 
-def build(A, part, N, delta, tau, levels=2, nev=None, inner_rtol=1e-4, shift=None, coarsen=64):
-    """Full setup (Sec. 3.2), recursively for levels >= 3 (multilevel remark, R8)."""
+def build(A, part, N, delta, tau, levels=2, nev=None, inner_rtol=1e-4, shift=None, coarsen=64,
+          variant="additive"):
+    """Full setup (Sec. 3.2), recursively for levels >= 3 (multilevel remark,
+    R8); variant "deflated" for M_deflated and GMRES coarse solves (R12)."""
     if levels < 2:
         raise ValueError("levels >= 2")
     locs = build_locals(A, part, N, delta, tau, nev, shift)
     if levels == 2:
-        return TwoLevel(A, locs)
-    pre = TwoLevel(A, locs, coarse_solver=lambda y: y)  # E assembled, solver set below
+        return TwoLevel(A, locs, variant=variant)
+    pre = TwoLevel(A, locs, coarse_solver=lambda y: y, variant=variant)  # E assembled, solver set below
     E = pre.E
     if pre.nC == 0:
         pre.coarse_solver = None
@@ -423,11 +455,16 @@ def build(A, part, N, delta, tau, levels=2, nev=None, inner_rtol=1e-4, shift=Non
     remap = -np.ones(int(part_blocks.max()) + 1, dtype=np.int64)
     remap[used] = np.arange(used.size)
     part2 = remap[part2].astype(np.int32)
-    inner = build(sp.csr_matrix(E), part2, int(used.size), delta, tau, levels - 1, nev, inner_rtol, shift, coarsen)
+    inner = build(sp.csr_matrix(E), part2, int(used.size), delta, tau, levels - 1, nev, inner_rtol, shift, coarsen,
+                  variant)
     Esp = sp.csr_matrix(E)
 
     def coarse_solve(y):
-        x, its, rr = pcg(Esp, y, inner.apply, rtol=inner_rtol, maxit=1000)
+        if variant == "deflated":
+            x, its, rr = gmres(Esp, y, inner.apply, rtol=inner_rtol, restart=30, maxit=1000,
+                               flexible=levels - 1 >= 3)
+        else:
+            x, its, rr = pcg(Esp, y, inner.apply, rtol=inner_rtol, maxit=1000)
         return x
 
     pre.coarse_solver = coarse_solve
@@ -492,6 +529,71 @@ def flexible_pcg(A, b, Minv, rtol=1e-8, maxit=1000):
             rz = r @ z
             p = z + beta * p
     return x, its, float(np.linalg.norm(b - A @ x) / bn)
+
+
+def gmres(A, b, Minv, rtol=1e-8, restart=30, maxit=1000, flexible=False):
+    """Right-preconditioned GMRES(restart) (Saad & Schultz 1986) and its
+    flexible form (Saad 1993), R12: x0 = 0; Arnoldi on A M by modified
+    Gram-Schmidt; Givens rotations reduce the Hessenberg matrix; a cycle ends
+    when the estimate |g_{j+1}| of ||b - A x_j||_2 reaches rtol ||b||_2, after
+    `restart` steps, on breakdown (h_{j+1,j} = 0) or at maxit steps in total.
+    At the end of a cycle x += M V_k y (flexible: x += [M_1 v_1 ... M_k v_k] y)
+    and the true residual starts the next one.  Returns (x, Arnoldi steps,
+    true relative residual)."""
+    A = as_scipy(A)
+    n = b.size
+    x = np.zeros_like(b)
+    bn = float(np.linalg.norm(b))
+    if bn == 0.0:
+        return x, 0, 0.0
+    its = 0
+    r = b.copy()
+    beta = bn
+    while beta > rtol * bn and its < maxit:
+        m = restart
+        V = np.zeros((n, m + 1))
+        Zs = []
+        Hm = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        k = 0
+        for j in range(m):
+            zj = Minv(V[:, j])
+            if flexible:
+                Zs.append(zj)
+            w = A @ zj
+            for i in range(j + 1):
+                Hm[i, j] = w @ V[:, i]
+                w = w - Hm[i, j] * V[:, i]
+            Hm[j + 1, j] = np.linalg.norm(w)
+            if Hm[j + 1, j] > 0.0:
+                V[:, j + 1] = w / Hm[j + 1, j]
+            for i in range(j):  # earlier rotations on the new column
+                t = cs[i] * Hm[i, j] + sn[i] * Hm[i + 1, j]
+                Hm[i + 1, j] = -sn[i] * Hm[i, j] + cs[i] * Hm[i + 1, j]
+                Hm[i, j] = t
+            d = math.hypot(Hm[j, j], Hm[j + 1, j])
+            cs[j] = Hm[j, j] / d
+            sn[j] = Hm[j + 1, j] / d
+            Hm[j, j] = d
+            Hm[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            k = j + 1
+            if abs(g[j + 1]) <= rtol * bn or its >= maxit or sn[j] == 0.0:
+                break
+        y = sla.solve_triangular(Hm[:k, :k], g[:k])
+        if flexible:
+            x = x + np.column_stack(Zs) @ y
+        else:
+            x = x + Minv(V[:, :k] @ y)
+        r = b - A @ x
+        beta = float(np.linalg.norm(r))
+    return x, its, beta / bn
 
 
 # ---------------------------------------------------------------------------
