@@ -61,6 +61,10 @@ typedef struct {
 #define DD_FP32 1
 #define DD_SEL_THRESHOLD      0  /* keep lambda > 1/tau  (3.3) */
 #define DD_SEL_THRESHOLD_CAP  1  /* keep lambda > 1/tau, at most nev_cap per subdomain (the largest lambda) */
+#define DD_SCHWARZ_ADDITIVE   0  /* M = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1), symmetric: dd_pcg */
+#define DD_SCHWARZ_DEFLATED   1  /* M = R_0^T E^{-1} R_0 + M_RAS (I - A R_0^T E^{-1} R_0), the variant of the
+                                    experiments (Sec. 4), M_RAS = sum_i R_i^T D_i A_ii^{-1} R_i with the Boolean
+                                    D_i (1 on Omega_Ii, 0 on Gamma_i); not symmetric: dd_gmres */
 
 typedef struct {
     int32_t local_prec;   /* DD_FP64 (default) or DD_FP32: precision of the local Cholesky factors of A_ii
@@ -69,7 +73,8 @@ typedef struct {
     int32_t nev_cap;      /* cap per subdomain for DD_SEL_THRESHOLD_CAP */
     int32_t validate;     /* nonzero: check pattern symmetry and finite values of A (O(nnz)) */
     int32_t coarsen;      /* levels >= 3: subdomains per coarse part (default 64) */
-    int32_t reserved[7];
+    int32_t schwarz;      /* DD_SCHWARZ_ADDITIVE (default) or DD_SCHWARZ_DEFLATED */
+    int32_t reserved[6];
 } dd_options;
 
 typedef struct dd_handle_s* dd_handle;
@@ -151,7 +156,10 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
 
 /* z = M^{-1} r with M^{-1} = R_0^T E^{-1} R_0 + sum_i R_i^T A_ii^{-1} R_i  (2.1); with more than
  * two levels E^{-1} is the inner PCG described at dd_setup (M then varies slightly with r).
- * r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */
+ * A handle set up with schwarz = DD_SCHWARZ_DEFLATED applies instead the deflated variant of
+ * Sec. 4, z = y + M_RAS (r - A y) with y = R_0^T E^{-1} R_0 r, whose coarse solves on levels
+ * that are not the last are right-preconditioned GMRES(30) to 1e-4 with the next level's
+ * deflated M.  r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t stream);
 
 /* Preconditioned CG with M from dd_apply (FP64 dots and residual recurrence); with more than
@@ -162,6 +170,23 @@ int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t 
  * (may be NULL).  Returns DD_WARN_MAXIT if some RHS did not converge. */
 int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit,
            int32_t* iters, double* relres, hipStream_t stream);
+/* (dd_pcg returns DD_ERR_INVALID_ARG on a handle with the deflated variant, which is not
+ * symmetric.) */
+
+/* Right-preconditioned GMRES(restart) (Saad & Schultz) with M from dd_apply: the outer solver of
+ * the paper's experiments (Sec. 4), flexible GMRES when the handle has more than two levels
+ * (M varies between iterations).  Works with either variant of the handle.
+ * Arnoldi by classical Gram-Schmidt applied twice; a restart cycle ends when the Arnoldi
+ * estimate of ||b_j - A x_j||_2 (the unpreconditioned residual) reaches rtol ||b_j||_2, after
+ * `restart` steps or at maxit steps in total; the true residual is recomputed at the end of
+ * every cycle and reported.
+ * b: device n x nrhs; x: device n x nrhs, in: initial guess, out: solution.
+ * restart: 1..64.  iters (Arnoldi steps over all cycles), relres (true relative residual):
+ * host arrays [nrhs] (may be NULL).  Returns DD_WARN_MAXIT if some RHS did not converge;
+ * DD_ERR_INVALID_ARG for bad arguments or a batch handle (dd_setup_batch: use dd_pcg);
+ * DD_ERR_NAN on NaN or a breakdown with a singular Hessenberg matrix. */
+int dd_gmres(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit,
+             int32_t restart, int32_t* iters, double* relres, hipStream_t stream);
 
 /* y = A x for the fine-level matrix held by the handle (SpMV kernel), device pointers. */
 int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t stream);

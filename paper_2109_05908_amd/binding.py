@@ -16,6 +16,7 @@ _LIB = None
 
 DD_FP64, DD_FP32 = 0, 1
 DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP = 0, 1
+DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED = 0, 1
 DD_NPHASE = 12
 DD_MAX_LEVELS = 4
 
@@ -34,7 +35,8 @@ class _Csr(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("local_prec", C.c_int32), ("select", C.c_int32), ("nev_cap", C.c_int32),
-                ("validate", C.c_int32), ("coarsen", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("validate", C.c_int32), ("coarsen", C.c_int32), ("schwarz", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class _Info(C.Structure):
@@ -83,6 +85,7 @@ def lib():
         "dd_setup_batch": ([P(_Csr), P(vp), P(i32), i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
         "dd_apply": ([vp, vp, vp, i32, vp], i32),
         "dd_pcg": ([vp, vp, vp, i32, f64, i32, P(i32), P(f64), vp], i32),
+        "dd_gmres": ([vp, vp, vp, i32, f64, i32, i32, P(i32), P(f64), vp], i32),
         "dd_spmv": ([vp, vp, vp, vp], i32),
         "dd_info": ([vp, P(_Info)], i32),
         "dd_phase_name": ([i32], C.c_char_p),
@@ -107,7 +110,7 @@ def lib():
 
 
 def exported_symbols() -> list[str]:
-    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_spmv", "dd_info", "dd_phase_name",
+    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
             "dd_meter_start", "dd_meter_read"]
@@ -158,16 +161,17 @@ def partition_ggg(A: DeviceCSR, N: int, seed: int):
 class Preconditioner:
     """Handle of dd_setup: the additive Schwarz preconditioner with `levels`
     levels (2 = fine + coarse E; more levels recurse on E, coarsening the
-    subdomain graph by `coarsen`)."""
+    subdomain graph by `coarsen`); schwarz=DD_SCHWARZ_DEFLATED for the
+    deflated variant (solve with gmres)."""
 
     def __init__(self, A: DeviceCSR, part, N: int, overlap: int, tau: float, levels: int = 2,
                  local_prec: int = DD_FP64, select: int = DD_SEL_THRESHOLD, nev_cap: int = 0,
-                 validate: bool = False, coarsen: int = 0):
+                 validate: bool = False, coarsen: int = 0, schwarz: int = DD_SCHWARZ_ADDITIVE):
         import torch
         self.A = A
         self.n = A.n
         part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device)
-        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), (C.c_int32 * 7)())
+        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), int(schwarz), (C.c_int32 * 6)())
         h = C.c_void_p()
         cs = A.cstruct()
         self.setup_status = _check(
@@ -178,7 +182,8 @@ class Preconditioner:
 
     @classmethod
     def batch(cls, As, parts, Ns, overlap: int, tau: float, levels: int = 2, local_prec: int = DD_FP64,
-              select: int = DD_SEL_THRESHOLD, nev_cap: int = 0, validate: bool = False, coarsen: int = 0):
+              select: int = DD_SEL_THRESHOLD, nev_cap: int = 0, validate: bool = False, coarsen: int = 0,
+              schwarz: int = DD_SCHWARZ_ADDITIVE):
         """dd_setup_batch: independent systems As[j] (DeviceCSR) with partitions
         parts[j] into Ns[j] parts, one handle over their block-diagonal union.
         Vectors are the systems concatenated; pcg returns per-system counts."""
@@ -189,7 +194,7 @@ class Preconditioner:
         csrs = (_Csr * k)(*[A.cstruct() for A in As])
         pp = (C.c_void_p * k)(*[t.data_ptr() for t in tparts])
         ns = (C.c_int32 * k)(*[int(x) for x in Ns])
-        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), (C.c_int32 * 7)())
+        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), int(schwarz), (C.c_int32 * 6)())
         h = C.c_void_p()
         self = cls.__new__(cls)
         self.setup_status = _check(
@@ -245,6 +250,18 @@ class Preconditioner:
         its = (C.c_int32 * (nrhs * self.nsys))()
         rr = (C.c_double * (nrhs * self.nsys))()
         code = _check(lib().dd_pcg(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, its, rr, _stream()), "dd_pcg")
+        return x, list(its), list(rr), code
+
+    def gmres(self, b, x0=None, rtol: float = 1e-8, maxit: int = 1000, restart: int = 30):
+        """dd_gmres: right-preconditioned GMRES(restart), flexible with more than two levels."""
+        import torch
+        b = b.contiguous()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        its = (C.c_int32 * nrhs)()
+        rr = (C.c_double * nrhs)()
+        code = _check(lib().dd_gmres(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, restart, its, rr, _stream()),
+                      "dd_gmres")
         return x, list(its), list(rr), code
 
     def spmv(self, x):

@@ -49,6 +49,43 @@ struct Opts {
     int nev_cap = 0;
     int validate = 0;
     int coarsen = 64;
+    int schwarz = DD_SCHWARZ_ADDITIVE;
+};
+
+// Workspace of right-preconditioned GMRES on one level: Krylov basis V
+// (n x (restart + 1)), preconditioned directions of the flexible form
+// (n x restart), two vectors, the partial sums of V^T w and the device and
+// pinned host copies of a Hessenberg column.
+constexpr int kMaxRestart = 64;
+constexpr int kGemvBlocks = 256;
+constexpr int kHcol = 2 * (kMaxRestart + 1) + 1;  // first pass, second pass, ||w||^2
+struct GmresWork {
+    int cap = 0;
+    bool flex = false;
+    int64_t n = 0;
+    DBuf<double> V, Zf, w, t, part, h;
+    double* hp = nullptr;
+    GmresWork() = default;
+    GmresWork(const GmresWork&) = delete;
+    GmresWork& operator=(const GmresWork&) = delete;
+    ~GmresWork() {
+        if (hp) (void)hipHostFree(hp);
+    }
+    void ensure(int64_t nn, int restart, bool flexible) {
+        if (nn == n && restart <= cap && (!flexible || flex)) return;
+        const int c = std::max(restart, cap);
+        const bool f = flexible || flex;
+        V.alloc((size_t)nn * (c + 1));
+        Zf.alloc(f ? (size_t)nn * c : 0);
+        w.alloc(nn);
+        t.alloc(nn);
+        part.alloc((size_t)kGemvBlocks * (kMaxRestart + 1));
+        h.alloc(kHcol + kMaxRestart);
+        if (!hp) DD_HIP(hipHostMalloc(&hp, (kHcol + kMaxRestart) * sizeof(double)));
+        cap = c;
+        flex = f;
+        n = nn;
+    }
 };
 
 enum Phase { PH_SETS, PH_EXTRACT, PH_CHOL, PH_QR, PH_POLAR, PH_SIGMA, PH_SCHUR, PH_EIG, PH_BASIS, PH_E, PH_EFACT, PH_OTHER };
@@ -97,6 +134,8 @@ struct Level {
 
     // Krylov workspace for systems with this level's matrix
     DBuf<double> kr, kz, kp, kq, kro, kx;
+    GmresWork gm;
+    DBuf<double> dy, dt;  // deflated apply: coarse correction and the residual it leaves
 
     // apply workspace
     DBuf<double> rloc, yloc, tpart, yC;
@@ -1023,10 +1062,12 @@ constexpr double kInnerRtol = 1e-4;  // coarse solves by PCG on levels >= 2 (Sec
 
 static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
                   bool true_res, int* iters, double* relres, hipStream_t s);
+static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, bool flexible,
+                 int* iters, double* relres, hipStream_t s);
 
 // y := E_m^{-1} y: exact block Cholesky solve on the last level, otherwise PCG
-// on E_m (the next level's matrix) to kInnerRtol, preconditioned by the next
-// level, from x0 = 0.
+// (deflated variant: right-preconditioned GMRES(30)) on E_m, the next level's
+// matrix, to kInnerRtol, preconditioned by the next level, from x0 = 0.
 static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
     Level& Lv = *H.lv[m];
     if (m + 1 >= H.lv.size()) {
@@ -1037,13 +1078,58 @@ static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
     int its = 0;
     double rr = 0.0;
     fill(Nx.kx.p, Nx.n, 0.0, s);
-    const int rc = krylov(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, &its, &rr, s);
+    const int rc = H.opt.schwarz == DD_SCHWARZ_DEFLATED
+                       ? gmres(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, 30, m + 2 < H.lv.size(), &its, &rr, s)
+                       : krylov(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, &its, &rr, s);
     DD_CHECK(rc >= 0, rc, "inner coarse solve failed");
     DD_HIP(hipMemcpyAsync(y, Nx.kx.p, Nx.n * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
-// z = M_m^{-1} r, the additive preconditioner (2.1) of level m
+// z[g] = base[g] + (local solution of g's own part at g): the prolongation of
+// the restricted method with the Boolean partition of unity (base optional)
+__global__ void k_ras_prolong(const double* rloc, const int64_t* offO, const int32_t* part, const int32_t* ilocal,
+                              const double* base, double* z, int64_t n) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const double v = rloc[offO[part[g]] + ilocal[g]];
+        z[g] = base ? base[g] + v : v;
+    }
+}
+
+// z = M_deflated r = y + M_RAS (r - A y), y = Z E^{-1} Z^T r (Sec. 4): the
+// coarse correction first, then the restricted one-level method on the
+// residual it leaves.  The coarse solve of a level that is not the last is
+// right-preconditioned GMRES(30) to kInnerRtol with the next level's M_deflated.
+static void apply_deflated(Handle& H, size_t m, const double* r, double* z, hipStream_t s) {
+    Level& Lv = *H.lv[m];
+    const int64_t n = Lv.n;
+    const double* rr = r;
+    const double* base = nullptr;
+    if (Lv.nC > 0) {
+        SubInfo S = Lv.sub();
+        restrict_coarse(S, Lv.nC, r, Lv.yC.p, s);
+        coarse_solve(H, m, Lv.yC.p, s);
+        fill(Lv.dy.p, n, 0.0, s);
+        prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, Lv.dy.p, s);
+        spmv(Lv.A(), Lv.dy.p, Lv.dt.p, 1, s);
+        hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, r, Lv.dt.p, n);  // dt = r - A y
+        rr = Lv.dt.p;
+        base = Lv.dy.p;
+    }
+    gather(rr, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
+    if (Lv.fp32) trinv_apply_vb(Lv.Tb32, s);
+    else trinv_apply_vb(Lv.Tb, s);
+    hipLaunchKernelGGL(k_ras_prolong, dim3(vgrid(n)), dim3(256), 0, s, Lv.rloc.p, Lv.offO.p, Lv.part.p, Lv.ilocal.p,
+                       base, z, n);
+    launch_check("apply_deflated");
+}
+
+// z = M_m^{-1} r: the additive preconditioner (2.1) of level m, or the
+// deflated one of Sec. 4
 static void apply_level(Handle& H, size_t m, const double* r, double* z, hipStream_t s) {
+    if (H.opt.schwarz == DD_SCHWARZ_DEFLATED) {
+        apply_deflated(H, m, r, z, s);
+        return;
+    }
     Level& Lv = *H.lv[m];
     gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
     if (Lv.fp32) trinv_apply_vb(Lv.Tb32, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
@@ -1057,8 +1143,12 @@ static void apply_level(Handle& H, size_t m, const double* r, double* z, hipStre
     }
 }
 
-static void alloc_krylov(Level& Lv) {
+static void alloc_krylov(Level& Lv, bool deflated) {
     const int64_t n = std::max<int64_t>(1, Lv.n);
+    if (deflated) {
+        Lv.dy.alloc(n);
+        Lv.dt.alloc(n);
+    }
     Lv.kr.alloc(n);
     Lv.kz.alloc(n);
     Lv.kp.alloc(n);
@@ -1128,6 +1218,173 @@ static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, 
     *iters = its;
     *relres = rel;
     return conv ? DD_OK : DD_WARN_MAXIT;
+}
+
+// ---------------------------------------------------------------------------
+// Right-preconditioned GMRES(restart) (R12): Arnoldi on A M with classical
+// Gram-Schmidt applied twice, so each orthogonalisation is two tall-skinny
+// products with the basis (V^T w, then w -= V h) instead of j dependent dot
+// products; the Hessenberg column comes to the host once per step, where the
+// Givens rotations and the small triangular solve run.
+// ---------------------------------------------------------------------------
+// part[c * gridDim.x + blockIdx.x] = sum over the block's rows of V[i + c ld] w[i],
+// c < k; four columns per pass share each w[i] load
+__global__ __launch_bounds__(256) void k_gemv_t_part(const double* V, int64_t ld, int k, const double* w, int64_t n,
+                                                     double* part) {
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int c0 = 0; c0 < k; c0 += 4) {
+        const int nc = k - c0 < 4 ? k - c0 : 4;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < nc) a[c] += V[i + (int64_t)(c0 + c) * ld] * wi;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double v = a[c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[c][wv] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < nc)
+            part[(int64_t)(c0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+                red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        __syncthreads();
+    }
+}
+// out[c] = sum_b part[c * nb + b], fixed order; a wave per column
+__global__ __launch_bounds__(256) void k_gemv_t_final(const double* part, int nb, int k, double* out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < k; c += 4) {
+        double v = 0.0;
+        for (int b = lane; b < nb; b += 64) v += part[(int64_t)c * nb + b];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) out[c] = v;
+    }
+}
+// w := (accumulate ? w : 0) + alpha V h, V n x k (ld), h on the device (k <= kMaxRestart + 1)
+__global__ __launch_bounds__(256) void k_gemv_n(const double* V, int64_t ld, int k, const double* h, double alpha,
+                                                double* w, int64_t n, int accumulate) {
+    __shared__ double hs[kMaxRestart + 1];
+    for (int c = threadIdx.x; c < k; c += blockDim.x) hs[c] = h[c];
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c < k; ++c) acc += V[i + (int64_t)c * ld] * hs[c];
+        w[i] = (accumulate ? w[i] : 0.0) + alpha * acc;
+    }
+}
+__global__ void k_scale_to(const double* x, double a, double* y, int64_t n) {  // y = a x
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+
+static void gemv_t(const double* V, int64_t n, int k, const double* w, double* part, double* out, hipStream_t s) {
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kGemvBlocks, (n + 255) / 256));
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(nb), dim3(256), 0, s, V, n, k, w, n, part);
+    hipLaunchKernelGGL(k_gemv_t_final, dim3(1), dim3(256), 0, s, part, nb, k, out);
+}
+
+// GMRES(restart) on the matrix of level m, right-preconditioned by level m's
+// M (additive or deflated), x holds x0 on entry.  A cycle ends when the
+// Arnoldi estimate |g_{j+1}| reaches rtol ||b||, after `restart` steps, on
+// breakdown or at maxit steps in total; the true residual then starts the next
+// cycle and is the one reported.  flexible: the preconditioned directions are
+// kept (x += [M v_1 ...] y), for a preconditioner with inner iterative solves.
+static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, bool flexible,
+                 int* iters, double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[m];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    GmresWork& G = Lv.gm;
+    G.ensure(n, restart, flexible);
+    double *V = G.V.p, *w = G.w.p, *t = G.t.p, *hd = G.h.p, *hp = G.hp;
+    double* yd = hd + kHcol;  // device copy of the cycle's y
+    double* yh = hp + kHcol;  // pinned host copy
+    const int g1 = vgrid(n);
+    const double bn = std::sqrt(dot_host(H, b, b, n, s));
+    DD_CHECK(std::isfinite(bn), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+    if (bn == 0.0) {
+        fill(x, n, 0.0, s);
+        *iters = 0;
+        *relres = 0.0;
+        return DD_OK;
+    }
+    spmv(A, x, w, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(g1), dim3(256), 0, s, b, w, n);  // w = b - A x
+    double beta = std::sqrt(dot_host(H, w, w, n, s));
+    DD_CHECK(std::isfinite(beta), DD_ERR_NAN, "GMRES produced NaN");
+    const int ldh = restart + 1;
+    std::vector<double> Hm((size_t)ldh * restart), cs(restart), sn(restart), g(restart + 1);
+    int its = 0;
+    while (beta > rtol * bn && its < maxit) {
+        hipLaunchKernelGGL(k_scale_to, dim3(g1), dim3(256), 0, s, w, 1.0 / beta, V, n);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < restart; ++j) {
+            const double* vj = V + (int64_t)j * n;
+            double* zj = flexible ? G.Zf.p + (int64_t)j * n : t;
+            apply_level(H, m, vj, zj, s);
+            spmv(A, zj, w, 1, s);
+            // two passes of classical Gram-Schmidt against v_0 .. v_j
+            gemv_t(V, n, j + 1, w, G.part.p, hd, s);
+            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, V, n, j + 1, hd, -1.0, w, n, 1);
+            gemv_t(V, n, j + 1, w, G.part.p, hd + kMaxRestart + 1, s);
+            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, V, n, j + 1, hd + kMaxRestart + 1, -1.0, w, n, 1);
+            dot(w, w, n, 1, H.partial.p, hd + 2 * (kMaxRestart + 1), s);
+            DD_HIP(hipMemcpyAsync(hp, hd, kHcol * sizeof(double), hipMemcpyDeviceToHost, s));
+            DD_HIP(hipStreamSynchronize(s));
+            double* col = Hm.data() + (size_t)j * ldh;
+            for (int i = 0; i <= j; ++i) col[i] = hp[i] + hp[kMaxRestart + 1 + i];
+            const double hn = std::sqrt(hp[2 * (kMaxRestart + 1)]);
+            DD_CHECK(std::isfinite(hn), DD_ERR_NAN, "GMRES produced NaN");
+            col[j + 1] = hn;
+            if (hn > 0.0)
+                hipLaunchKernelGGL(k_scale_to, dim3(g1), dim3(256), 0, s, w, 1.0 / hn, V + (int64_t)(j + 1) * n, n);
+            for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
+                const double a = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = a;
+            }
+            const double d = std::hypot(col[j], col[j + 1]);
+            DD_CHECK(d > 0.0, DD_ERR_NAN, "GMRES breakdown (singular Hessenberg matrix)");
+            cs[j] = col[j] / d;
+            sn[j] = col[j + 1] / d;
+            col[j] = d;
+            col[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++its;
+            k = j + 1;
+            if (std::fabs(g[j + 1]) <= rtol * bn || its >= maxit || sn[j] == 0.0) break;
+        }
+        // y = R^{-1} g by back substitution, then the update of x
+        for (int i = k - 1; i >= 0; --i) {
+            double v = g[i];
+            for (int l = i + 1; l < k; ++l) v -= Hm[(size_t)l * ldh + i] * yh[l];
+            yh[i] = v / Hm[(size_t)i * ldh + i];
+        }
+        DD_HIP(hipMemcpyAsync(yd, yh, k * sizeof(double), hipMemcpyHostToDevice, s));
+        if (flexible) {
+            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, G.Zf.p, n, k, yd, 1.0, x, n, 1);
+        } else {
+            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, V, n, k, yd, 1.0, t, n, 0);
+            apply_level(H, m, t, w, s);
+            hipLaunchKernelGGL(k_xpby, dim3(g1), dim3(256), 0, s, w, x, 1.0, n);  // x = M V y + x
+        }
+        spmv(A, x, w, 1, s);
+        hipLaunchKernelGGL(k_sub, dim3(g1), dim3(256), 0, s, b, w, n);
+        beta = std::sqrt(dot_host(H, w, w, n, s));  // synchronises: yh may be rewritten next cycle
+        DD_CHECK(std::isfinite(beta), DD_ERR_NAN, "GMRES produced NaN");
+    }
+    *iters = its;
+    *relres = beta / bn;
+    return beta <= rtol * bn ? DD_OK : DD_WARN_MAXIT;
 }
 
 // ---------------------------------------------------------------------------
@@ -1417,7 +1674,7 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
         partition_next(Lv, *nx, H.opt.coarsen, s);
         H.lv.push_back(std::move(nx));
     }
-    for (auto& l : H.lv) alloc_krylov(*l);
+    for (auto& l : H.lv) alloc_krylov(*l, H.opt.schwarz == DD_SCHWARZ_DEFLATED);
     // diagnostics
     dd_info_t& I = H.info;
     I.levels = (int32_t)H.lv.size() + 1;
@@ -1468,6 +1725,8 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
         H.opt.validate = opt->validate;
         if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
         if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
+        if (opt->schwarz != DD_SCHWARZ_ADDITIVE && opt->schwarz != DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;
+        H.opt.schwarz = opt->schwarz;
     }
     const int rc = build_handle(H, A->n, A->nnz, A->rowptr, A->colind, A->val, part, N, overlap, tau, levels, s);
     if (rc < 0) return rc;
@@ -1521,6 +1780,8 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
         H.opt.validate = opt->validate;
         if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
         if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
+        if (opt->schwarz != DD_SCHWARZ_ADDITIVE && opt->schwarz != DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;
+        H.opt.schwarz = opt->schwarz;
     }
     // the block-diagonal union of the systems, its partition and the system of every dof
     const int64_t n = noff[nsys], nnz = zoff[nsys];
@@ -1564,6 +1825,7 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
     DD_GUARD_BEGIN
     if (!h || !b || !x || nrhs < 1 || maxit < 0 || !(rtol > 0.0)) return DD_ERR_INVALID_ARG;
     Handle& H = h->h;
+    if (H.opt.schwarz == DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;  // not symmetric: dd_gmres
     const int64_t n = H.lv[0]->n;
     int rc = DD_OK;
     if (H.nsys() > 1) {  // batch: one PCG per system, nsys results per right-hand side
@@ -1589,6 +1851,32 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
         int it = 0;
         double rr = 0.0;
         const int c = krylov(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, &it, &rr, s);
+        if (c < 0) return c;
+        if (c > 0) rc = c;
+        if (iters) iters[k] = it;
+        if (relres) relres[k] = rr;
+        if (k == 0) {
+            H.info.last_iters = it;
+            H.info.last_relres = rr;
+        }
+    }
+    return rc;
+    DD_GUARD_END
+}
+
+int dd_gmres(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit, int32_t restart,
+             int32_t* iters, double* relres, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!h || !b || !x || nrhs < 1 || maxit < 0 || !(rtol > 0.0) || restart < 1 || restart > kMaxRestart)
+        return DD_ERR_INVALID_ARG;
+    Handle& H = h->h;
+    if (H.nsys() > 1) return DD_ERR_INVALID_ARG;  // batch handles: one PCG per system (dd_pcg)
+    const int64_t n = H.lv[0]->n;
+    int rc = DD_OK;
+    for (int k = 0; k < nrhs; ++k) {
+        int it = 0;
+        double rr = 0.0;
+        const int c = gmres(H, 0, b + k * n, x + k * n, rtol, maxit, restart, H.lv.size() > 1, &it, &rr, s);
         if (c < 0) return c;
         if (c > 0) rc = c;
         if (iters) iters[k] = it;
