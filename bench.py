@@ -201,7 +201,8 @@ def main():
     import torch
 
     import workloads as W
-    from paper_2109_05908_amd import DD_FP32, DD_FP64, DeviceCSR, Preconditioner, meter_read, meter_start, partition_ggg
+    from paper_2109_05908_amd import (DD_FP32, DD_FP64, DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED, DeviceCSR,
+                                      Preconditioner, meter_read, meter_start, partition_ggg)
 
     if args.calibrate_copy:
         calibrate_copy()
@@ -217,13 +218,17 @@ def main():
     prec = DD_FP32 if args.form == "fp32" else DD_FP64
     torch.cuda.synchronize()
 
-    def step(prec=prec):
+    def step(prec=prec, schwarz=DD_SCHWARZ_ADDITIVE):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, levels=cfg.levels, local_prec=prec)
+        pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, levels=cfg.levels, local_prec=prec,
+                             schwarz=schwarz)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, its, rr, code = pre.pcg(b, rtol=1e-8, maxit=1000)
+        if schwarz == DD_SCHWARZ_DEFLATED:  # the variant of the paper's experiments: GMRES(30)
+            x, its, rr, code = pre.gmres(b, rtol=1e-8, maxit=1000, restart=30)
+        else:
+            x, its, rr, code = pre.pcg(b, rtol=1e-8, maxit=1000)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         assert code == 0 and rr[0] <= 1e-8, (code, rr)
@@ -281,6 +286,20 @@ def main():
             print(f"[bench] form {other} step {k}: {ts + tv:.3f}s its {its} relres {rr:.2e}", file=sys.stderr, flush=True)
         forms[other] = {"setup_plus_solve_s": float(np.median([t[0] for t in ot])), "pcg_iterations": ot[-1][1],
                         "final_relres": ot[-1][2]}
+        # the deflated variant with the one-level restricted method under
+        # right-preconditioned GMRES(30), as in the paper's experiments (same setup)
+        ot = []
+        for k in range(1 + args.steps):
+            pre, ts, tv, its, rr = step(prec, DD_SCHWARZ_DEFLATED)
+            del pre
+            if k > 0:
+                ot.append((ts, tv, its, rr))
+            print(f"[bench] form deflated_gmres step {k}: setup {ts:.3f}s solve {tv:.3f}s its {its} relres {rr:.2e}",
+                  file=sys.stderr, flush=True)
+        forms[f"deflated_gmres_{args.form}"] = {
+            "setup_plus_solve_s": float(np.median([t[0] + t[1] for t in ot])),
+            "solve_s_median": float(np.median([t[1] for t in ot])), "gmres_iterations": ot[-1][2],
+            "final_relres": ot[-1][3]}
     conf["forms"] = forms
     if not args.no_cpu_baseline:
         part_h = part.cpu().numpy()
