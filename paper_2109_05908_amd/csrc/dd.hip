@@ -414,15 +414,24 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 Batch<DMat> Sbot = mats(sbot, two_ni, ni, ni, s, &actQ);
                 std::vector<double> sqc(N, 0.0);
                 for (int i = 0; i < N; ++i) sqc[i] = actQ[i] ? std::sqrt(cc[i]) : 0.0;
-                // top = sqrt(c) * Xt^T : copy transposed then scale per item
-                copy_vb(Xq, Stop, true, 1.0, s);
-                {
-                    std::vector<double> sa, sz;
-                    for (int i = 0; i < N; ++i) if (actQ[i]) { sa.push_back(sqc[i]); sz.push_back(0.0); }
-                    DBuf<double> d1 = upload(sa, s), d2 = upload(sz, s);
-                    axpby_vb(Stop, Stop, d1.p, d2.p, s);
+                // The first iterate Xt = R^T / alpha is lower triangular, so S = [sqrt(c) Xt^T; I]
+                // is [upper triangular; I]: with its rows interleaved, column j is zero below row
+                // 2j + 1 and the QR and the explicit Q only touch rows up to about 2 (block end)
+                // instead of ni + (block end).  Later iterates are full.
+                const bool tri = it == 0;
+                std::vector<double> sa, sz;
+                for (int i = 0; i < N; ++i) if (actQ[i]) { sa.push_back(sqc[i]); sz.push_back(0.0); }
+                DBuf<double> dsc = upload(sa, s), dzero = upload(sz, s);
+                Batch<DMat> Sfull = mats(sp, two_ni, two_ni, ni, s, &actQ);
+                if (tri) {
+                    stack_interleaved_vb(Xq, Sfull, dsc.p, s);
+                } else {
+                    // top = sqrt(c) * Xt^T : copy transposed then scale per item
+                    copy_vb(Xq, Stop, true, 1.0, s);
+                    axpby_vb(Stop, Stop, dsc.p, dzero.p, s);
+                    set_identity_vb(Sbot, 1.0, s);
                 }
-                set_identity_vb(Sbot, 1.0, s);
+                const int zr = tri ? 1 : 0, zs = tri ? 2 : 1;
                 Arena tq, tT, tW, tG;
                 std::vector<int64_t> a1(N), a2(N), a3(N), a4(N);
                 for (int i = 0; i < N; ++i) {
@@ -436,9 +445,10 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 Batch<ORItem> ob;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
-                    // [sqrt(c) Xt^T; I]: column j is zero below row ni + j
-                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i], tG.ptr[i], ni[i]});
-                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i], tG.ptr[i], ni[i]});
+                    // [sqrt(c) Xt^T; I]: column j is zero below row ni + j (interleaved: 1 + 2j)
+                    const int zrow = tri ? zr : ni[i];
+                    qb.h.push_back(QRItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tq.ptr[i], tT.ptr[i], tW.ptr[i], QR_NB, ni[i], tG.ptr[i], zrow, zs});
+                    ob.h.push_back(ORItem{DMat{sp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tT.ptr[i], DMat{qp[i], 2 * ni[i], 2 * ni[i], ni[i]}, tW.ptr[i], tG.ptr[i], zrow, zs});
                 }
                 qb.sync(s);
                 ob.sync(s);
@@ -446,11 +456,14 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
                 Batch<DMat> Qb = mats(qp, two_ni, two_ni, ni, s, &actQ);
                 set_identity_vb(Qb, 1.0, s);
                 orgqr_vb(ob, s);
+                // Q = [Q1; Q2] (interleaved: de-interleaved into the reflector storage, now free)
+                const std::vector<double*>& qsrc = tri ? sp : qp;
+                if (tri) deinterleave_rows_vb(Qb, Sfull, s);
                 Batch<GemmItem> g;
                 for (int i = 0; i < N; ++i) {
                     if (!actQ[i]) continue;
-                    g.h.push_back(GemmItem{qp[i] + ni[i], 2 * ni[i], qp[i], 2 * ni[i], Xt.ptr[i], ni[i], ni[i], ni[i], ni[i],
-                                           coefQ[i], beta[i]});
+                    g.h.push_back(GemmItem{qsrc[i] + ni[i], 2 * ni[i], qsrc[i], 2 * ni[i], Xt.ptr[i], ni[i], ni[i], ni[i],
+                                           ni[i], coefQ[i], beta[i]});
                 }
                 g.sync(s);
                 gemm_vb(g, false, true, s);

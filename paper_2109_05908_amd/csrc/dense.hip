@@ -781,7 +781,7 @@ __global__ void __launch_bounds__(PANEL_THREADS) k_qr_panel(const QRItem* q, int
     const QRItem it = q[b];
     if (it.nfac <= col0 || it.A.m <= col0) return;
     const int w = min(QR_NB, it.nfac - col0);
-    const int mp = qr_rows(it.A.m, it.zrow, col0, QR_NB) - col0;
+    const int mp = qr_rows(it.A.m, it.zrow, it.zslope, col0, QR_NB) - col0;
     const int64_t ld = it.A.ld;
     double* V = it.A.p + col0 + (int64_t)col0 * ld;
     const int w1 = (w > QR_HB) ? QR_HB : w;  // first half
@@ -912,7 +912,7 @@ struct OpPanelGram {
     const ORItem* o;
     double* const* Wp;  // per item: ceil(mp / QR_GKS) partials of 32 x 32
     int col0;
-    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, col0, QR_NB) - col0; }
+    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, o[b].zslope, col0, QR_NB) - col0; }
     __device__ int tiles(int b) const {
         if (o[b].V.n <= col0 || o[b].V.m <= col0) return 0;
         return (mrows(b) + QR_GKS - 1) / QR_GKS;
@@ -971,7 +971,7 @@ struct OpBuildT {
         __shared__ double T[32][33];
         const DMat Vm = o[b].V;
         const int w = min(QR_NB, Vm.n - col0);
-        const int mp = qr_rows(Vm.m, o[b].zrow, col0, QR_NB) - col0;
+        const int mp = qr_rows(Vm.m, o[b].zrow, o[b].zslope, col0, QR_NB) - col0;
         const int nks = (mp + QR_GKS - 1) / QR_GKS;
         const double* P = Wp[b];
         for (int e = threadIdx.x; e < 1024; e += blockDim.x) {
@@ -1042,7 +1042,7 @@ struct BlkOp {
         r = blk_range(o[b], c0, cap, mode, oend);
         return r.wb > 0 && r.cc1 > r.cc0;
     }
-    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, c0, cap) - c0; }
+    __device__ int mrows(int b) const { return qr_rows(o[b].V.m, o[b].zrow, o[b].zslope, c0, cap) - c0; }
     __device__ int nks(int b) const { return (mrows(b) + QR_KS - 1) / QR_KS; }
     __device__ int pstride(int b) const { return PLD * max(PLD, o[b].C.n); }
 };
@@ -1322,7 +1322,7 @@ static void build_t_panel(Batch<ORItem>& o, QrScratch& sc, const double* const* 
     for (auto& x : o.h) {
         if (x.V.n <= col0 || x.V.m <= col0) continue;
         ++nt;
-        ng += ceil_div(qr_rows(x.V.m, x.zrow, col0, QR_NB) - col0, QR_GKS);
+        ng += ceil_div(qr_rows(x.V.m, x.zrow, x.zslope, col0, QR_NB) - col0, QR_GKS);
     }
     if (nt == 0) return;
     launch_tiles(OpPanelGram{o.d.p, sc.ptr.p, col0}, o.size(), ng, s, "qr_panel_gram");
@@ -1342,7 +1342,7 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
         else { cc0 = c0; cc1 = x.C.n; }
         if (wb <= 0 || cc1 <= cc0) continue;
         const int ntc = ceil_div(cc1 - cc0, 64);
-        const int mp = qr_rows(x.V.m, x.zrow, c0, cap) - c0;
+        const int mp = qr_rows(x.V.m, x.zrow, x.zslope, c0, cap) - c0;
         nw += ntc;
         np += (int64_t)ceil_div(wb, 64) * ntc * ceil_div(mp, QR_KS);
         nu += (int64_t)ceil_div(mp, 64) * ntc;
@@ -1366,7 +1366,7 @@ static void apply_block(Batch<ORItem>& o, QrScratch& sc, int c0, int cap, int mo
             else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
             else { cc0 = c0; cc1 = x.C.n; }
             if (wb <= 0 || cc1 <= cc0) continue;
-            const double mp = qr_rows(x.V.m, x.zrow, c0, cap) - c0, nc = cc1 - cc0;
+            const double mp = qr_rows(x.V.m, x.zrow, x.zslope, c0, cap) - c0, nc = cc1 - cc0;
             const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
             fl += 2.0 * nc * nzv;
             by += 8.0 * ((nzv - wb) + (double)wb * nc + 2.0 * mp * nc);
@@ -1382,7 +1382,7 @@ static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
         const int wb = std::min(QR_OB, x.V.n - c0);
         if (wb <= QR_NB) continue;  // a single panel needs no G
         const int T = ceil_div(wb, 64);
-        np += (int64_t)T * T * ceil_div(qr_rows(x.V.m, x.zrow, c0, QR_OB) - c0, QR_KS);
+        np += (int64_t)T * T * ceil_div(qr_rows(x.V.m, x.zrow, x.zslope, c0, QR_OB) - c0, QR_KS);
         ++nr;
     }
     if (nr == 0) return;
@@ -1396,7 +1396,7 @@ static void gram_block(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
 // Partials over row chunks, then an ordered sum (rows of Gx past V_b's width are 0).
 struct OpGramXP : BlkOp {
     __device__ int wbb(int b) const { return min(QR_OB, o[b].V.n - c0 - QR_OB); }
-    __device__ int mx(int b) const { return qr_rows(o[b].V.m, o[b].zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB); }
+    __device__ int mx(int b) const { return qr_rows(o[b].V.m, o[b].zrow, o[b].zslope, c0 + QR_OB, QR_OB) - (c0 + QR_OB); }
     __device__ int tiles(int b) const {
         if (o[b].V.n <= c0 + QR_OB || mx(b) <= 0) return 0;
         return ((wbb(b) + 63) / 64) * 2 * ((mx(b) + QR_KS - 1) / QR_KS);
@@ -1427,7 +1427,7 @@ struct OpGramXR : BlkOp {
     __device__ void operator()(int b, int) const {
         const ORItem& it = o[b];
         const int wb = min(QR_OB, it.V.n - c0 - QR_OB);
-        const int m = qr_rows(it.V.m, it.zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
+        const int m = qr_rows(it.V.m, it.zrow, it.zslope, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
         const int nks_ = m > 0 ? (m + QR_KS - 1) / QR_KS : 0;
         const int ps = pstride(b);
         const int nblk = (it.V.n + QR_OB - 1) / QR_OB;
@@ -1447,7 +1447,7 @@ static void gram_cross(Batch<ORItem>& o, QrScratch& sc, int c0, hipStream_t s) {
     for (auto& x : o.h) {
         if (x.V.n <= c0 + QR_OB) continue;
         const int wbb = std::min(QR_OB, x.V.n - c0 - QR_OB);
-        const int m = qr_rows(x.V.m, x.zrow, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
+        const int m = qr_rows(x.V.m, x.zrow, x.zslope, c0 + QR_OB, QR_OB) - (c0 + QR_OB);
         ++nr;
         if (m > 0) np += (int64_t)ceil_div(wbb, 64) * 2 * ceil_div(m, QR_KS);
     }
@@ -1472,7 +1472,7 @@ static void apply_pair(Batch<ORItem>& o, QrScratch& sc, int c0, int mode, int oe
         else { cc0 = c0; cc1 = x.C.n; }
         if (wb <= 0 || cc1 <= cc0) continue;
         const int ntc = ceil_div(cc1 - cc0, 64);
-        const int mp = qr_rows(x.V.m, x.zrow, c0, QR_PAIR) - c0;
+        const int mp = qr_rows(x.V.m, x.zrow, x.zslope, c0, QR_PAIR) - c0;
         np += (int64_t)ceil_div(wb, 64) * ntc * ceil_div(mp, QR_KS);
         nwa += ntc;
         if (wb > QR_OB) {
@@ -1506,7 +1506,7 @@ static void apply_pair(Batch<ORItem>& o, QrScratch& sc, int c0, int mode, int oe
             else if (mode == 2) { cc0 = c0 + wb; cc1 = std::min(std::min(x.C.n, oend), x.V.n); }
             else { cc0 = c0; cc1 = x.C.n; }
             if (wb <= 0 || cc1 <= cc0) continue;
-            const double mp = qr_rows(x.V.m, x.zrow, c0, QR_PAIR) - c0, nc = cc1 - cc0;
+            const double mp = qr_rows(x.V.m, x.zrow, x.zslope, c0, QR_PAIR) - c0, nc = cc1 - cc0;
             const double nzv = mp * wb - 0.5 * wb * (wb - 1.0);
             fl += 2.0 * nc * nzv;
             by += 8.0 * ((nzv - wb) + (double)wb * nc + 2.0 * mp * nc);
@@ -1521,7 +1521,7 @@ void geqrf_vb(Batch<QRItem>& q, hipStream_t s) {
     std::vector<double*> htau;
     for (auto& x : q.h) {
         nmax = std::max(nmax, std::min(x.nfac, x.A.m));
-        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W, x.G, x.zrow});
+        o.h.push_back(ORItem{DMat{x.A.p, x.A.ld, x.A.m, x.nfac}, x.T, x.A, x.W, x.G, x.zrow, x.zslope});
         htau.push_back(x.tau);
     }
     o.sync(s);
@@ -2266,6 +2266,57 @@ struct OpCopy {
         }
     }
 };
+// S (2n x n) = [sc X^T; I] interleaved by rows: 64 x 64 tiles of (i, j), X^T
+// read through LDS as in the transposed copy
+struct OpStackInterleaved {
+    const DMat* X;
+    const DMat* S;
+    const double* sc;
+    __device__ int tiles(int b) const { return ((X[b].n + 63) / 64) * ((X[b].n + 63) / 64); }
+    __device__ void operator()(int b, int t) const {
+        __shared__ double tile[64][65];
+        const DMat x = X[b], d = S[b];
+        const int n = x.n, T = (n + 63) / 64;
+        const int i0 = (t % T) * 64, j0 = (t / T) * 64;
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int cc = e & 63, rr = e >> 6;  // X(j0 + cc, i0 + rr), coalesced in cc
+            tile[rr][cc] = (j0 + cc < n && i0 + rr < n) ? x.p[(j0 + cc) + (int64_t)(i0 + rr) * x.ld] : 0.0;
+        }
+        __syncthreads();
+        const double a = sc[b];
+        for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
+            const int r = e & 63, c = e >> 6, i = i0 + r, j = j0 + c;
+            if (i < n && j < n) {
+                d.p[2 * i + (int64_t)j * d.ld] = a * tile[r][c];
+                d.p[2 * i + 1 + (int64_t)j * d.ld] = i == j ? 1.0 : 0.0;
+            }
+        }
+    }
+};
+void stack_interleaved_vb(Batch<DMat>& X, Batch<DMat>& S, const double* dscale, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : X.h) tot += (int64_t)ceil_div(x.n, 64) * ceil_div(x.n, 64);
+    launch_tiles(OpStackInterleaved{X.d.p, S.d.p, dscale}, X.size(), tot, s, "stack_interleaved");
+}
+
+// D[i] = Q[2i], D[n + i] = Q[2i + 1] (rows), 256 rows of D per tile and column
+struct OpDeinterleave {
+    const DMat* Q;
+    const DMat* D;
+    __device__ int tiles(int b) const { return ((D[b].m + 255) / 256) * D[b].n; }
+    __device__ void operator()(int b, int t) const {
+        const DMat q = Q[b], d = D[b];
+        const int nb = (d.m + 255) / 256, h = d.m / 2;
+        const int j = t / nb, r = (t % nb) * 256 + threadIdx.x;
+        if (r < d.m) d.p[r + (int64_t)j * d.ld] = q.p[(r < h ? 2 * r : 2 * (r - h) + 1) + (int64_t)j * q.ld];
+    }
+};
+void deinterleave_rows_vb(Batch<DMat>& Q, Batch<DMat>& D, hipStream_t s) {
+    int64_t tot = 0;
+    for (auto& x : D.h) tot += (int64_t)ceil_div(x.m, 256) * x.n;
+    launch_tiles(OpDeinterleave{Q.d.p, D.d.p}, D.size(), tot, s, "deinterleave");
+}
+
 void copy_vb(Batch<DMat>& src, Batch<DMat>& dst, bool transpose, double scale, hipStream_t s) {
     int64_t tot = 0;
     for (auto& x : dst.h) tot += (int64_t)ceil_div(x.m, 64) * ceil_div(x.n, 64);

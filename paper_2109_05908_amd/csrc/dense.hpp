@@ -30,9 +30,12 @@ struct Batch {
 // triangular compact-WY factor per 32-column panel (qr_t_size); G holds the
 // Gram matrix V^T V of every 128-column block of reflectors (qr_g_size); W is
 // scratch of qr_w_size(max columns of the matrices the reflectors touch).
-// zrow (optional structure): column j of A has zeros in rows > zrow + j, as
-// for a stack [X; I] with zrow = rows of X.  Reflector j then vanishes below
-// row zrow + j too, so every step only touches rows < zrow + (block end).
+// zrow, zslope (optional structure): column j of A has zeros in rows
+// > zrow + zslope * j, as for a stack [X; I] (zrow = rows of X, zslope = 1) or
+// for [T; I] with T upper triangular and the rows interleaved t_0, i_0, t_1,
+// i_1, ... (zrow = 1, zslope = 2).  Householder steps keep the structure, so
+// reflector j vanishes below row zrow + zslope * j too and every step only
+// touches rows < zrow + zslope * (block end).
 constexpr int QR_NOZ = 1 << 29;
 struct QRItem {
     DMat A;
@@ -43,6 +46,7 @@ struct QRItem {
     int nfac;  // factor only the first nfac columns (<= n); the rest receive Q^T
     double* G;
     int zrow = QR_NOZ;
+    int zslope = 1;
 };
 
 // Application of the Q stored in V (m x k reflectors, T and G as above) to C
@@ -53,10 +57,14 @@ struct ORItem {
     DMat C;
     double* W;  // qr_w_size(C.n)
     double* G;
-    int zrow = QR_NOZ;  // reflector j is zero below row zrow + j
+    int zrow = QR_NOZ;  // reflector j is zero below row zrow + zslope * j
+    int zslope = 1;
 };
 // rows touched by the reflectors in columns [c0, c0 + w) of an m-row matrix
-__host__ __device__ inline int qr_rows(int m, int zrow, int c0, int w) { return m < zrow + c0 + w ? m : zrow + c0 + w; }
+__host__ __device__ inline int qr_rows(int m, int zrow, int zslope, int c0, int w) {
+    const int64_t r = (int64_t)zrow + (int64_t)zslope * (c0 + w);
+    return r < m ? (int)r : m;
+}
 
 constexpr int QR_NB = 32;   // inner panel width
 constexpr int QR_OB = 128;  // outer block (four inner panels)
@@ -195,6 +203,11 @@ void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s);
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)
+// S (2n x n) := [sc_b X^T ; I] with rows interleaved (row 2i: sc_b X^T row i, row
+// 2i+1: identity row i), X n x n (item b of X, S), scale per item on the device
+void stack_interleaved_vb(Batch<DMat>& X, Batch<DMat>& S, const double* dscale, hipStream_t s);
+// D (2n x n) := the rows of Q (2n x n) de-interleaved: D[i] = Q[2i], D[n + i] = Q[2i + 1]
+void deinterleave_rows_vb(Batch<DMat>& Q, Batch<DMat>& D, hipStream_t s);
 void copy_vb(Batch<DMat>& src, Batch<DMat>& dst, bool transpose, double scale, hipStream_t s);
 void add_diag_vb(Batch<DMat>& A, const double* dshift, hipStream_t s);  // A(i,i) += shift[b]
 void symmetrize_vb(Batch<DMat>& A, hipStream_t s);                     // A := (A + A^T)/2
