@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 # sources still hash to what was profiled.
 ROOFLINE_KERNEL = "qr_blk_upd"
 ROOFLINE_SOURCES = ["common.hpp", "dense.hpp", "dense.hip"]
-TRAFFIC = {"sha256": "6302077c154661cd", "bytes_per_launch": 3.7012e9,
+TRAFFIC = {"sha256": "5f28b5efdb5ad099", "bytes_per_launch": 3.0847e9,
            "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6"}
 
 
@@ -232,6 +232,8 @@ def main():
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         assert code == 0 and rr[0] <= 1e-8, (code, rr)
+        ph = " ".join(f"{k}={v:.0f}" for k, v in pre.info()["phase_ms"].items() if v >= 1.0)
+        print(f"[bench]   setup phases (ms): {ph}", file=sys.stderr, flush=True)
         return pre, t1 - t0, t2 - t1, its[0], rr[0]
 
     for w in range(args.warmup):
