@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--no-compare-forms", action="store_true",
                    help="skip timing the other local-solve precision form (after the timed steps)")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
+    p.add_argument("--achievable", action="store_true",
+                   help="only measure the achievable copy bandwidth and FP64/FP32 GEMM rates on this GPU and exit")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run a plain device copy of 1 GiB three times (PMC byte-counter calibration) and exit")
     return p.parse_args()
@@ -77,6 +79,43 @@ def calibrate_copy():
         dt = time.perf_counter() - t0
         print(f"[bench] copy 1 GiB -> 1 GiB: {dt * 1e3:.3f} ms, {2 * n * 8 / dt / 1e9:.0f} GB/s", file=sys.stderr,
               flush=True)
+
+
+def achievable():
+    """Achievable rates on this GPU, for the fractions beside the published peaks:
+    device-to-device copy of 4 GiB (read + write bytes) and square FP64 / FP32
+    matrix products through the vendor BLAS (torch.matmul), timed with events."""
+    import torch
+    out = {}
+    n = (4 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_GBs"] = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    for name, dt, m in (("gemm_fp64_TFs", torch.float64, 8192), ("gemm_fp32_TFs", torch.float32, 8192)):
+        a = torch.randn(m, m, dtype=dt, device="cuda:0")
+        b = torch.randn(m, m, dtype=dt, device="cuda:0")
+        c = a @ b
+        torch.cuda.synchronize()
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = 2.0 * m ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        del a, b, c
+    out.update({"peak_hbm_GBs": 8000.0, "peak_fp64_TFs": 78.6, "peak_fp32_TFs": 157.3})
+    print(json.dumps(out), flush=True)
 
 
 def workload(name):
@@ -204,6 +243,9 @@ def main():
     from paper_2109_05908_amd import (DD_FP32, DD_FP64, DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED, DeviceCSR,
                                       Preconditioner, meter_read, meter_start, partition_ggg)
 
+    if args.achievable:
+        achievable()
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return

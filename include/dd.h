@@ -193,7 +193,15 @@ int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t stream);
 
 int  dd_info(dd_handle h, dd_info_t* out);
 const char* dd_phase_name(int32_t phase);
+/* Frees the handle.  Its device memory goes back to the library's device cache, which hands
+ * it to later setups of the same process instead of hipMalloc/hipFree (large hipMalloc calls
+ * were seen to stall for seconds after a few setup cycles); a cached block is reused only
+ * after a device synchronisation that follows its release.  The cache holds at most
+ * DD_DEVICE_CACHE_GB GiB per process (environment, read once; default 96, 0 disables it). */
 void dd_destroy(dd_handle h);
+/* Returns every cached device block to hipFree (after a device synchronisation), for callers
+ * that need the memory elsewhere.  Thread-safe.  Returns DD_OK. */
+int dd_trim_device_cache(void);
 const char* dd_strerror(int code);
 
 /* ---- inspection (tests and diagnostics; all outputs are host memory) ---- */

@@ -90,6 +90,7 @@ def lib():
         "dd_info": ([vp, P(_Info)], i32),
         "dd_phase_name": ([i32], C.c_char_p),
         "dd_destroy": ([vp], None),
+        "dd_trim_device_cache": ([], i32),
         "dd_strerror": ([C.c_int], C.c_char_p),
         "dd_subdomain_count": ([vp, i32, P(i32)], i32),
         "dd_subdomain_sizes": ([vp, i32, vp], i32),
@@ -111,7 +112,7 @@ def lib():
 
 def exported_symbols() -> list[str]:
     return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
-            "dd_destroy", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
+            "dd_destroy", "dd_trim_device_cache", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
             "dd_meter_start", "dd_meter_read"]
 
@@ -148,6 +149,11 @@ def _check(code: int, what: str, allow_warn: bool = True) -> int:
     if code < 0 or (code > 0 and not allow_warn):
         raise DDError(code, what)
     return code
+
+
+def trim_device_cache() -> None:
+    """dd_trim_device_cache: return the library's cached device memory to the runtime."""
+    _check(lib().dd_trim_device_cache(), "dd_trim_device_cache")
 
 
 def partition_ggg(A: DeviceCSR, N: int, seed: int):

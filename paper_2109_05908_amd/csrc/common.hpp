@@ -39,8 +39,15 @@ inline void launch_check(const char* what) {
 }
 
 // ---------------------------------------------------------------------------
-// device memory owned by RAII buffers
+// device memory owned by RAII buffers, through the library's device cache:
+// a setup allocates and frees tens of GB in a few hundred blocks, and
+// hipMalloc of a large block has been seen to stall for seconds once the
+// device has gone through a few such cycles.  Freed blocks are therefore kept
+// per device and size class and handed to later requests (dev_alloc, dev_free
+// in dd.hip; dd_trim_device_cache returns them).
 // ---------------------------------------------------------------------------
+void* dev_alloc(size_t bytes);              // throws Error(DD_ERR_OOM / DD_ERR_HIP)
+void dev_free(void* p, size_t bytes) noexcept;
 template <class T>
 struct DBuf {
     T* p = nullptr;
@@ -58,10 +65,10 @@ struct DBuf {
     void alloc(size_t count) {
         release();
         n = count;
-        if (count) DD_HIP(hipMalloc(&p, count * sizeof(T)));
+        if (count) p = static_cast<T*>(dev_alloc(count * sizeof(T)));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p, n * sizeof(T));
         p = nullptr;
         n = 0;
     }

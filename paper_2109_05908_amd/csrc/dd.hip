@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
+#include <unordered_map>
 
 #include "bchol.hpp"
 #include "coarse.hpp"
@@ -1555,6 +1558,115 @@ Meter& meter() {
     static Meter m;
     return m;
 }
+// ---------------------------------------------------------------------------
+// Device cache behind DBuf.  Requests are rounded to a size class (4 KiB steps
+// below 64 KiB, 2 MiB steps below 1 GiB, then 1/16 of the power of two below
+// the size) and served by the smallest cached block of the same device whose
+// class is at most 25 % larger.  A freed block may still be in use by work
+// queued before its release, so it is handed out again only after a device
+// synchronisation that follows the release (one is made here when needed).
+// The cache holds at most DD_DEVICE_CACHE_GB GiB (default 96, 0 disables it);
+// beyond that, or on dd_trim_device_cache, blocks go back to hipFree, and a
+// failed hipMalloc empties the cache of that device and is retried once.
+// ---------------------------------------------------------------------------
+namespace {
+struct CacheBlock {
+    size_t cls;
+    int dev;
+    uint64_t epoch;
+};
+struct DeviceCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<std::pair<void*, uint64_t>>> free_;  // (dev, cls) -> blocks
+    std::unordered_map<void*, CacheBlock> live_;
+    uint64_t epoch = 1;  // advanced by every device synchronisation made here
+    size_t cached = 0, cap = 0;
+    DeviceCache() {
+        const char* e = std::getenv("DD_DEVICE_CACHE_GB");
+        const double gb = e ? std::atof(e) : 96.0;
+        cap = gb > 0.0 ? (size_t)(gb * (double)(1ull << 30)) : 0;
+    }
+};
+DeviceCache& device_cache() {
+    static DeviceCache* c = new DeviceCache;  // never destroyed: the process teardown releases device memory
+    return *c;
+}
+size_t size_class(size_t b) {
+    if (b < (64u << 10)) return (b + 4095) / 4096 * 4096;
+    if (b < (1ull << 30)) return (b + (2u << 20) - 1) / (2u << 20) * (2u << 20);
+    const size_t step = (size_t(1) << (63 - __builtin_clzll(b))) / 16;
+    return (b + step - 1) / step * step;
+}
+// every cached block of device `dev` back to hipFree (caller holds the lock)
+void trim_locked(DeviceCache& c, int dev) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    for (auto it = c.free_.begin(); it != c.free_.end();) {
+        if (it->first.first != dev) { ++it; continue; }
+        for (auto& b : it->second) {
+            (void)hipFree(b.first);
+            c.cached -= it->first.second;
+        }
+        it = c.free_.erase(it);
+    }
+    if (cur != dev) (void)hipSetDevice(cur);
+}
+}  // namespace
+
+void* dd::dev_alloc(size_t bytes) {
+    DeviceCache& c = device_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    const size_t cls = size_class(bytes);
+    auto it = c.free_.lower_bound({dev, cls});
+    if (it != c.free_.end() && it->first.first == dev && it->first.second <= cls + cls / 4) {
+        auto& v = it->second;
+        const auto blk = v.back();
+        if (blk.second >= c.epoch) {  // released since the last synchronisation
+            DD_HIP(hipDeviceSynchronize());
+            ++c.epoch;
+        }
+        v.pop_back();
+        const size_t got = it->first.second;
+        if (v.empty()) c.free_.erase(it);
+        c.cached -= got;
+        c.live_[blk.first] = CacheBlock{got, dev, 0};
+        return blk.first;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e == hipErrorOutOfMemory && c.cached > 0) {
+        (void)hipGetLastError();
+        trim_locked(c, dev);
+        e = hipMalloc(&p, cls);
+    }
+    DD_HIP(e);
+    c.live_[p] = CacheBlock{cls, dev, 0};
+    return p;
+}
+
+void dd::dev_free(void* p, size_t) noexcept {
+    DeviceCache& c = device_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live_.find(p);
+    if (it == c.live_.end()) return;
+    const CacheBlock b = it->second;
+    c.live_.erase(it);
+    if (c.cached + b.cls > c.cap) {
+        (void)hipFree(p);
+        return;
+    }
+    try {
+        c.free_[{b.dev, b.cls}].push_back({p, c.epoch});
+        c.cached += b.cls;
+    } catch (...) {
+        (void)hipFree(p);
+    }
+}
+
 hipEvent_t Meter::get() {
     if (!pool.empty()) {
         hipEvent_t e = pool.back();
@@ -1596,6 +1708,19 @@ int dd_meter_read(dd_meter_t* out) {
     out->total_ms = ms;
     out->flops = m.flops;
     out->bytes = m.bytes;
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_trim_device_cache(void) {
+    DD_GUARD_BEGIN
+    DeviceCache& c = device_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    std::vector<int> devs;
+    for (auto& kv : c.free_) devs.push_back(kv.first.first);
+    std::sort(devs.begin(), devs.end());
+    devs.erase(std::unique(devs.begin(), devs.end()), devs.end());
+    for (int d : devs) trim_locked(c, d);
     return DD_OK;
     DD_GUARD_END
 }
