@@ -175,7 +175,8 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
 
 /* Right-preconditioned GMRES(restart) (Saad & Schultz) with M from dd_apply: the outer solver of
  * the paper's experiments (Sec. 4), flexible GMRES when the handle has more than two levels
- * (M varies between iterations).  Works with either variant of the handle.
+ * (M varies between iterations) or FP32 local solves (M linear only up to FP32 rounding).
+ * Works with either variant of the handle.
  * Arnoldi by classical Gram-Schmidt applied twice; a restart cycle ends when the Arnoldi
  * estimate of ||b_j - A x_j||_2 (the unpreconditioned residual) reaches rtol ||b_j||_2, after
  * `restart` steps or at maxit steps in total; the true residual is recomputed at the end of

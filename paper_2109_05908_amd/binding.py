@@ -240,35 +240,46 @@ class Preconditioner:
         return self.setup_status
 
     # ---- solve phase ----
+    # Vectors are 1-D (n) or 2-D (n, nrhs); the C-ABI takes column-major n x nrhs,
+    # i.e. the storage of the transposed (nrhs, n) tensor.
+    @staticmethod
+    def _cm(t):
+        return t.t().contiguous() if t.dim() == 2 else t.contiguous()
+
+    @staticmethod
+    def _uncm(t, two_d):
+        return t.t() if two_d else t
+
     def apply(self, r):
         import torch
-        r = r.contiguous()
-        z = torch.empty_like(r)
+        rc = self._cm(r)
+        z = torch.empty_like(rc)
         nrhs = 1 if r.dim() == 1 else r.shape[1]
-        _check(lib().dd_apply(self._h, _ptr(r), _ptr(z), nrhs, _stream()), "dd_apply")
-        return z
+        _check(lib().dd_apply(self._h, _ptr(rc), _ptr(z), nrhs, _stream()), "dd_apply")
+        return self._uncm(z, r.dim() == 2)
 
     def pcg(self, b, x0=None, rtol: float = 1e-8, maxit: int = 1000):
+        """dd_pcg; iters and relres hold nsys entries per right-hand side (system j of RHS k at k*nsys + j)."""
         import torch
-        b = b.contiguous()
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        bc = self._cm(b)
+        x = torch.zeros_like(bc) if x0 is None else self._cm(x0).clone()
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         its = (C.c_int32 * (nrhs * self.nsys))()
         rr = (C.c_double * (nrhs * self.nsys))()
-        code = _check(lib().dd_pcg(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, its, rr, _stream()), "dd_pcg")
-        return x, list(its), list(rr), code
+        code = _check(lib().dd_pcg(self._h, _ptr(bc), _ptr(x), nrhs, rtol, maxit, its, rr, _stream()), "dd_pcg")
+        return self._uncm(x, b.dim() == 2), list(its), list(rr), code
 
     def gmres(self, b, x0=None, rtol: float = 1e-8, maxit: int = 1000, restart: int = 30):
         """dd_gmres: right-preconditioned GMRES(restart), flexible with more than two levels."""
         import torch
-        b = b.contiguous()
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        bc = self._cm(b)
+        x = torch.zeros_like(bc) if x0 is None else self._cm(x0).clone()
         nrhs = 1 if b.dim() == 1 else b.shape[1]
         its = (C.c_int32 * nrhs)()
         rr = (C.c_double * nrhs)()
-        code = _check(lib().dd_gmres(self._h, _ptr(b), _ptr(x), nrhs, rtol, maxit, restart, its, rr, _stream()),
+        code = _check(lib().dd_gmres(self._h, _ptr(bc), _ptr(x), nrhs, rtol, maxit, restart, its, rr, _stream()),
                       "dd_gmres")
-        return x, list(its), list(rr), code
+        return self._uncm(x, b.dim() == 2), list(its), list(rr), code
 
     def spmv(self, x):
         import torch

@@ -2014,7 +2014,10 @@ int dd_gmres(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol,
     for (int k = 0; k < nrhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        const int c = gmres(H, 0, b + k * n, x + k * n, rtol, maxit, restart, H.lv.size() > 1, &it, &rr, s);
+        // flexible when M varies (inner iterative coarse solves) or is linear only up to
+        // FP32 rounding (FP32 local solves): the preconditioned directions are then kept
+        const bool flex = H.lv.size() > 1 || H.lv[0]->fp32;
+        const int c = gmres(H, 0, b + k * n, x + k * n, rtol, maxit, restart, flex, &it, &rr, s);
         if (c < 0) return c;
         if (c > 0) rc = c;
         if (iters) iters[k] = it;
