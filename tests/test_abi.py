@@ -18,7 +18,8 @@ def declared_functions():
 
 def test_header_declares_core_entry_points():
     names = declared_functions()
-    for f in ("dd_setup", "dd_apply", "dd_pcg", "dd_info", "dd_destroy", "dd_partition_ggg"):
+    for f in ("dd_setup", "dd_apply", "dd_pcg", "dd_info", "dd_destroy", "dd_partition_ggg", "dd_gmres",
+              "dd_setup_batch", "dd_update_values", "dd_trim_device_cache"):
         assert f in names
 
 
