@@ -174,9 +174,10 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
  * symmetric.) */
 
 /* Right-preconditioned GMRES(restart) (Saad & Schultz) with M from dd_apply: the outer solver of
- * the paper's experiments (Sec. 4), flexible GMRES when the handle has more than two levels
- * (M varies between iterations) or FP32 local solves (M linear only up to FP32 rounding).
- * Works with either variant of the handle.
+ * the paper's experiments (Sec. 4).  It runs in the flexible form (Saad), keeping z_j = M v_j and
+ * updating x with them: for a fixed M that is the same iterate with one apply fewer per cycle,
+ * and it also serves M that varies between iterations (more than two levels) or is linear only
+ * up to FP32 rounding (FP32 local solves).  Works with either variant of the handle.
  * Arnoldi by classical Gram-Schmidt applied twice; a restart cycle ends when the Arnoldi
  * estimate of ||b_j - A x_j||_2 (the unpreconditioned residual) reaches rtol ||b_j||_2, after
  * `restart` steps or at maxit steps in total; the true residual is recomputed at the end of

@@ -56,17 +56,16 @@ struct Opts {
 };
 
 // Workspace of right-preconditioned GMRES on one level: Krylov basis V
-// (n x (restart + 1)), preconditioned directions of the flexible form
-// (n x restart), two vectors, the partial sums of V^T w and the device and
-// pinned host copies of a Hessenberg column.
+// (n x (restart + 1)), the preconditioned directions M v_j (n x restart), a
+// vector, the partial sums of V^T w and the device and pinned host copies of a
+// Hessenberg column.
 constexpr int kMaxRestart = 64;
 constexpr int kGemvBlocks = 256;
 constexpr int kHcol = 2 * (kMaxRestart + 1) + 1;  // first pass, second pass, ||w||^2
 struct GmresWork {
     int cap = 0;
-    bool flex = false;
     int64_t n = 0;
-    DBuf<double> V, Zf, w, t, part, h;
+    DBuf<double> V, Zf, w, part, h;
     double* hp = nullptr;
     GmresWork() = default;
     GmresWork(const GmresWork&) = delete;
@@ -74,19 +73,16 @@ struct GmresWork {
     ~GmresWork() {
         if (hp) (void)hipHostFree(hp);
     }
-    void ensure(int64_t nn, int restart, bool flexible) {
-        if (nn == n && restart <= cap && (!flexible || flex)) return;
+    void ensure(int64_t nn, int restart) {
+        if (nn == n && restart <= cap) return;
         const int c = std::max(restart, cap);
-        const bool f = flexible || flex;
         V.alloc((size_t)nn * (c + 1));
-        Zf.alloc(f ? (size_t)nn * c : 0);
+        Zf.alloc((size_t)nn * c);
         w.alloc(nn);
-        t.alloc(nn);
         part.alloc((size_t)kGemvBlocks * (kMaxRestart + 1));
         h.alloc(kHcol + kMaxRestart);
         if (!hp) DD_HIP(hipHostMalloc(&hp, (kHcol + kMaxRestart) * sizeof(double)));
         cap = c;
-        flex = f;
         n = nn;
     }
 };
@@ -1078,8 +1074,8 @@ constexpr double kInnerRtol = 1e-4;  // coarse solves by PCG on levels >= 2 (Sec
 
 static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
                   bool true_res, int* iters, double* relres, hipStream_t s);
-static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, bool flexible,
-                 int* iters, double* relres, hipStream_t s);
+static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, int* iters,
+                 double* relres, hipStream_t s);
 
 // y := E_m^{-1} y: exact block Cholesky solve on the last level, otherwise PCG
 // (deflated variant: right-preconditioned GMRES(30)) on E_m, the next level's
@@ -1095,7 +1091,7 @@ static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
     double rr = 0.0;
     fill(Nx.kx.p, Nx.n, 0.0, s);
     const int rc = H.opt.schwarz == DD_SCHWARZ_DEFLATED
-                       ? gmres(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, 30, m + 2 < H.lv.size(), &its, &rr, s)
+                       ? gmres(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, 30, &its, &rr, s)
                        : krylov(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, &its, &rr, s);
     DD_CHECK(rc >= 0, rc, "inner coarse solve failed");
     DD_HIP(hipMemcpyAsync(y, Nx.kx.p, Nx.n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1309,16 +1305,19 @@ static void gemv_t(const double* V, int64_t n, int k, const double* w, double* p
 // M (additive or deflated), x holds x0 on entry.  A cycle ends when the
 // Arnoldi estimate |g_{j+1}| reaches rtol ||b||, after `restart` steps, on
 // breakdown or at maxit steps in total; the true residual then starts the next
-// cycle and is the one reported.  flexible: the preconditioned directions are
-// kept (x += [M v_1 ...] y), for a preconditioner with inner iterative solves.
-static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, bool flexible,
-                 int* iters, double* relres, hipStream_t s) {
+// cycle and is the one reported.  The preconditioned directions z_j = M v_j
+// are kept and x += [z_1 ... z_k] y (the flexible form): for a fixed M this is
+// the same iterate as x += M (V y) and saves that apply at the end of every
+// cycle; it also serves a preconditioner that varies (inner iterative coarse
+// solves) or is linear only up to FP32 rounding (FP32 local solves).
+static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, int* iters,
+                 double* relres, hipStream_t s) {
     Level& Lv = *H.lv[m];
     const int64_t n = Lv.n;
     const CsrDev A = Lv.A();
     GmresWork& G = Lv.gm;
-    G.ensure(n, restart, flexible);
-    double *V = G.V.p, *w = G.w.p, *t = G.t.p, *hd = G.h.p, *hp = G.hp;
+    G.ensure(n, restart);
+    double *V = G.V.p, *w = G.w.p, *hd = G.h.p, *hp = G.hp;
     double* yd = hd + kHcol;  // device copy of the cycle's y
     double* yh = hp + kHcol;  // pinned host copy
     const int g1 = vgrid(n);
@@ -1344,7 +1343,7 @@ static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, i
         int k = 0;
         for (int j = 0; j < restart; ++j) {
             const double* vj = V + (int64_t)j * n;
-            double* zj = flexible ? G.Zf.p + (int64_t)j * n : t;
+            double* zj = G.Zf.p + (int64_t)j * n;
             apply_level(H, m, vj, zj, s);
             spmv(A, zj, w, 1, s);
             // two passes of classical Gram-Schmidt against v_0 .. v_j
@@ -1386,13 +1385,7 @@ static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, i
             yh[i] = v / Hm[(size_t)i * ldh + i];
         }
         DD_HIP(hipMemcpyAsync(yd, yh, k * sizeof(double), hipMemcpyHostToDevice, s));
-        if (flexible) {
-            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, G.Zf.p, n, k, yd, 1.0, x, n, 1);
-        } else {
-            hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, V, n, k, yd, 1.0, t, n, 0);
-            apply_level(H, m, t, w, s);
-            hipLaunchKernelGGL(k_xpby, dim3(g1), dim3(256), 0, s, w, x, 1.0, n);  // x = M V y + x
-        }
+        hipLaunchKernelGGL(k_gemv_n, dim3(g1), dim3(256), 0, s, G.Zf.p, n, k, yd, 1.0, x, n, 1);
         spmv(A, x, w, 1, s);
         hipLaunchKernelGGL(k_sub, dim3(g1), dim3(256), 0, s, b, w, n);
         beta = std::sqrt(dot_host(H, w, w, n, s));  // synchronises: yh may be rewritten next cycle
@@ -2014,10 +2007,7 @@ int dd_gmres(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol,
     for (int k = 0; k < nrhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        // flexible when M varies (inner iterative coarse solves) or is linear only up to
-        // FP32 rounding (FP32 local solves): the preconditioned directions are then kept
-        const bool flex = H.lv.size() > 1 || H.lv[0]->fp32;
-        const int c = gmres(H, 0, b + k * n, x + k * n, rtol, maxit, restart, flex, &it, &rr, s);
+        const int c = gmres(H, 0, b + k * n, x + k * n, rtol, maxit, restart, &it, &rr, s);
         if (c < 0) return c;
         if (c > 0) rc = c;
         if (iters) iters[k] = it;
