@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 # sources still hash to what was profiled.
 ROOFLINE_KERNEL = "qr_blk_upd"
 ROOFLINE_SOURCES = ["common.hpp", "dense.hpp", "dense.hip"]
-TRAFFIC = {"sha256": "2bc2b9d0cd4c1fbf", "bytes_per_launch": 3.0952e9,
+TRAFFIC = {"sha256": "2b8863b42dd6ed06", "bytes_per_launch": 3.1845e9,
            "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6"}
 
 

@@ -1235,7 +1235,9 @@ struct OpBlkUpd : BlkOp {
         const int ld = it.C.ld;
         double4_t acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, PLD, mp, nc, R.wb, i0, j0, sm.t, acc);
+        // row tiles below the block's unit trapezoid read V_b as a plain operand
+        if (i0 >= R.wb) mfma_tile_64<false, false, 0, 0>(V, it.V.ld, it.W, PLD, mp, nc, R.wb, i0, j0, sm.t, acc);
+        else mfma_tile_64<false, false, 1, 0>(V, it.V.ld, it.W, PLD, mp, nc, R.wb, i0, j0, sm.t, acc);
         acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < mp && gj < nc) C[gi + (int64_t)gj * ld] -= v;
