@@ -1,0 +1,38 @@
+"""Host logic of bench.py (CPU only): the one-GPU refusal and the roofline
+arithmetic of the reported kernel."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_roofline_fields():
+    met = {"launches": 4, "total_ms": 2.0, "flops": 4 * 3.0e10, "bytes": 4 * 1.0e9}
+    r = bench.roofline(met, "not-the-profiled-workload")
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert abs(r["avg_launch_ms"] - 0.5) < 1e-12
+    assert abs(r["achieved"] - 60.0) < 1e-9           # 3e10 flops per 0.5 ms
+    assert abs(r["frac"] - 60.0 / 78.6) < 1e-12
+    assert abs(r["achieved_algorithmic_GBs"] - 2000.0) < 1e-9
+    assert r["traffic"] is None                      # counters were taken on another workload
+    assert bench.roofline({"launches": 0, "total_ms": 0.0, "flops": 0.0, "bytes": 0.0}, "x") is None
+
+
+def test_traffic_reported_only_for_the_profiled_sources():
+    met = {"launches": 1, "total_ms": 1.0, "flops": 1.0e10, "bytes": 1.0e9}
+    r = bench.roofline(met, bench.TRAFFIC["workload"])
+    if bench.TRAFFIC["sha256"] == bench.source_hash():
+        assert r["traffic"] == bench.TRAFFIC["bytes_per_launch"]
+    else:
+        assert r["traffic"] is None
