@@ -8,7 +8,9 @@
  * Setup (Sec. 2-3): from A alone, build overlapping subdomains, local SPSD
  * splittings (3.1)-(3.2), the thresholded local eigenproblems (3.3), the
  * coarse space Z and coarse operator E = Z^T A Z, recursively for more
- * levels.  Apply: the two-level additive Schwarz preconditioner (2.1).
+ * levels.  Apply: the two-level additive Schwarz preconditioner (2.1) inside
+ * PCG, or the deflated variant with the restricted one-level method used in
+ * the experiments (Sec. 4) inside right-preconditioned GMRES.
  *
  * Conventions for every entry point
  *  - Pointers documented "device" must point to GPU memory of the current
@@ -40,7 +42,7 @@ extern "C" {
 #define DD_ERR_OOM             -5  /* device allocation failed */
 #define DD_ERR_HIP             -6  /* other HIP runtime error */
 #define DD_ERR_INTERNAL        -7
-#define DD_WARN_MAXIT           1  /* PCG stopped at maxit before reaching rtol */
+#define DD_WARN_MAXIT           1  /* PCG or GMRES stopped at maxit before reaching rtol */
 #define DD_WARN_FULL_COARSE     2  /* tau >= 1 with Boolean D: every mode is kept (lambda >= 1 always) */
 #define DD_WARN_FP32_FALLBACK   3  /* an FP32 local factor broke down and was recomputed in FP64 */
 
