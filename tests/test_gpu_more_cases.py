@@ -120,3 +120,24 @@ def test_fp32_local_solves_deflated_gmres():
     log(f"[more] FP32 local solves, deflated: GMRES its {its[0]} (oracle FP64 {itso}), relres {rr[0]:.2e}")
     assert code == 0 and rr[0] <= 1e-13
     assert np.linalg.norm(x.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_gmres_edge_cases():
+    # a system smaller than the restart length: Arnoldi ends on a happy breakdown
+    A = W.poisson2d(4)
+    part = W.grid2d_partition(4, 2, 1)
+    pre = Preconditioner(DeviceCSR.from_workload(A), part, 2, 1, 1e-30, schwarz=DD_SCHWARZ_DEFLATED)
+    b = W.rhs(A.n, 1)
+    x, its, rr, code = pre.gmres(torch.as_tensor(b, device="cuda"), rtol=1e-13, restart=30)
+    xd = np.linalg.solve(A.to_scipy().toarray(), b)
+    log(f"[more] n={A.n} with restart 30: its {its[0]}, relres {rr[0]:.2e}")
+    assert code == 0 and its[0] <= A.n and rr[0] <= 1e-13
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-10 * np.linalg.norm(xd)
+    # maxit reached: the warning code, the iterations done and the true residual of the iterate
+    cfg = W.config_c1()
+    pre = Preconditioner(DeviceCSR.from_workload(cfg.A), cfg.part, cfg.N, cfg.overlap, cfg.tau)
+    b = W.rhs(cfg.A.n, 2)
+    x, its, rr, code = pre.gmres(torch.as_tensor(b, device="cuda"), rtol=1e-13, maxit=3, restart=2)
+    true = np.linalg.norm(b - cfg.A.to_scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert code == 1 and its[0] == 3
+    assert abs(true - rr[0]) <= 1e-10 * true and 1e-13 < true < 1.0
