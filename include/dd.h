@@ -73,7 +73,10 @@ typedef struct {
                              and of the local solves in the apply; splitting, eigen, E and PCG stay FP64 */
     int32_t select;       /* DD_SEL_THRESHOLD (default) or DD_SEL_THRESHOLD_CAP */
     int32_t nev_cap;      /* cap per subdomain for DD_SEL_THRESHOLD_CAP */
-    int32_t validate;     /* nonzero: check pattern symmetry and finite values of A (O(nnz)) */
+    int32_t validate;     /* nonzero: check the CSR structure of A first (O(nnz)): rowptr[0] = 0,
+                             rowptr[n] = nnz, column indices in range, strictly increasing within each
+                             row, pattern symmetric; DD_ERR_INVALID_ARG if not.  Without it a malformed
+                             CSR is undefined behaviour.  Values are always checked for NaN/Inf. */
     int32_t coarsen;      /* levels >= 3: subdomains per coarse part (default 64) */
     int32_t schwarz;      /* DD_SCHWARZ_ADDITIVE (default) or DD_SCHWARZ_DEFLATED */
     int32_t reserved[6];

@@ -1754,6 +1754,49 @@ __global__ void k_check_finite(const double* v, int64_t n, int32_t* bad) {
         if (!isfinite(v[i])) atomicOr(bad, 1);
 }
 
+// The CSR structure dd_setup assumes (full symmetric storage): rowptr[0] = 0,
+// rowptr[n] = nnz, rows non-decreasing, column indices in [0, n) and strictly
+// increasing within each row, and (j, i) stored whenever (i, j) is (binary
+// search of row j).  Every read is checked first, so a malformed input only
+// sets the flag.
+__global__ void k_check_pattern(const int32_t* rowptr, const int32_t* colind, int64_t n, int64_t nnz, int32_t* bad) {
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t0 == 0 && (rowptr[0] != 0 || rowptr[n] != nnz)) atomicOr(bad, 1);
+    for (int64_t i = t0; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rowptr[i], e = rowptr[i + 1];
+        if (b < 0 || e < b || e > nnz) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        int64_t prev = -1;
+        for (int64_t k = b; k < e; ++k) {
+            const int64_t j = colind[k];
+            if (j < 0 || j >= n || j <= prev) {
+                atomicOr(bad, 1);
+                break;
+            }
+            prev = j;
+            int64_t lo = rowptr[j], hi = (int64_t)rowptr[j + 1] - 1;
+            if (lo < 0 || hi >= nnz) {
+                atomicOr(bad, 1);
+                break;
+            }
+            bool found = false;
+            while (lo <= hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int64_t c = colind[mid];
+                if (c == i) { found = true; break; }
+                if (c < i) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (!found) {
+                atomicOr(bad, 1);
+                break;
+            }
+        }
+    }
+}
+
 }  // extern "C"
 
 namespace dd {
@@ -1782,6 +1825,15 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
         DD_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DD_HIP(hipStreamSynchronize(s));
         if (hb) return DD_ERR_NAN;
+        if (H.opt.validate) {
+            DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_check_pattern, dim3(vgrid(n)), dim3(256), 0, s, L0.rowptr.p, L0.colind.p, n, nnz,
+                               bad.p);
+            launch_check("check_pattern");
+            DD_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DD_HIP(hipStreamSynchronize(s));
+            if (hb) return DD_ERR_INVALID_ARG;
+        }
     }
     L0.N = N;
     L0.delta = overlap;

@@ -167,3 +167,35 @@ def test_invalid_arguments_rejected():
     with pytest.raises(DDError) as e:
         Preconditioner(dn, cfg.part, cfg.N, 1, 0.1)
     assert e.value.code == -4
+
+
+def test_validate_option_rejects_malformed_csr():
+    """validate=True checks the CSR structure before anything else; each case
+    below is caught by that check (no other kernel sees the malformed input)."""
+    A = sp.csr_matrix(W.poisson2d(8).to_scipy())
+    A.sort_indices()
+    n = A.shape[0]
+    part = W.grid2d_partition(8, 2, 2)
+    ok = Preconditioner(DeviceCSR(n, A.indptr, A.indices, A.data), part, 4, 1, 0.1, validate=True)
+    assert ok.info()["n_C"] > 0
+    cases = []
+    # unsymmetric pattern: drop the entry (1, 0) but keep (0, 1)
+    B = A.tolil()
+    B[1, 0] = 0.0
+    B = sp.csr_matrix(B)
+    B.eliminate_zeros()
+    B.sort_indices()
+    cases.append(("unsymmetric", B.indptr, B.indices, B.data))
+    # unsorted row 5
+    ind = A.indices.copy()
+    r0, r1 = A.indptr[5], A.indptr[6]
+    ind[r0:r1] = ind[r0:r1][::-1]
+    cases.append(("unsorted", A.indptr, ind, A.data))
+    # column index out of range
+    ind = A.indices.copy()
+    ind[A.indptr[3]] = n
+    cases.append(("out of range", A.indptr, ind, A.data))
+    for name, ip, ix, va in cases:
+        with pytest.raises(DDError) as e:
+            Preconditioner(DeviceCSR(n, ip, ix, va), part, 4, 1, 0.1, validate=True)
+        assert e.value.code == -1, name
