@@ -92,14 +92,14 @@ typedef struct {
     int32_t N[DD_MAX_LEVELS];       /* subdomains per decomposed level */
     int64_t n[DD_MAX_LEVELS];       /* matrix size per level (n[1] = n_C of level 0) */
     int64_t n_C;                    /* coarse size of the finest level */
-    double  grid_complexity;        /* (n + n_C) / n  (Sec. 4) */
+    double  grid_complexity;        /* (sum of the level sizes) / n, (n + n_C) / n with two levels (Sec. 4) */
     int32_t p_min, p_max;           /* kept modes per fine subdomain */
     int32_t fp32_fallbacks;         /* local factors recomputed in FP64 */
     int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap */
     double  phase_ms[DD_NPHASE];    /* setup phase times, see dd_phase_name */
-    int32_t last_iters;             /* last dd_pcg: iterations (first RHS) */
-    double  last_relres;            /* last dd_pcg: true relative residual (first RHS) */
-    int64_t device_bytes;           /* device memory held by the handle */
+    int32_t last_iters;             /* last dd_pcg or dd_gmres: iterations (first RHS; a batch: the largest) */
+    double  last_relres;            /* last dd_pcg or dd_gmres: true relative residual (first RHS; a batch: the largest) */
+    int64_t device_bytes;           /* device memory of the handle's factors, bases and index maps */
 } dd_info_t;
 
 /* ---- entry points ------------------------------------------------------ */
