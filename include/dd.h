@@ -151,8 +151,10 @@ int dd_update_values(dd_handle h, const double* val, hipStream_t stream);
  * Vectors passed to dd_apply and dd_pcg are the systems' vectors concatenated (sum n_j per RHS).
  * dd_pcg on such a handle runs one PCG per system in lockstep (per-system dot products, alpha
  * and beta; each system stops on its own residual) and writes nsys entries of iters and relres
- * per RHS (system j of RHS k at k*nsys + j).  With more than two levels the systems share the
- * inner coarse solves of the union.  The caller keeps ownership of all inputs (copied).
+ * per RHS (system j of RHS k at k*nsys + j).  With more than two levels every level is
+ * partitioned system by system and the inner coarse solves run one PCG per system, so each
+ * system gets the hierarchy and the solve of its own dd_setup (with the deflated variant the
+ * inner GMRES solves run on the union).  The caller keeps ownership of all inputs (copied).
  * Errors and warnings as for dd_setup; DD_ERR_INVALID_ARG also for n or nnz of the union
  * beyond int32. */
 int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t* Ns, int32_t nsys,

@@ -131,6 +131,15 @@ struct Level {
     std::vector<double> Ecopy;  // small coarse operators only (inspection)
     std::vector<uint8_t> hadj;  // block graph of E: hadj[i*N+j] = 1 iff A(Omega_Ii, Omega_Ij) != 0, i != j
 
+    // batch of independent systems (dd_setup_batch): the subdomains
+    // [hsub[j], hsub[j+1]) of system j; on levels >= 1 also its dofs
+    // [hseg[j], hseg[j+1]) and the system of every dof (level 0 keeps these in
+    // the handle)
+    std::vector<int32_t> hsub;
+    std::vector<int64_t> hseg;
+    DBuf<int64_t> dseg;
+    DBuf<int32_t> seg_id;
+
     // Krylov workspace for systems with this level's matrix
     DBuf<double> kr, kz, kp, kq, kro, kx;
     GmresWork gm;
@@ -160,6 +169,7 @@ struct Handle {
     std::vector<int64_t> sys_off;
     DBuf<int64_t> dsys_off;
     DBuf<int32_t> sys_id;
+    std::vector<int32_t> sub_off;  // subdomains of each system on level 0
     DBuf<double> dscal;
     double* hscal = nullptr;
     int nsys() const { return sys_off.size() > 1 ? (int)sys_off.size() - 1 : 1; }
@@ -1007,7 +1017,13 @@ static void build_e_csr(Level& Lv, Level& next, hipStream_t s) {
 // Partition of the next level (R8): the nodes of E's block graph are this
 // level's subdomains; seeded greedy graph growing into ceil(N / coarsen) parts
 // (seed 0), expanded to the coarse dofs, empty parts removed.
+static void partition_next_batch(const Level& Lv, Level& next, int coarsen, hipStream_t s);
+
 static void partition_next(const Level& Lv, Level& next, int coarsen, hipStream_t s) {
+    if (!Lv.hsub.empty()) {
+        partition_next_batch(Lv, next, coarsen, s);
+        return;
+    }
     const int N = Lv.N;
     std::vector<int32_t> rp(N + 1, 0), ci;
     for (int i = 0; i < N; ++i) {
@@ -1035,6 +1051,56 @@ static void partition_next(const Level& Lv, Level& next, int coarsen, hipStream_
         for (int a = 0; a < Lv.p[i]; ++a) part2[Lv.hoffC[i] + a] = remap[pb[i]];
     next.part = upload(part2, s);
     next.N = cnt;
+    next.delta = Lv.delta;
+    next.tau = Lv.tau;
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+// The same partition of a batch level, system by system: the subdomain graph
+// of each system gets its own ceil(N_j / coarsen) parts by the same rule and
+// seed, so every system's next level is the one its own setup would build;
+// the parts, coarse dofs and their system ranges stay contiguous per system.
+static void partition_next_batch(const Level& Lv, Level& next, int coarsen, hipStream_t s) {
+    const int N = Lv.N, ns = (int)Lv.hsub.size() - 1;
+    std::vector<int32_t> part2(Lv.nC);
+    next.hsub.assign(1, 0);
+    next.hseg.assign(1, 0);
+    int total = 0;
+    for (int j = 0; j < ns; ++j) {
+        const int s0 = Lv.hsub[j], s1 = Lv.hsub[j + 1], Nj = s1 - s0;
+        std::vector<int32_t> rp(Nj + 1, 0), ci;
+        for (int i = 0; i < Nj; ++i) {
+            for (int k = 0; k < Nj; ++k)
+                if (k != i && Lv.hadj[(size_t)(s0 + i) * N + (s0 + k)]) ci.push_back(k);
+            rp[i + 1] = (int32_t)ci.size();
+        }
+        if (ci.empty()) ci.push_back(0);
+        const int N2 = std::max(1, std::min(Nj, ceil_div(Nj, std::max(1, coarsen))));
+        DBuf<int32_t> drp = upload(rp, s), dci = upload(ci, s);
+        DBuf<double> dval(std::max<size_t>(1, ci.size()));
+        CsrDev G{Nj, (int64_t)rp[Nj], drp.p, dci.p, dval.p};
+        DBuf<int32_t> dpart(std::max(1, Nj));
+        ggg_partition(G, N2, 0, dpart.p, s);
+        std::vector<int32_t> pb = to_host(dpart.p, Nj, s);
+        std::vector<int32_t> used(N2, 0), remap(N2, -1);
+        for (int i = 0; i < Nj; ++i)
+            if (Lv.p[s0 + i] > 0) used[pb[i]] = 1;
+        int cnt = 0;
+        for (int k = 0; k < N2; ++k)
+            if (used[k]) remap[k] = cnt++;
+        for (int i = 0; i < Nj; ++i)
+            for (int a = 0; a < Lv.p[s0 + i]; ++a) part2[Lv.hoffC[s0 + i] + a] = total + remap[pb[i]];
+        total += cnt;
+        next.hsub.push_back(total);
+        next.hseg.push_back(Lv.hoffC[s1]);
+    }
+    std::vector<int32_t> sid(std::max<int64_t>(1, Lv.nC), 0);
+    for (int j = 0; j < ns; ++j)
+        for (int64_t d = next.hseg[j]; d < next.hseg[j + 1]; ++d) sid[d] = j;
+    next.part = upload(part2, s);
+    next.dseg = upload(next.hseg, s);
+    next.seg_id = upload(sid, s);
+    next.N = total;
     next.delta = Lv.delta;
     next.tau = Lv.tau;
     DD_HIP(hipStreamSynchronize(s));
@@ -1076,6 +1142,8 @@ static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, 
                   bool true_res, int* iters, double* relres, hipStream_t s);
 static int gmres(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, int restart, int* iters,
                  double* relres, hipStream_t s);
+static int krylov_seg(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
+                      bool true_res, int* iters, double* relres, hipStream_t s);
 
 // y := E_m^{-1} y: exact block Cholesky solve on the last level, otherwise PCG
 // (deflated variant: right-preconditioned GMRES(30)) on E_m, the next level's
@@ -1090,8 +1158,12 @@ static void coarse_solve(Handle& H, size_t m, double* y, hipStream_t s) {
     int its = 0;
     double rr = 0.0;
     fill(Nx.kx.p, Nx.n, 0.0, s);
+    // a batch solves each system's coarse system on its own (the systems' inner
+    // levels are kept apart by the per-system partition of every level)
     const int rc = H.opt.schwarz == DD_SCHWARZ_DEFLATED
                        ? gmres(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, 30, &its, &rr, s)
+                   : H.nsys() > 1
+                       ? krylov_seg(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, nullptr, nullptr, s)
                        : krylov(H, m + 1, y, Nx.kx.p, kInnerRtol, 1000, false, false, &its, &rr, s);
     DD_CHECK(rc >= 0, rc, "inner coarse solve failed");
     DD_HIP(hipMemcpyAsync(y, Nx.kx.p, Nx.n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1416,9 +1488,21 @@ __global__ void k_xpby_seg(const double* z, double* p, const double* beta, const
         p[i] = z[i] + beta[sid[i]] * p[i];
 }
 
-static std::vector<double> dot_sys(Handle& H, const double* x, const double* y, hipStream_t s) {
+// the systems' dof ranges on level m of a batch (level 0: the handle's)
+struct SegView {
+    const std::vector<int64_t>* off;
+    const int64_t* doff;
+    const int32_t* sid;
+};
+static SegView seg_of(Handle& H, size_t m) {
+    if (m == 0) return SegView{&H.sys_off, H.dsys_off.p, H.sys_id.p};
+    Level& Lv = *H.lv[m];
+    return SegView{&Lv.hseg, Lv.dseg.p, Lv.seg_id.p};
+}
+
+static std::vector<double> dot_sys(Handle& H, const SegView& g, const double* x, const double* y, hipStream_t s) {
     const int ns = H.nsys();
-    dot_seg(x, y, H.dsys_off.p, ns, H.partial.p, H.dots.p, s);
+    dot_seg(x, y, g.doff, ns, H.partial.p, H.dots.p, s);
     DD_HIP(hipMemcpyAsync(H.hpin, H.dots.p, ns * sizeof(double), hipMemcpyDeviceToHost, s));
     DD_HIP(hipStreamSynchronize(s));
     return std::vector<double>(H.hpin, H.hpin + ns);
@@ -1434,22 +1518,27 @@ static const double* put_sys(Handle& H, const std::vector<double>& v, int slot, 
     return d;
 }
 
-static int krylov_seg(Handle& H, const double* b, double* x, double rtol, int maxit, bool flexible, int* iters,
-                      double* relres, hipStream_t s) {
-    Level& Lv = *H.lv[0];
+// One PCG per system on level m of a batch (the outer solve on level 0, the
+// inner coarse solves below it); iters and relres (nsys entries) may be null.
+// true_res: the true residual of every system is computed at exit.
+static int krylov_seg(Handle& H, size_t m, const double* b, double* x, double rtol, int maxit, bool flexible,
+                      bool true_res, int* iters, double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[m];
     const int64_t n = Lv.n;
     const int ns = H.nsys();
     const CsrDev A = Lv.A();
+    const SegView g = seg_of(H, m);
+    const std::vector<int64_t>& off = *g.off;
     double *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p, *q = Lv.kq.p, *ro = Lv.kro.p;
-    std::vector<double> bn = dot_sys(H, b, b, s);
+    std::vector<double> bn = dot_sys(H, g, b, b, s);
     for (int k = 0; k < ns; ++k) {
         DD_CHECK(std::isfinite(bn[k]), DD_ERR_NAN, "right-hand side contains NaN/Inf");
         bn[k] = std::sqrt(bn[k]);
-        if (bn[k] == 0.0) DD_HIP(hipMemsetAsync(x + H.sys_off[k], 0, (H.sys_off[k + 1] - H.sys_off[k]) * sizeof(double), s));
+        if (bn[k] == 0.0 && off[k + 1] > off[k]) fill(x + off[k], off[k + 1] - off[k], 0.0, s);
     }
     spmv(A, x, r, 1, s);
     hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
-    std::vector<double> rn = dot_sys(H, r, r, s);
+    std::vector<double> rn = dot_sys(H, g, r, r, s);
     std::vector<int> its(ns, 0);
     std::vector<char> conv(ns, 0);
     int left = 0;
@@ -1459,21 +1548,21 @@ static int krylov_seg(Handle& H, const double* b, double* x, double rtol, int ma
         left += conv[k] ? 0 : 1;
     }
     if (left) {
-        apply_level(H, 0, r, z, s);
+        apply_level(H, m, r, z, s);
         DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        std::vector<double> rz = dot_sys(H, r, z, s);
+        std::vector<double> rz = dot_sys(H, g, r, z, s);
         std::vector<double> alpha(ns), beta(ns);
         for (int it = 1; it <= maxit && left; ++it) {
             spmv(A, p, q, 1, s);
-            const std::vector<double> pq = dot_sys(H, p, q, s);
+            const std::vector<double> pq = dot_sys(H, g, p, q, s);
             for (int k = 0; k < ns; ++k) {
                 alpha[k] = conv[k] ? 0.0 : rz[k] / pq[k];
                 DD_CHECK(std::isfinite(alpha[k]), DD_ERR_NAN, "PCG produced NaN");
             }
             if (flexible) DD_HIP(hipMemcpyAsync(ro, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             hipLaunchKernelGGL(k_axpy2_seg, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, put_sys(H, alpha, 0, s),
-                               H.sys_id.p, n);
-            rn = dot_sys(H, r, r, s);
+                               g.sid, n);
+            rn = dot_sys(H, g, r, r, s);
             for (int k = 0; k < ns; ++k) {
                 if (conv[k]) continue;
                 its[k] = it;
@@ -1483,24 +1572,26 @@ static int krylov_seg(Handle& H, const double* b, double* x, double rtol, int ma
                 }
             }
             if (!left) break;
-            apply_level(H, 0, r, z, s);
+            apply_level(H, m, r, z, s);
             if (flexible) {
                 hipLaunchKernelGGL(k_diff, dim3(vgrid(n)), dim3(256), 0, s, r, ro, q, n);  // q := r - r_old
-                const std::vector<double> zq = dot_sys(H, z, q, s);
+                const std::vector<double> zq = dot_sys(H, g, z, q, s);
                 for (int k = 0; k < ns; ++k) beta[k] = conv[k] ? 0.0 : zq[k] / rz[k];
-                rz = dot_sys(H, r, z, s);
+                rz = dot_sys(H, g, r, z, s);
             } else {
-                const std::vector<double> rzn = dot_sys(H, r, z, s);
+                const std::vector<double> rzn = dot_sys(H, g, r, z, s);
                 for (int k = 0; k < ns; ++k) beta[k] = conv[k] ? 0.0 : rzn[k] / rz[k];
                 rz = rzn;
             }
-            hipLaunchKernelGGL(k_xpby_seg, dim3(vgrid(n)), dim3(256), 0, s, z, p, put_sys(H, beta, 1, s), H.sys_id.p,
+            hipLaunchKernelGGL(k_xpby_seg, dim3(vgrid(n)), dim3(256), 0, s, z, p, put_sys(H, beta, 1, s), g.sid,
                                n);
         }
     }
-    spmv(A, x, r, 1, s);
-    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
-    const std::vector<double> tr = dot_sys(H, r, r, s);
+    if (true_res) {  // else the recurrence residual r
+        spmv(A, x, r, 1, s);
+        hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    }
+    const std::vector<double> tr = dot_sys(H, g, r, r, s);
     bool all = true;
     for (int k = 0; k < ns; ++k) {
         const double rel = bn[k] > 0.0 ? std::sqrt(tr[k]) / bn[k] : 0.0;
@@ -1840,6 +1931,7 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
     L0.tau = tau;
     L0.part.alloc(n);
     DD_HIP(hipMemcpyAsync(L0.part.p, part, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    L0.hsub = H.sub_off;  // empty unless a batch
     {
         DBuf<int32_t> cnt(N);
         const int rc = validate_partition(L0.part.p, n, N, cnt.p, s);
@@ -1983,6 +2075,7 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
     }
     H.sys_off = noff;
     H.dsys_off = upload(noff, s);
+    H.sub_off.assign(poff.begin(), poff.end());
     H.dscal.alloc(2 * nsys);
     DD_HIP(hipHostMalloc(&H.hscal, 2 * nsys * sizeof(double)));
     const int rc = build_handle(H, n, nnz, rowptr.p, colind.p, val.p, part.p, (int32_t)poff[nsys], overlap, tau,
@@ -2016,7 +2109,8 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
         std::vector<int> it(ns);
         std::vector<double> rr(ns);
         for (int k = 0; k < nrhs; ++k) {
-            const int c = krylov_seg(H, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, it.data(), rr.data(), s);
+            const int c = krylov_seg(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, it.data(),
+                                     rr.data(), s);
             if (c < 0) return c;
             if (c > 0) rc = c;
             for (int j = 0; j < ns; ++j) {
