@@ -87,6 +87,9 @@ typedef struct dd_handle_s* dd_handle;
 /* ---- diagnostics ------------------------------------------------------- */
 #define DD_MAX_LEVELS 4
 #define DD_NPHASE 12
+#define DD_PHIST 16
+/* Setup and solve statistics of a handle (Sec. 3.2: the constants of the condition-number bound;
+ * Sec. 4: coarse sizes and grid complexity as the experiments report them). */
 typedef struct {
     int32_t levels;                 /* levels built (2 = fine + coarse) */
     int32_t N[DD_MAX_LEVELS];       /* subdomains per decomposed level */
@@ -94,6 +97,12 @@ typedef struct {
     int64_t n_C;                    /* coarse size of the finest level */
     double  grid_complexity;        /* (sum of the level sizes) / n, (n + n_C) / n with two levels (Sec. 4) */
     int32_t p_min, p_max;           /* kept modes per fine subdomain */
+    int32_t p_hist[DD_PHIST];       /* fine subdomains by kept modes p_i: bin 0 holds p_i = 0, bin b >= 1
+                                       holds 2^(b-1) <= p_i < 2^b, the last bin everything above */
+    int32_t k_c;                    /* colours of a greedy colouring (subdomains in index order, smallest free
+                                       colour) of the fine subdomain graph, i ~ j iff A(Omega_i, Omega_j) != 0
+                                       (overlapping sets): the k_c of the bound (k_c + 1)(2 + (2 k_c + 1) k_m / tau)
+                                       of Sec. 3.2; computed on the host at the first dd_info call */
     int32_t fp32_fallbacks;         /* local factors recomputed in FP64 */
     int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap */
     double  phase_ms[DD_NPHASE];    /* setup phase times, see dd_phase_name */
@@ -141,7 +150,9 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
  * (DD_ERR_NAN for non-finite values). */
 int dd_update_values(dd_handle h, const double* val, hipStream_t stream);
 
-/* Several independent systems in one handle: As[j] (device CSR, n_j unknowns) with partition
+/* Several independent systems in one handle (Sec. 2: the subdomains of a decomposition are set up
+ * independently of each other, one per process in the paper; here the subdomains of several
+ * systems share the batched launches of one GPU): As[j] (device CSR, n_j unknowns) with partition
  * parts[j] (device, n_j entries in [0, Ns[j])), all with the same overlap, tau, levels and
  * options.  The handle holds the block-diagonal union of the systems (unknowns and parts
  * numbered system after system), so every setup phase runs all subdomains of all systems in
@@ -153,10 +164,13 @@ int dd_update_values(dd_handle h, const double* val, hipStream_t stream);
  * and beta; each system stops on its own residual) and writes nsys entries of iters and relres
  * per RHS (system j of RHS k at k*nsys + j).  With more than two levels every level is
  * partitioned system by system and the inner coarse solves run one PCG per system, so each
- * system gets the hierarchy and the solve of its own dd_setup (with the deflated variant the
- * inner GMRES solves run on the union).  The caller keeps ownership of all inputs (copied).
+ * system gets the hierarchy and the solve of its own dd_setup.  With opt->validate each system's
+ * CSR structure is checked on its own, before the union is formed.  The deflated variant
+ * (schwarz = DD_SCHWARZ_DEFLATED) is refused: it needs GMRES, which has no per-system form.
+ * dd_update_values on a batch handle takes the nnz values of the union (system after system).
+ * The caller keeps ownership of all inputs (copied).
  * Errors and warnings as for dd_setup; DD_ERR_INVALID_ARG also for n or nnz of the union
- * beyond int32. */
+ * beyond int32 and for the deflated variant. */
 int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t* Ns, int32_t nsys,
                    int32_t overlap, double tau, int32_t levels, const dd_options* opt,
                    hipStream_t stream, dd_handle* out);
@@ -169,7 +183,9 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
  * deflated M.  r, z: device, column-major n x nrhs, must not alias.  Errors: DD_ERR_INVALID_ARG. */
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t stream);
 
-/* Preconditioned CG with M from dd_apply (FP64 dots and residual recurrence); with more than
+/* Solve A x = b (Sec. 1) by preconditioned CG, the solver the condition-number bound of Sec. 3.2
+ * speaks to, stopped at a relative residual as in Sec. 4 (1e-8 there).
+ * M from dd_apply (FP64 dots and residual recurrence); with more than
  * two levels, flexible CG (Polak-Ribiere beta) since M varies between iterations.
  * b: device n x nrhs; x: device n x nrhs, in: initial guess, out: solution.
  * Stops RHS j when ||b_j - A x_j||_2 <= rtol ||b_j||_2 (recurrence residual,
@@ -197,12 +213,21 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
 int dd_gmres(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, int32_t maxit,
              int32_t restart, int32_t* iters, double* relres, hipStream_t stream);
 
-/* y = A x for the fine-level matrix held by the handle (SpMV kernel), device pointers. */
+/* y = A x (the operator of Sec. 1) for the fine-level matrix held by the handle (SpMV kernel).
+ * x, y: device double[n] (n of the handle; a batch: the union), must not alias.
+ * Errors: DD_ERR_INVALID_ARG for a null handle or pointer. */
 int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t stream);
 
+/* Copies the handle's statistics (dd_info_t above: level sizes and grid complexity as reported in
+ * Sec. 4, kept modes, the colouring constant k_c of the bound of Sec. 3.2, phase times, the last
+ * solve) into *out (host).  Synchronous; the first call computes k_c on the host from the
+ * handle's index sets.  Errors: DD_ERR_INVALID_ARG for a null handle or out. */
 int  dd_info(dd_handle h, dd_info_t* out);
+/* Name of setup phase `phase` (0 <= phase < DD_NPHASE) of dd_info_t.phase_ms; "?" otherwise. */
 const char* dd_phase_name(int32_t phase);
-/* Frees the handle.  Its device memory goes back to the library's device cache, which hands
+/* Frees the handle (the caller owns it from dd_setup / dd_setup_batch on; NULL is ignored).
+ * Work queued on the handle must be complete or ordered before later use of the memory, which the
+ * cache below guarantees by synchronising before reuse.  Its device memory goes back to the library's device cache, which hands
  * it to later setups of the same process instead of hipMalloc/hipFree (large hipMalloc calls
  * were seen to stall for seconds after a few setup cycles); a cached block is reused only
  * after a device synchronisation that follows its release.  The cache holds at most
@@ -225,6 +250,15 @@ int dd_subdomain_sets(dd_handle h, int32_t level, int32_t i, int32_t* I, int32_t
 int dd_subdomain_eigs(dd_handle h, int32_t level, int32_t i, double* mu);
 /* Orthonormal basis of D_i Z_i restricted to Omega_Ii: Z[n_Ii x p_i], column-major. */
 int dd_subdomain_basis(dd_handle h, int32_t level, int32_t i, double* Z);
+/* Steps a1-a2 alone, for inspection: the ordered sets of Sec. 2 and the dense blocks of
+ * Sec. 3.1 of subdomain i of the decomposition (A, part, N, overlap) as dd_setup forms them, without
+ * building a preconditioner.  A, part: device, as for dd_setup.  Outputs (host, each may be NULL):
+ * sizes int32[3] = {n_Ii, n_Gamma_i, n_Delta_i}; Aii double[n_i x n_i] = A(Omega_i, Omega_i);
+ * X double[n_i x n~_i] = X_i = A(Omega_i, Omega~_i) (3.1), both column-major, rows and columns in
+ * the order [Omega_Ii, Gamma_i] and [Omega_Ii, Gamma_i, Delta_i].  Synchronous.
+ * Errors: DD_ERR_INVALID_ARG (as dd_setup, or i outside [0, N)), DD_ERR_OOM. */
+int dd_extract_local(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, int32_t i, int32_t* sizes,
+                     double* Aii, double* X, hipStream_t stream);
 /* Largest singular value sigma_1 of X_i for every subdomain: sigma1[N]. */
 int dd_subdomain_sigma1(dd_handle h, int32_t level, double* sigma1);
 /* Coarse operator E of `level` (n_C x n_C dense, column-major), only if n_C <= max_n. */

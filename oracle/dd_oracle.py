@@ -63,7 +63,7 @@ __all__ = [
     "EPS", "splitmix64", "ggg_partition", "Sets", "subdomain_sets", "extract",
     "Splitting", "local_splitting", "schur_via_qr", "local_eigen", "LocalResult",
     "TwoLevel", "build", "pcg", "flexible_pcg", "gmres", "coloring_kc", "diagnostics",
-    "coarse_partition", "as_scipy",
+    "coarse_partition", "as_scipy", "build_locals",
 ]
 
 
@@ -469,15 +469,20 @@ def build(A, part, N, delta, tau, levels=2, nev=None, inner_rtol=1e-4, shift=Non
 
     pre.coarse_solver = coarse_solve
     pre.inner = inner
+    pre.block_graph = G            # for inspection: the graph the next level is partitioned on
+    pre.block_part = part_blocks   # its partition into ceil(N / coarsen) parts
+    pre.coarse_part = part2        # expanded to the coarse dofs, empty parts removed
     return pre
 
 
 # ---------------------------------------------------------------------------
 # Krylov solvers (R6, R8)
 # ---------------------------------------------------------------------------
-def pcg(A, b, Minv, rtol=1e-8, maxit=1000, x0=None):
+def pcg(A, b, Minv, rtol=1e-8, maxit=1000, x0=None, callback=None):
     """Preconditioned CG; stop when ||r_k||_2 <= rtol ||b||_2 (recurrence
-    residual); return (x, iterations, true relative residual)."""
+    residual); return (x, iterations, true relative residual).  callback(k,
+    x, r, p), if given, sees iteration k's iterate, residual and direction
+    after the update (observation only)."""
     A = as_scipy(A)
     x = np.zeros_like(b) if x0 is None else x0.copy()
     bn = np.linalg.norm(b)
@@ -494,6 +499,8 @@ def pcg(A, b, Minv, rtol=1e-8, maxit=1000, x0=None):
             alpha = rz / (p @ q)
             x += alpha * p
             r -= alpha * q
+            if callback is not None:
+                callback(its, x, r, p)
             if np.linalg.norm(r) <= rtol * bn:
                 break
             z = Minv(r)
@@ -503,8 +510,9 @@ def pcg(A, b, Minv, rtol=1e-8, maxit=1000, x0=None):
     return x, its, float(np.linalg.norm(b - A @ x) / bn)
 
 
-def flexible_pcg(A, b, Minv, rtol=1e-8, maxit=1000):
-    """Flexible CG (Polak-Ribiere beta) for a variable preconditioner (R8)."""
+def flexible_pcg(A, b, Minv, rtol=1e-8, maxit=1000, callback=None):
+    """Flexible CG (Polak-Ribiere beta) for a variable preconditioner (R8):
+    beta_k = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k).  callback as in pcg."""
     A = as_scipy(A)
     x = np.zeros_like(b)
     bn = np.linalg.norm(b)
@@ -522,6 +530,8 @@ def flexible_pcg(A, b, Minv, rtol=1e-8, maxit=1000):
             x += alpha * p
             r_old = r.copy()
             r -= alpha * q
+            if callback is not None:
+                callback(its, x, r, p)
             if np.linalg.norm(r) <= rtol * bn:
                 break
             z = Minv(r)
@@ -628,7 +638,10 @@ def diagnostics(A, pre: TwoLevel, tau: float) -> dict:
     A = as_scipy(A)
     Ad = A.toarray()
     n = Ad.shape[0]
-    Minv = np.column_stack([pre.apply(e) for e in np.eye(n)])
+    if pre.coarse_solver is None:  # linear: the whole identity in one block apply
+        Minv = pre.apply(np.eye(n))
+    else:
+        Minv = np.column_stack([pre.apply(e) for e in np.eye(n)])
     Minv = 0.5 * (Minv + Minv.T)
     CA = np.linalg.cholesky(Ad)
     lam = np.linalg.eigvalsh(CA.T @ Minv @ CA)

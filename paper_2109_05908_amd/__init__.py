@@ -9,5 +9,5 @@ the first call does, and fails loudly if it has not been built.
 from .binding import (  # noqa: F401
     DD_FP32, DD_FP64, DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED, DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP, DDError,
     DeviceCSR, Preconditioner,
-    lib, library_path, meter_read, meter_start, partition_ggg, trim_device_cache,
+    extract_local, lib, library_path, meter_read, meter_start, partition_ggg, trim_device_cache,
 )

@@ -19,6 +19,7 @@ DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP = 0, 1
 DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED = 0, 1
 DD_NPHASE = 12
 DD_MAX_LEVELS = 4
+DD_PHIST = 16
 
 
 class DDError(RuntimeError):
@@ -42,7 +43,8 @@ class _Opts(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("levels", C.c_int32), ("N", C.c_int32 * DD_MAX_LEVELS), ("n", C.c_int64 * DD_MAX_LEVELS),
                 ("n_C", C.c_int64), ("grid_complexity", C.c_double), ("p_min", C.c_int32),
-                ("p_max", C.c_int32), ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32),
+                ("p_max", C.c_int32), ("p_hist", C.c_int32 * DD_PHIST), ("k_c", C.c_int32),
+                ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32),
                 ("phase_ms", C.c_double * DD_NPHASE), ("last_iters", C.c_int32), ("last_relres", C.c_double),
                 ("device_bytes", C.c_int64)]
 
@@ -98,6 +100,7 @@ def lib():
         "dd_subdomain_eigs": ([vp, i32, i32, vp], i32),
         "dd_subdomain_basis": ([vp, i32, i32, vp], i32),
         "dd_subdomain_sigma1": ([vp, i32, vp], i32),
+        "dd_extract_local": ([P(_Csr), vp, i32, i32, i32, vp, vp, vp, vp], i32),
         "dd_coarse_matrix": ([vp, i32, vp, i64], i32),
         "dd_meter_start": ([C.c_char_p], i32),
         "dd_meter_read": ([P(_Meter)], i32),
@@ -113,7 +116,7 @@ def lib():
 def exported_symbols() -> list[str]:
     return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_trim_device_cache", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
-            "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix",
+            "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix", "dd_extract_local",
             "dd_meter_start", "dd_meter_read"]
 
 
@@ -164,6 +167,22 @@ def partition_ggg(A: DeviceCSR, N: int, seed: int):
     return part
 
 
+def extract_local(A: DeviceCSR, part, N: int, overlap: int, i: int):
+    """dd_extract_local: (sizes (n_I, n_Gamma, n_Delta), A_ii, X_i) of subdomain i as the setup forms them."""
+    import torch
+    part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device).contiguous()
+    cs = A.cstruct()
+    sz = np.zeros(3, dtype=np.int32)
+    _check(lib().dd_extract_local(C.byref(cs), _ptr(part), N, overlap, i, sz.ctypes.data_as(C.c_void_p), None,
+                                  None, _stream()), "dd_extract_local")
+    ni, nt = int(sz[0] + sz[1]), int(sz.sum())
+    Aii = np.zeros(ni * ni)
+    X = np.zeros(ni * nt)
+    _check(lib().dd_extract_local(C.byref(cs), _ptr(part), N, overlap, i, None, Aii.ctypes.data_as(C.c_void_p),
+                                  X.ctypes.data_as(C.c_void_p), _stream()), "dd_extract_local")
+    return tuple(int(v) for v in sz), Aii.reshape(ni, ni).T.copy(), X.reshape(nt, ni).T.copy()
+
+
 class Preconditioner:
     """Handle of dd_setup: the additive Schwarz preconditioner with `levels`
     levels (2 = fine + coarse E; more levels recurse on E, coarsening the
@@ -211,6 +230,8 @@ class Preconditioner:
         self.sys_n = [A.n for A in As]
         self.n = sum(self.sys_n)
         self.A = None
+        self._batch_nnz = sum(A.nnz for A in As)
+        self._dev = dev
         self._keep = tparts
         return self
 
@@ -226,10 +247,16 @@ class Preconditioner:
             pass
 
     def update_values(self, val):
-        """dd_update_values: new matrix values (same pattern, CSR order), whole setup redone."""
+        """dd_update_values: new matrix values (same pattern, CSR order), whole setup redone.
+        A batch handle takes the values of all systems concatenated (system after system)."""
         import torch
         if self.A is None:
-            raise ValueError("update_values: use the C-ABI for a batch handle (values of the union in order)")
+            val = torch.as_tensor(val, dtype=torch.float64).to(self._dev).contiguous()
+            if val.numel() != self._batch_nnz:
+                raise ValueError("update_values: expected the nnz values of all systems")
+            self.setup_status = _check(lib().dd_update_values(self._h, _ptr(val), _stream()), "dd_update_values")
+            self._keep_val = val
+            return self.setup_status
         val = torch.as_tensor(val, dtype=torch.float64).to(self.A.val.device).contiguous()
         if val.numel() != self.A.val.numel():
             raise ValueError("update_values: expected nnz values")
@@ -295,6 +322,7 @@ class Preconditioner:
         return {
             "levels": inf.levels, "N": list(inf.N), "n": list(inf.n), "n_C": inf.n_C,
             "grid_complexity": inf.grid_complexity, "p_min": inf.p_min, "p_max": inf.p_max,
+            "p_hist": list(inf.p_hist), "k_c": inf.k_c,
             "fp32_fallbacks": inf.fp32_fallbacks, "eig_maxit_hits": inf.eig_maxit_hits,
             "phase_ms": {L.dd_phase_name(i).decode(): inf.phase_ms[i] for i in range(DD_NPHASE)},
             "last_iters": inf.last_iters, "last_relres": inf.last_relres, "device_bytes": inf.device_bytes,

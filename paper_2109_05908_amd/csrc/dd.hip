@@ -212,10 +212,10 @@ static Batch<DMat> mats(const std::vector<double*>& p, const std::vector<int>& l
 // ---------------------------------------------------------------------------
 static void build_e_csr(Level& Lv, Level& next, hipStream_t s);
 
-// `next` (nullable): when given, E is not factored but handed to the next
-// level as its CSR matrix (multilevel recursion).
-static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s, Level* next) {
-    Timer tm(s);
+// a1 and a2 of one level: the ordered sets I, Gamma, Delta and the index maps
+// (Sec. 2), then the dense blocks Y_i = X_i^T (n~_i x n_i) into Y and A_ii
+// (n_i x n_i) into Lv.L (Sec. 3.1, (3.1)).
+static void sets_and_extract(Level& Lv, dd_info_t& info, Timer& tm, Arena& Y, hipStream_t s) {
     const int N = Lv.N;
     const int delta = Lv.delta;
     const int64_t n = Lv.n;
@@ -259,12 +259,8 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
 
     const auto& ni = Lv.ni;
     const auto& nt = Lv.nt;
-    const auto& nI = Lv.nI;
-    std::vector<int> nc(N);
-    for (int i = 0; i < N; ++i) nc[i] = nt[i] - nI[i];
 
     // ---- a2: dense Y_i = X_i^T and A_ii ------------------------------------------------
-    Arena Y;
     {
         std::vector<int64_t> sy(N), sa(N);
         for (int i = 0; i < N; ++i) {
@@ -283,6 +279,21 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     }
     dist.release();
     info.phase_ms[PH_EXTRACT] += tm.lap();
+}
+
+// `next` (nullable): when given, E is not factored but handed to the next
+// level as its CSR matrix (multilevel recursion).
+static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s, Level* next) {
+    Timer tm(s);
+    const int N = Lv.N;
+    const CsrDev A = Lv.A();
+    Arena Y;
+    sets_and_extract(Lv, info, tm, Y, s);
+    const auto& ni = Lv.ni;
+    const auto& nt = Lv.nt;
+    const auto& nI = Lv.nI;
+    std::vector<int> nc(N);
+    for (int i = 0; i < N; ++i) nc[i] = nt[i] - nI[i];
 
     // ---- a4: local Cholesky A_ii = L_i L_i^T (exact subdomain solver) -------------------
     {
@@ -1068,6 +1079,11 @@ static void partition_next_batch(const Level& Lv, Level& next, int coarsen, hipS
     int total = 0;
     for (int j = 0; j < ns; ++j) {
         const int s0 = Lv.hsub[j], s1 = Lv.hsub[j + 1], Nj = s1 - s0;
+        if (Nj == 0) {  // this system kept no coarse mode on the level above: nothing to partition
+            next.hsub.push_back(total);
+            next.hseg.push_back(Lv.hoffC[s1]);
+            continue;
+        }
         std::vector<int32_t> rp(Nj + 1, 0), ci;
         for (int i = 0; i < Nj; ++i) {
             for (int k = 0; k < Nj; ++k)
@@ -1495,8 +1511,15 @@ struct SegView {
     const int32_t* sid;
 };
 static SegView seg_of(Handle& H, size_t m) {
-    if (m == 0) return SegView{&H.sys_off, H.dsys_off.p, H.sys_id.p};
+    const size_t want = (size_t)H.nsys() + 1;
+    if (m == 0) {
+        DD_CHECK(H.sys_off.size() == want && H.dsys_off.p && H.sys_id.p, DD_ERR_INTERNAL,
+                 "batch handle without system ranges on level 0");
+        return SegView{&H.sys_off, H.dsys_off.p, H.sys_id.p};
+    }
     Level& Lv = *H.lv[m];
+    DD_CHECK(Lv.hseg.size() == want && Lv.dseg.p && Lv.seg_id.p, DD_ERR_INTERNAL,
+             "batch level without per-system ranges");
     return SegView{&Lv.hseg, Lv.dseg.p, Lv.seg_id.p};
 }
 
@@ -1610,6 +1633,41 @@ __global__ void k_copy_add_i32(const int32_t* src, int32_t* dst, int64_t n, int6
 __global__ void k_set_i32(int32_t* dst, int64_t n, int32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = v;
+}
+
+// k_c of the bound of Sec. 3.2: greedy colouring, subdomains in index order,
+// each taking the smallest colour none of its neighbours has, on the graph
+// i ~ j iff A(Omega_i, Omega_j) != 0.  The columns of the rows Omega_i are
+// exactly Omega~_i = [Omega_i, Delta_i] (every dof of Omega_i has its
+// diagonal entry, every dof of Delta_i a neighbour in Omega_i), so i ~ j iff
+// Omega~_i meets Omega_j.
+static int coloring_kc(const Level& L) {
+    const int N = L.N;
+    const auto ext = to_host(L.ext.p, (size_t)L.hoffE[N], nullptr);
+    std::vector<int64_t> cnt(L.n + 1, 0);  // subdomains whose Omega holds each dof (CSR)
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < L.ni[j]; ++k) cnt[ext[L.hoffE[j] + k] + 1] += 1;
+    for (int64_t g = 0; g < L.n; ++g) cnt[g + 1] += cnt[g];
+    std::vector<int32_t> who(cnt[L.n]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < L.ni[j]; ++k) who[pos[ext[L.hoffE[j] + k]]++] = j;
+    std::vector<int> color(N, -1), mark(N + 1, -1);
+    int kc = 0;
+    for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < L.nt[i]; ++k) {
+            const int64_t g = ext[L.hoffE[i] + k];
+            for (int64_t q = cnt[g]; q < cnt[g + 1]; ++q) {
+                const int j = who[q];
+                if (j != i && color[j] >= 0) mark[color[j]] = i;
+            }
+        }
+        int c = 0;
+        while (mark[c] == i) ++c;
+        color[i] = c;
+        kc = std::max(kc, c + 1);
+    }
+    return kc;
 }
 
 }  // namespace dd
@@ -1965,6 +2023,13 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
     I.grid_complexity = gsum / double(n);
     I.p_min = N ? *std::min_element(L0.p.begin(), L0.p.end()) : 0;
     I.p_max = N ? *std::max_element(L0.p.begin(), L0.p.end()) : 0;
+    for (int b = 0; b < DD_PHIST; ++b) I.p_hist[b] = 0;
+    for (int i = 0; i < N; ++i) {
+        int b = 0;
+        while (b + 1 < DD_PHIST && L0.p[i] >= (1 << b)) ++b;
+        I.p_hist[b] += 1;
+    }
+    I.k_c = 0;  // computed at the first dd_info call
     if (!H.partial.p) {
         const int w = std::max(64, H.nsys());
         H.partial.alloc((int64_t)512 * w);
@@ -2010,6 +2075,53 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
     DD_GUARD_END
 }
 
+int dd_extract_local(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, int32_t i, int32_t* sizes,
+                     double* Aii, double* X, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!A || !part || A->n <= 0 || A->nnz <= 0 || N < 1 || N > A->n || overlap < 1 || overlap > 200 || i < 0 ||
+        i >= N)
+        return DD_ERR_INVALID_ARG;
+    Level L;
+    L.n = A->n;
+    L.nnz = A->nnz;
+    L.rowptr.alloc(L.n + 1);
+    L.colind.alloc(L.nnz);
+    L.val.alloc(L.nnz);
+    DD_HIP(hipMemcpyAsync(L.rowptr.p, A->rowptr, (L.n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L.colind.p, A->colind, L.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    DD_HIP(hipMemcpyAsync(L.val.p, A->val, L.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    L.N = N;
+    L.delta = overlap;
+    L.part.alloc(L.n);
+    DD_HIP(hipMemcpyAsync(L.part.p, part, L.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    {
+        DBuf<int32_t> cnt(N);
+        const int rc = validate_partition(L.part.p, L.n, N, cnt.p, s);
+        if (rc != DD_OK) return rc;
+    }
+    dd_info_t info{};
+    Timer tm(s);
+    Arena Y;
+    sets_and_extract(L, info, tm, Y, s);
+    const int ni = L.ni[i], nt = L.nt[i];
+    if (sizes) {
+        sizes[0] = L.nI[i];
+        sizes[1] = L.nG[i];
+        sizes[2] = L.nD[i];
+    }
+    if (Aii) {
+        d2h(Aii, L.L.ptr[i], (size_t)ni * ni, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    if (X) {  // Y_i = X_i^T is n~_i x n_i, column-major: X_i(r, c) = Y_i(c, r)
+        const auto y = to_host(Y.ptr[i], (size_t)nt * ni, s);
+        for (int r = 0; r < ni; ++r)
+            for (int c = 0; c < nt; ++c) X[r + (int64_t)c * ni] = y[c + (int64_t)r * nt];
+    }
+    return DD_OK;
+    DD_GUARD_END
+}
+
 int dd_update_values(dd_handle h, const double* val, hipStream_t s) {
     DD_GUARD_BEGIN
     if (!h || !val || h->h.lv.empty()) return DD_ERR_INVALID_ARG;
@@ -2018,6 +2130,10 @@ int dd_update_values(dd_handle h, const double* val, hipStream_t s) {
     auto fresh = std::make_unique<dd_handle_s>();
     Handle& F = fresh->h;
     F.opt = h->h.opt;
+    // a batch handle: the systems' subdomain ranges, so that every level is
+    // partitioned system by system again (the dof ranges stay with the handle)
+    F.sub_off = h->h.sub_off;
+    F.sys_off = h->h.sys_off;
     const int rc = build_handle(F, L0.n, L0.nnz, L0.rowptr.p, L0.colind.p, val, L0.part.p, L0.N, L0.delta, L0.tau,
                                 h->h.levels_req, s);
     if (rc < 0) return rc;
@@ -2055,8 +2171,23 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
         H.opt.validate = opt->validate;
         if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
         if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
-        if (opt->schwarz != DD_SCHWARZ_ADDITIVE && opt->schwarz != DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;
-        H.opt.schwarz = opt->schwarz;
+        // the deflated variant needs GMRES, which has no per-system form: refused for a batch
+        if (opt->schwarz != DD_SCHWARZ_ADDITIVE) return DD_ERR_INVALID_ARG;
+    }
+    // every system's own CSR structure is checked before the union shifts its
+    // indices (an out-of-range column must not land inside another system)
+    if (H.opt.validate) {
+        DBuf<int32_t> bad(1);
+        for (int j = 0; j < nsys; ++j) {
+            DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_check_pattern, dim3(vgrid(As[j].n)), dim3(256), 0, s, As[j].rowptr, As[j].colind,
+                               As[j].n, As[j].nnz, bad.p);
+            launch_check("check_pattern");
+            int32_t hb = 0;
+            DD_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DD_HIP(hipStreamSynchronize(s));
+            if (hb) return DD_ERR_INVALID_ARG;
+        }
     }
     // the block-diagonal union of the systems, its partition and the system of every dof
     const int64_t n = noff[nsys], nnz = zoff[nsys];
@@ -2176,9 +2307,13 @@ int dd_spmv(dd_handle h, const double* x, double* y, hipStream_t s) {
 }
 
 int dd_info(dd_handle h, dd_info_t* out) {
+    DD_GUARD_BEGIN
     if (!h || !out) return DD_ERR_INVALID_ARG;
-    *out = h->h.info;
+    Handle& H = h->h;
+    if (H.info.k_c == 0 && !H.lv.empty() && H.lv[0]->N > 0) H.info.k_c = coloring_kc(*H.lv[0]);
+    *out = H.info;
     return DD_OK;
+    DD_GUARD_END
 }
 
 void dd_destroy(dd_handle h) { delete h; }

@@ -72,28 +72,41 @@ __global__ void k_ggg_rest(int32_t* part, int64_t n, const int32_t* sizes, int N
 
 static int grid_for(int64_t n, int block = 256) { return (int)std::min<int64_t>((n + block - 1) / block, 65536); }
 
+// The growing rule on caller-provided device buffers: round (n), sizes (N) and
+// a flag (1).  Everything that must start at a value is set by fill kernels;
+// the flag of every round comes back through *hflag (host memory).
+static void ggg_run(const CsrDev& A, int N, uint64_t seed, int32_t* part, int32_t* round, int32_t* sizes,
+                    int32_t* changed, int32_t* hflag, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(A.n)), dim3(256), 0, s, round, A.n, -1);
+    hipLaunchKernelGGL(k_ggg_seeds, dim3(1), dim3(1), 0, s, A.n, N, seed, part, round);
+    launch_check("ggg_seeds");
+    for (int r = 1;; ++r) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, changed, (int64_t)1, 0);
+        hipLaunchKernelGGL(k_ggg_round, dim3(grid_for(A.n)), dim3(256), 0, s, A, part, round, r, changed);
+        launch_check("ggg_round");
+        DD_HIP(hipMemcpyAsync(hflag, changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DD_HIP(hipStreamSynchronize(s));
+        if (!*hflag) break;
+    }
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(N)), dim3(256), 0, s, sizes, (int64_t)N, 0);
+    hipLaunchKernelGGL(k_part_sizes, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, sizes);
+    hipLaunchKernelGGL(k_ggg_rest, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, sizes, N);
+    launch_check("ggg_rest");
+    DD_HIP(hipStreamSynchronize(s));
+}
+
 void ggg_partition(const CsrDev& A, int N, uint64_t seed, int32_t* part, hipStream_t s) {
     DD_CHECK(N >= 1 && N <= A.n, DD_ERR_INVALID_ARG, "partition: need 1 <= N <= n");
     DBuf<int32_t> round(A.n), changed(1), sizes(N);
     int32_t* hchg = nullptr;
     DD_HIP(hipHostMalloc(&hchg, sizeof(int32_t)));
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, -1);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(A.n)), dim3(256), 0, s, round.p, A.n, -1);
-    hipLaunchKernelGGL(k_ggg_seeds, dim3(1), dim3(1), 0, s, A.n, N, seed, part, round.p);
-    launch_check("ggg_seeds");
-    for (int r = 1;; ++r) {
-        DD_HIP(hipMemsetAsync(changed.p, 0, sizeof(int32_t), s));
-        hipLaunchKernelGGL(k_ggg_round, dim3(grid_for(A.n)), dim3(256), 0, s, A, part, round.p, r, changed.p);
-        launch_check("ggg_round");
-        DD_HIP(hipMemcpyAsync(hchg, changed.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        DD_HIP(hipStreamSynchronize(s));
-        if (!*hchg) break;
+    try {
+        ggg_run(A, N, seed, part, round.p, sizes.p, changed.p, hchg, s);
+    } catch (...) {
+        (void)hipHostFree(hchg);
+        throw;
     }
-    DD_HIP(hipMemsetAsync(sizes.p, 0, N * sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_part_sizes, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, sizes.p);
-    hipLaunchKernelGGL(k_ggg_rest, dim3(grid_for(A.n)), dim3(256), 0, s, part, A.n, sizes.p, N);
-    launch_check("ggg_rest");
-    DD_HIP(hipStreamSynchronize(s));
     (void)hipHostFree(hchg);
 }
 

@@ -71,12 +71,29 @@ def test_fullsize_sets_bit_exact():
         np.testing.assert_array_equal(D, s.Delta)
 
 
+def _sample(which):
+    st = state()
+    ni = np.array([s.Omega.size for s in st["sets"]])
+    order = np.argsort(ni, kind="stable")
+    if which == "largest":
+        return [int(order[-1])]
+    return [int(order[0]), int(order[len(order) // 4]), int(order[len(order) // 2])]
+
+
 def test_fullsize_sampled_eigenvalues():
+    _check_sample(_sample("strata"))
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_largest_subdomain_eigenvalues():
+    """The largest subdomain (n_i about 4500, n~_i about 5600), where the QR, the
+    polar iteration and Lanczos run longest."""
+    _check_sample(_sample("largest"))
+
+
+def _check_sample(sample):
     st = state()
     pre, sets, A, tau = st["pre"], st["sets"], st["A"], st["cfg"].tau
-    ni = np.array([s.Omega.size for s in sets])
-    order = np.argsort(ni, kind="stable")
-    sample = [int(order[0]), int(order[len(order) // 4]), int(order[len(order) // 2])]
     sizes = pre.sizes()
     s1 = pre.sigma1()
     for i in sample:
