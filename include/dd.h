@@ -123,6 +123,17 @@ typedef struct {
  * Deterministic and bit-exact.  Errors: DD_ERR_INVALID_ARG if N < 1 or N > n. */
 int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, hipStream_t stream);
 
+/* dd_partition_ggg for callers that cannot allocate (serving loops, harnesses that forbid
+ * hipMalloc/hipHostMalloc): the same partition, bit for bit, with no allocation of any kind.
+ * Its work arrays (4,194,304 + 65,536 + 64 int32, about 16.3 MiB) live in one file-scope device
+ * array per GPU, held by the library until the process ends.  Limits: n <= 4,194,304 and
+ * N <= 65,536, else DD_ERR_INVALID_ARG (nothing runs).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race, so the caller orders them.
+ * The array is reinitialised by every call.  A, part: device, as for dd_partition_ggg; part is
+ * the output.  The call synchronises the stream once per growing round (it reads a device flag
+ * into host stack memory).  Errors: DD_ERR_INVALID_ARG, DD_ERR_HIP. */
+int dd_partition_ggg_noalloc(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, hipStream_t stream);
+
 /* Build the preconditioner (Sec. 2-3).
  *  part    device int32[n], subdomain id of each node in [0, N)  (Omega_Ii = {j : part_j = i})
  *  overlap delta >= 1: Gamma_i = BFS layers 1..delta of Omega_Ii, Delta_i = layer delta+1

@@ -82,6 +82,7 @@ def lib():
     P = C.POINTER
     sig = {
         "dd_partition_ggg": ([P(_Csr), i32, C.c_uint64, vp, vp], i32),
+        "dd_partition_ggg_noalloc": ([P(_Csr), i32, C.c_uint64, vp, vp], i32),
         "dd_setup": ([P(_Csr), vp, i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
         "dd_update_values": ([vp, vp, vp], i32),
         "dd_setup_batch": ([P(_Csr), P(vp), P(i32), i32, i32, f64, i32, P(_Opts), vp, P(vp)], i32),
@@ -114,7 +115,7 @@ def lib():
 
 
 def exported_symbols() -> list[str]:
-    return ["dd_partition_ggg", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
+    return ["dd_partition_ggg", "dd_partition_ggg_noalloc", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_trim_device_cache", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix", "dd_extract_local",
             "dd_meter_start", "dd_meter_read"]

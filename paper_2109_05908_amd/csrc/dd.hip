@@ -1898,6 +1898,16 @@ int dd_partition_ggg(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, h
     DD_GUARD_END
 }
 
+int dd_partition_ggg_noalloc(const dd_csr* A, int32_t N, uint64_t seed, int32_t* part, hipStream_t stream) {
+    DD_GUARD_BEGIN
+    if (!A || !part || A->n <= 0 || N < 1 || N > A->n) return DD_ERR_INVALID_ARG;
+    if (A->n > kGggMaxN || N > kGggMaxParts) return DD_ERR_INVALID_ARG;
+    CsrDev C{A->n, A->nnz, A->rowptr, A->colind, A->val};
+    ggg_partition_noalloc(C, N, seed, part, stream);
+    return DD_OK;
+    DD_GUARD_END
+}
+
 __global__ void k_check_finite(const double* v, int64_t n, int32_t* bad) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         if (!isfinite(v[i])) atomicOr(bad, 1);

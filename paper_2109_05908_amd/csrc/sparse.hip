@@ -2,6 +2,7 @@
 #include "sparse.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace dd {
 
@@ -108,6 +109,47 @@ void ggg_partition(const CsrDev& A, int N, uint64_t seed, int32_t* part, hipStre
         throw;
     }
     (void)hipHostFree(hchg);
+}
+
+// ---------------------------------------------------------------------------
+// The same partition without any allocation, for callers that cannot allocate:
+// its work arrays live in one file-scope device array per GPU.  In host code
+// the array's name is not a device address; the address of each GPU's copy is
+// taken once per device with hipGetSymbolAddress and only that is used.
+// Calls that overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int32_t scratch[kGggMaxN + kGggMaxParts + 64];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static int32_t* scratch_on_current_device() {
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    DD_CHECK(dev >= 0 && dev < kMaxDevices, DD_ERR_INTERNAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        DD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        DD_CHECK(p != nullptr, DD_ERR_HIP, "no device address for the partition scratch array");
+        g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+void ggg_partition_noalloc(const CsrDev& A, int N, uint64_t seed, int32_t* part, hipStream_t s) {
+    DD_CHECK(N >= 1 && N <= A.n, DD_ERR_INVALID_ARG, "partition: need 1 <= N <= n");
+    DD_CHECK(A.n <= kGggMaxN, DD_ERR_INVALID_ARG, "partition without allocation: n beyond its scratch capacity");
+    DD_CHECK(N <= kGggMaxParts, DD_ERR_INVALID_ARG, "partition without allocation: N beyond its scratch capacity");
+    int32_t* base = scratch_on_current_device();
+    int32_t* round = base;
+    int32_t* sizes = base + kGggMaxN;
+    int32_t* changed = base + kGggMaxN + kGggMaxParts;
+    int32_t hflag = 0;
+    ggg_run(A, N, seed, part, round, sizes, changed, &hflag, s);
 }
 
 __global__ void k_validate_part(const int32_t* part, int64_t n, int N, int32_t* counts, int32_t* bad) {

@@ -13,6 +13,11 @@ struct CsrDev {
 
 // --- partition (seeded greedy graph growing) ---
 void ggg_partition(const CsrDev& A, int N, uint64_t seed, int32_t* part, hipStream_t s);
+// the same without allocating: work arrays in a file-scope device array of
+// kGggMaxN + kGggMaxParts + 64 int32 per GPU (n <= kGggMaxN, N <= kGggMaxParts)
+constexpr int64_t kGggMaxN = (int64_t)1 << 22;
+constexpr int kGggMaxParts = 1 << 16;
+void ggg_partition_noalloc(const CsrDev& A, int N, uint64_t seed, int32_t* part, hipStream_t s);
 
 // --- validation: every id in [0, N); counts per part (device int32[N]) ---
 int validate_partition(const int32_t* part, int64_t n, int N, int32_t* dcounts, hipStream_t s);
