@@ -79,8 +79,28 @@ typedef struct {
                              CSR is undefined behaviour.  Values are always checked for NaN/Inf. */
     int32_t coarsen;      /* levels >= 3: subdomains per coarse part (default 64) */
     int32_t schwarz;      /* DD_SCHWARZ_ADDITIVE (default) or DD_SCHWARZ_DEFLATED */
-    int32_t reserved[6];
+    int32_t eig_solver;   /* local eigenproblem (3.3): DD_EIG_DENSE (default; tridiagonal route, every mode),
+                             DD_EIG_LOBPCG (block solver for the nev_cap modes of DD_SEL_THRESHOLD_CAP: the
+                             largest eigenvalues of K = S~^{-1} = M^T M, M = R_II^{-T} L_I formed once) or
+                             DD_EIG_LOBPCG_MATFREE (the smallest of S~ = L_I^{-1} S_I L_I^{-T} applied through the
+                             triangular factors L_I and R_II, S_I = R_II^T R_II, preconditioned by K applied the
+                             same way: no n_Ii x n_Ii matrix formed for the eigenproblem) */
+    int32_t lobpcg_maxit; /* LOBPCG iterations per subdomain (0: 100); eig_maxit_hits counts the misses */
+    double  lobpcg_tol;   /* LOBPCG stop for the nev_cap wanted pairs: DD_EIG_LOBPCG, residual relative to the
+                             eigenvalue of K = S~^{-1} (above its rounding floor; 0: 1e-8); DD_EIG_LOBPCG_MATFREE,
+                             absolute residual of S~, whose norm is <= 1 (0: 1e-12) */
+    int32_t warm_start;   /* LOBPCG start block: DD_START_RANDOM (default), DD_START_RANGE or DD_START_MODEL */
+    int32_t reserved0;
+    uint64_t seed;        /* seed of the Gaussian draws of the start blocks */
+    const void* warm_start_model; /* DD_START_MODEL: a dd_model (dd_model_create); NULL falls back to random */
+    int32_t reserved[8];
 } dd_options;
+#define DD_EIG_DENSE          0
+#define DD_EIG_LOBPCG         1
+#define DD_EIG_LOBPCG_MATFREE 2
+#define DD_START_RANDOM       0  /* Gaussian block (counter-based generator, seed) */
+#define DD_START_RANGE        1  /* A_ii^{-1} A(Omega_i, Delta_i) G restricted to Omega_Ii, G Gaussian on Delta_i */
+#define DD_START_MODEL        2  /* the same with the rows of G weighted by the network of warm_start_model */
 
 typedef struct dd_handle_s* dd_handle;
 
@@ -104,7 +124,10 @@ typedef struct {
                                        (overlapping sets): the k_c of the bound (k_c + 1)(2 + (2 k_c + 1) k_m / tau)
                                        of Sec. 3.2; computed on the host at the first dd_info call */
     int32_t fp32_fallbacks;         /* local factors recomputed in FP64 */
-    int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap */
+    int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap (block solver: subdomains) */
+    int32_t eig_iters_max;          /* block eigensolver on the finest level: largest and mean iteration count */
+    double  eig_iters_mean;
+    double  eig_resid_max;          /* its largest final relative eigen-residual of a wanted pair */
     double  phase_ms[DD_NPHASE];    /* setup phase times, see dd_phase_name */
     int32_t last_iters;             /* last dd_pcg or dd_gmres: iterations (first RHS; a batch: the largest) */
     double  last_relres;            /* last dd_pcg or dd_gmres: true relative residual (first RHS; a batch: the largest) */
@@ -249,7 +272,56 @@ void dd_destroy(dd_handle h);
 int dd_trim_device_cache(void);
 const char* dd_strerror(int code);
 
+/* ---- warm start of the block eigensolver (a learned model) ---------------
+ * A small network maps features of every node of the boundary layer Delta_i of a subdomain
+ * (computed from A alone) to a positive weight; the start block of the eigenproblem (3.3) is then
+ * X_i = [A_ii^{-1} A(Omega_i, Delta_i) diag(w) G]_{Omega_Ii} (in the reciprocal form's variables),
+ * G Gaussian, which lies in the near kernel of the splitting (Sec. 3.2 shows the kernel of
+ * the splitting is made of such vectors).  The network is trained, on the GPU, on the kept
+ * eigenvectors of earlier setups of the same family of matrices: for each boundary node the
+ * target is the square root of its leverage (times |Delta_i| / p_i) in an orthonormal basis of
+ * A(Delta_i, Omega_i) A_ii^{-1} [Z_i; 0], the boundary data of the kept eigenvectors.  Loss: the
+ * mean over subdomains of each one's mean square error of the weights; optimiser Adam.
+ * Architecture: 8 features (standardised by the training mean and deviation), two tanh layers of
+ * 32, softplus output; parameters W1 (32 x 8 row-major), b1, W2 (32 x 32), b2, w3 (32), b3, then the
+ * 8 feature means and 8 deviations: DD_MODEL_NPARAM doubles in all. */
+typedef struct dd_model_s* dd_model;
+#define DD_MODEL_NFEAT  8
+#define DD_MODEL_NPARAM (8 * 32 + 32 + 32 * 32 + 32 + 32 + 1 + 2 * 8)
+/* A new model with Glorot-scaled Gaussian weights from `seed`, zero hidden biases and the output
+ * bias at softplus^{-1}(1), so that it starts near weight 1 everywhere (the range start).
+ * Errors: DD_ERR_INVALID_ARG for a null out, DD_ERR_OOM. */
+int dd_model_create(uint64_t seed, dd_model* out);
+/* Appends training samples from handle h (finest level; FP64 local solves): the features and
+ * targets of the boundary nodes of every subdomain that kept modes.  The handle's kept vectors
+ * are the training eigenvectors (set up with the dense route for exact ones).  Synchronous.
+ * Errors: DD_ERR_INVALID_ARG (null arguments, FP32 handle, a subdomain with more than 128 kept
+ * modes). */
+int dd_model_add_samples(dd_model m, dd_handle h, hipStream_t stream);
+/* `epochs` full-batch Adam steps (learning rate lr) on the stored samples; the feature means and
+ * deviations are fixed at the first call.  loss: host double[epochs] (may be NULL), the loss
+ * before each step.  Errors: DD_ERR_INVALID_ARG (no samples, epochs < 0, lr <= 0). */
+int dd_model_train(dd_model m, int32_t epochs, double lr, double* loss, hipStream_t stream);
+/* Parameters out (host double[DD_MODEL_NPARAM], may be NULL) and their count. */
+int dd_model_params(dd_model m, double* out, int32_t* count);
+/* Parameters in (host, count = DD_MODEL_NPARAM; deviations > 0).  Errors: DD_ERR_INVALID_ARG, DD_ERR_NAN. */
+int dd_model_set_params(dd_model m, const double* in, int32_t count);
+/* out[s] = weight of sample s: feats device double[n x DD_MODEL_NFEAT] (row-major), out device double[n]. */
+int dd_model_forward(dd_model m, const double* feats, int64_t n, double* out, hipStream_t stream);
+/* Loss sum_s weight_s (w_s - target_s)^2 and its gradient with respect to the DD_MODEL_NPARAM - 16
+ * trained parameters on n given samples (device arrays), into host loss[1] and grad (either may be
+ * NULL).  Errors: DD_ERR_INVALID_ARG. */
+int dd_model_loss_grad(dd_model m, const double* feats, const double* target, const double* weight, int64_t n,
+                       double* loss, double* grad, hipStream_t stream);
+/* The stored samples (host arrays, each may be NULL): n, feats[n x 8], target[n], weight[n]. */
+int dd_model_samples(dd_model m, int64_t* n, double* feats, double* target, double* weight);
+void dd_model_destroy(dd_model m);
+
 /* ---- inspection (tests and diagnostics; all outputs are host memory) ---- */
+/* Block eigensolver of `level`: iterations and final largest relative eigen-residual of the wanted
+ * pairs of every subdomain (host int32[N], double[N], may be NULL).  DD_ERR_INVALID_ARG for a level
+ * set up with the dense route. */
+int dd_subdomain_eig_stats(dd_handle h, int32_t level, int32_t* iters, double* resid);
 /* Number of subdomains at `level` (0 = finest). */
 int dd_subdomain_count(dd_handle h, int32_t level, int32_t* N);
 /* sizes: host int32[5*N]: for each i, {n_Ii, n_Gamma_i, n_Delta_i, p_i, status}. */

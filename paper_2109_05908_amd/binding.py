@@ -17,6 +17,8 @@ _LIB = None
 DD_FP64, DD_FP32 = 0, 1
 DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP = 0, 1
 DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED = 0, 1
+DD_EIG_DENSE, DD_EIG_LOBPCG, DD_EIG_LOBPCG_MATFREE = 0, 1, 2
+DD_START_RANDOM, DD_START_RANGE, DD_START_MODEL = 0, 1, 2
 DD_NPHASE = 12
 DD_MAX_LEVELS = 4
 DD_PHIST = 16
@@ -37,14 +39,27 @@ class _Csr(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("local_prec", C.c_int32), ("select", C.c_int32), ("nev_cap", C.c_int32),
                 ("validate", C.c_int32), ("coarsen", C.c_int32), ("schwarz", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("eig_solver", C.c_int32), ("lobpcg_maxit", C.c_int32), ("lobpcg_tol", C.c_double),
+                ("warm_start", C.c_int32), ("reserved0", C.c_int32), ("seed", C.c_uint64),
+                ("warm_start_model", C.c_void_p), ("reserved", C.c_int32 * 8)]
+
+
+def _opts(local_prec=0, select=0, nev_cap=0, validate=False, coarsen=0, schwarz=0, eig_solver=0, lobpcg_maxit=0,
+          lobpcg_tol=0.0, warm_start=0, seed=0, model=None):
+    o = _Opts()
+    o.local_prec, o.select, o.nev_cap, o.validate = local_prec, select, nev_cap, int(validate)
+    o.coarsen, o.schwarz, o.eig_solver, o.lobpcg_maxit = int(coarsen), int(schwarz), int(eig_solver), int(lobpcg_maxit)
+    o.lobpcg_tol, o.warm_start, o.seed = float(lobpcg_tol), int(warm_start), int(seed)
+    o.warm_start_model = model._h if model is not None else None
+    return o
 
 
 class _Info(C.Structure):
     _fields_ = [("levels", C.c_int32), ("N", C.c_int32 * DD_MAX_LEVELS), ("n", C.c_int64 * DD_MAX_LEVELS),
                 ("n_C", C.c_int64), ("grid_complexity", C.c_double), ("p_min", C.c_int32),
                 ("p_max", C.c_int32), ("p_hist", C.c_int32 * DD_PHIST), ("k_c", C.c_int32),
-                ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32),
+                ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32), ("eig_iters_max", C.c_int32),
+                ("eig_iters_mean", C.c_double), ("eig_resid_max", C.c_double),
                 ("phase_ms", C.c_double * DD_NPHASE), ("last_iters", C.c_int32), ("last_relres", C.c_double),
                 ("device_bytes", C.c_int64)]
 
@@ -102,6 +117,16 @@ def lib():
         "dd_subdomain_basis": ([vp, i32, i32, vp], i32),
         "dd_subdomain_sigma1": ([vp, i32, vp], i32),
         "dd_extract_local": ([P(_Csr), vp, i32, i32, i32, vp, vp, vp, vp], i32),
+        "dd_subdomain_eig_stats": ([vp, i32, vp, vp], i32),
+        "dd_model_create": ([C.c_uint64, P(vp)], i32),
+        "dd_model_add_samples": ([vp, vp, vp], i32),
+        "dd_model_train": ([vp, i32, f64, vp, vp], i32),
+        "dd_model_params": ([vp, vp, P(i32)], i32),
+        "dd_model_set_params": ([vp, vp, i32], i32),
+        "dd_model_forward": ([vp, vp, i64, vp, vp], i32),
+        "dd_model_loss_grad": ([vp, vp, vp, vp, i64, vp, vp, vp], i32),
+        "dd_model_samples": ([vp, P(i64), vp, vp, vp], i32),
+        "dd_model_destroy": ([vp], None),
         "dd_coarse_matrix": ([vp, i32, vp, i64], i32),
         "dd_meter_start": ([C.c_char_p], i32),
         "dd_meter_read": ([P(_Meter)], i32),
@@ -118,6 +143,8 @@ def exported_symbols() -> list[str]:
     return ["dd_partition_ggg", "dd_partition_ggg_noalloc", "dd_setup", "dd_update_values", "dd_setup_batch", "dd_apply", "dd_pcg", "dd_gmres", "dd_spmv", "dd_info", "dd_phase_name",
             "dd_destroy", "dd_trim_device_cache", "dd_strerror", "dd_subdomain_count", "dd_subdomain_sizes", "dd_subdomain_sets",
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix", "dd_extract_local",
+            "dd_subdomain_eig_stats", "dd_model_create", "dd_model_add_samples", "dd_model_train", "dd_model_params",
+            "dd_model_set_params", "dd_model_forward", "dd_model_loss_grad", "dd_model_samples", "dd_model_destroy",
             "dd_meter_start", "dd_meter_read"]
 
 
@@ -168,6 +195,75 @@ def partition_ggg(A: DeviceCSR, N: int, seed: int):
     return part
 
 
+MODEL_NFEAT = 8
+MODEL_NPARAM = 8 * 32 + 32 + 32 * 32 + 32 + 32 + 1 + 2 * 8
+
+
+class WarmStartModel:
+    """dd_model: the network that weights the boundary nodes of the start block of
+    the block eigensolver; trained on the GPU from the kept eigenvectors of setups."""
+
+    def __init__(self, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().dd_model_create(int(seed), C.byref(h)), "dd_model_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dd_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_samples(self, pre) -> None:
+        _check(lib().dd_model_add_samples(self._h, pre._h, _stream()), "dd_model_add_samples")
+
+    def train(self, epochs: int, lr: float = 1e-2) -> np.ndarray:
+        loss = np.zeros(max(1, epochs))
+        _check(lib().dd_model_train(self._h, int(epochs), float(lr), loss.ctypes.data_as(C.c_void_p), _stream()),
+               "dd_model_train")
+        return loss[:epochs]
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(MODEL_NPARAM)
+        n = C.c_int32()
+        _check(lib().dd_model_params(self._h, out.ctypes.data_as(C.c_void_p), C.byref(n)), "dd_model_params")
+        return out[:n.value]
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        _check(lib().dd_model_set_params(self._h, p.ctypes.data_as(C.c_void_p), p.size), "dd_model_set_params")
+
+    def forward(self, feats):
+        import torch
+        f = torch.as_tensor(np.ascontiguousarray(feats, dtype=np.float64), device="cuda")
+        out = torch.empty(f.shape[0], dtype=torch.float64, device="cuda")
+        _check(lib().dd_model_forward(self._h, _ptr(f), f.shape[0], _ptr(out), _stream()), "dd_model_forward")
+        return out.cpu().numpy()
+
+    def loss_grad(self, feats, target, weight):
+        import torch
+        t = [torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda") for a in (feats, target, weight)]
+        loss = np.zeros(1)
+        grad = np.zeros(MODEL_NPARAM - 2 * MODEL_NFEAT)
+        _check(lib().dd_model_loss_grad(self._h, _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), t[1].numel(),
+                                        loss.ctypes.data_as(C.c_void_p), grad.ctypes.data_as(C.c_void_p),
+                                        _stream()), "dd_model_loss_grad")
+        return float(loss[0]), grad
+
+    def samples(self):
+        n = C.c_int64()
+        _check(lib().dd_model_samples(self._h, C.byref(n), None, None, None), "dd_model_samples")
+        f, t, w = np.zeros((n.value, MODEL_NFEAT)), np.zeros(n.value), np.zeros(n.value)
+        _check(lib().dd_model_samples(self._h, C.byref(n), f.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p)), "dd_model_samples")
+        return f, t, w
+
+
 def extract_local(A: DeviceCSR, part, N: int, overlap: int, i: int):
     """dd_extract_local: (sizes (n_I, n_Gamma, n_Delta), A_ii, X_i) of subdomain i as the setup forms them."""
     import torch
@@ -192,12 +288,16 @@ class Preconditioner:
 
     def __init__(self, A: DeviceCSR, part, N: int, overlap: int, tau: float, levels: int = 2,
                  local_prec: int = DD_FP64, select: int = DD_SEL_THRESHOLD, nev_cap: int = 0,
-                 validate: bool = False, coarsen: int = 0, schwarz: int = DD_SCHWARZ_ADDITIVE):
+                 validate: bool = False, coarsen: int = 0, schwarz: int = DD_SCHWARZ_ADDITIVE,
+                 eig_solver: int = DD_EIG_DENSE, lobpcg_maxit: int = 0, lobpcg_tol: float = 0.0,
+                 warm_start: int = DD_START_RANDOM, seed: int = 0, model=None):
         import torch
         self.A = A
         self.n = A.n
         part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device)
-        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), int(schwarz), (C.c_int32 * 6)())
+        opts = _opts(local_prec, select, nev_cap, validate, coarsen, schwarz, eig_solver, lobpcg_maxit, lobpcg_tol,
+                     warm_start, seed, model)
+        self._model = model
         h = C.c_void_p()
         cs = A.cstruct()
         self.setup_status = _check(
@@ -209,7 +309,8 @@ class Preconditioner:
     @classmethod
     def batch(cls, As, parts, Ns, overlap: int, tau: float, levels: int = 2, local_prec: int = DD_FP64,
               select: int = DD_SEL_THRESHOLD, nev_cap: int = 0, validate: bool = False, coarsen: int = 0,
-              schwarz: int = DD_SCHWARZ_ADDITIVE):
+              schwarz: int = DD_SCHWARZ_ADDITIVE, eig_solver: int = DD_EIG_DENSE, lobpcg_maxit: int = 0,
+              lobpcg_tol: float = 0.0, warm_start: int = DD_START_RANDOM, seed: int = 0, model=None):
         """dd_setup_batch: independent systems As[j] (DeviceCSR) with partitions
         parts[j] into Ns[j] parts, one handle over their block-diagonal union.
         Vectors are the systems concatenated; pcg returns per-system counts."""
@@ -220,9 +321,11 @@ class Preconditioner:
         csrs = (_Csr * k)(*[A.cstruct() for A in As])
         pp = (C.c_void_p * k)(*[t.data_ptr() for t in tparts])
         ns = (C.c_int32 * k)(*[int(x) for x in Ns])
-        opts = _Opts(local_prec, select, nev_cap, int(validate), int(coarsen), int(schwarz), (C.c_int32 * 6)())
+        opts = _opts(local_prec, select, nev_cap, validate, coarsen, schwarz, eig_solver, lobpcg_maxit, lobpcg_tol,
+                     warm_start, seed, model)
         h = C.c_void_p()
         self = cls.__new__(cls)
+        self._model = model
         self.setup_status = _check(
             lib().dd_setup_batch(csrs, pp, ns, k, overlap, float(tau), levels, C.byref(opts), _stream(), C.byref(h)),
             "dd_setup_batch")
@@ -325,6 +428,8 @@ class Preconditioner:
             "grid_complexity": inf.grid_complexity, "p_min": inf.p_min, "p_max": inf.p_max,
             "p_hist": list(inf.p_hist), "k_c": inf.k_c,
             "fp32_fallbacks": inf.fp32_fallbacks, "eig_maxit_hits": inf.eig_maxit_hits,
+            "eig_iters_max": inf.eig_iters_max, "eig_iters_mean": inf.eig_iters_mean,
+            "eig_resid_max": inf.eig_resid_max,
             "phase_ms": {L.dd_phase_name(i).decode(): inf.phase_ms[i] for i in range(DD_NPHASE)},
             "last_iters": inf.last_iters, "last_relres": inf.last_relres, "device_bytes": inf.device_bytes,
         }
@@ -358,6 +463,15 @@ class Preconditioner:
         Z = np.zeros(nI * p)
         _check(lib().dd_subdomain_basis(self._h, level, i, Z.ctypes.data_as(C.c_void_p)), "dd_subdomain_basis")
         return Z.reshape(p, nI).T.copy()
+
+    def eig_stats(self, level=0):
+        """dd_subdomain_eig_stats: block eigensolver iterations and final residual per subdomain."""
+        N = self.count(level)
+        it = np.zeros(N, dtype=np.int32)
+        rr = np.zeros(N)
+        _check(lib().dd_subdomain_eig_stats(self._h, level, it.ctypes.data_as(C.c_void_p),
+                                            rr.ctypes.data_as(C.c_void_p)), "dd_subdomain_eig_stats")
+        return it, rr
 
     def sigma1(self, level=0) -> np.ndarray:
         out = np.zeros(self.count(level))

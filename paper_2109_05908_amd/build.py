@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["dense.hip", "sparse.hip", "coarse.hip", "bchol.hip", "dd.hip"]
+SOURCES = ["dense.hip", "sparse.hip", "coarse.hip", "bchol.hip", "lobpcg.hip", "warm.hip", "dd.hip"]
 ARCH = os.environ.get("DD_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -47,10 +47,10 @@ def build(verbose: bool = False) -> str:
             print(r.stderr[-3000:], file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-6000:]}")

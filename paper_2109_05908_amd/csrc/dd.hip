@@ -12,6 +12,8 @@
 
 #include "bchol.hpp"
 #include "coarse.hpp"
+#include "lobpcg.hpp"
+#include "warm.hpp"
 
 namespace dd {
 
@@ -46,6 +48,7 @@ struct Timer {
     }
 };
 
+struct Model;  // warm-start network (warm.hip)
 struct Opts {
     int local_prec = DD_FP64;
     int select = DD_SEL_THRESHOLD;
@@ -53,7 +56,45 @@ struct Opts {
     int validate = 0;
     int coarsen = 64;
     int schwarz = DD_SCHWARZ_ADDITIVE;
+    int eig_solver = DD_EIG_DENSE;
+    int lobpcg_maxit = 100;
+    double lobpcg_tol = 1e-8;
+    bool lobpcg_tol_set = false;
+    int warm_start = DD_START_RANDOM;
+    uint64_t seed = 0;
+    const void* model = nullptr;
 };
+
+// dd_options -> Opts; DD_ERR_INVALID_ARG for values out of range
+static int parse_opts(const dd_options* o, Opts& out) {
+    if (!o) return DD_OK;
+    if (o->local_prec != DD_FP64 && o->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
+    if (o->select != DD_SEL_THRESHOLD && o->select != DD_SEL_THRESHOLD_CAP) return DD_ERR_INVALID_ARG;
+    if (o->select == DD_SEL_THRESHOLD_CAP && o->nev_cap < 0) return DD_ERR_INVALID_ARG;
+    if (o->schwarz != DD_SCHWARZ_ADDITIVE && o->schwarz != DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;
+    if (o->eig_solver < DD_EIG_DENSE || o->eig_solver > DD_EIG_LOBPCG_MATFREE) return DD_ERR_INVALID_ARG;
+    // the block solver computes the nev_cap wanted pairs of the cap mode (1..32 per subdomain)
+    if (o->eig_solver != DD_EIG_DENSE && (o->select != DD_SEL_THRESHOLD_CAP || o->nev_cap < 1 || o->nev_cap > 32))
+        return DD_ERR_INVALID_ARG;
+    if (o->lobpcg_maxit < 0 || !(o->lobpcg_tol >= 0.0)) return DD_ERR_INVALID_ARG;
+    if (o->warm_start < DD_START_RANDOM || o->warm_start > DD_START_MODEL) return DD_ERR_INVALID_ARG;
+    out.local_prec = o->local_prec;
+    out.select = o->select;
+    out.nev_cap = o->nev_cap;
+    out.validate = o->validate;
+    if (o->coarsen > 0) out.coarsen = o->coarsen;
+    out.schwarz = o->schwarz;
+    out.eig_solver = o->eig_solver;
+    if (o->lobpcg_maxit > 0) out.lobpcg_maxit = o->lobpcg_maxit;
+    if (o->lobpcg_tol > 0.0) {
+        out.lobpcg_tol = o->lobpcg_tol;
+        out.lobpcg_tol_set = true;
+    }
+    out.warm_start = o->warm_start;
+    out.seed = o->seed;
+    out.model = o->warm_start_model;
+    return DD_OK;
+}
 
 // Workspace of right-preconditioned GMRES on one level: Krylov basis V
 // (n x (restart + 1)), the preconditioned directions M v_j (n x restart), a
@@ -126,6 +167,8 @@ struct Level {
     DBuf<double*> dZ;
     std::vector<std::vector<double>> mu;
     std::vector<double> sigma1;
+    std::vector<int> lob_iters;      // block eigensolver: iterations and final residual per subdomain
+    std::vector<double> lob_resid;
     int64_t nC = 0;
     BlockChol E;                // block-sparse Cholesky factor of the coarse operator
     std::vector<double> Ecopy;  // small coarse operators only (inspection)
@@ -281,6 +324,230 @@ static void sets_and_extract(Level& Lv, dd_info_t& info, Timer& tm, Arena& Y, hi
     info.phase_ms[PH_EXTRACT] += tm.lap();
 }
 
+// ---------------------------------------------------------------------------
+// warm-start network (a dd_model)
+// ---------------------------------------------------------------------------
+struct Model {
+    DBuf<double> params, mean, stdv, m1, m2, grad, dloss;
+    DBuf<double> feats, target, weight;  // training samples (device)
+    int64_t ns = 0;                      // samples stored
+    int nsub = 0;                        // subdomains they came from
+    int step = 0;                        // Adam steps taken
+    bool stats = false;                  // mean / stdv fixed
+    Model() {
+        params.alloc(WS_P); m1.alloc(WS_P); m2.alloc(WS_P); grad.alloc(WS_P); dloss.alloc(1);
+        mean.alloc(WS_F); stdv.alloc(WS_F);
+    }
+};
+
+static WsMaps ws_maps(const Level& Lv) {
+    return WsMaps{Lv.A(), Lv.N, Lv.offE.p, Lv.counts.p, Lv.ext.p};
+}
+
+// Start blocks of the block eigensolver, X_i (n_Ii x k_i) into Yev.  Random: a
+// Gaussian block.  Range / model: by the near-kernel characterisation of the
+// splitting (its kernel is A_ii^{-1} A(Omega_i, Delta_i) applied to data on
+// Delta_i), X_i = L_I^T [A_ii^{-1} A(Omega_i, Delta_i) diag(w) G]_I with G
+// Gaussian on Delta_i and w = 1 (range) or the network's weight of every
+// boundary node (model); L_I^T maps the pencil's vectors to those of the
+// reciprocal form.  A subdomain with fewer boundary nodes than columns takes
+// the random block.
+static void start_blocks(Level& Lv, const Opts& opt, const std::vector<int>& kb, Arena& Yev, hipStream_t s) {
+    const int N = Lv.N;
+    const auto& ni = Lv.ni;
+    const auto& nI = Lv.nI;
+    const auto& nD = Lv.nD;
+    const Model* model = static_cast<const Model*>(opt.model);
+    const bool structured = opt.warm_start == DD_START_RANGE || (opt.warm_start == DD_START_MODEL && model);
+    std::vector<int> rnd(N, 1);
+    if (structured)
+        for (int i = 0; i < N; ++i) rnd[i] = nD[i] < kb[i];
+    auto item_seed = [&](int i, uint64_t salt) {
+        return opt.seed * 0x9E3779B97F4A7C15ull + (uint64_t)Lv.n * 0x100000001B3ull + (uint64_t)i * 2654435761ull + salt;
+    };
+    {
+        Batch<RandItem> rb;
+        for (int i = 0; i < N; ++i)
+            if (rnd[i]) rb.h.push_back(RandItem{Yev.ptr[i], nI[i], nI[i], kb[i], item_seed(i, 0)});
+        if (rb.size()) {
+            rb.sync(s);
+            gaussian_vb(rb, s);
+        }
+    }
+    if (!structured) return;
+    std::vector<int> act(N);
+    for (int i = 0; i < N; ++i) act[i] = !rnd[i];
+    std::vector<int64_t> hoffD(N + 1, 0);
+    for (int i = 0; i < N; ++i) hoffD[i + 1] = hoffD[i] + nD[i];
+    const int64_t totD = hoffD[N];
+    if (!totD) return;
+    DBuf<int64_t> offD = upload(hoffD, s);
+    const WsMaps M = ws_maps(Lv);
+    DBuf<double> w;
+    if (opt.warm_start == DD_START_MODEL) {
+        DBuf<double> smean(N), feats((size_t)totD * WS_F);
+        w.alloc(totD);
+        ws_subdomain_logdiag(M, smean.p, s);
+        ws_features(M, smean.p, offD.p, totD, feats.p, s);
+        mlp_forward(model->params.p, model->mean.p, model->stdv.p, feats.p, totD, w.p, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    Arena G, B;
+    std::vector<int64_t> sg(N), sb(N);
+    for (int i = 0; i < N; ++i) {
+        sg[i] = (int64_t)std::max(1, nD[i]) * kb[i];
+        sb[i] = (int64_t)ni[i] * kb[i];
+    }
+    G.alloc(sg);
+    B.alloc(sb);
+    {
+        Batch<RandItem> rb;
+        for (int i = 0; i < N; ++i)
+            if (act[i]) rb.h.push_back(RandItem{G.ptr[i], nD[i], nD[i], kb[i], item_seed(i, 0x5bd1e995ull)});
+        rb.sync(s);
+        gaussian_vb(rb, s);
+    }
+    DBuf<double*> dG(N), dB(N);
+    h2d(dG.p, G.ptr.data(), N, s);
+    h2d(dB.p, B.ptr.data(), N, s);
+    std::vector<int32_t> kc(N);
+    for (int i = 0; i < N; ++i) kc[i] = act[i] ? kb[i] : 0;  // random items: no columns
+    DBuf<int32_t> dk = upload(kc, s);
+    ws_range_product(M, Lv.offO.p, Lv.hoffO[N], offD.p, w.p, dG.p, dB.p, dk.p, s);
+    // U = A_ii^{-1} B by the local Cholesky factor, then X = L_I^T U_I
+    Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s, &act);
+    Batch<DMat> Bb = mats(B.ptr, ni, ni, kb, s, &act);
+    trsm_vb(Lb, Bb, false, s);
+    trsm_vb(Lb, Bb, true, s);
+    Batch<GemmItem> g;
+    for (int i = 0; i < N; ++i)
+        if (act[i]) g.h.push_back(GemmItem{Lv.L.ptr[i], ni[i], B.ptr[i], ni[i], Yev.ptr[i], nI[i], nI[i], kb[i], nI[i], 1.0, 0.0});
+    g.sync(s);
+    gemm_vb(g, true, false, s);
+    // a weighted block can be numerically rank-deficient (weight on a few boundary
+    // nodes, or an exactly zero column): every column gets a Gaussian component of
+    // relative size 1e-10, above the level at which the start block's
+    // orthonormalisation drops a direction (1e-13), so the block stays full rank
+    // while its useful directions are untouched
+    Arena Gr;
+    std::vector<int64_t> sr(N);
+    for (int i = 0; i < N; ++i) sr[i] = act[i] ? (int64_t)nI[i] * kb[i] : 1;
+    Gr.alloc(sr);
+    {
+        Batch<RandItem> rb;
+        Batch<MixItem> mb;
+        for (int i = 0; i < N; ++i) {
+            if (!act[i]) continue;
+            rb.h.push_back(RandItem{Gr.ptr[i], nI[i], nI[i], kb[i], item_seed(i, 0x27d4eb2full)});
+            mb.h.push_back(MixItem{Yev.ptr[i], Gr.ptr[i], nI[i], kb[i], 1e-10});
+        }
+        rb.sync(s);
+        mb.sync(s);
+        gaussian_vb(rb, s);
+        mix_random_vb(mb, s);
+    }
+    DD_HIP(hipStreamSynchronize(s));
+}
+
+// (3.3) in cap mode by the block solver.  With Boolean D_i the wanted pairs are
+// the nev smallest mu of S~ = L_I^{-1} S_I L_I^{-T} (reciprocal form), i.e. the
+// nev largest lambda of K = S~^{-1}.  The QR of the permuted factor was taken
+// over every column, so S_I = R_II^T R_II with R_II upper triangular, and
+// K = M^T M with M = R_II^{-T} L_I (lower triangular): either formed (one
+// triangular solve) or, matrix-free, applied as L_I^T R_II^{-1} R_II^{-T} L_I.
+// The largest lambda are well separated (they grow like 1/s towards the near
+// kernel), so LOBPCG on K converges in a few iterations.  The kept mu are the
+// Rayleigh quotients of S~ itself, mu_j = ||R_II L_I^{-T} y_j||^2, which are
+// accurate to eps in absolute terms (the lambda form only to eps ||K||).
+// Output as the dense route's: Yev (n_Ii x p_i, orthonormal, mu ascending),
+// Lv.p, Lv.mu.
+static void eigen_lobpcg(Level& Lv, const Opts& opt, dd_info_t& info, Arena& Fp, const std::vector<int>& nc,
+                         Arena& Yev, hipStream_t s) {
+    const int N = Lv.N;
+    const auto& nt = Lv.nt;
+    const auto& ni = Lv.ni;
+    const auto& nI = Lv.nI;
+    const bool mf = opt.eig_solver == DD_EIG_LOBPCG_MATFREE;
+    const int nev = opt.nev_cap;
+    constexpr int kGuard = 8;  // block size nev + 8: the guard vectors speed up the last wanted pairs
+    std::vector<int> kb(N);
+    std::vector<int64_t> sI2(N), sk(N), skk(N);
+    for (int i = 0; i < N; ++i) {
+        kb[i] = std::min(nI[i], nev + kGuard);
+        sI2[i] = (int64_t)nI[i] * nI[i];
+        sk[i] = (int64_t)nI[i] * kb[i];
+        skk[i] = kb[i];
+    }
+    // RL = R_II^T (lower); R_II sits at rows and columns [nc, nt) of the factored Fp
+    Arena RL;
+    RL.alloc(sI2);
+    {
+        std::vector<double*> rii(N);
+        for (int i = 0; i < N; ++i) rii[i] = Fp.ptr[i] + nc[i] + (int64_t)nc[i] * nt[i];
+        Batch<DMat> Rsrc = mats(rii, nt, nI, nI, s);
+        Batch<DMat> Rb = mats(RL.ptr, nI, nI, nI, s);
+        copy_vb(Rsrc, Rb, true, 1.0, s);
+        zero_upper_vb(Rb, s);  // the reflectors below R_II's diagonal land above RL's
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    Fp.release();
+    Batch<DMat> LI = mats(Lv.L.ptr, ni, nI, nI, s);
+    Batch<DMat> RLb = mats(RL.ptr, nI, nI, nI, s);
+    Arena Mx;
+    if (!mf) {
+        Mx.alloc(sI2);
+        Batch<DMat> Mb = mats(Mx.ptr, nI, nI, nI, s);
+        copy_vb(LI, Mb, false, 1.0, s);
+        trsm_vb(RLb, Mb, false, s, true);  // M = RL^{-1} L_I, lower triangular
+    }
+    // start blocks
+    Yev.alloc(sk);
+    start_blocks(Lv, opt, kb, Yev, s);
+    Arena th;
+    th.alloc(skk);
+    std::vector<LobItem> items(N);
+    for (int i = 0; i < N; ++i)
+        items[i] = LobItem{nI[i], kb[i], std::min(nev, kb[i]), mf ? nullptr : Mx.ptr[i], nI[i], Lv.L.ptr[i], ni[i],
+                           RL.ptr[i], nI[i], Yev.ptr[i], th.ptr[i]};
+    LobStats st;
+    // the matrix-free form tests an absolute residual of S~ (norm <= 1): a tighter default
+    const double tol = (mf && !opt.lobpcg_tol_set) ? 1e-12 : opt.lobpcg_tol;
+    lobpcg_vb(items, mf, tol, opt.lobpcg_maxit, s, st);
+    Mx.release();
+    info.eig_maxit_hits += st.maxit_hits;
+    Lv.lob_iters = st.iters;
+    Lv.lob_resid = st.resid;
+    // mu_j = ||R_II L_I^{-T} y_j||^2
+    Arena T1, T2, mu;
+    T1.alloc(sk);
+    T2.alloc(sk);
+    mu.alloc(skk);
+    {
+        Batch<DMat> Ys = mats(Yev.ptr, nI, nI, kb, s), Tb = mats(T1.ptr, nI, nI, kb, s);
+        copy_vb(Ys, Tb, false, 1.0, s);
+        trsm_vb(LI, Tb, true, s);
+        Batch<GemmItem> g;
+        for (int i = 0; i < N; ++i)
+            g.h.push_back(GemmItem{RL.ptr[i], nI[i], T1.ptr[i], nI[i], T2.ptr[i], nI[i], nI[i], kb[i], nI[i], 1.0, 0.0});
+        g.sync(s);
+        gemm_vb(g, true, false, s);
+        Batch<ColItem> cb;
+        for (int i = 0; i < N; ++i) cb.h.push_back(ColItem{T2.ptr[i], nI[i], nI[i], kb[i], mu.ptr[i]});
+        cb.sync(s);
+        colnorm2_vb(cb, s);
+    }
+    const auto hmu = to_host(mu.buf.p, mu.buf.n, s);
+    Lv.p.assign(N, 0);
+    Lv.mu.assign(N, {});
+    for (int i = 0; i < N; ++i) {
+        const double* m = hmu.data() + (mu.ptr[i] - mu.buf.p);
+        int p = 0;
+        while (p < std::min(nev, kb[i]) && m[p] < Lv.tau) ++p;  // prefix: mu ascending, keep mu < tau
+        Lv.p[i] = p;
+        Lv.mu[i].assign(m, m + p);
+    }
+}
+
 // `next` (nullable): when given, E is not factored but handed to the next
 // level as its CSR matrix (multilevel recursion).
 static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t s, Level* next) {
@@ -289,6 +556,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     const CsrDev A = Lv.A();
     Arena Y;
     sets_and_extract(Lv, info, tm, Y, s);
+    const bool lob = opt.eig_solver != DD_EIG_DENSE;
     const auto& ni = Lv.ni;
     const auto& nt = Lv.nt;
     const auto& nI = Lv.nI;
@@ -626,23 +894,31 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         copy_vb(sI, dI, true, 1.0, s);
         DD_HIP(hipStreamSynchronize(s));
         Ft.release();
+        // the block eigensolver needs S_I = R_II^T R_II with R_II triangular: the QR
+        // then factors every column (the trailing n_Ii columns too)
+        std::vector<int> nfac(N);
+        for (int i = 0; i < N; ++i) nfac[i] = lob ? nt[i] : nc[i];
         Arena ft, fT, fW, fG;
         std::vector<int64_t> a1(N), a2(N), a3(N), a4(N);
         for (int i = 0; i < N; ++i) {
             a1[i] = nt[i];
-            a2[i] = qr_t_size(std::max(1, nc[i]));
+            a2[i] = qr_t_size(std::max(1, nfac[i]));
             a3[i] = qr_w_size(nt[i]);
-            a4[i] = qr_g_size(std::max(1, nc[i]));
+            a4[i] = qr_g_size(std::max(1, nfac[i]));
         }
         ft.alloc(a1); fT.alloc(a2); fW.alloc(a3); fG.alloc(a4);
         Batch<QRItem> qb;
         for (int i = 0; i < N; ++i)
-            qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB, nc[i], fG.ptr[i]});
+            qb.h.push_back(QRItem{DMat{Fp.ptr[i], nt[i], nt[i], nt[i]}, ft.ptr[i], fT.ptr[i], fW.ptr[i], QR_NB, nfac[i], fG.ptr[i]});
         qb.sync(s);
         geqrf_vb(qb, s);
     }
     info.phase_ms[PH_SCHUR] += tm.lap();
 
+    Arena Yev;
+    if (lob) {
+        eigen_lobpcg(Lv, opt, info, Fp, nc, Yev, s);
+    } else {
     // ---- (3.3) reciprocal form: B2 = L_I^{-1} R_II^T, S~ = B2 B2^T, eigenpairs mu < tau --------
     Arena B2, Sm;
     std::vector<int64_t> sI2(N);
@@ -707,7 +983,6 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         d2h(Lv.mu[i].data(), tmu.ptr[i], Lv.p[i], s);
     }
     DD_HIP(hipStreamSynchronize(s));
-    Arena Yev;
     {
         std::vector<int64_t> sy(N), sw(N);
         for (int i = 0; i < N; ++i) {
@@ -749,6 +1024,7 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         DD_HIP(hipStreamSynchronize(s));
     }
     Sm.release();
+    }
     info.phase_ms[PH_EIG] += tm.lap();
 
     // ---- Z_i = orth(L_I^{-T} Y_keep)  (D_i u with Boolean D_i) --------------------------------
@@ -2040,6 +2316,18 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
         I.p_hist[b] += 1;
     }
     I.k_c = 0;  // computed at the first dd_info call
+    I.eig_iters_max = 0;
+    I.eig_iters_mean = 0.0;
+    I.eig_resid_max = 0.0;
+    if ((int)L0.lob_iters.size() == N && N > 0) {
+        double sum = 0.0;
+        for (int i = 0; i < N; ++i) {
+            I.eig_iters_max = std::max(I.eig_iters_max, L0.lob_iters[i]);
+            sum += L0.lob_iters[i];
+            I.eig_resid_max = std::max(I.eig_resid_max, L0.lob_resid[i]);
+        }
+        I.eig_iters_mean = sum / N;
+    }
     if (!H.partial.p) {
         const int w = std::max(64, H.nsys());
         H.partial.alloc((int64_t)512 * w);
@@ -2067,17 +2355,7 @@ int dd_setup(const dd_csr* A, const int32_t* part, int32_t N, int32_t overlap, d
         return DD_ERR_INVALID_ARG;
     auto hd = std::make_unique<dd_handle_s>();
     Handle& H = hd->h;
-    if (opt) {
-        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
-        H.opt.local_prec = opt->local_prec;
-        H.opt.select = opt->select;
-        H.opt.nev_cap = opt->nev_cap;
-        H.opt.validate = opt->validate;
-        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
-        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
-        if (opt->schwarz != DD_SCHWARZ_ADDITIVE && opt->schwarz != DD_SCHWARZ_DEFLATED) return DD_ERR_INVALID_ARG;
-        H.opt.schwarz = opt->schwarz;
-    }
+    if (parse_opts(opt, H.opt) != DD_OK) return DD_ERR_INVALID_ARG;
     const int rc = build_handle(H, A->n, A->nnz, A->rowptr, A->colind, A->val, part, N, overlap, tau, levels, s);
     if (rc < 0) return rc;
     *out = hd.release();
@@ -2173,17 +2451,9 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
         return DD_ERR_INVALID_ARG;
     auto hd = std::make_unique<dd_handle_s>();
     Handle& H = hd->h;
-    if (opt) {
-        if (opt->local_prec != DD_FP64 && opt->local_prec != DD_FP32) return DD_ERR_INVALID_ARG;
-        H.opt.local_prec = opt->local_prec;
-        H.opt.select = opt->select;
-        H.opt.nev_cap = opt->nev_cap;
-        H.opt.validate = opt->validate;
-        if (opt->coarsen > 0) H.opt.coarsen = opt->coarsen;
-        if (opt->select == DD_SEL_THRESHOLD_CAP && opt->nev_cap < 0) return DD_ERR_INVALID_ARG;
-        // the deflated variant needs GMRES, which has no per-system form: refused for a batch
-        if (opt->schwarz != DD_SCHWARZ_ADDITIVE) return DD_ERR_INVALID_ARG;
-    }
+    if (parse_opts(opt, H.opt) != DD_OK) return DD_ERR_INVALID_ARG;
+    // the deflated variant needs GMRES, which has no per-system form: refused for a batch
+    if (H.opt.schwarz != DD_SCHWARZ_ADDITIVE) return DD_ERR_INVALID_ARG;
     // every system's own CSR structure is checked before the union shifts its
     // indices (an out-of-range column must not land inside another system)
     if (H.opt.validate) {
@@ -2226,6 +2496,261 @@ int dd_setup_batch(const dd_csr* As, const int32_t* const* parts, const int32_t*
     *out = hd.release();
     return rc;
     DD_GUARD_END
+}
+
+// ---------------------------------------------------------------------------
+// warm-start network
+// ---------------------------------------------------------------------------
+struct dd_model_s {
+    Model m;
+};
+
+static Level* level_of(dd_handle h, int32_t level) {
+    if (!h || level < 0 || level >= (int)h->h.lv.size()) return nullptr;
+    return h->h.lv[level].get();
+}
+
+int dd_model_create(uint64_t seed, dd_model* out) {
+    DD_GUARD_BEGIN
+    if (!out) return DD_ERR_INVALID_ARG;
+    *out = nullptr;
+    auto md = std::make_unique<dd_model_s>();
+    // Glorot-scaled normal weights from a SplitMix64 stream (Box-Muller),
+    // zero biases, output bias softplus^{-1}(1) so that every weight starts at 1
+    std::vector<double> p(WS_P, 0.0);
+    uint64_t k = 0;
+    auto draw = [&]() {
+        auto mix = [&](uint64_t c) {
+            uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            return z ^ (z >> 31);
+        };
+        const double u1 = ((mix(k) >> 11) + 1.0) * 0x1.0p-53, u2 = (mix(k + 1) >> 11) * 0x1.0p-53;
+        k += 2;
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    };
+    int o = 0;
+    for (int i = 0; i < WS_H * WS_F; ++i) p[o++] = draw() * std::sqrt(1.0 / WS_F);
+    o += WS_H;
+    for (int i = 0; i < WS_H * WS_H; ++i) p[o++] = draw() * std::sqrt(1.0 / WS_H);
+    o += WS_H;
+    for (int i = 0; i < WS_H; ++i) p[o++] = draw() * std::sqrt(1.0 / WS_H) * 0.1;
+    p[o] = std::log(std::exp(1.0) - 1.0);
+    Model& M = md->m;
+    h2d(M.params.p, p.data(), WS_P, nullptr);
+    std::vector<double> zero(WS_P, 0.0), one(WS_F, 1.0);
+    h2d(M.m1.p, zero.data(), WS_P, nullptr);
+    h2d(M.m2.p, zero.data(), WS_P, nullptr);
+    h2d(M.mean.p, zero.data(), WS_F, nullptr);
+    h2d(M.stdv.p, one.data(), WS_F, nullptr);
+    DD_HIP(hipStreamSynchronize(nullptr));
+    *out = md.release();
+    return DD_OK;
+    DD_GUARD_END
+}
+
+void dd_model_destroy(dd_model m) { delete m; }
+
+int dd_model_add_samples(dd_model md, dd_handle h, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!md || !h || h->h.lv.empty()) return DD_ERR_INVALID_ARG;
+    Level& Lv = *h->h.lv[0];
+    if (Lv.fp32 || !Lv.W.buf.p) return DD_ERR_INVALID_ARG;  // needs the FP64 local inverses
+    Model& M = md->m;
+    const int N = Lv.N;
+    const auto& ni = Lv.ni;
+    const auto& nI = Lv.nI;
+    const auto& nD = Lv.nD;
+    std::vector<int> act(N);
+    std::vector<int64_t> hoffD(N + 1, 0);
+    int nsub = 0;
+    for (int i = 0; i < N; ++i) {
+        if (Lv.p[i] > JAC_MAX) return DD_ERR_INVALID_ARG;  // the basis of the target needs p_i <= 128
+        act[i] = Lv.p[i] > 0 && nD[i] > 0;
+        hoffD[i + 1] = hoffD[i] + (act[i] ? nD[i] : 0);
+        nsub += act[i];
+    }
+    const int64_t tot = hoffD[N];
+    if (!tot) return DD_OK;
+    // U_i = A_ii^{-1} [Z_i; 0] = W_i^T W_i [Z_i; 0]
+    Arena U0, U1, Gt, Q;
+    std::vector<int64_t> su(N), sg(N);
+    for (int i = 0; i < N; ++i) {
+        su[i] = act[i] ? (int64_t)ni[i] * Lv.p[i] : 1;
+        sg[i] = act[i] ? (int64_t)nD[i] * Lv.p[i] : 1;
+    }
+    U0.alloc(su); U1.alloc(su); Gt.alloc(sg); Q.alloc(sg);
+    fill(U0.buf.p, U0.buf.n, 0.0, s);
+    {
+        std::vector<double*> zp(Lv.Z.ptr.begin(), Lv.Z.ptr.end());
+        Batch<DMat> Zs = mats(zp, nI, nI, Lv.p, s, &act), Zd = mats(U0.ptr, ni, nI, Lv.p, s, &act);
+        copy_vb(Zs, Zd, false, 1.0, s);
+        Batch<GemmItem> g1, g2;
+        for (int i = 0; i < N; ++i) {
+            if (!act[i]) continue;
+            g1.h.push_back(GemmItem{Lv.W.ptr[i], ni[i], U0.ptr[i], ni[i], U1.ptr[i], ni[i], ni[i], Lv.p[i], ni[i], 1.0, 0.0});
+            g2.h.push_back(GemmItem{Lv.W.ptr[i], ni[i], U1.ptr[i], ni[i], U0.ptr[i], ni[i], ni[i], Lv.p[i], ni[i], 1.0, 0.0});
+        }
+        g1.sync(s);
+        g2.sync(s);
+        gemm_vb(g1, false, false, s);
+        gemm_vb(g2, true, false, s);
+    }
+    // Gt_i = A(Delta_i, Omega_i) U_i; target^2 = (row leverage of orth(Gt_i)) * |Delta_i| / p_i
+    DBuf<int64_t> offD = upload(hoffD, s);
+    std::vector<int32_t> pc(N);
+    for (int i = 0; i < N; ++i) pc[i] = act[i] ? Lv.p[i] : 0;
+    DBuf<int32_t> dpc = upload(pc, s);
+    DBuf<double*> dU(N), dG(N);
+    h2d(dU.p, U0.ptr.data(), N, s);
+    h2d(dG.p, Gt.ptr.data(), N, s);
+    // a level's own offsets of Delta (all subdomains) are needed by the kernel: inactive ones have 0 rows
+    const WsMaps WM = ws_maps(Lv);
+    {
+        // the kernel walks rows offD[i] .. offD[i+1] of subdomain i; for an inactive
+        // subdomain that range is empty, so its Delta count in the maps is never used
+        ws_adjoint_product(WM, offD.p, tot, dU.p, dG.p, dpc.p, s);
+    }
+    std::vector<OrthItem> oi;
+    for (int i = 0; i < N; ++i)
+        if (act[i]) oi.push_back(OrthItem{Gt.ptr[i], nD[i], Lv.p[i], Q.ptr[i]});
+    orth_basis_vb(oi, s);
+    DBuf<double> lev(tot), feats((size_t)tot * WS_F), smean(N);
+    {
+        Batch<RowItem> rb;
+        for (int i = 0; i < N; ++i)
+            if (act[i])
+                rb.h.push_back(RowItem{Q.ptr[i], nD[i], nD[i], Lv.p[i], lev.p + hoffD[i], (double)nD[i] / Lv.p[i]});
+        rb.sync(s);
+        ws_row_leverage(rb, s);
+    }
+    ws_subdomain_logdiag(WM, smean.p, s);
+    ws_features(WM, smean.p, offD.p, tot, feats.p, s);
+    auto hl = to_host(lev.p, tot, s);
+    std::vector<double> ht(tot), hw(tot);
+    for (int i = 0; i < N; ++i)
+        for (int64_t e = hoffD[i]; e < hoffD[i + 1]; ++e) {
+            ht[e] = std::sqrt(std::max(0.0, hl[e]));
+            hw[e] = 1.0 / (double)(hoffD[i + 1] - hoffD[i]);
+        }
+    // append to the store
+    const int64_t n0 = M.ns, n1 = n0 + tot;
+    auto grow = [&](DBuf<double>& b, int64_t per) {
+        DBuf<double> nb((size_t)n1 * per);
+        if (n0) DD_HIP(hipMemcpyAsync(nb.p, b.p, (size_t)n0 * per * sizeof(double), hipMemcpyDeviceToDevice, s));
+        DD_HIP(hipStreamSynchronize(s));
+        b = std::move(nb);
+    };
+    grow(M.feats, WS_F);
+    grow(M.target, 1);
+    grow(M.weight, 1);
+    DD_HIP(hipMemcpyAsync(M.feats.p + n0 * WS_F, feats.p, (size_t)tot * WS_F * sizeof(double), hipMemcpyDeviceToDevice, s));
+    h2d(M.target.p + n0, ht.data(), tot, s);
+    h2d(M.weight.p + n0, hw.data(), tot, s);
+    DD_HIP(hipStreamSynchronize(s));
+    M.ns = n1;
+    M.nsub += nsub;
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_train(dd_model md, int32_t epochs, double lr, double* loss, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!md || epochs < 0 || !(lr > 0.0)) return DD_ERR_INVALID_ARG;
+    Model& M = md->m;
+    if (M.ns == 0) return DD_ERR_INVALID_ARG;
+    if (!M.stats) {
+        ws_feature_stats(M.feats.p, M.ns, M.mean.p, M.stdv.p, s);
+        M.stats = true;
+    }
+    const double scale = 1.0 / std::max(1, M.nsub);  // mean over subdomains of each one's mean square error
+    for (int e = 0; e < epochs; ++e) {
+        mlp_loss_grad(M.params.p, M.mean.p, M.stdv.p, M.feats.p, M.target.p, M.weight.p, M.ns, M.grad.p, M.dloss.p, s);
+        mlp_adam(M.params.p, M.grad.p, M.m1.p, M.m2.p, lr, ++M.step, s);
+        if (loss) {
+            double l = 0.0;
+            d2h(&l, M.dloss.p, 1, s);
+            DD_HIP(hipStreamSynchronize(s));
+            loss[e] = l * scale;
+        }
+    }
+    DD_HIP(hipStreamSynchronize(s));
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_params(dd_model md, double* out, int32_t* count) {
+    DD_GUARD_BEGIN
+    if (!md) return DD_ERR_INVALID_ARG;
+    if (count) *count = WS_P + 2 * WS_F;
+    if (out) {
+        d2h(out, md->m.params.p, WS_P, nullptr);
+        d2h(out + WS_P, md->m.mean.p, WS_F, nullptr);
+        d2h(out + WS_P + WS_F, md->m.stdv.p, WS_F, nullptr);
+        DD_HIP(hipStreamSynchronize(nullptr));
+    }
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_set_params(dd_model md, const double* in, int32_t count) {
+    DD_GUARD_BEGIN
+    if (!md || !in || count != WS_P + 2 * WS_F) return DD_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i)
+        if (!std::isfinite(in[i])) return DD_ERR_NAN;
+    for (int f = 0; f < WS_F; ++f)
+        if (!(in[WS_P + WS_F + f] > 0.0)) return DD_ERR_INVALID_ARG;
+    h2d(md->m.params.p, in, WS_P, nullptr);
+    h2d(md->m.mean.p, in + WS_P, WS_F, nullptr);
+    h2d(md->m.stdv.p, in + WS_P + WS_F, WS_F, nullptr);
+    DD_HIP(hipStreamSynchronize(nullptr));
+    md->m.stats = true;
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_forward(dd_model md, const double* feats, int64_t n, double* out, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!md || n < 0 || (n > 0 && (!feats || !out))) return DD_ERR_INVALID_ARG;
+    mlp_forward(md->m.params.p, md->m.mean.p, md->m.stdv.p, feats, n, out, s);
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_loss_grad(dd_model md, const double* feats, const double* target, const double* weight, int64_t n,
+                       double* loss, double* grad, hipStream_t s) {
+    DD_GUARD_BEGIN
+    if (!md || n < 1 || !feats || !target || !weight) return DD_ERR_INVALID_ARG;
+    Model& M = md->m;
+    mlp_loss_grad(M.params.p, M.mean.p, M.stdv.p, feats, target, weight, n, M.grad.p, M.dloss.p, s);
+    if (loss) d2h(loss, M.dloss.p, 1, s);
+    if (grad) d2h(grad, M.grad.p, WS_P, s);
+    DD_HIP(hipStreamSynchronize(s));
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_model_samples(dd_model md, int64_t* n, double* feats, double* target, double* weight) {
+    DD_GUARD_BEGIN
+    if (!md) return DD_ERR_INVALID_ARG;
+    const Model& M = md->m;
+    if (n) *n = M.ns;
+    if (feats) d2h(feats, M.feats.p, (size_t)M.ns * WS_F, nullptr);
+    if (target) d2h(target, M.target.p, M.ns, nullptr);
+    if (weight) d2h(weight, M.weight.p, M.ns, nullptr);
+    DD_HIP(hipStreamSynchronize(nullptr));
+    return DD_OK;
+    DD_GUARD_END
+}
+
+int dd_subdomain_eig_stats(dd_handle h, int32_t level, int32_t* iters, double* resid) {
+    Level* L = level_of(h, level);
+    if (!L) return DD_ERR_INVALID_ARG;
+    if ((int)L->lob_iters.size() != L->N) return DD_ERR_INVALID_ARG;  // dense route: no iterations
+    if (iters) std::copy(L->lob_iters.begin(), L->lob_iters.end(), iters);
+    if (resid) std::copy(L->lob_resid.begin(), L->lob_resid.end(), resid);
+    return DD_OK;
 }
 
 int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t s) {
@@ -2328,10 +2853,6 @@ int dd_info(dd_handle h, dd_info_t* out) {
 
 void dd_destroy(dd_handle h) { delete h; }
 
-static Level* level_of(dd_handle h, int32_t level) {
-    if (!h || level < 0 || level >= (int)h->h.lv.size()) return nullptr;
-    return h->h.lv[level].get();
-}
 
 int dd_subdomain_count(dd_handle h, int32_t level, int32_t* N) {
     Level* L = level_of(h, level);
