@@ -90,7 +90,12 @@ typedef struct {
                              eigenvalue of K = S~^{-1} (above its rounding floor; 0: 1e-8); DD_EIG_LOBPCG_MATFREE,
                              absolute residual of S~, whose norm is <= 1 (0: 1e-12) */
     int32_t warm_start;   /* LOBPCG start block: DD_START_RANDOM (default), DD_START_RANGE or DD_START_MODEL */
-    int32_t reserved0;
+    int32_t graph_pcg;    /* 1..64: dd_pcg on a two-level additive handle with one system runs each iteration
+                             as one captured HIP graph (alpha, beta and the stopping test on the device),
+                             replayed in batches of at most graph_pcg between host checks, each batch sized from
+                             the residual contraction so that few iterations run past the stop; the iterates are
+                             those of the host-driven loop, bit for bit.  0 (default): host-driven.  Other
+                             handles ignore it. */
     uint64_t seed;        /* seed of the Gaussian draws of the start blocks */
     const void* warm_start_model; /* DD_START_MODEL: a dd_model (dd_model_create); NULL falls back to random */
     int32_t reserved[8];
@@ -365,6 +370,19 @@ typedef struct {
 } dd_meter_t;
 int dd_meter_start(const char* kernel);
 int dd_meter_read(dd_meter_t* out);
+
+/* ---- launch-mapping autotuner ----------------------------------------------
+ * Every batched tile launch (all subdomains of a level in one launch) picks how
+ * its tiles map onto workgroups: static round-robin, XCD-chunked, or a
+ * persistent work queue (a device counter; items ordered by decreasing tile
+ * count, longest first), each at a grid cap.  The library tries the candidates
+ * on the launches of every kernel family as they come, times them with events,
+ * and keeps the fastest per tile after three samples each.  The mapping never
+ * changes a result (every tile is computed once, by one workgroup, with the same
+ * arithmetic).  DD_AUTOTUNE=0 in the environment (read once) switches it off.
+ * Writes a text table of the candidates (mean microseconds per tile, samples;
+ * the chosen one starred) into buf (may be NULL) and returns its length. */
+int dd_autotune_report(char* buf, int64_t len);
 
 #ifdef __cplusplus
 }

@@ -10,5 +10,5 @@ from .binding import (  # noqa: F401
     DD_EIG_DENSE, DD_EIG_LOBPCG, DD_EIG_LOBPCG_MATFREE, DD_FP32, DD_FP64, DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED,
     DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP, DD_START_MODEL, DD_START_RANDOM, DD_START_RANGE, DDError,
     DeviceCSR, Preconditioner, WarmStartModel,
-    extract_local, lib, library_path, meter_read, meter_start, partition_ggg, trim_device_cache,
+    autotune_report, extract_local, lib, library_path, meter_read, meter_start, partition_ggg, trim_device_cache,
 )

@@ -40,16 +40,17 @@ class _Opts(C.Structure):
     _fields_ = [("local_prec", C.c_int32), ("select", C.c_int32), ("nev_cap", C.c_int32),
                 ("validate", C.c_int32), ("coarsen", C.c_int32), ("schwarz", C.c_int32),
                 ("eig_solver", C.c_int32), ("lobpcg_maxit", C.c_int32), ("lobpcg_tol", C.c_double),
-                ("warm_start", C.c_int32), ("reserved0", C.c_int32), ("seed", C.c_uint64),
+                ("warm_start", C.c_int32), ("graph_pcg", C.c_int32), ("seed", C.c_uint64),
                 ("warm_start_model", C.c_void_p), ("reserved", C.c_int32 * 8)]
 
 
 def _opts(local_prec=0, select=0, nev_cap=0, validate=False, coarsen=0, schwarz=0, eig_solver=0, lobpcg_maxit=0,
-          lobpcg_tol=0.0, warm_start=0, seed=0, model=None):
+          lobpcg_tol=0.0, warm_start=0, seed=0, model=None, graph_pcg=0):
     o = _Opts()
     o.local_prec, o.select, o.nev_cap, o.validate = local_prec, select, nev_cap, int(validate)
     o.coarsen, o.schwarz, o.eig_solver, o.lobpcg_maxit = int(coarsen), int(schwarz), int(eig_solver), int(lobpcg_maxit)
     o.lobpcg_tol, o.warm_start, o.seed = float(lobpcg_tol), int(warm_start), int(seed)
+    o.graph_pcg = int(graph_pcg)
     o.warm_start_model = model._h if model is not None else None
     return o
 
@@ -78,6 +79,14 @@ def meter_read() -> dict:
     m = _Meter()
     _check(lib().dd_meter_read(C.byref(m)), "dd_meter_read")
     return {"launches": m.launches, "total_ms": m.total_ms, "flops": m.flops, "bytes": m.bytes}
+
+
+def autotune_report() -> str:
+    """dd_autotune_report: the launch-mapping candidates per kernel family (chosen one starred)."""
+    n = lib().dd_autotune_report(None, 0)
+    buf = C.create_string_buffer(max(1, n) + 1)
+    lib().dd_autotune_report(buf, len(buf))
+    return buf.value.decode()
 
 
 def library_path() -> str:
@@ -130,6 +139,7 @@ def lib():
         "dd_coarse_matrix": ([vp, i32, vp, i64], i32),
         "dd_meter_start": ([C.c_char_p], i32),
         "dd_meter_read": ([P(_Meter)], i32),
+        "dd_autotune_report": ([C.c_char_p, i64], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -145,7 +155,7 @@ def exported_symbols() -> list[str]:
             "dd_subdomain_eigs", "dd_subdomain_basis", "dd_subdomain_sigma1", "dd_coarse_matrix", "dd_extract_local",
             "dd_subdomain_eig_stats", "dd_model_create", "dd_model_add_samples", "dd_model_train", "dd_model_params",
             "dd_model_set_params", "dd_model_forward", "dd_model_loss_grad", "dd_model_samples", "dd_model_destroy",
-            "dd_meter_start", "dd_meter_read"]
+            "dd_meter_start", "dd_meter_read", "dd_autotune_report"]
 
 
 def _stream():
@@ -290,13 +300,13 @@ class Preconditioner:
                  local_prec: int = DD_FP64, select: int = DD_SEL_THRESHOLD, nev_cap: int = 0,
                  validate: bool = False, coarsen: int = 0, schwarz: int = DD_SCHWARZ_ADDITIVE,
                  eig_solver: int = DD_EIG_DENSE, lobpcg_maxit: int = 0, lobpcg_tol: float = 0.0,
-                 warm_start: int = DD_START_RANDOM, seed: int = 0, model=None):
+                 warm_start: int = DD_START_RANDOM, seed: int = 0, model=None, graph_pcg: int = 0):
         import torch
         self.A = A
         self.n = A.n
         part = torch.as_tensor(part, dtype=torch.int32).to(A.val.device)
         opts = _opts(local_prec, select, nev_cap, validate, coarsen, schwarz, eig_solver, lobpcg_maxit, lobpcg_tol,
-                     warm_start, seed, model)
+                     warm_start, seed, model, graph_pcg)
         self._model = model
         h = C.c_void_p()
         cs = A.cstruct()

@@ -194,12 +194,77 @@ struct XcdChunked {
     static constexpr bool value = false;
 };
 
+// Mapping of the tiles of one launch onto its workgroups (every mapping runs
+// each tile once, by one workgroup, with the same arithmetic: the results do
+// not depend on it).  TM_STATIC: workgroup g takes tiles g, g + G, ...;
+// TM_XCD: the XCD-chunked order above; TM_LPT: a persistent work queue, every
+// workgroup takes the next tile from a device counter until none is left, the
+// items ordered by decreasing tile count (longest processing time first), so
+// that the large subdomains start first and the small ones fill the end.
+enum TileMode { TM_STATIC = 0, TM_XCD = 1, TM_LPT = 2 };
+
+constexpr int kLptItems = 256;  // the queue mode sorts at most this many items (small LDS footprint)
 template <class Op>
-__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base) {
+__device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, int* counter, int* pre) {
+    __shared__ int cnt[kLptItems], perm[kLptItems];
+    __shared__ int tnext;
+    int P = 1;
+    while (P < nitems) P <<= 1;
+    for (int b = threadIdx.x; b < P; b += blockDim.x) {
+        cnt[b] = b < nitems ? op.tiles(base + b) : -1;
+        perm[b] = b;
+    }
+    __syncthreads();
+    // bitonic sort of (count descending, item ascending)
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int ci = cnt[i], cl = cnt[l], pi = perm[i], pl = perm[l];
+                    const bool i_first = ci > cl || (ci == cl && pi < pl);  // i before l in the wanted order
+                    const bool up = (i & k) == 0;
+                    if (up != i_first) {
+                        cnt[i] = cl; cnt[l] = ci;
+                        perm[i] = pl; perm[l] = pi;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        int run = 0;
+        pre[0] = 0;
+        for (int q = 0; q < nitems; ++q) {
+            run += cnt[q];
+            pre[q + 1] = run;
+        }
+    }
+    __syncthreads();
+    const int total = pre[nitems];
+    for (;;) {
+        if (threadIdx.x == 0) tnext = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tnext;
+        __syncthreads();
+        if (t >= total) break;
+        const int q = find_item(pre, nitems, t);
+        op(base + perm[q], t - pre[q]);
+        __syncthreads();
+    }
+}
+
+template <class Op>
+__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base, int mode, int* counter) {
     __shared__ int pre[kMaxItems + 1];
+    if (mode == TM_LPT && nitems <= kLptItems) {
+        tiles_lpt(op, nitems, base, counter, pre);
+        return;
+    }
     const int total = item_prefix(op, nitems, pre, base);
     const int G = gridDim.x, g = blockIdx.x;
-    if (!XcdChunked<Op>::value || G % kXcds != 0 || G < kXcds * kXcdChunk) {
+    if (mode != TM_XCD || G % kXcds != 0 || G < kXcds * kXcdChunk) {
         for (int t = g; t < total; t += G) {
             const int b = find_item(pre, nitems, t);
             op(base + b, t - pre[b]);
@@ -239,6 +304,23 @@ struct NoWork {
     void operator()(int, int, double&, double&) const {}
 };
 
+// Launch-mapping autotuner (dd.hip): for every launch name it tries the
+// candidate mappings (TM_STATIC or TM_LPT at two grid caps, TM_XCD where the op
+// allows it) on the launches as they come, times them with events, and keeps
+// the fastest per tile once every candidate has three samples.  Disabled with
+// DD_AUTOTUNE=0 (then TM_STATIC, or TM_XCD where the op opts in) and while a
+// stream is being captured into a graph (then the decision so far is used).
+struct TileChoice {
+    int mode;
+    int grid;
+    int cand;  // candidate being sampled, -1 if none
+};
+TileChoice tile_choice(const char* name, bool xcd_ok, int max_grid, hipStream_t s);
+void tile_sample(const char* name, int cand, hipEvent_t e0, hipEvent_t e1, int64_t tiles);
+hipEvent_t tile_event();
+int* tile_counter();  // a zeroed-before-use device counter of the current device (rotating slots)
+__global__ void k_zero_counter(int* c);
+
 // Items are processed in chunks of kMaxItems (one launch per chunk).  work(base,
 // cnt, flops, bytes) adds the algorithmic work of items [base, base+cnt); it is
 // only called while the meter is armed for this launch name.
@@ -247,17 +329,33 @@ inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream
                          int max_grid = 4096, const Work& work = Work()) {
     if (nitems <= 0 || total_hint <= 0) return;
     const bool m = meter().armed(name);
+    const TileChoice ch = tile_choice(name, XcdChunked<Op>::value, max_grid, s);
     for (int base = 0; base < nitems; base += kMaxItems) {
         const int cnt = std::min(kMaxItems, nitems - base);
-        int grid = (int)std::min<int64_t>(total_hint, max_grid);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int grid = (int)std::min<int64_t>(total_hint, ch.grid);
+        int* ctr = nullptr;
+        const int mode = (ch.mode == TM_LPT && cnt > kLptItems) ? TM_STATIC : ch.mode;
+        if (mode == TM_LPT) {
+            ctr = tile_counter();
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, ctr);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
         if (m) {
             e0 = meter().get();
             e1 = meter().get();
             DD_HIP(hipEventRecord(e0, s));
         }
-        hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base);
+        if (ch.cand >= 0) {
+            t0 = tile_event();
+            t1 = tile_event();
+            DD_HIP(hipEventRecord(t0, s));
+        }
+        hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base, mode, ctr);
         launch_check(name);
+        if (ch.cand >= 0) {
+            DD_HIP(hipEventRecord(t1, s));
+            tile_sample(name, ch.cand, t0, t1, total_hint);
+        }
         if (m) {
             DD_HIP(hipEventRecord(e1, s));
             meter().record_pair(e0, e1);

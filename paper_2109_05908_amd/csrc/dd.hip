@@ -63,6 +63,7 @@ struct Opts {
     int warm_start = DD_START_RANDOM;
     uint64_t seed = 0;
     const void* model = nullptr;
+    int graph_pcg = 0;
 };
 
 // dd_options -> Opts; DD_ERR_INVALID_ARG for values out of range
@@ -93,6 +94,8 @@ static int parse_opts(const dd_options* o, Opts& out) {
     out.warm_start = o->warm_start;
     out.seed = o->seed;
     out.model = o->warm_start_model;
+    if (o->graph_pcg < 0 || o->graph_pcg > 64) return DD_ERR_INVALID_ARG;
+    out.graph_pcg = o->graph_pcg;
     return DD_OK;
 }
 
@@ -198,7 +201,30 @@ struct Level {
     }
 };
 
+// A PCG iteration captured as a HIP graph (two-level additive handles), replayed
+// in batches of at most `chunk` between host checks; the scalars live on the
+// device, slots below
+enum GSlot { G_RZ, G_PQ, G_ALPHA, G_RN2, G_RZN, G_BETA, G_THR, G_ITS, G_STATE, G_MAXIT, G_NSLOT };
+struct GraphPcg {
+    int chunk = 0;
+    hipStream_t cs = nullptr;  // capture stream (default priority)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DBuf<double> S;            // G_NSLOT device scalars
+    double* hS = nullptr;      // pinned copy
+    GraphPcg() = default;
+    GraphPcg(const GraphPcg&) = delete;
+    GraphPcg& operator=(const GraphPcg&) = delete;
+    ~GraphPcg() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (hS) (void)hipHostFree(hS);
+    }
+};
+
 struct Handle {
+    std::unique_ptr<GraphPcg> gp;
     std::vector<std::unique_ptr<Level>> lv;
     int32_t levels_req = 2;  // levels asked for at setup
     Opts opt;
@@ -1597,6 +1623,156 @@ static int krylov(Handle& H, size_t m, const double* b, double* x, double rtol, 
 }
 
 // ---------------------------------------------------------------------------
+// PCG as a captured graph (the host-driven krylov() above, with its scalars on
+// the device).  One iteration: q = A p; pq = p.q; alpha = rz / pq; x += alpha p,
+// r -= alpha q; rn2 = r.r; stop test sqrt(rn2) <= rtol ||b|| (or maxit); z = M r;
+// rzn = r.z; beta = rzn / rz, rz = rzn; p = z + beta p.  After the stop every
+// update is skipped (state != 0), so the iterate stays that of the step that
+// stopped, and the iterations replayed past it only cost time.  The divisions
+// and dots are the host loop's (IEEE double, the same deterministic dot
+// kernels), so the iterates agree bit for bit.
+// state: 0 running, 1 converged, 2 maxit, 3 non-finite p.q
+// ---------------------------------------------------------------------------
+__global__ void k_g_alpha(double* S) {
+    if (S[G_STATE] != 0.0) {
+        S[G_ALPHA] = 0.0;
+        return;
+    }
+    if (!isfinite(S[G_PQ])) {
+        S[G_STATE] = 3.0;
+        S[G_ALPHA] = 0.0;
+        return;
+    }
+    S[G_ALPHA] = S[G_RZ] / S[G_PQ];
+}
+__global__ void k_g_check(double* S) {
+    if (S[G_STATE] != 0.0) return;
+    S[G_ITS] += 1.0;
+    if (sqrt(S[G_RN2]) <= S[G_THR]) S[G_STATE] = 1.0;
+    else if (S[G_ITS] >= S[G_MAXIT]) S[G_STATE] = 2.0;
+}
+__global__ void k_g_beta(double* S) {
+    if (S[G_STATE] != 0.0) return;
+    S[G_BETA] = S[G_RZN] / S[G_RZ];
+    S[G_RZ] = S[G_RZN];
+}
+__global__ void k_g_axpy2(double* x, double* r, const double* p, const double* q, const double* S, int64_t n) {
+    const double a = S[G_ALPHA];
+    if (a == 0.0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += a * p[i];
+        r[i] -= a * q[i];
+    }
+}
+__global__ void k_g_xpby(const double* z, double* p, const double* S, int64_t n) {
+    if (S[G_STATE] != 0.0) return;
+    const double b = S[G_BETA];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + b * p[i];
+}
+
+static void graph_iteration(Handle& H, double* S, hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    double *x = Lv.kx.p, *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p, *q = Lv.kq.p;
+    spmv(A, p, q, 1, s);
+    dot(p, q, n, 1, H.partial.p, S + G_PQ, s);
+    hipLaunchKernelGGL(k_g_alpha, dim3(1), dim3(1), 0, s, S);
+    hipLaunchKernelGGL(k_g_axpy2, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, S, n);
+    dot(r, r, n, 1, H.partial.p, S + G_RN2, s);
+    hipLaunchKernelGGL(k_g_check, dim3(1), dim3(1), 0, s, S);
+    apply_level(H, 0, r, z, s);
+    dot(r, z, n, 1, H.partial.p, S + G_RZN, s);
+    hipLaunchKernelGGL(k_g_beta, dim3(1), dim3(1), 0, s, S);
+    hipLaunchKernelGGL(k_g_xpby, dim3(vgrid(n)), dim3(256), 0, s, z, p, S, n);
+    launch_check("graph_pcg");
+}
+
+static int krylov_graph(Handle& H, const double* b, double* xio, double rtol, int maxit, int* iters, double* relres,
+                        hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    if (!H.gp || H.gp->chunk != H.opt.graph_pcg) {
+        H.gp = std::make_unique<GraphPcg>();
+        GraphPcg& G = *H.gp;
+        G.chunk = H.opt.graph_pcg;
+        G.S.alloc(G_NSLOT);
+        DD_HIP(hipHostMalloc(&G.hS, G_NSLOT * sizeof(double)));
+        DD_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+        DD_HIP(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
+        try {
+            graph_iteration(H, G.S.p, G.cs);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(G.cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            H.gp.reset();
+            throw;
+        }
+        DD_HIP(hipStreamEndCapture(G.cs, &G.graph));
+        DD_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+    }
+    GraphPcg& G = *H.gp;
+    double *x = Lv.kx.p, *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p;
+    DD_HIP(hipMemcpyAsync(x, xio, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the start as in krylov(): r = b - A x, stop test, z = M r, p = z, rz = r.z
+    const double bn = std::sqrt(dot_host(H, b, b, n, s));
+    DD_CHECK(std::isfinite(bn), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+    if (bn == 0.0) {
+        fill(xio, n, 0.0, s);
+        *iters = 0;
+        *relres = 0.0;
+        return DD_OK;
+    }
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    double rn = std::sqrt(dot_host(H, r, r, n, s));
+    int its = 0;
+    bool conv = rn <= rtol * bn;
+    if (!conv && maxit > 0) {
+        apply_level(H, 0, r, z, s);
+        DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const double rz = dot_host(H, r, z, n, s);
+        double* hS = G.hS;
+        for (int k = 0; k < G_NSLOT; ++k) hS[k] = 0.0;
+        hS[G_RZ] = rz;
+        hS[G_THR] = rtol * bn;
+        hS[G_MAXIT] = maxit;
+        h2d(G.S.p, hS, G_NSLOT, s);
+        // batches of replays between host checks, sized from the observed residual
+        // contraction so that few iterations run past the stop (those only cost time)
+        int batch = std::min(2, G.chunk);
+        double rprev = rn;
+        for (;;) {
+            for (int j = 0; j < batch; ++j) DD_HIP(hipGraphLaunch(G.exec, s));
+            d2h(hS, G.S.p, G_NSLOT, s);
+            DD_HIP(hipStreamSynchronize(s));
+            if (hS[G_STATE] != 0.0) break;
+            const double rcur = std::sqrt(hS[G_RN2]);
+            const double rate = std::pow(rcur / rprev, 1.0 / batch);
+            rprev = rcur;
+            double est = G.chunk;
+            if (rate > 0.0 && rate < 1.0) est = std::log(hS[G_THR] / rcur) / std::log(rate);
+            batch = (int)std::max(1.0, std::min<double>(G.chunk, std::floor(est)));
+        }
+        DD_CHECK(hS[G_STATE] != 3.0, DD_ERR_NAN, "PCG produced NaN");
+        its = (int)hS[G_ITS];
+        conv = hS[G_STATE] == 1.0;
+    }
+    // true residual at exit
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    const double rel = std::sqrt(dot_host(H, r, r, n, s)) / bn;
+    DD_CHECK(std::isfinite(rel), DD_ERR_NAN, "PCG produced NaN");
+    DD_HIP(hipMemcpyAsync(xio, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    *iters = its;
+    *relres = rel;
+    return conv ? DD_OK : DD_WARN_MAXIT;
+}
+
+// ---------------------------------------------------------------------------
 // Right-preconditioned GMRES(restart) (R12): Arnoldi on A M with classical
 // Gram-Schmidt applied twice, so each orthogonalisation is two tall-skinny
 // products with the basis (V^T w, then w -= V h) instead of j dependent dot
@@ -2085,6 +2261,140 @@ void dd::dev_free(void* p, size_t) noexcept {
     }
 }
 
+// ---------------------------------------------------------------------------
+// launch-mapping autotuner of launch_tiles
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneCand {
+    int mode, grid;
+    double ms = 0.0;
+    double tiles = 0.0;
+    int n = 0;
+};
+struct TuneEntry {
+    std::vector<TuneCand> cand;
+    int next = 0;
+    int best = -1;
+    struct Pending {
+        int cand;
+        hipEvent_t e0, e1;
+        int64_t tiles;
+    };
+    std::vector<Pending> pending;
+};
+struct Tuner {
+    std::mutex mu;
+    std::unordered_map<std::string, TuneEntry> table;
+    std::vector<hipEvent_t> events;  // recycled
+    int enabled = -1;
+};
+Tuner& tuner() {
+    static Tuner t;
+    return t;
+}
+constexpr int kTuneSamples = 3;
+constexpr int kTileCounters = 4096;
+}  // namespace
+
+static __device__ int tile_counters[kTileCounters];
+
+__global__ void k_zero_counter(int* c) { *c = 0; }
+
+int* tile_counter() {
+    static std::mutex mu;
+    static int* base[64] = {};
+    static unsigned next = 0;
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    DD_CHECK(dev >= 0 && dev < 64, DD_ERR_INTERNAL, "device index beyond the counter table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!base[dev]) {
+        void* p = nullptr;
+        DD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(tile_counters)));
+        base[dev] = static_cast<int*>(p);
+    }
+    return base[dev] + (next++ % kTileCounters);
+}
+
+hipEvent_t tile_event() {
+    Tuner& T = tuner();
+    std::lock_guard<std::mutex> lk(T.mu);
+    if (!T.events.empty()) {
+        hipEvent_t e = T.events.back();
+        T.events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    DD_HIP(hipEventCreate(&e));
+    return e;
+}
+
+// completed samples of an entry into its candidates; decide once every
+// candidate has kTuneSamples (called with the lock held)
+static void tune_poll(Tuner& T, TuneEntry& E) {
+    std::vector<TuneEntry::Pending> keep;
+    for (auto& q : E.pending) {
+        if (hipEventQuery(q.e1) != hipSuccess) {
+            keep.push_back(q);
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, q.e0, q.e1) == hipSuccess) {
+            TuneCand& c = E.cand[q.cand];
+            c.ms += ms;
+            c.tiles += (double)q.tiles;
+            c.n += 1;
+        }
+        T.events.push_back(q.e0);
+        T.events.push_back(q.e1);
+    }
+    E.pending.swap(keep);
+    if (E.best >= 0) return;
+    int best = -1;
+    double bt = 0.0;
+    for (size_t c = 0; c < E.cand.size(); ++c) {
+        if (E.cand[c].n < kTuneSamples) return;
+        const double per = E.cand[c].ms / std::max(1.0, E.cand[c].tiles);
+        if (best < 0 || per < bt) {
+            best = (int)c;
+            bt = per;
+        }
+    }
+    E.best = best;
+}
+
+TileChoice tile_choice(const char* name, bool xcd_ok, int max_grid, hipStream_t s) {
+    Tuner& T = tuner();
+    const TileChoice fixed{xcd_ok ? TM_XCD : TM_STATIC, max_grid, -1};
+    std::lock_guard<std::mutex> lk(T.mu);
+    if (T.enabled < 0) {
+        const char* e = std::getenv("DD_AUTOTUNE");
+        T.enabled = (e && std::atoi(e) == 0) ? 0 : 1;
+    }
+    if (!T.enabled) return fixed;
+    TuneEntry& E = T.table[name];
+    if (E.cand.empty()) {
+        E.cand.push_back(TuneCand{fixed.mode, max_grid});
+        E.cand.push_back(TuneCand{TM_STATIC, std::max(256, max_grid / 2)});
+        E.cand.push_back(TuneCand{TM_LPT, max_grid});
+        E.cand.push_back(TuneCand{TM_LPT, std::max(256, max_grid / 4)});
+        if (xcd_ok) E.cand.push_back(TuneCand{TM_STATIC, max_grid});
+    }
+    tune_poll(T, E);
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone;
+    if (E.best >= 0) return TileChoice{E.cand[E.best].mode, E.cand[E.best].grid, -1};
+    if (capturing) return fixed;
+    const int c = E.next++ % (int)E.cand.size();
+    return TileChoice{E.cand[c].mode, E.cand[c].grid, c};
+}
+
+void tile_sample(const char* name, int cand, hipEvent_t e0, hipEvent_t e1, int64_t tiles) {
+    Tuner& T = tuner();
+    std::lock_guard<std::mutex> lk(T.mu);
+    T.table[name].pending.push_back(TuneEntry::Pending{cand, e0, e1, tiles});
+}
+
 hipEvent_t Meter::get() {
     if (!pool.empty()) {
         hipEvent_t e = pool.back();
@@ -2098,6 +2408,37 @@ hipEvent_t Meter::get() {
 }  // namespace dd
 
 extern "C" {
+
+int dd_autotune_report(char* buf, int64_t len) {
+    DD_GUARD_BEGIN
+    Tuner& T = tuner();
+    std::lock_guard<std::mutex> lk(T.mu);
+    std::string out;
+    static const char* mname[3] = {"static", "xcd", "lpt-queue"};
+    std::vector<std::string> names;
+    for (auto& kv : T.table) names.push_back(kv.first);
+    std::sort(names.begin(), names.end());
+    for (const auto& nm : names) {
+        TuneEntry& E = T.table[nm];
+        tune_poll(T, E);
+        out += nm + ":";
+        for (size_t c = 0; c < E.cand.size(); ++c) {
+            const TuneCand& C = E.cand[c];
+            char tmp[160];
+            std::snprintf(tmp, sizeof tmp, " %s%s/%d=%.3gus/tile(%d)", (int)c == E.best ? "*" : "", mname[C.mode],
+                          C.grid, C.tiles > 0 ? 1e3 * C.ms / C.tiles : 0.0, C.n);
+            out += tmp;
+        }
+        out += "\n";
+    }
+    if (buf && len > 0) {
+        const size_t k = std::min<size_t>(out.size(), (size_t)len - 1);
+        std::memcpy(buf, out.data(), k);
+        buf[k] = 0;
+    }
+    return (int)std::min<size_t>(out.size(), (size_t)INT32_MAX);
+    DD_GUARD_END
+}
 
 int dd_meter_start(const char* kernel) {
     DD_GUARD_BEGIN
@@ -2790,10 +3131,12 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
         }
         return rc;
     }
+    const bool graph = H.opt.graph_pcg > 0 && H.lv.size() == 1 && H.opt.schwarz == DD_SCHWARZ_ADDITIVE;
     for (int k = 0; k < nrhs; ++k) {
         int it = 0;
         double rr = 0.0;
-        const int c = krylov(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, &it, &rr, s);
+        const int c = graph ? krylov_graph(H, b + k * n, x + k * n, rtol, maxit, &it, &rr, s)
+                            : krylov(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, &it, &rr, s);
         if (c < 0) return c;
         if (c > 0) rc = c;
         if (iters) iters[k] = it;
