@@ -36,3 +36,15 @@ def test_traffic_reported_only_for_the_profiled_sources():
         assert r["traffic"] == bench.TRAFFIC["bytes_per_launch"]
     else:
         assert r["traffic"] is None
+
+
+def test_cpu_baseline_pool_on_a_small_case():
+    """The oracle baseline: a spawned pool of worker processes (single-threaded
+    BLAS) over a size-stratified sample, extrapolated; every field reported."""
+    import workloads as W
+    cfg = W.config_c1()
+    host = bench.cpu_baseline_host(cfg, cfg.part, reps=1, sample=4)
+    out = bench.cpu_baseline_value(host, 17)
+    assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
+    assert out["setup_s"] > 0 and out["solve_s"] > 0 and out["pcg_iterations_used"] == 17
+    assert out["cpu_model"] and out["blas"] and "pool of" in out["sample"]
