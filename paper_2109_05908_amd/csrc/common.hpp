@@ -193,6 +193,12 @@ template <class Op>
 struct XcdChunked {
     static constexpr bool value = false;
 };
+// Ops built on mfma_tile_128 set this to 2: their kernel is compiled for two
+// waves per SIMD (256 VGPRs), which holds the 64 x 64 accumulator of a wave.
+template <class Op>
+struct TileWaves {
+    static constexpr int value = 0;
+};
 
 // Mapping of the tiles of one launch onto its workgroups (every mapping runs
 // each tile once, by one workgroup, with the same arithmetic: the results do
@@ -256,7 +262,7 @@ __device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, in
 }
 
 template <class Op>
-__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base, int mode, int* counter) {
+__device__ __forceinline__ void tiles_body(const Op& op, int nitems, int base, int mode, int* counter) {
     __shared__ int pre[kMaxItems + 1];
     if (mode == TM_LPT && nitems <= kLptItems) {
         tiles_lpt(op, nitems, base, counter, pre);
@@ -284,6 +290,16 @@ __global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base, int 
     }
 }
 
+template <class Op>
+__global__ void __launch_bounds__(256) k_tiles(Op op, int nitems, int base, int mode, int* counter) {
+    tiles_body(op, nitems, base, mode, counter);
+}
+// the same for ops that hold a 64 x 64 accumulator per wave (see TileWaves)
+template <class Op>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_tiles_w2(Op op, int nitems, int base, int mode, int* counter) {
+    tiles_body(op, nitems, base, mode, counter);
+}
 // Kernel meter: when armed with a launch name, every dispatch of that name is
 // bracketed by a pair of HIP events on its own stream and its algorithmic
 // work (flops, bytes) is recorded, so that the achieved rate of one kernel
@@ -350,7 +366,10 @@ inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream
             t1 = tile_event();
             DD_HIP(hipEventRecord(t0, s));
         }
-        hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base, mode, ctr);
+        if constexpr (TileWaves<Op>::value == 2)
+            hipLaunchKernelGGL(k_tiles_w2<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base, mode, ctr);
+        else
+            hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(256), 0, s, op, cnt, base, mode, ctr);
         launch_check(name);
         if (ch.cand >= 0) {
             DD_HIP(hipEventRecord(t1, s));
@@ -373,6 +392,7 @@ inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream
 // GATHER: op(A) row i is stored row ga[i] (no-transpose A only).
 // ---------------------------------------------------------------------------
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double4_t mfma_f64(double a, double b, double4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -513,6 +533,222 @@ __device__ __forceinline__ void acc_foreach(const double4_t (&acc)[2][2], F f) {
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int j = 0; j < 4; ++j) f(wr + 16 * x + 4 * j + (lane >> 4), wc + 16 * y + (lane & 15), acc[x][y][j]);
+}
+
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA tile, 128 x 128: 4 waves of 64 x 64 (4 x 4 MFMA 16x16x4 blocks),
+// K consumed in stages of KC through two LDS buffers with one barrier per
+// stage.  Same contract as mfma_tile_64 (column-major operands, transposes,
+// operand mode 1 = unit lower trapezoid), without gathers.
+//
+// Full tiles with K a multiple of KC take a scheduled path: the whole stage is
+// one basic block in which the next stage's global loads, the next k-step's
+// LDS reads and the stage's LDS writes are interleaved with the MFMAs, so a
+// wave's memory traffic overlaps its own matrix work (two waves per SIMD are
+// too few to hide it otherwise).  Operands whose base is 16-byte aligned with
+// an even leading dimension are read as double2.  Partial tiles take a
+// bounds-checked path with the same accumulation order, so every element sees
+// its K products summed in the same sequence whichever path computed it.
+//
+// The MFMA's first operand is taken from op(B) and its second from op(A), so
+// that lane l of element e of acc[x][y] holds the tile entry (row 16y + l%16,
+// column 16x + 4e + l/16) of its wave's 64 x 64 block: consecutive lanes hold
+// consecutive rows of a column, and a column-major epilogue is coalesced.
+// Ops that use it launch with two waves per SIMD (TileWaves).
+// ---------------------------------------------------------------------------
+struct TileSmem128 {
+    double a[2][KC][128 + 1];
+    double b[2][KC][128 + 1];
+};
+typedef double4_t Acc128[4][4];
+
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+__device__ __forceinline__ void acc128_zero(Acc128& acc) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = double4_t{0.0, 0.0, 0.0, 0.0};
+}
+
+// f(row, col, value), tile-relative; consecutive lanes visit consecutive rows
+template <class F>
+__device__ __forceinline__ void acc128_foreach(const Acc128& acc, F f) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 64, wc = (w >> 1) * 64;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f(wr + 16 * y + (l & 15), wc + 16 * x + 4 * e + (l >> 4), acc[x][y][e]);
+}
+
+// stored (r, c) under operand mode 1: the unit lower trapezoid
+template <int MODE>
+__device__ __forceinline__ double mode_sel(double v, int r, int c) {
+    if (MODE == 1) return (r < c) ? 0.0 : (r == c ? 1.0 : v);
+    return v;
+}
+
+// One operand of the tile: rows `idx` (M or N index, 128) by KC.  CONTIG_IDX:
+// the tile index is the contiguous storage direction (A not transposed, B
+// transposed); otherwise K is.  Stored (r, c) = (idx, k) if CONTIG_IDX else
+// (k, idx).  EDGE: entries with idx >= lim_i or k >= lim_k read a clamped
+// (valid) address and are replaced by zero, without branches.
+template <bool CONTIG_IDX, int MODE, bool VEC, bool EDGE>
+struct TileOperand {
+    const double* p;
+    int64_t ld;
+    int idx0, lim_i, lim_k;
+    double2_t r[4];  // 128 x KC / 256 threads = 8 values, as 4 pairs
+    __device__ __forceinline__ void map(int q, int& i, int& k) const {
+        const int e = threadIdx.x + 256 * q;
+        if (CONTIG_IDX) { i = (e & 63) * 2; k = e >> 6; }
+        else { k = (e & (KC / 2 - 1)) * 2; i = e >> 3; }
+    }
+    __device__ __forceinline__ const double* at(int gi, int gk) const {
+        return CONTIG_IDX ? p + gi + (int64_t)gk * ld : p + gk + (int64_t)gi * ld;
+    }
+    __device__ __forceinline__ void load(int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            map(q, i, k);
+            const int gi = idx0 + i, gk = k0 + k;
+            // the pair's second entry: next idx (CONTIG_IDX) or next k
+            const int gi1 = CONTIG_IDX ? gi + 1 : gi, gk1 = CONTIG_IDX ? gk : gk + 1;
+            if (EDGE) {
+                const bool in0 = gi < lim_i && gk < lim_k, in1 = gi1 < lim_i && gk1 < lim_k;
+                const double v0 = gload(at(min(gi, lim_i - 1), min(gk, lim_k - 1)));
+                const double v1 = gload(at(min(gi1, lim_i - 1), min(gk1, lim_k - 1)));
+                r[q][0] = in0 ? v0 : 0.0;
+                r[q][1] = in1 ? v1 : 0.0;
+            } else if (VEC) {
+                r[q] = gload((const double2_t*)at(gi, gk));
+            } else {
+                r[q][0] = gload(at(gi, gk));
+                r[q][1] = gload(at(gi, gk) + 1);  // the pair is contiguous in either layout
+            }
+            if (MODE == 1) {
+                if (CONTIG_IDX) { r[q][0] = mode_sel<1>(r[q][0], gi, gk); r[q][1] = mode_sel<1>(r[q][1], gi1, gk1); }
+                else { r[q][0] = mode_sel<1>(r[q][0], gk, gi); r[q][1] = mode_sel<1>(r[q][1], gk1, gi1); }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(double (&s)[KC][128 + 1]) const {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            map(q, i, k);
+            if (CONTIG_IDX) { s[k][i] = r[q][0]; s[k][i + 1] = r[q][1]; }
+            else { s[k][i] = r[q][0]; s[k + 1][i] = r[q][1]; }
+        }
+    }
+};
+
+template <bool TA, bool TB, int MODEA, int MODEB, bool VA, bool VB, bool EDGE>
+__device__ __forceinline__ void tile128_run(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                            int64_t ldb, int M, int N, int K, int i0, int j0, TileSmem128& sm,
+                                            Acc128& acc) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w & 1) * 64, wc = (w >> 1) * 64;
+    TileOperand<!TA, MODEA, VA, EDGE> oa{A, lda, i0, M, K};
+    TileOperand<TB, MODEB, VB, EDGE> ob{B, ldb, j0, N, K};
+    const int ns = (K + KC - 1) / KC;
+    oa.load(0);
+    ob.load(0);
+    oa.store(sm.a[0]);
+    ob.store(sm.b[0]);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+        const int buf = s & 1;
+        const int kn = min(s + 1, ns - 1) * KC;  // the last stage reloads itself (unused)
+        oa.load(kn);
+        ob.load(kn);
+        double fa[2][4], fb[2][4];
+#pragma unroll
+        for (int kq = 0; kq < KC / 4; ++kq) {
+            if (kq == 0) {
+                const int kk = l >> 4;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) fb[0][x] = sm.b[buf][kk][wc + 16 * x + (l & 15)];
+#pragma unroll
+                for (int y = 0; y < 4; ++y) fa[0][y] = sm.a[buf][kk][wr + 16 * y + (l & 15)];
+            }
+            if (kq + 1 < KC / 4) {
+                const int kk = (kq + 1) * 4 + (l >> 4), p = (kq + 1) & 1;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) fb[p][x] = sm.b[buf][kk][wc + 16 * x + (l & 15)];
+#pragma unroll
+                for (int y = 0; y < 4; ++y) fa[p][y] = sm.a[buf][kk][wr + 16 * y + (l & 15)];
+            }
+            const int p = kq & 1;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = mfma_f64(fb[p][x], fa[p][y], acc[x][y]);
+        }
+        oa.store(sm.a[buf ^ 1]);
+        ob.store(sm.b[buf ^ 1]);
+        // 64 MFMAs: a DS read after each of the first 24, the global loads
+        // from the third on, the 16 DS writes with the last 16
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            if (i < 24) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            if (i >= 2 && i < (VA && VB ? 10 : 18)) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+            if (i >= 48) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        }
+        __syncthreads();
+    }
+}
+
+// acc += op(A)[i0:i0+128, 0:K] * op(B)[0:K, j0:j0+128] (entries outside M x N
+// are computed as zero rows/columns and must not be stored by the caller)
+template <bool TA, bool TB, int MODEA = 0, int MODEB = 0>
+__device__ __forceinline__ void mfma_tile_128(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+                                              int64_t ldb, int M, int N, int K, int i0, int j0, TileSmem128& sm,
+                                              Acc128& acc) {
+    if (K <= 0) return;
+    if (i0 + 128 <= M && j0 + 128 <= N && K % KC == 0) {
+        const bool va = (((uintptr_t)A & 15) == 0) && (lda & 1) == 0;
+        const bool vb = (((uintptr_t)B & 15) == 0) && (ldb & 1) == 0;
+        if (va && vb) tile128_run<TA, TB, MODEA, MODEB, true, true, false>(A, lda, B, ldb, M, N, K, i0, j0, sm, acc);
+        else tile128_run<TA, TB, MODEA, MODEB, false, false, false>(A, lda, B, ldb, M, N, K, i0, j0, sm, acc);
+    } else {
+        tile128_run<TA, TB, MODEA, MODEB, false, false, true>(A, lda, B, ldb, M, N, K, i0, j0, sm, acc);
+    }
+}
+
+// C[i0 + r, j0 + c] = alpha acc + beta C, for r < M - i0, c < N - j0 (loads
+// of one x block issued before its stores)
+__device__ __forceinline__ void acc128_axpby(const Acc128& acc, double* C, int64_t ld, int i0, int j0, int M, int N,
+                                             double alpha, double beta) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = i0 + (w & 1) * 64 + (l & 15), c0 = j0 + (w >> 1) * 64 + (l >> 4);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        double cv[4][4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + 16 * y, c = c0 + 16 * x + 4 * e;
+                cv[y][e] = (r < M && c < N) ? gload(C + r + (int64_t)c * ld) : 0.0;
+            }
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + 16 * y, c = c0 + 16 * x + 4 * e;
+                if (r < M && c < N) C[r + (int64_t)c * ld] = alpha * acc[x][y][e] + beta * cv[y][e];
+            }
+    }
 }
 
 }  // namespace dd

@@ -37,7 +37,73 @@ struct OpGemm {
     }
 };
 
+// The same on 128 x 128 tiles (mfma_tile_128), for batches of large products
+template <bool TA, bool TB>
+struct OpGemm128 {
+    const GemmItem* g;
+    __device__ int tiles(int b) const { return ((g[b].M + 127) / 128) * ((g[b].N + 127) / 128); }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem128 sm;
+        const GemmItem& G = g[b];
+        if (G.M <= 0 || G.N <= 0) return;
+        const int tm = (G.M + 127) / 128;
+        const int i0 = (t % tm) * 128, j0 = (t / tm) * 128;
+        Acc128 acc;
+        acc128_zero(acc);
+        mfma_tile_128<TA, TB>(G.A, G.lda, G.B, G.ldb, G.M, G.N, G.K, i0, j0, sm, acc);
+        double* C = G.C;
+        const int64_t ldc = G.ldc;
+        const int M = G.M, N = G.N;
+        const double al = G.alpha, be = G.beta;
+        if (be == 0.0) {
+            acc128_foreach(acc, [&](int r, int c, double v) {
+                const int gi = i0 + r, gj = j0 + c;
+                if (gi < M && gj < N) C[gi + (int64_t)gj * ldc] = al * v;
+            });
+        } else {
+            acc128_axpby(acc, C, ldc, i0, j0, M, N, al, be);
+        }
+    }
+};
+template <bool TA, bool TB>
+struct TileWaves<OpGemm128<TA, TB>> {
+    static constexpr int value = 2;
+};
+
+// 128 x 128 tiles pay when the batch fills the GPU several times over with
+// them and little of their area falls outside the matrices
+static bool use_tile128(const std::vector<GemmItem>& items, bool lower_only) {
+    double area = 0.0, padded = 0.0;
+    int64_t t128 = 0;
+    for (auto& x : items) {
+        if (x.M <= 0 || x.N <= 0) continue;
+        const int64_t a = ceil_div(x.M, 128), b = ceil_div(x.N, 128);
+        const int64_t t = lower_only ? a * (a + 1) / 2 : a * b;
+        t128 += t;
+        padded += (double)t * 128.0 * 128.0;
+        area += lower_only ? 0.5 * x.M * (x.M + 128.0) : (double)x.M * x.N;
+    }
+    return t128 >= 2048 && area >= 0.85 * padded;
+}
+
 void gemm_vb(Batch<GemmItem>& g, bool ta, bool tb, hipStream_t s) {
+    if (use_tile128(g.h, false)) {
+        int64_t total = 0;
+        for (auto& x : g.h) total += (int64_t)ceil_div(x.M, 128) * ceil_div(x.N, 128);
+        auto work = [&](int b0, int cnt, double& fl, double& by) {
+            for (int i = b0; i < b0 + cnt; ++i) {
+                const GemmItem& x = g.h[i];
+                const double M = x.M, N = x.N, K = x.K;
+                fl += 2.0 * M * N * K;
+                by += 8.0 * (M * K + K * N + M * N * (x.beta != 0.0 ? 2.0 : 1.0));
+            }
+        };
+        if (ta && tb) launch_tiles(OpGemm128<true, true>{g.d.p}, g.size(), total, s, "gemm_tt", 4096, work);
+        else if (ta) launch_tiles(OpGemm128<true, false>{g.d.p}, g.size(), total, s, "gemm_tn", 4096, work);
+        else if (tb) launch_tiles(OpGemm128<false, true>{g.d.p}, g.size(), total, s, "gemm_nt", 4096, work);
+        else launch_tiles(OpGemm128<false, false>{g.d.p}, g.size(), total, s, "gemm_nn", 4096, work);
+        return;
+    }
     int64_t total = 0;
     for (auto& x : g.h) total += (int64_t)ceil_div(x.M, 64) * ceil_div(x.N, 64);
     // 2MNK flops; bytes = read A and B once, write C (and read it when beta != 0)
@@ -88,7 +154,57 @@ struct OpSyrk {
         });
     }
 };
+// The same on 128 x 128 tiles
+struct OpSyrk128 {
+    const GemmItem* g;
+    __device__ int tiles(int b) const {
+        const int T = (g[b].M + 127) / 128;
+        return T * (T + 1) / 2;
+    }
+    __device__ void operator()(int b, int t) const {
+        __shared__ TileSmem128 sm;
+        const GemmItem& G = g[b];
+        if (G.M <= 0) return;
+        int tj = 0, r = t;
+        const int T = (G.M + 127) / 128;
+        while (r >= T - tj) {
+            r -= T - tj;
+            ++tj;
+        }
+        const int ti = tj + r;
+        const int i0 = ti * 128, j0 = tj * 128;
+        Acc128 acc;
+        acc128_zero(acc);
+        mfma_tile_128<false, true>(G.A, G.lda, G.A, G.lda, G.M, G.M, G.K, i0, j0, sm, acc);
+        double* C = G.C;
+        const int64_t ldc = G.ldc;
+        const int M = G.M;
+        const double al = G.alpha, be = G.beta;
+        if (be == 0.0) {
+            acc128_foreach(acc, [&](int rr, int c, double v) {
+                const int gi = i0 + rr, gj = j0 + c;
+                if (gi < M && gj < M) C[gi + (int64_t)gj * ldc] = al * v;
+            });
+        } else {
+            acc128_axpby(acc, C, ldc, i0, j0, M, M, al, be);
+        }
+    }
+};
+template <>
+struct TileWaves<OpSyrk128> {
+    static constexpr int value = 2;
+};
+
 void syrk_vb(Batch<GemmItem>& g, hipStream_t s) {
+    if (use_tile128(g.h, true)) {
+        int64_t total = 0;
+        for (auto& x : g.h) {
+            const int64_t T = ceil_div(x.M, 128);
+            total += T * (T + 1) / 2;
+        }
+        launch_tiles(OpSyrk128{g.d.p}, g.size(), total, s, "syrk");
+        return;
+    }
     int64_t total = 0;
     for (auto& x : g.h) {
         const int64_t T = ceil_div(x.M, 64);

@@ -35,7 +35,7 @@ struct Batch {
 // for [T; I] with T upper triangular and the rows interleaved t_0, i_0, t_1,
 // i_1, ... (zrow = 1, zslope = 2).  Householder steps keep the structure, so
 // reflector j vanishes below row zrow + zslope * j too and every step only
-// touches rows < zrow + zslope * (block end).
+// touches rows <= zrow + zslope * (last column of the block).
 constexpr int QR_NOZ = 1 << 29;
 struct QRItem {
     DMat A;
@@ -61,8 +61,9 @@ struct ORItem {
     int zslope = 1;
 };
 // rows touched by the reflectors in columns [c0, c0 + w) of an m-row matrix
+// rows that columns [c0, c0 + w) can have nonzero: up to row zrow + zslope * (c0 + w - 1)
 __host__ __device__ inline int qr_rows(int m, int zrow, int zslope, int c0, int w) {
-    const int64_t r = (int64_t)zrow + (int64_t)zslope * (c0 + w);
+    const int64_t r = (int64_t)zrow + (int64_t)zslope * (c0 + w - 1) + 1;
     return r < m ? (int)r : m;
 }
 
