@@ -44,7 +44,7 @@ extern "C" {
 #define DD_ERR_INTERNAL        -7
 #define DD_WARN_MAXIT           1  /* PCG or GMRES stopped at maxit before reaching rtol */
 #define DD_WARN_FULL_COARSE     2  /* tau >= 1 with Boolean D: every mode is kept (lambda >= 1 always) */
-#define DD_WARN_FP32_FALLBACK   3  /* an FP32 local factor broke down and was recomputed in FP64 */
+#define DD_WARN_FP32_FALLBACK   3  /* an FP32 local factor failed; that subdomain uses FP64 */
 
 /* ---- inputs ------------------------------------------------------------ */
 /* Sparse matrix A in CSR, full symmetric storage (both triangles), column
@@ -69,8 +69,13 @@ typedef struct {
                                     D_i (1 on Omega_Ii, 0 on Gamma_i); not symmetric: dd_gmres */
 
 typedef struct {
-    int32_t local_prec;   /* DD_FP64 (default) or DD_FP32: precision of the local Cholesky factors of A_ii
-                             and of the local solves in the apply; splitting, eigen, E and PCG stay FP64 */
+    int32_t local_prec;   /* DD_FP64 (default) or DD_FP32: precision of the exact local solver A_ii^{-1} of
+                             (2.1).  DD_FP32: D A_ii D (symmetric Jacobi scaling, d_k = a_kk^{-1/2}) is
+                             factored in FP32 on FP32 MFMA with FP32 accumulation, its inverse formed in
+                             FP32, and the local solves of the apply run in FP32 on FP64 vectors; a
+                             subdomain whose FP32 factor fails keeps FP64 (dd_info_t.fp32_fallbacks).
+                             The splitting, the eigenproblem (which also uses an FP64 factor of the
+                             leading block of A_ii), E and PCG stay FP64. */
     int32_t select;       /* DD_SEL_THRESHOLD (default) or DD_SEL_THRESHOLD_CAP */
     int32_t nev_cap;      /* cap per subdomain for DD_SEL_THRESHOLD_CAP */
     int32_t validate;     /* nonzero: check the CSR structure of A first (O(nnz)): rowptr[0] = 0,
@@ -128,7 +133,9 @@ typedef struct {
                                        colour) of the fine subdomain graph, i ~ j iff A(Omega_i, Omega_j) != 0
                                        (overlapping sets): the k_c of the bound (k_c + 1)(2 + (2 k_c + 1) k_m / tau)
                                        of Sec. 3.2; computed on the host at the first dd_info call */
-    int32_t fp32_fallbacks;         /* local factors recomputed in FP64 */
+    int32_t fp32_fallbacks;         /* FP32 form: subdomains (all levels) whose FP32 factor of D A_ii D met a
+                                       pivot <= n_max eps_32 or gave a non-finite inverse, and that keep
+                                       the FP64 inverse instead */
     int32_t eig_maxit_hits;         /* local eigen/polar iterations that hit their cap (block solver: subdomains) */
     int32_t eig_iters_max;          /* block eigensolver on the finest level: largest and mean iteration count */
     double  eig_iters_mean;

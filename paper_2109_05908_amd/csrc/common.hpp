@@ -108,6 +108,11 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane_t(double v, int lane) { return readlane_d(v, lane); }
+__device__ __forceinline__ float readlane_t(float v, int lane) { return readlane_f(v, lane); }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -397,45 +402,69 @@ typedef double double2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double4_t mfma_f64(double a, double b, double4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// FP32 inputs and FP32 accumulation (the FP32 local factors)
+typedef float float4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4_t mfma_f32(float a, float b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ double4_t mma16(double a, double b, double4_t c) { return mfma_f64(a, b, c); }
+__device__ __forceinline__ float4_t mma16(float a, float b, float4_t c) { return mfma_f32(a, b, c); }
+template <class T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+    typedef double4_t type;
+};
+template <>
+struct Vec4<float> {
+    typedef float4_t type;
+};
+// Row of element e of lane l in the 16 x 16 result block (column l % 16 in
+// both): the FP64 instruction interleaves the four elements over the lane
+// groups, the FP32 one gives each lane group four consecutive rows.
+__device__ __forceinline__ int acc_row(const double4_t*, int e, int l) { return 4 * e + (l >> 4); }
+__device__ __forceinline__ int acc_row(const float4_t*, int e, int l) { return 4 * (l >> 4) + e; }
 
 constexpr int KC = 16;  // K depth of one LDS stage
 
-struct TileSmem {
-    double a[KC][64 + 1];
-    double b[KC][64 + 1];
+template <class T>
+struct TileSmemT {
+    T a[KC][64 + 1];
+    T b[KC][64 + 1];
 };
+using TileSmem = TileSmemT<double>;
 
-template <bool TA, int MODEA>
-__device__ __forceinline__ double load_a(const double* __restrict__ A, int64_t lda, int i, int k, int M, int K,
-                                         const int* __restrict__ ga) {
-    if (i >= M || k >= K) return 0.0;
+template <bool TA, int MODEA, class T>
+__device__ __forceinline__ T load_a(const T* __restrict__ A, int64_t lda, int i, int k, int M, int K,
+                                    const int* __restrict__ ga) {
+    if (i >= M || k >= K) return T(0);
     int r = TA ? k : i, c = TA ? i : k;
     if (ga) r = ga[r];
-    if (MODEA == 1) return (r < c) ? 0.0 : (r == c ? 1.0 : A[r + (int64_t)c * lda]);
+    if (MODEA == 1) return (r < c) ? T(0) : (r == c ? T(1) : A[r + (int64_t)c * lda]);
     return A[r + (int64_t)c * lda];
 }
-template <bool TB, int MODEB>
-__device__ __forceinline__ double load_b(const double* __restrict__ B, int64_t ldb, int k, int j, int K, int N,
-                                         const int* __restrict__ gb) {
-    if (j >= N || k >= K) return 0.0;
+template <bool TB, int MODEB, class T>
+__device__ __forceinline__ T load_b(const T* __restrict__ B, int64_t ldb, int k, int j, int K, int N,
+                                    const int* __restrict__ gb) {
+    if (j >= N || k >= K) return T(0);
     int r = TB ? j : k, c = TB ? k : j;
     if (gb) r = gb[r];
-    if (MODEB == 1) return (r < c) ? 0.0 : (r == c ? 1.0 : B[r + (int64_t)c * ldb]);
+    if (MODEB == 1) return (r < c) ? T(0) : (r == c ? T(1) : B[r + (int64_t)c * ldb]);
     return B[r + (int64_t)c * ldb];
 }
 
 // acc += op(A)[i0:i0+64, :] * op(B)[:, j0:j0+64].  K is consumed in stages of
 // KC; the next stage's operands are loaded into registers while the MFMAs of
 // the current stage run from LDS.
-template <bool TA, bool TB, int MODEA = 0, int MODEB = 0>
-__device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
-                                             int64_t ldb, int M, int N, int K, int i0, int j0, TileSmem& sm,
-                                             double4_t (&acc)[2][2], const int* ga = nullptr,
+template <bool TA, bool TB, int MODEA = 0, int MODEB = 0, class T>
+__device__ __forceinline__ void mfma_tile_64(const T* __restrict__ A, int64_t lda, const T* __restrict__ B,
+                                             int64_t ldb, int M, int N, int K, int i0, int j0, TileSmemT<T>& sm,
+                                             typename Vec4<T>::type (&acc)[2][2], const int* ga = nullptr,
                                              const int* gb = nullptr) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     constexpr int PER = (64 * KC) / 256;  // elements of each operand per thread and stage
-    double ra[PER], rb[PER];
+    T ra[PER], rb[PER];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -466,22 +495,23 @@ __device__ __forceinline__ void mfma_tile_64(const double* __restrict__ A, int64
 #pragma unroll 1
         for (int kq = 0; kq < KC / 4; ++kq) {
             const int kk = kq * 4 + (lane >> 4);
-            const double a0 = sm.a[kk][wr + (lane & 15)], a1 = sm.a[kk][wr + 16 + (lane & 15)];
-            const double b0 = sm.b[kk][wc + (lane & 15)], b1 = sm.b[kk][wc + 16 + (lane & 15)];
-            acc[0][0] = mfma_f64(a0, b0, acc[0][0]);
-            acc[0][1] = mfma_f64(a0, b1, acc[0][1]);
-            acc[1][0] = mfma_f64(a1, b0, acc[1][0]);
-            acc[1][1] = mfma_f64(a1, b1, acc[1][1]);
+            const T a0 = sm.a[kk][wr + (lane & 15)], a1 = sm.a[kk][wr + 16 + (lane & 15)];
+            const T b0 = sm.b[kk][wc + (lane & 15)], b1 = sm.b[kk][wc + 16 + (lane & 15)];
+            acc[0][0] = mma16(a0, b0, acc[0][0]);
+            acc[0][1] = mma16(a0, b1, acc[0][1]);
+            acc[1][0] = mma16(a1, b0, acc[1][0]);
+            acc[1][1] = mma16(a1, b1, acc[1][1]);
         }
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
+template <class V>
+__device__ __forceinline__ void acc_zero(V (&acc)[2][2]) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = double4_t{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < 2; ++y) acc[x][y] = V{0, 0, 0, 0};
 }
 
 // Stage the accumulator through LDS and hand it out in column-major order:
@@ -490,15 +520,18 @@ __device__ __forceinline__ void acc_zero(double4_t (&acc)[2][2]) {
 // coalesced.  Reuses the tile's operand buffers (needs a sync before reuse).
 // Operand buffers of the MFMA tile shared with a 64 x 65 staging area for
 // the accumulator (epilogues that write C coalesced).
-union TileSmemC {
-    TileSmem t;
-    double c[64 * 65];
+template <class T>
+union TileSmemCT {
+    TileSmemT<T> t;
+    T c[64 * 65];
 };
+using TileSmemC = TileSmemCT<double>;
 
 // acc -> LDS as a 64 x 64 column-major tile with ld 65; returns the buffer
 // (synchronised: every thread may read any element).
-__device__ __forceinline__ const double* acc_stage(const double4_t (&acc)[2][2], TileSmemC& sm) {
-    double* buf = sm.c;
+template <class T>
+__device__ __forceinline__ const T* acc_stage(const typename Vec4<T>::type (&acc)[2][2], TileSmemCT<T>& sm) {
+    T* buf = sm.c;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     __syncthreads();
@@ -508,23 +541,24 @@ __device__ __forceinline__ const double* acc_stage(const double4_t (&acc)[2][2],
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                buf[(wc + 16 * y + (lane & 15)) * 65 + wr + 16 * x + 4 * j + (lane >> 4)] = acc[x][y][j];
+                buf[(wc + 16 * y + (lane & 15)) * 65 + wr + 16 * x + acc_row(&acc[0][0], j, lane)] = acc[x][y][j];
     __syncthreads();
     return buf;
 }
 
-template <class F>
-__device__ __forceinline__ void acc_store_coalesced(const double4_t (&acc)[2][2], TileSmemC& sm, F f) {
-    const double* buf = acc_stage(acc, sm);
+template <class T, class F>
+__device__ __forceinline__ void acc_store_coalesced(const typename Vec4<T>::type (&acc)[2][2], TileSmemCT<T>& sm,
+                                                    F f) {
+    const T* buf = acc_stage(acc, sm);
     const int r = threadIdx.x & 63;
 #pragma unroll 4
     for (int c = threadIdx.x >> 6; c < 64; c += 4) f(r, c, buf[c * 65 + r]);
 }
 
 // Visit the accumulator: f(row, col, value) with tile-relative indices.  The
-// 16x16x4 f64 MFMA leaves D(4*e + lane/16, lane%16) in element e of each lane.
-template <class F>
-__device__ __forceinline__ void acc_foreach(const double4_t (&acc)[2][2], F f) {
+// element e of each lane is the entry at row acc_row(e, lane), column lane % 16.
+template <class V, class F>
+__device__ __forceinline__ void acc_foreach(const V (&acc)[2][2], F f) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
 #pragma unroll
@@ -532,7 +566,7 @@ __device__ __forceinline__ void acc_foreach(const double4_t (&acc)[2][2], F f) {
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) f(wr + 16 * x + 4 * j + (lane >> 4), wc + 16 * y + (lane & 15), acc[x][y][j]);
+            for (int j = 0; j < 4; ++j) f(wr + 16 * x + acc_row(&acc[0][0], j, lane), wc + 16 * y + (lane & 15), acc[x][y][j]);
 }
 
 

@@ -1,6 +1,7 @@
 // Host orchestration of the setup (Sec. 2-3 of the paper), the two-level
 // additive Schwarz apply (2.1) and PCG, behind the C-ABI of include/dd.h.
 #include <algorithm>
+#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -22,9 +23,10 @@ constexpr double kEps = 2.220446049250313e-16;  // 2^-52, the shift's epsilon
 // ---------------------------------------------------------------------------
 // per-item arenas
 // ---------------------------------------------------------------------------
-struct Arena {
-    DBuf<double> buf;
-    std::vector<double*> ptr;
+template <class T>
+struct ArenaT {
+    DBuf<T> buf;
+    std::vector<T*> ptr;
     void alloc(const std::vector<int64_t>& sizes) {
         std::vector<int64_t> off(sizes.size() + 1, 0);
         for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + ((std::max<int64_t>(sizes[i], 1) + 31) / 32) * 32;
@@ -34,6 +36,8 @@ struct Arena {
     }
     void release() { buf.release(); ptr.clear(); }
 };
+using Arena = ArenaT<double>;
+using ArenaF = ArenaT<float>;
 
 struct Timer {
     hipStream_t s;
@@ -159,8 +163,13 @@ struct Level {
 
     Arena L;  // local Cholesky factors (n_i x n_i, lower); released after setup
     Arena W;  // explicit inverses W_i = L_i^{-1} (lower), used by the apply
-    DBuf<float> W32;  // FP32 copy of W (FP32 local-solve form); W is released then
-    bool fp32 = false;
+    ArenaF W32;  // FP32 form: W_i = Lhat_i^{-1} D_i from the FP32 factor of D_i A_ii D_i
+    bool fp32 = false;  // the FP32 form (subdomains that fell back keep an FP64 W_i)
+    // FP32 form, during the setup only: the FP32 factors Lhat_i, the scales d_i
+    // (offsets hoffO) and which subdomains fell back to FP64
+    ArenaF L32;
+    DBuf<double> jd;
+    std::vector<int> fp64;
     std::vector<int> p;
     std::vector<int32_t> status;
     DBuf<int32_t> pcnt;
@@ -440,11 +449,43 @@ static void start_blocks(Level& Lv, const Opts& opt, const std::vector<int>& kb,
     for (int i = 0; i < N; ++i) kc[i] = act[i] ? kb[i] : 0;  // random items: no columns
     DBuf<int32_t> dk = upload(kc, s);
     ws_range_product(M, Lv.offO.p, Lv.hoffO[N], offD.p, w.p, dG.p, dB.p, dk.p, s);
-    // U = A_ii^{-1} B by the local Cholesky factor, then X = L_I^T U_I
-    Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s, &act);
-    Batch<DMat> Bb = mats(B.ptr, ni, ni, kb, s, &act);
-    trsm_vb(Lb, Bb, false, s);
-    trsm_vb(Lb, Bb, true, s);
+    // U = A_ii^{-1} B by the local Cholesky factor (FP32 form: D Lhat^{-T} Lhat^{-1} D
+    // by the FP32 factor, ample for a start block), then X = L_I^T U_I
+    std::vector<int> a64(N), a32(N);
+    for (int i = 0; i < N; ++i) {
+        a32[i] = act[i] && Lv.fp32 && !Lv.fp64[i];
+        a64[i] = act[i] && !a32[i];
+    }
+    {
+        Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s, &a64);
+        Batch<DMat> Bb = mats(B.ptr, ni, ni, kb, s, &a64);
+        if (Bb.size()) {
+            trsm_vb(Lb, Bb, false, s);
+            trsm_vb(Lb, Bb, true, s);
+        }
+    }
+    if (std::count(a32.begin(), a32.end(), 1)) {
+        ArenaF B32;
+        std::vector<int64_t> s32(N);
+        for (int i = 0; i < N; ++i) s32[i] = a32[i] ? (int64_t)ni[i] * kb[i] : 1;
+        B32.alloc(s32);
+        Batch<RowScaleItem> rs;
+        Batch<FMat> Lf, Bf;
+        for (int i = 0; i < N; ++i) {
+            if (!a32[i]) continue;
+            rs.h.push_back(RowScaleItem{B.ptr[i], B32.ptr[i], Lv.jd.p + Lv.hoffO[i], ni[i], kb[i]});
+            Lf.h.push_back(FMat{Lv.L32.ptr[i], ni[i], ni[i], ni[i]});
+            Bf.h.push_back(FMat{B32.ptr[i], ni[i], ni[i], kb[i]});
+        }
+        rs.sync(s);
+        Lf.sync(s);
+        Bf.sync(s);
+        rowscale_fp32_vb(rs, true, s);
+        trsm_vb(Lf, Bf, false, s);
+        trsm_vb(Lf, Bf, true, s);
+        rowscale_fp32_vb(rs, false, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
     Batch<GemmItem> g;
     for (int i = 0; i < N; ++i)
         if (act[i]) g.h.push_back(GemmItem{Lv.L.ptr[i], ni[i], B.ptr[i], ni[i], Yev.ptr[i], nI[i], nI[i], kb[i], nI[i], 1.0, 0.0});
@@ -590,8 +631,57 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     for (int i = 0; i < N; ++i) nc[i] = nt[i] - nI[i];
 
     // ---- a4: local Cholesky A_ii = L_i L_i^T (exact subdomain solver) -------------------
+    // FP32 form: D_i A_ii D_i (d_k = a_kk^{-1/2}) is rounded to FP32 and factored
+    // Lhat_i Lhat_i^T on FP32 MFMA with FP32 accumulation, and W_i = Lhat_i^{-1} D_i
+    // is formed (W_i^T W_i = A_ii^{-1}).  A subdomain whose FP32 factor meets a
+    // pivot at or below n_max eps_32 (the rounding level of the scaled entries:
+    // the factor would carry no digits) or whose W_i is not finite falls back to
+    // FP64.  The FP64 factor is then needed only for its leading block L_I (the
+    // eigenproblem), except for the subdomains that fell back; the start blocks
+    // solve with the FP32 factor.  All of this is decided before the FP64
+    // factorisation overwrites A_ii.
+    const bool f32 = opt.local_prec == DD_FP32;
+    Lv.fp64.assign(N, 1);
+    Lv.fp32 = f32;
+    if (f32) {
+        std::vector<int64_t> sa(N);
+        int nmax = 0;
+        for (int i = 0; i < N; ++i) {
+            sa[i] = (int64_t)ni[i] * ni[i];
+            nmax = std::max(nmax, ni[i]);
+        }
+        Lv.L32.alloc(sa);
+        Lv.W32.alloc(sa);
+        Lv.jd.alloc(std::max<int64_t>(1, Lv.hoffO[N]));
+        DBuf<int32_t> fbad(N), finfo(N);
+        DD_HIP(hipMemsetAsync(fbad.p, 0, N * sizeof(int32_t), s));
+        DD_HIP(hipMemsetAsync(finfo.p, 0, N * sizeof(int32_t), s));
+        Batch<Fp32Item> fb;
+        Batch<FMat> Lf, Wf;
+        for (int i = 0; i < N; ++i) {
+            fb.h.push_back(Fp32Item{Lv.L.ptr[i], Lv.jd.p + Lv.hoffO[i], Lv.L32.ptr[i], Lv.W32.ptr[i], ni[i], fbad.p + i});
+            Lf.h.push_back(FMat{Lv.L32.ptr[i], ni[i], ni[i], ni[i]});
+            Wf.h.push_back(FMat{Lv.W32.ptr[i], ni[i], ni[i], ni[i]});
+        }
+        fb.sync(s);
+        Lf.sync(s);
+        Wf.sync(s);
+        jacobi_fp32_vb(fb, s);
+        potrf_vb(Lf, finfo.p, (float)nmax * FLT_EPSILON, s);
+        identity_fp32_vb(fb, s);
+        trsm_vb(Lf, Wf, false, s, true);
+        scale_cols_fp32_vb(fb, s);
+        const auto hi = to_host(finfo.p, N, s), hb = to_host(fbad.p, N, s);
+        for (int i = 0; i < N; ++i) {
+            Lv.fp64[i] = (hi[i] != 0 || hb[i] != 0) ? 1 : 0;
+            info.fp32_fallbacks += Lv.fp64[i];
+        }
+    }
     {
-        Batch<DMat> Ab = mats(Lv.L.ptr, ni, ni, ni, s);
+        // FP64: the whole A_ii, or its leading block A_I where the FP32 factor stands
+        std::vector<int> mf(N);
+        for (int i = 0; i < N; ++i) mf[i] = Lv.fp64[i] ? ni[i] : nI[i];
+        Batch<DMat> Ab = mats(Lv.L.ptr, ni, mf, mf, s);
         DBuf<int32_t> dinfo(N);
         DD_HIP(hipMemsetAsync(dinfo.p, 0, N * sizeof(int32_t), s));
         potrf_vb(Ab, dinfo.p, s);
@@ -1093,31 +1183,23 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
     info.phase_ms[PH_BASIS] += tm.lap();
 
     // ---- W_i = L_i^{-1}: the local solves of the apply become two triangular
-    // matrix-vector products (HBM-bound, fully parallel) ----------------------
+    // matrix-vector products (HBM-bound, fully parallel); in the FP32 form only
+    // the subdomains that fell back need it (the others have W_i in FP32) ------
+    const std::vector<int>& fp64 = Lv.fp64;
+    Lv.L32.release();
+    Lv.jd.release();
     {
         std::vector<int64_t> sa(N);
-        for (int i = 0; i < N; ++i) sa[i] = (int64_t)ni[i] * ni[i];
+        for (int i = 0; i < N; ++i) sa[i] = fp64[i] ? (int64_t)ni[i] * ni[i] : 1;
         Lv.W.alloc(sa);
-        Batch<DMat> Wb = mats(Lv.W.ptr, ni, ni, ni, s);
-        set_identity_vb(Wb, 1.0, s);
-        Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s);
-        trsm_vb(Lb, Wb, false, s, true);
+        Batch<DMat> Wb = mats(Lv.W.ptr, ni, ni, ni, s, &fp64);
+        if (Wb.size()) {
+            set_identity_vb(Wb, 1.0, s);
+            Batch<DMat> Lb = mats(Lv.L.ptr, ni, ni, ni, s, &fp64);
+            trsm_vb(Lb, Wb, false, s, true);
+        }
         DD_HIP(hipStreamSynchronize(s));
         Lv.L.release();
-        if (opt.local_prec == DD_FP32) {
-            // FP32 local-solve form: W rounded once; kept in FP64 if that overflows
-            Lv.W32.alloc(Lv.W.buf.n);
-            DBuf<int32_t> bad(1);
-            DD_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
-            to_fp32(Lv.W.buf.p, Lv.W32.p, Lv.W.buf.n, bad.p, s);
-            const auto hb = to_host(bad.p, 1, s);
-            if (hb[0] == 0) {
-                Lv.fp32 = true;
-            } else {
-                Lv.W32.release();
-                info.fp32_fallbacks += 1;
-            }
-        }
     }
     info.phase_ms[PH_CHOL] += tm.lap();
 
@@ -1209,20 +1291,17 @@ static void build_level(Level& Lv, const Opts& opt, dd_info_t& info, hipStream_t
         Lv.Tb.h.clear();
         Lv.Tb32.h.clear();
         for (int i = 0; i < N; ++i) {
-            if (Lv.fp32)
-                Lv.Tb32.h.push_back(TrmvItem32{Lv.W32.p + (Lv.W.ptr[i] - Lv.W.buf.p), ni[i], ni[i],
-                                               Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i], Lv.tpart.p + poff[i]});
+            if (!fp64[i])
+                Lv.Tb32.h.push_back(TrmvItem32{Lv.W32.ptr[i], ni[i], ni[i], Lv.rloc.p + Lv.hoffO[i],
+                                               Lv.yloc.p + Lv.hoffO[i], Lv.tpart.p + poff[i]});
             else
                 Lv.Tb.h.push_back(TrmvItem{Lv.W.ptr[i], ni[i], ni[i], Lv.rloc.p + Lv.hoffO[i], Lv.yloc.p + Lv.hoffO[i],
                                            Lv.tpart.p + poff[i]});
         }
-        if (Lv.fp32) {
-            Lv.Tb32.sync(s);
-            DD_HIP(hipStreamSynchronize(s));
-            Lv.W.release();  // the apply reads the FP32 copy only
-        } else {
-            Lv.Tb.sync(s);
-        }
+        if (!Lv.Tb32.h.empty()) Lv.Tb32.sync(s);
+        if (!Lv.Tb.h.empty()) Lv.Tb.sync(s);
+        if (Lv.Tb32.h.empty()) Lv.W32.release();
+        if (Lv.Tb.h.empty()) Lv.W.release();
     }
     info.phase_ms[PH_OTHER] += tm.lap();
 }
@@ -1497,6 +1576,13 @@ __global__ void k_ras_prolong(const double* rloc, const int64_t* offO, const int
     }
 }
 
+// rloc_i := W_i^T W_i rloc_i for every subdomain (FP32 and FP64 inverses in
+// their own launches; each writes only its subdomains' segments)
+static void local_solves(Level& Lv, hipStream_t s) {
+    if (!Lv.Tb32.h.empty()) trinv_apply_vb(Lv.Tb32, s);
+    if (!Lv.Tb.h.empty()) trinv_apply_vb(Lv.Tb, s);
+}
+
 // z = M_deflated r = y + M_RAS (r - A y), y = Z E^{-1} Z^T r (Sec. 4): the
 // coarse correction first, then the restricted one-level method on the
 // residual it leaves.  The coarse solve of a level that is not the last is
@@ -1518,8 +1604,7 @@ static void apply_deflated(Handle& H, size_t m, const double* r, double* z, hipS
         base = Lv.dy.p;
     }
     gather(rr, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
-    if (Lv.fp32) trinv_apply_vb(Lv.Tb32, s);
-    else trinv_apply_vb(Lv.Tb, s);
+    local_solves(Lv, s);
     hipLaunchKernelGGL(k_ras_prolong, dim3(vgrid(n)), dim3(256), 0, s, Lv.rloc.p, Lv.offO.p, Lv.part.p, Lv.ilocal.p,
                        base, z, n);
     launch_check("apply_deflated");
@@ -1534,8 +1619,7 @@ static void apply_level(Handle& H, size_t m, const double* r, double* z, hipStre
     }
     Level& Lv = *H.lv[m];
     gather(r, Lv.omega_flat.p, Lv.hoffO[Lv.N], Lv.rloc.p, s);
-    if (Lv.fp32) trinv_apply_vb(Lv.Tb32, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
-    else trinv_apply_vb(Lv.Tb, s);
+    local_solves(Lv, s);  // rloc_i := W_i^T W_i rloc_i = A_ii^{-1} rloc_i
     scatter_sum(Lv.rloc.p, Lv.memb_ptr.p, Lv.memb.p, Lv.n, z, false, s);
     if (Lv.nC > 0) {
         SubInfo S = Lv.sub();
@@ -2677,7 +2761,7 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
     }
     int64_t bytes = 0;
     for (auto& l : H.lv)
-        bytes += l->W.buf.bytes() + l->W32.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
+        bytes += l->W.buf.bytes() + l->W32.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
     if (tau >= 1.0) return DD_WARN_FULL_COARSE;
     return I.fp32_fallbacks > 0 ? DD_WARN_FP32_FALLBACK : DD_OK;
@@ -2897,7 +2981,7 @@ int dd_model_add_samples(dd_model md, dd_handle h, hipStream_t s) {
     DD_GUARD_BEGIN
     if (!md || !h || h->h.lv.empty()) return DD_ERR_INVALID_ARG;
     Level& Lv = *h->h.lv[0];
-    if (Lv.fp32 || !Lv.W.buf.p) return DD_ERR_INVALID_ARG;  // needs the FP64 local inverses
+    if (!Lv.Tb32.h.empty() || !Lv.W.buf.p) return DD_ERR_INVALID_ARG;  // needs the FP64 local inverses
     Model& M = md->m;
     const int N = Lv.N;
     const auto& ni = Lv.ni;

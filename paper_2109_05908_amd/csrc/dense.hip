@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace dd {
 
@@ -453,41 +454,138 @@ void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s) 
 }
 
 // ===========================================================================
+// FP32 local factors: Jacobi scaling, identity, column scaling (one column of
+// one item per tile, 256 rows per pass)
+// ===========================================================================
+struct OpJacobiDiag {
+    const Fp32Item* f;
+    __device__ int tiles(int b) const { return (f[b].n + 255) / 256; }
+    __device__ void operator()(int b, int t) const {
+        const Fp32Item& it = f[b];
+        const int k = t * 256 + (int)threadIdx.x;
+        if (k < it.n) {
+            const double a = it.A[k + (int64_t)k * it.n];
+            it.d[k] = a > 0.0 ? 1.0 / sqrt(a) : 1.0;
+        }
+    }
+};
+struct OpJacobiScale {
+    const Fp32Item* f;
+    __device__ int tiles(int b) const { return f[b].n; }
+    __device__ void operator()(int b, int c) const {
+        const Fp32Item& it = f[b];
+        const int n = it.n;
+        const double dc = it.d[c];
+        const double* a = it.A + (int64_t)c * n;
+        float* o = it.A32 + (int64_t)c * n;
+        for (int r = threadIdx.x; r < n; r += blockDim.x) o[r] = r >= c ? (float)(a[r] * it.d[r] * dc) : 0.0f;
+    }
+};
+struct OpIdentity32 {
+    const Fp32Item* f;
+    __device__ int tiles(int b) const { return f[b].n; }
+    __device__ void operator()(int b, int c) const {
+        const Fp32Item& it = f[b];
+        float* o = it.W32 + (int64_t)c * it.n;
+        for (int r = threadIdx.x; r < it.n; r += blockDim.x) o[r] = r == c ? 1.0f : 0.0f;
+    }
+};
+struct OpScaleCols32 {
+    const Fp32Item* f;
+    __device__ int tiles(int b) const { return f[b].n; }
+    __device__ void operator()(int b, int c) const {
+        const Fp32Item& it = f[b];
+        const float dc = (float)it.d[c];
+        float* o = it.W32 + (int64_t)c * it.n;
+        bool fin = true;
+        for (int r = c + threadIdx.x; r < it.n; r += blockDim.x) {
+            const float v = o[r] * dc;
+            o[r] = v;
+            fin = fin && isfinite(v);
+        }
+        if (!fin) *it.bad = 1;  // every writer stores the same value
+    }
+};
+template <bool TO32>
+struct OpRowScale {
+    const RowScaleItem* r;
+    __device__ int tiles(int b) const { return r[b].k; }
+    __device__ void operator()(int b, int c) const {
+        const RowScaleItem& it = r[b];
+        double* B = it.B + (int64_t)c * it.n;
+        float* B32 = it.B32 + (int64_t)c * it.n;
+        for (int i = threadIdx.x; i < it.n; i += blockDim.x) {
+            if (TO32) B32[i] = (float)(it.d[i] * B[i]);
+            else B[i] = it.d[i] * (double)B32[i];
+        }
+    }
+};
+void rowscale_fp32_vb(Batch<RowScaleItem>& r, bool to32, hipStream_t s) {
+    int64_t nc = 0;
+    for (auto& x : r.h) nc += x.k;
+    if (!nc) return;
+    if (to32) launch_tiles(OpRowScale<true>{r.d.p}, r.size(), nc, s, "rowscale_to32");
+    else launch_tiles(OpRowScale<false>{r.d.p}, r.size(), nc, s, "rowscale_from32");
+}
+void jacobi_fp32_vb(Batch<Fp32Item>& f, hipStream_t s) {
+    int64_t nd = 0, nc = 0;
+    for (auto& x : f.h) {
+        nd += ceil_div(x.n, 256);
+        nc += x.n;
+    }
+    launch_tiles(OpJacobiDiag{f.d.p}, f.size(), nd, s, "jacobi_diag");
+    launch_tiles(OpJacobiScale{f.d.p}, f.size(), nc, s, "jacobi_fp32");
+}
+void identity_fp32_vb(Batch<Fp32Item>& f, hipStream_t s) {
+    int64_t nc = 0;
+    for (auto& x : f.h) nc += x.n;
+    launch_tiles(OpIdentity32{f.d.p}, f.size(), nc, s, "identity_fp32");
+}
+void scale_cols_fp32_vb(Batch<Fp32Item>& f, hipStream_t s) {
+    int64_t nc = 0;
+    for (auto& x : f.h) nc += x.n;
+    launch_tiles(OpScaleCols32{f.d.p}, f.size(), nc, s, "scale_cols_fp32");
+}
+
+// ===========================================================================
 // Cholesky (right-looking, 64-column blocks)
 // Cholesky of the 64 x 64 diagonal block at k0 by one wave: lane i holds
 // row i in registers; column j's pivot and entries reach the other lanes by
 // cross-lane shuffles, so no step waits on a workgroup barrier.  A
-// non-positive pivot records info = its 1-based column and continues with 1.
+// pivot not above piv_min (0 in FP64) records info = its 1-based column and
+// continues with 1.  T = double or float (the FP32 local factors).
+template <class T>
 struct OpPotrfDiag {
-    const DMat* A;
+    const MatT<T>* A;
     int* info;
     int k0;
+    T piv_min;
     __device__ int tiles(int b) const { return A[b].n > k0 ? 1 : 0; }
     __device__ void operator()(int b, int) const {
         if (threadIdx.x >= 64) return;  // one wave; no workgroup barrier below
-        const DMat M = A[b];
+        const MatT<T> M = A[b];
         const int w = min(64, M.n - k0);
         const int64_t ld = M.ld;
-        double* base = M.p + k0 + (int64_t)k0 * ld;
+        T* base = M.p + k0 + (int64_t)k0 * ld;
         const int i = threadIdx.x;
-        double a[64];
+        T a[64];
 #pragma unroll
-        for (int c = 0; c < 64; ++c) a[c] = (i < w && c < w && i >= c) ? base[i + c * ld] : 0.0;
+        for (int c = 0; c < 64; ++c) a[c] = (i < w && c < w && i >= c) ? base[i + c * ld] : T(0);
         int bad = 0;
 #pragma unroll
         for (int j = 0; j < 64; ++j) {
             if (j < w) {
-                double d = readlane_d(a[j], j);
-                if (!(d > 0.0)) {
+                T d = readlane_t(a[j], j);
+                if (!(d > piv_min)) {
                     if (!bad) bad = j + 1;
-                    d = 1.0;
+                    d = T(1);
                 }
-                const double piv = sqrt(d);
-                const double l = (i > j) ? a[j] / piv : (i == j ? piv : 0.0);
+                const T piv = sqrt(d);
+                const T l = (i > j) ? a[j] / piv : (i == j ? piv : T(0));
                 if (i < w && i >= j) base[i + j * ld] = l;  // column j is final
 #pragma unroll
                 for (int c = j + 1; c < 64; ++c) {
-                    const double lc = readlane_d(l, c);
+                    const T lc = readlane_t(l, c);
                     if (i >= c) a[c] -= l * lc;
                 }
             }
@@ -498,8 +596,9 @@ struct OpPotrfDiag {
 
 // A21 := A21 L11^{-T} for the rows below the diagonal block (down to m) by
 // forward substitution, one row per thread, 256 rows per workgroup.
+template <class T>
 struct OpPotrfPanel {
-    const DMat* A;
+    const MatT<T>* A;
     int k0;
     __device__ int tiles(int b) const {
         if (A[b].n <= k0) return 0;
@@ -508,25 +607,25 @@ struct OpPotrfPanel {
         return rem > 0 ? (rem + 255) / 256 : 0;
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ double L[64][65];
-        const DMat M = A[b];
+        __shared__ T L[64][65];
+        const MatT<T> M = A[b];
         const int w = min(64, M.n - k0);
-        double* base = M.p + k0 + (int64_t)k0 * M.ld;
+        T* base = M.p + k0 + (int64_t)k0 * M.ld;
         for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
             const int r = e & 63, c = e >> 6;
-            L[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : 0.0;
+            L[r][c] = (r < w && c < w && r >= c) ? base[r + (int64_t)c * M.ld] : T(0);
         }
         __syncthreads();
         const int row = k0 + w + t * 256 + (int)threadIdx.x;
         if (row < M.m) {
-            double x[64];
-            double* a = M.p + row + (int64_t)k0 * M.ld;
+            T x[64];
+            T* a = M.p + row + (int64_t)k0 * M.ld;
 #pragma unroll
-            for (int j = 0; j < 64; ++j) x[j] = (j < w) ? a[(int64_t)j * M.ld] : 0.0;
+            for (int j = 0; j < 64; ++j) x[j] = (j < w) ? a[(int64_t)j * M.ld] : T(0);
 #pragma unroll
             for (int j = 0; j < 64; ++j) {
                 if (j < w) {
-                    double v = x[j];
+                    T v = x[j];
 #pragma unroll
                     for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
                     x[j] = v / L[j][j];
@@ -542,10 +641,11 @@ struct OpPotrfPanel {
 // Left-looking block update of the recursion: columns [mid, c1) and rows
 // [mid, m) take -= A[mid:m, c0:mid] A[mid:c1, c0:mid]^T (lower part only
 // inside the square block).
+template <class T>
 struct OpPotrfUpdate {
-    const DMat* A;
+    const MatT<T>* A;
     int c0, mid, c1;
-    __device__ void dims(const DMat& M, int& TR, int& TC) const {
+    __device__ void dims(const MatT<T>& M, int& TR, int& TC) const {
         const int rows = M.m - mid, cols = min(c1, M.n) - mid;
         TR = rows > 0 ? (rows + 63) / 64 : 0;
         TC = cols > 0 ? (cols + 63) / 64 : 0;
@@ -557,8 +657,8 @@ struct OpPotrfUpdate {
         return TC * TR - TC * (TC - 1) / 2;
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmemC sm;
-        const DMat M = A[b];
+        __shared__ TileSmemCT<T> sm;
+        const MatT<T> M = A[b];
         int TR, TC;
         dims(M, TR, TC);
         int tj = 0, rem_t = t;
@@ -568,12 +668,12 @@ struct OpPotrfUpdate {
         }
         const int ti = tj + rem_t;
         const int rows = M.m - mid, cols = min(c1, M.n) - mid;
-        const double* A21 = M.p + mid + (int64_t)c0 * M.ld;
-        double4_t acc[2][2];
+        const T* A21 = M.p + mid + (int64_t)c0 * M.ld;
+        typename Vec4<T>::type acc[2][2];
         acc_zero(acc);
         mfma_tile_64<false, true>(A21, M.ld, A21, M.ld, rows, cols, mid - c0, ti * 64, tj * 64, sm.t, acc);
-        double* C = M.p + mid + (int64_t)mid * M.ld;
-        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
+        T* C = M.p + mid + (int64_t)mid * M.ld;
+        acc_store_coalesced(acc, sm, [&](int r, int c, T v) {
             const int gi = ti * 64 + r, gj = tj * 64 + c;
             if (gi < rows && gj < cols && gi >= gj) C[gi + (int64_t)gj * M.ld] -= v;
         });
@@ -581,7 +681,13 @@ struct OpPotrfUpdate {
 };
 
 // Recursive (left half, update, right half) Cholesky of columns [c0, c1).
-static void potrf_rec(Batch<DMat>& A, int* dinfo, int c0, int c1, hipStream_t s) {
+template <class T>
+static const char* fp_name(const char* f64, const char* f32) {
+    return std::is_same<T, float>::value ? f32 : f64;
+}
+
+template <class T>
+static void potrf_rec(Batch<MatT<T>>& A, int* dinfo, T piv_min, int c0, int c1, hipStream_t s) {
     if (c1 - c0 <= 64) {
         int64_t nd = 0, np = 0;
         for (auto& x : A.h) {
@@ -591,27 +697,33 @@ static void potrf_rec(Batch<DMat>& A, int* dinfo, int c0, int c1, hipStream_t s)
             if (rem > 0) np += ceil_div(rem, 256);
         }
         if (!nd) return;
-        launch_tiles(OpPotrfDiag{A.d.p, dinfo, c0}, A.size(), nd, s, "potrf_diag");
-        if (np) launch_tiles(OpPotrfPanel{A.d.p, c0}, A.size(), np, s, "potrf_panel");
+        launch_tiles(OpPotrfDiag<T>{A.d.p, dinfo, c0, piv_min}, A.size(), nd, s, fp_name<T>("potrf_diag", "potrf32_diag"));
+        if (np) launch_tiles(OpPotrfPanel<T>{A.d.p, c0}, A.size(), np, s, fp_name<T>("potrf_panel", "potrf32_panel"));
         return;
     }
     const int mid = c0 + ceil_div(c1 - c0, 128) * 64;
-    potrf_rec(A, dinfo, c0, mid, s);
+    potrf_rec(A, dinfo, piv_min, c0, mid, s);
     int64_t nu = 0;
     for (auto& x : A.h) {
         if (x.n <= mid) continue;
         const int TR = ceil_div(x.m - mid, 64), TC = ceil_div(std::min(c1, x.n) - mid, 64);
         nu += (int64_t)TC * TR - (int64_t)TC * (TC - 1) / 2;
     }
-    if (nu) launch_tiles(OpPotrfUpdate{A.d.p, c0, mid, c1}, A.size(), nu, s, "potrf_update");
-    potrf_rec(A, dinfo, mid, c1, s);
+    if (nu) launch_tiles(OpPotrfUpdate<T>{A.d.p, c0, mid, c1}, A.size(), nu, s, fp_name<T>("potrf_update", "potrf32_update"));
+    potrf_rec(A, dinfo, piv_min, mid, c1, s);
 }
 
 void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
     int nmax = 0;
     for (auto& x : A.h) nmax = std::max(nmax, x.n);
     if (nmax == 0) return;
-    potrf_rec(A, dinfo, 0, ceil_div(nmax, 64) * 64, s);
+    potrf_rec(A, dinfo, 0.0, 0, ceil_div(nmax, 64) * 64, s);
+}
+void potrf_vb(Batch<FMat>& A, int* dinfo, float piv_min, hipStream_t s) {
+    int nmax = 0;
+    for (auto& x : A.h) nmax = std::max(nmax, x.n);
+    if (nmax == 0) return;
+    potrf_rec(A, dinfo, piv_min, 0, ceil_div(nmax, 64) * 64, s);
 }
 
 // ===========================================================================
@@ -621,35 +733,36 @@ void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s) {
 // goes to D[b] + 4096 t (column-major, ld 64), padded with the identity past
 // the matrix edge.  Forward substitution on the identity, 4 threads per
 // column sharing each dot product.
+template <class T>
 struct OpTrtri64 {
-    const DMat* L;
-    double* const* D;
+    const MatT<T>* L;
+    T* const* D;
     __device__ int tiles(int b) const { return (L[b].n + 63) / 64; }
     __device__ void operator()(int b, int t) const {
-        __shared__ double Ls[64][65];
-        __shared__ double X[64][65];
-        __shared__ double red[4][64];
-        const DMat Lm = L[b];
+        __shared__ T Ls[64][65];
+        __shared__ T X[64][65];
+        __shared__ T red[4][64];
+        const MatT<T> Lm = L[b];
         const int k0 = t * 64, w = min(64, Lm.n - k0);
-        const double* lb = Lm.p + k0 + (int64_t)k0 * Lm.ld;
+        const T* lb = Lm.p + k0 + (int64_t)k0 * Lm.ld;
         for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
             const int r = e & 63, c = e >> 6;
-            double v = 0.0;
-            if (r >= c) v = (r < w) ? lb[r + (int64_t)c * Lm.ld] : (r == c ? 1.0 : 0.0);
+            T v = T(0);
+            if (r >= c) v = (r < w) ? lb[r + (int64_t)c * Lm.ld] : (r == c ? T(1) : T(0));
             Ls[r][c] = v;
-            X[r][c] = 0.0;
+            X[r][c] = T(0);
         }
         __syncthreads();
         const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
         for (int i = 0; i < 64; ++i) {
-            double sum = 0.0;
+            T sum = T(0);
             for (int l = q; l < i; l += 4) sum += Ls[i][l] * X[l][c];
             red[q][c] = sum;
             __syncthreads();
-            if (q == 0) X[i][c] = ((i == c ? 1.0 : 0.0) - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]))) / Ls[i][i];
+            if (q == 0) X[i][c] = ((i == c ? T(1) : T(0)) - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]))) / Ls[i][i];
             __syncthreads();
         }
-        double* out = D[b] + (int64_t)t * 4096;
+        T* out = D[b] + (int64_t)t * 4096;
         for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) out[e] = X[e & 63][e >> 6];
     }
 };
@@ -657,26 +770,26 @@ struct OpTrtri64 {
 // Diagonal step: B[kb:kb+w, cols] := L_kk^{-1} B (or L_kk^{-T} B) as an MFMA
 // product with the precomputed inverse; each tile owns 64 right-hand-side
 // columns and reads them completely before writing them back.
-template <bool TRANS>
+template <class T, bool TRANS>
 struct OpTrsmDiag {
-    const DMat* L;
-    const DMat* B;
-    double* const* D;
+    const MatT<T>* L;
+    const MatT<T>* B;
+    T* const* D;
     int kb;   // first row of the diagonal block
     int ncap; // column tiles that can be nonzero (lower-triangular right-hand side), or a large value
     __device__ int tiles(int b) const { return (L[b].n > kb) ? min((B[b].n + 63) / 64, ncap) : 0; }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmemC sm;
-        const DMat Lm = L[b], Bm = B[b];
+        __shared__ TileSmemCT<T> sm;
+        const MatT<T> Lm = L[b], Bm = B[b];
         const int w = min(64, Lm.n - kb);
         const int c0 = t * 64;
-        const double* Di = D[b] + (int64_t)(kb / 64) * 4096;
-        double* bb = Bm.p + kb;
-        double4_t acc[2][2];
+        const T* Di = D[b] + (int64_t)(kb / 64) * 4096;
+        T* bb = Bm.p + kb;
+        typename Vec4<T>::type acc[2][2];
         acc_zero(acc);
-        mfma_tile_64<TRANS, false>(Di, 64, bb, Bm.ld, w, Bm.n, w, 0, c0, sm.t, acc);
+        mfma_tile_64<TRANS, false>(Di, 64, (const T*)bb, Bm.ld, w, Bm.n, w, 0, c0, sm.t, acc);
         const int ld = Bm.ld, N = Bm.n;
-        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, T v) {
             const int gj = c0 + c;
             if (r < w && gj < N) bb[r + (int64_t)gj * ld] = v;
         });
@@ -686,10 +799,10 @@ struct OpTrsmDiag {
 // Recursive update of a triangular solve over rows [r0, r1) split at mid:
 // forward  B[mid:e, :] -= L[mid:e, r0:mid] B[r0:mid, :]
 // backward B[r0:mid, :] -= L[mid:e, r0:mid]^T B[mid:e, :],  e = min(n, r1)
-template <bool TRANS>
+template <class T, bool TRANS>
 struct OpTrsmGemm {
-    const DMat* L;
-    const DMat* B;
+    const MatT<T>* L;
+    const MatT<T>* B;
     int r0, mid, r1;
     int ncap;  // column tiles that can be nonzero (lower-triangular right-hand side), or a large value
     __device__ int tiles(int b) const {
@@ -700,26 +813,26 @@ struct OpTrsmGemm {
         return ((M + 63) / 64) * min((B[b].n + 63) / 64, ncap);
     }
     __device__ void operator()(int b, int t) const {
-        __shared__ TileSmemC sm;
-        const DMat Lm = L[b], Bm = B[b];
+        __shared__ TileSmemCT<T> sm;
+        const MatT<T> Lm = L[b], Bm = B[b];
         const int e = min(Lm.n, r1);
         const int M = TRANS ? mid - r0 : e - mid;
         const int K = TRANS ? e - mid : mid - r0;
         const int tm = (M + 63) / 64;
         const int i0 = (t % tm) * 64, j0 = (t / tm) * 64;
-        double4_t acc[2][2];
+        typename Vec4<T>::type acc[2][2];
         acc_zero(acc);
-        const double* A = Lm.p + mid + (int64_t)r0 * Lm.ld;  // L[mid:e, r0:mid]
-        double* Cp;
+        const T* A = Lm.p + mid + (int64_t)r0 * Lm.ld;  // L[mid:e, r0:mid]
+        T* Cp;
         if (!TRANS) {
-            mfma_tile_64<false, false>(A, Lm.ld, Bm.p + r0, Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
+            mfma_tile_64<false, false>(A, Lm.ld, (const T*)(Bm.p + r0), Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
             Cp = Bm.p + mid;
         } else {
-            mfma_tile_64<true, false>(A, Lm.ld, Bm.p + mid, Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
+            mfma_tile_64<true, false>(A, Lm.ld, (const T*)(Bm.p + mid), Bm.ld, M, Bm.n, K, i0, j0, sm.t, acc);
             Cp = Bm.p + r0;
         }
         const int N = Bm.n, ld = Bm.ld;
-        acc_store_coalesced(acc, sm, [&](int r, int c, double v) {
+        acc_store_coalesced(acc, sm, [&](int r, int c, T v) {
             const int gi = i0 + r, gj = j0 + c;
             if (gi < M && gj < N) Cp[gi + (int64_t)gj * ld] -= v;
         });
@@ -729,7 +842,8 @@ struct OpTrsmGemm {
 // lower_rhs (forward solves only): B is lower triangular on entry (e.g. the
 // identity), so column j stays zero in rows < j and column tiles right of the
 // rows being solved are skipped.
-static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool trans, bool lower_rhs, int r0, int r1,
+template <class T>
+static void trsm_rec(Batch<MatT<T>>& L, Batch<MatT<T>>& B, T* const* D, bool trans, bool lower_rhs, int r0, int r1,
                      hipStream_t s) {
     constexpr int kAll = 1 << 30;
     if (r1 - r0 <= 64) {
@@ -738,8 +852,8 @@ static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool tran
         for (int b = 0; b < L.size(); ++b)
             if (L.h[b].n > r0) nd += std::min(ceil_div(B.h[b].n, 64), cap);
         if (!nd) return;
-        if (!trans) launch_tiles(OpTrsmDiag<false>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, "trsm_diag");
-        else launch_tiles(OpTrsmDiag<true>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, "trsmT_diag");
+        if (!trans) launch_tiles(OpTrsmDiag<T, false>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, fp_name<T>("trsm_diag", "trsm32_diag"));
+        else launch_tiles(OpTrsmDiag<T, true>{L.d.p, B.d.p, D, r0, cap}, L.size(), nd, s, fp_name<T>("trsmT_diag", "trsm32T_diag"));
         return;
     }
     const int mid = r0 + ceil_div(r1 - r0, 128) * 64;
@@ -754,16 +868,17 @@ static void trsm_rec(Batch<DMat>& L, Batch<DMat>& B, double* const* D, bool tran
     }
     if (!trans) {
         trsm_rec(L, B, D, trans, lower_rhs, r0, mid, s);
-        if (nu) launch_tiles(OpTrsmGemm<false>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, "trsm_gemm");
+        if (nu) launch_tiles(OpTrsmGemm<T, false>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, fp_name<T>("trsm_gemm", "trsm32_gemm"));
         trsm_rec(L, B, D, trans, lower_rhs, mid, r1, s);
     } else {
         trsm_rec(L, B, D, trans, lower_rhs, mid, r1, s);
-        if (nu) launch_tiles(OpTrsmGemm<true>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, "trsmT_gemm");
+        if (nu) launch_tiles(OpTrsmGemm<T, true>{L.d.p, B.d.p, r0, mid, r1, cap}, L.size(), nu, s, fp_name<T>("trsmT_gemm", "trsm32T_gemm"));
         trsm_rec(L, B, D, trans, lower_rhs, r0, mid, s);
     }
 }
 
-void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool lower_rhs) {
+template <class T>
+static void trsm_any(Batch<MatT<T>>& L, Batch<MatT<T>>& B, bool trans, hipStream_t s, bool lower_rhs) {
     int nmax = 0;
     for (auto& x : L.h) nmax = std::max(nmax, x.n);
     if (nmax == 0) return;
@@ -775,14 +890,20 @@ void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool low
         off[b + 1] = off[b] + (int64_t)k * 4096;
         nblk += k;
     }
-    DBuf<double> dbuf(std::max<int64_t>(1, off.back()));
-    std::vector<double*> hp(L.size());
+    DBuf<T> dbuf(std::max<int64_t>(1, off.back()));
+    std::vector<T*> hp(L.size());
     for (int b = 0; b < L.size(); ++b) hp[b] = dbuf.p + off[b];
-    DBuf<double*> dp(std::max<size_t>(1, hp.size()));
+    DBuf<T*> dp(std::max<size_t>(1, hp.size()));
     h2d(dp.p, hp.data(), hp.size(), s);
-    launch_tiles(OpTrtri64{L.d.p, dp.p}, L.size(), nblk, s, "trtri64");
+    launch_tiles(OpTrtri64<T>{L.d.p, dp.p}, L.size(), nblk, s, fp_name<T>("trtri64", "trtri64_32"));
     trsm_rec(L, B, dp.p, trans, lower_rhs && !trans, 0, ceil_div(nmax, 64) * 64, s);
     DD_HIP(hipStreamSynchronize(s));  // dbuf, dp are freed on return
+}
+void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool lower_rhs) {
+    trsm_any(L, B, trans, s, lower_rhs);
+}
+void trsm_vb(Batch<FMat>& L, Batch<FMat>& B, bool trans, hipStream_t s, bool lower_rhs) {
+    trsm_any(L, B, trans, s, lower_rhs);
 }
 
 // ===========================================================================

@@ -5,12 +5,15 @@
 namespace dd {
 
 // Column-major matrix view: element (r, c) at p[r + c*ld].
-struct DMat {
-    double* p;
+template <class T>
+struct MatT {
+    T* p;
     int ld;
     int m;
     int n;
 };
+using DMat = MatT<double>;
+using FMat = MatT<float>;
 
 // A batch of per-item descriptors with host and device copies.
 template <class T>
@@ -102,10 +105,15 @@ void gemm_upper_a_vb(Batch<GemmItem>& g, hipStream_t s);
 // against L^T (supernodal panel factorisation).  info[b] = 1-based column of
 // the first non-positive pivot (0 if none).
 void potrf_vb(Batch<DMat>& A, int* dinfo, hipStream_t s);
+// The same in FP32 (FP32 MFMA products with FP32 accumulation).  info[b] also
+// records a positive pivot below piv_min (the factor is then too inaccurate
+// for the caller's use): the 1-based column of the first such pivot.
+void potrf_vb(Batch<FMat>& A, int* dinfo, float piv_min, hipStream_t s);
 
 // B := L^{-1} B (trans = false) or L^{-T} B (trans = true), L lower (only the
 // lower triangle of L is read).  Item b: L[b] (n x n), B[b] (n x nrhs).
 void trsm_vb(Batch<DMat>& L, Batch<DMat>& B, bool trans, hipStream_t s, bool lower_rhs = false);
+void trsm_vb(Batch<FMat>& L, Batch<FMat>& B, bool trans, hipStream_t s, bool lower_rhs = false);
 
 // Householder QR in place (first nfac columns factored, all columns updated).
 void geqrf_vb(Batch<QRItem>& q, hipStream_t s);
@@ -201,6 +209,35 @@ void trmv_t_vb(Batch<TrmvItem>& t, hipStream_t s);  // x := W^T y
 void abs_sums_vb(Batch<DMat>& A, double* const* colsum, double* const* rowsum, hipStream_t s);
 // FP64 -> FP32 copy of n elements; *bad is set to 1 if a rounded value is not finite
 void to_fp32(const double* src, float* dst, int64_t n, int* bad, hipStream_t s);
+
+// FP32 local factors with symmetric Jacobi scaling.  Item: A (n x n FP64,
+// lower triangle read), d (n FP64), A32 (n x n FP32), W32 (n x n FP32),
+// bad (one flag per item).
+struct Fp32Item {
+    const double* A;
+    double* d;
+    float* A32;
+    float* W32;
+    int n;
+    int* bad;
+};
+// d_k = a_kk^{-1/2} (1 where a_kk <= 0: the FP64 factor reports that), then
+// A32 = fl32(D A D) on the lower triangle and zero above
+void jacobi_fp32_vb(Batch<Fp32Item>& f, hipStream_t s);
+// W32 := I
+void identity_fp32_vb(Batch<Fp32Item>& f, hipStream_t s);
+// W32 := W32 D (column j times d_j, lower triangle); bad = 1 if an entry is
+// not finite
+void scale_cols_fp32_vb(Batch<Fp32Item>& f, hipStream_t s);
+// B (n x k FP64, ld n) <-> B32 (n x k FP32, ld n) with the rows scaled by d:
+// to32: B32 = fl32(d o B); otherwise B = d o B32
+struct RowScaleItem {
+    double* B;
+    float* B32;
+    const double* d;
+    int n, k;
+};
+void rowscale_fp32_vb(Batch<RowScaleItem>& r, bool to32, hipStream_t s);
 
 // Elementwise helpers.
 void set_identity_vb(Batch<DMat>& A, double diag, hipStream_t s);  // A := diag * I (m x n)

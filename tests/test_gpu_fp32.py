@@ -63,3 +63,36 @@ def test_fp32_local_solves_reach_fp64_accuracy(name):
     assert its[0] <= 2 * itso + 5
     x8, its8, rr8, code8 = p32.pcg(torch.as_tensor(b, device="cuda"), rtol=1e-8)
     assert code8 == 0 and rr8[0] <= 1e-8
+
+
+def test_fp32_factor_falls_back_per_subdomain():
+    """Two adjacent nodes with c = 1e9 in the middle of subdomain 5 of the 4 x 4
+    split (64^2 grid, overlap 1, so no other subdomain reaches them): after
+    Jacobi scaling their coupling is -1/(1 + 6e-9), which rounds to -1 in FP32,
+    so the FP32 factor of that subdomain meets a pivot of 0 or below while the
+    FP64 one keeps about 1e-8.  Exactly that subdomain must keep its FP64
+    inverse; the others stay FP32.  The matrix's entries of 1e9 put the true
+    residual's rounding floor near 1e-8 relative (1.3e-8 measured for both
+    forms), so the solve is checked at rtol 1e-6 against the FP64 form on the
+    same matrix."""
+    A = W.poisson2d_stiff_pair()
+    part = W.grid2d_partition(64, 4, 4)
+    dA = DeviceCSR.from_workload(A)
+    p64 = Preconditioner(dA, part, 16, 1, 0.1, local_prec=DD_FP64)
+    p32 = Preconditioner(dA, part, 16, 1, 0.1, local_prec=DD_FP32)
+    fb = p32.info()["fp32_fallbacks"]
+    log(f"[fp32] stiff pair: FP32 fallbacks {fb}")
+    assert fb == 1
+    r = torch.as_tensor(W.rhs(A.n, 3), device="cuda")
+    z64 = p64.apply(r).cpu().numpy()
+    z32 = p32.apply(r).cpu().numpy()
+    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    log(f"[fp32] stiff pair: FP32 vs FP64 apply, relative difference {rel:.3e}")
+    assert np.isfinite(rel) and rel < 1e-3
+    b = torch.as_tensor(W.rhs(A.n, 0), device="cuda")
+    x64, i64, r64, c64 = p64.pcg(b, rtol=1e-6, maxit=500)
+    x32, i32, r32, c32 = p32.pcg(b, rtol=1e-6, maxit=500)
+    err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+    log(f"[fp32] stiff pair: PCG its fp64 {i64[0]} fp32 {i32[0]}, relres {r64[0]:.2e} {r32[0]:.2e}, x diff {err:.2e}")
+    assert c64 == 0 and c32 == 0 and r64[0] <= 1e-6 and r32[0] <= 1e-6
+    assert abs(i32[0] - i64[0]) <= 2

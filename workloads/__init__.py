@@ -79,6 +79,41 @@ def poisson2d(m: int) -> CSR:
     return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
 
 
+def diffusion2d(coeff: np.ndarray) -> CSR:
+    """5-point finite differences of -div(c grad u) on an m x m grid with the
+    node coefficients c (m x m, node k = iy*m + ix): the face coefficient is the
+    harmonic mean of its two nodes, a Dirichlet face adds the node's own c to
+    the diagonal.  With c = 1 this is poisson2d(m)."""
+    m = coeff.shape[0]
+    c = np.asarray(coeff, dtype=np.float64).reshape(-1)
+    n = m * m
+    k = np.arange(n, dtype=np.int64)
+    iy, ix = np.divmod(k, m)
+    diag = np.zeros(n)
+    rows, cols, vals = [], [], []
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        jy, jx = iy + dy, ix + dx
+        ok = (jy >= 0) & (jy < m) & (jx >= 0) & (jx < m)
+        nb = jy * m + jx
+        face = np.where(ok, 2.0 * c * c[np.where(ok, nb, 0)] / (c + c[np.where(ok, nb, 0)]), c)
+        diag += face
+        rows.append(k[ok])
+        cols.append(nb[ok])
+        vals.append(-face[ok])
+    rows.append(k)
+    cols.append(k)
+    vals.append(diag)
+    return _from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+def poisson2d_stiff_pair(m: int = 64, node: int = 24 * 64 + 24, kappa: float = 1e9) -> CSR:
+    """diffusion2d with c = 1 except two horizontally adjacent nodes (node,
+    node + 1) with c = kappa: a stiff inclusion that floats in its subdomain."""
+    c = np.ones((m, m))
+    c.reshape(-1)[[node, node + 1]] = kappa
+    return diffusion2d(c)
+
+
 def grid2d_partition(m: int, px: int, py: int) -> np.ndarray:
     """Geometric partition of an m x m grid into py x px blocks.
 
