@@ -144,6 +144,9 @@ typedef struct {
     int32_t last_iters;             /* last dd_pcg or dd_gmres: iterations (first RHS; a batch: the largest) */
     double  last_relres;            /* last dd_pcg or dd_gmres: true relative residual (first RHS; a batch: the largest) */
     int64_t device_bytes;           /* device memory of the handle's factors, bases and index maps */
+    int64_t coarse_factor_bytes;    /* the last level's Cholesky factor of E: supernode panels and the inverses
+                                       of their diagonal blocks; every coarse solve reads it twice (forward and
+                                       backward), so 2 x this is the HBM traffic of one coarse solve */
 } dd_info_t;
 
 /* ---- entry points ------------------------------------------------------ */

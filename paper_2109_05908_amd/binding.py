@@ -62,7 +62,7 @@ class _Info(C.Structure):
                 ("fp32_fallbacks", C.c_int32), ("eig_maxit_hits", C.c_int32), ("eig_iters_max", C.c_int32),
                 ("eig_iters_mean", C.c_double), ("eig_resid_max", C.c_double),
                 ("phase_ms", C.c_double * DD_NPHASE), ("last_iters", C.c_int32), ("last_relres", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("coarse_factor_bytes", C.c_int64)]
 
 
 class _Meter(C.Structure):
@@ -442,6 +442,7 @@ class Preconditioner:
             "eig_resid_max": inf.eig_resid_max,
             "phase_ms": {L.dd_phase_name(i).decode(): inf.phase_ms[i] for i in range(DD_NPHASE)},
             "last_iters": inf.last_iters, "last_relres": inf.last_relres, "device_bytes": inf.device_bytes,
+            "coarse_factor_bytes": inf.coarse_factor_bytes,
         }
 
     def count(self, level=0) -> int:

@@ -328,7 +328,8 @@ struct NoWork {
 // Launch-mapping autotuner (dd.hip): for every launch name it tries the
 // candidate mappings (TM_STATIC or TM_LPT at two grid caps, TM_XCD where the op
 // allows it) on the launches as they come, times them with events, and keeps
-// the fastest per tile once every candidate has three samples.  Disabled with
+// the fastest per tile once every candidate is measured (three samples, or one
+// for a long launch or a launch name whose candidates are all cheap).  Disabled with
 // DD_AUTOTUNE=0 (then TM_STATIC, or TM_XCD where the op opts in) and while a
 // stream is being captured into a graph (then the decision so far is used).
 struct TileChoice {

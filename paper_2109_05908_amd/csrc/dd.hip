@@ -2377,6 +2377,8 @@ Tuner& tuner() {
     return t;
 }
 constexpr int kTuneSamples = 3;
+constexpr double kTuneMs = 0.5;
+constexpr double kTuneCheapMs = 0.1;
 constexpr int kTileCounters = 4096;
 }  // namespace
 
@@ -2414,7 +2416,11 @@ hipEvent_t tile_event() {
 }
 
 // completed samples of an entry into its candidates; decide once every
-// candidate has kTuneSamples (called with the lock held)
+// candidate is measured well enough: kTuneSamples samples, or one sample for a
+// candidate whose samples total kTuneMs (a long launch times reliably once),
+// or one sample each when the fastest candidate averages under kTuneCheapMs
+// (the choice is then worth little, and gross differences show in one
+// sample).  Called with the lock held.
 static void tune_poll(Tuner& T, TuneEntry& E) {
     std::vector<TuneEntry::Pending> keep;
     for (auto& q : E.pending) {
@@ -2436,8 +2442,14 @@ static void tune_poll(Tuner& T, TuneEntry& E) {
     if (E.best >= 0) return;
     int best = -1;
     double bt = 0.0;
+    double fastest = 1e300;
+    for (const TuneCand& c : E.cand) {
+        if (c.n < 1) return;
+        fastest = std::min(fastest, c.ms / c.n);
+    }
+    const bool cheap = fastest < kTuneCheapMs;
     for (size_t c = 0; c < E.cand.size(); ++c) {
-        if (E.cand[c].n < kTuneSamples) return;
+        if (!cheap && E.cand[c].n < kTuneSamples && E.cand[c].ms < kTuneMs) return;
         const double per = E.cand[c].ms / std::max(1.0, E.cand[c].tiles);
         if (best < 0 || per < bt) {
             best = (int)c;
@@ -2763,6 +2775,7 @@ static int build_handle(Handle& H, int64_t n, int64_t nnz, const int32_t* rowptr
     for (auto& l : H.lv)
         bytes += l->W.buf.bytes() + l->W32.buf.bytes() + l->Z.buf.bytes() + l->E.bytes() + l->memb.bytes() + l->ext.bytes();
     I.device_bytes = bytes;
+    I.coarse_factor_bytes = H.lv.empty() ? 0 : H.lv.back()->E.bytes();
     if (tau >= 1.0) return DD_WARN_FULL_COARSE;
     return I.fp32_fallbacks > 0 ? DD_WARN_FP32_FALLBACK : DD_OK;
 }
