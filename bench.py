@@ -315,7 +315,16 @@ def roofline(met, workload_name):
             "flops_per_launch": met["flops"] / met["launches"],
             "algorithmic_bytes_per_launch": met["bytes"] / met["launches"],
             "achieved_algorithmic_GBs": met["bytes"] / (met["total_ms"] * 1e-3) / 1e9,
-            "source_sha256": source_hash()}
+            "source_sha256": source_hash(), "mapping": tuner_line(ROOFLINE_KERNEL)}
+
+
+def tuner_line(name):
+    """The launch-mapping tuner's candidates for one launch name (the chosen one starred)."""
+    from paper_2109_05908_amd import autotune_report
+    for ln in autotune_report().splitlines():
+        if ln.startswith(name + ":"):
+            return ln[len(name) + 1:].strip()
+    return None
 
 
 def main():

@@ -212,11 +212,14 @@ struct TileWaves {
 // workgroup takes the next tile from a device counter until none is left, the
 // items ordered by decreasing tile count (longest processing time first), so
 // that the large subdomains start first and the small ones fill the end.
-enum TileMode { TM_STATIC = 0, TM_XCD = 1, TM_LPT = 2 };
+// TM_XLPT: the LPT order cut into chunks of kXcdChunk consecutive tiles,
+// chunk c served by the workgroups of XCD c % 8 from a counter of that XCD
+// (the XCD-chunked locality with dynamic balancing inside each XCD).
+enum TileMode { TM_STATIC = 0, TM_XCD = 1, TM_LPT = 2, TM_XLPT = 3 };
 
 constexpr int kLptItems = 256;  // the queue mode sorts at most this many items (small LDS footprint)
 template <class Op>
-__device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, int* counter, int* pre) {
+__device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, int* counter, int* pre, bool xcd) {
     __shared__ int cnt[kLptItems], perm[kLptItems];
     __shared__ int tnext;
     int P = 1;
@@ -254,6 +257,25 @@ __device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, in
     }
     __syncthreads();
     const int total = pre[nitems];
+    if (xcd) {
+        // counter[x] for the workgroups of XCD x (dispatch is round-robin over the
+        // XCDs); every tile still runs once whatever the placement
+        const int x = blockIdx.x % kXcds;
+        for (;;) {
+            if (threadIdx.x == 0) tnext = atomicAdd(counter + x, 1);
+            __syncthreads();
+            const int k = tnext;
+            __syncthreads();
+            const int c0 = (x + kXcds * (k / kXcdChunk)) * kXcdChunk;
+            if (c0 >= total) break;  // later k of this XCD only visit later chunks
+            const int t = c0 + k % kXcdChunk;
+            if (t >= total) continue;
+            const int q = find_item(pre, nitems, t);
+            op(base + perm[q], t - pre[q]);
+            __syncthreads();
+        }
+        return;
+    }
     for (;;) {
         if (threadIdx.x == 0) tnext = atomicAdd(counter, 1);
         __syncthreads();
@@ -269,8 +291,8 @@ __device__ __forceinline__ void tiles_lpt(const Op& op, int nitems, int base, in
 template <class Op>
 __device__ __forceinline__ void tiles_body(const Op& op, int nitems, int base, int mode, int* counter) {
     __shared__ int pre[kMaxItems + 1];
-    if (mode == TM_LPT && nitems <= kLptItems) {
-        tiles_lpt(op, nitems, base, counter, pre);
+    if ((mode == TM_LPT || mode == TM_XLPT) && nitems <= kLptItems) {
+        tiles_lpt(op, nitems, base, counter, pre, mode == TM_XLPT);
         return;
     }
     const int total = item_prefix(op, nitems, pre, base);
@@ -340,8 +362,8 @@ struct TileChoice {
 TileChoice tile_choice(const char* name, bool xcd_ok, int max_grid, hipStream_t s);
 void tile_sample(const char* name, int cand, hipEvent_t e0, hipEvent_t e1, int64_t tiles);
 hipEvent_t tile_event();
-int* tile_counter();  // a zeroed-before-use device counter of the current device (rotating slots)
-__global__ void k_zero_counter(int* c);
+int* tile_counter(int n = 1);  // n device counters of the current device (rotating slots), zeroed before use
+__global__ void k_zero_counter(int* c, int n);
 
 // Items are processed in chunks of kMaxItems (one launch per chunk).  work(base,
 // cnt, flops, bytes) adds the algorithmic work of items [base, base+cnt); it is
@@ -356,10 +378,13 @@ inline void launch_tiles(const Op& op, int nitems, int64_t total_hint, hipStream
         const int cnt = std::min(kMaxItems, nitems - base);
         int grid = (int)std::min<int64_t>(total_hint, ch.grid);
         int* ctr = nullptr;
-        const int mode = (ch.mode == TM_LPT && cnt > kLptItems) ? TM_STATIC : ch.mode;
-        if (mode == TM_LPT) {
-            ctr = tile_counter();
-            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, ctr);
+        int mode = ch.mode;
+        if ((mode == TM_LPT || mode == TM_XLPT) && cnt > kLptItems) mode = TM_STATIC;
+        if (mode == TM_XLPT && grid < kXcds) mode = TM_LPT;  // every XCD queue needs a workgroup
+        if (mode == TM_LPT || mode == TM_XLPT) {
+            const int nc = mode == TM_XLPT ? kXcds : 1;
+            ctr = tile_counter(nc);
+            hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, ctr, nc);
         }
         hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
         if (m) {

@@ -2384,9 +2384,11 @@ constexpr int kTileCounters = 4096;
 
 static __device__ int tile_counters[kTileCounters];
 
-__global__ void k_zero_counter(int* c) { *c = 0; }
+__global__ void k_zero_counter(int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
 
-int* tile_counter() {
+int* tile_counter(int n) {
     static std::mutex mu;
     static int* base[64] = {};
     static unsigned next = 0;
@@ -2399,7 +2401,11 @@ int* tile_counter() {
         DD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(tile_counters)));
         base[dev] = static_cast<int*>(p);
     }
-    return base[dev] + (next++ % kTileCounters);
+    // n consecutive slots, never wrapping past the end of the array
+    const unsigned slot = (next % (kTileCounters / kXcds)) * kXcds;
+    next++;
+    DD_CHECK(n >= 1 && n <= kXcds, DD_ERR_INTERNAL, "tile counter request beyond one slot");
+    return base[dev] + slot;
 }
 
 hipEvent_t tile_event() {
@@ -2474,12 +2480,21 @@ TileChoice tile_choice(const char* name, bool xcd_ok, int max_grid, hipStream_t 
         E.cand.push_back(TuneCand{TM_STATIC, std::max(256, max_grid / 2)});
         E.cand.push_back(TuneCand{TM_LPT, max_grid});
         E.cand.push_back(TuneCand{TM_LPT, std::max(256, max_grid / 4)});
-        if (xcd_ok) E.cand.push_back(TuneCand{TM_STATIC, max_grid});
+        if (xcd_ok) {
+            E.cand.push_back(TuneCand{TM_STATIC, max_grid});
+            E.cand.push_back(TuneCand{TM_XLPT, max_grid});
+        }
     }
     tune_poll(T, E);
     hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(s, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone;
-    if (E.best >= 0) return TileChoice{E.cand[E.best].mode, E.cand[E.best].grid, -1};
+    // a captured launch keeps its counter slot for every replay, so graphs take
+    // no queue mapping (the slots rotate over later eager launches)
+    if (E.best >= 0) {
+        const TuneCand& B = E.cand[E.best];
+        if (capturing && (B.mode == TM_LPT || B.mode == TM_XLPT)) return fixed;
+        return TileChoice{B.mode, B.grid, -1};
+    }
     if (capturing) return fixed;
     const int c = E.next++ % (int)E.cand.size();
     return TileChoice{E.cand[c].mode, E.cand[c].grid, c};
@@ -2510,7 +2525,7 @@ int dd_autotune_report(char* buf, int64_t len) {
     Tuner& T = tuner();
     std::lock_guard<std::mutex> lk(T.mu);
     std::string out;
-    static const char* mname[3] = {"static", "xcd", "lpt-queue"};
+    static const char* mname[4] = {"static", "xcd", "lpt-queue", "xcd-lpt-queue"};
     std::vector<std::string> names;
     for (auto& kv : T.table) names.push_back(kv.first);
     std::sort(names.begin(), names.end());

@@ -1316,6 +1316,13 @@ struct OpBlkP : BlkOp {
     }
 };
 
+// the row tiles of one column tile and row chunk are consecutive tiles and
+// read the same block of C: XCD-chunked mappings keep them in one L2
+template <>
+struct XcdChunked<OpBlkP> {
+    static constexpr bool value = true;
+};
+
 // W from the summed partials for one 128-block (half of the range), per
 // 64-column tile: W_q = T_q^T (P_q - sum_j G_qj W_j) over its 32-column panels
 // (T_q (P_q - ...) for Q C)
