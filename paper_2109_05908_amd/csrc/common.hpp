@@ -19,10 +19,14 @@ struct Error : std::runtime_error {
     Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// A failed call also leaves HIP's last-error state set; it is cleared here,
+// since the exception reports it (else the next launch_check of a later call
+// would report this error again).
 #define DD_HIP(x)                                                                      \
     do {                                                                               \
         hipError_t e_ = (x);                                                           \
         if (e_ != hipSuccess) {                                                        \
+            (void)hipGetLastError();                                                   \
             int c_ = (e_ == hipErrorOutOfMemory) ? DD_ERR_OOM : DD_ERR_HIP;            \
             throw ::dd::Error(c_, std::string(#x) + ": " + hipGetErrorString(e_));     \
         }                                                                              \

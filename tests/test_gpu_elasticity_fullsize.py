@@ -157,6 +157,28 @@ def test_elasticity_threshold_two_levels():
     torch.cuda.empty_cache()
 
 
+def test_elasticity_cap_256_two_levels():
+    """Cap 256 per subdomain (threshold and cap) on two levels: the smallest
+    cap of the sweep 32..256 within twice the threshold's iterations (the
+    near-kernel cluster of an interior subdomain holds 456 modes, so smaller
+    caps leave most of it out: 179 iterations at 128, 392 at 64)."""
+    st = state()
+    cfg, A = st["cfg"], st["A"]
+    pre = Preconditioner(st["dA"], cfg.part, cfg.N, cfg.overlap, cfg.tau, levels=2, select=DD_SEL_THRESHOLD_CAP,
+                         nev_cap=256)
+    info = pre.info()
+    assert int(pre.sizes()[:, 3].max()) <= 256
+    b_h = W.rhs(A.shape[0], 0)
+    x, its, rr, code = pre.pcg(torch.as_tensor(b_h, device="cuda:0"), rtol=1e-8, maxit=1000)
+    x_h = x.cpu().numpy().reshape(-1)
+    true_rr = np.linalg.norm(b_h - A @ x_h) / np.linalg.norm(b_h)
+    log(f"[elasticity] cap 256, 2 levels: n_C={info['n_C']} PCG its={its[0]} relres {true_rr:.3e}")
+    assert code == 0 and true_rr <= 1e-8
+    assert its[0] <= 60
+    del pre
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("levels,cap", [(3, True), (2, False)], ids=["capped_3_levels", "threshold_2_levels"])
 def test_elasticity_deflated_gmres(levels, cap):
     """The deflated variant of the paper's experiments on the same matrix and
