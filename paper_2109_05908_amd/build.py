@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["dense.hip", "sparse.hip", "coarse.hip", "bchol.hip", "lobpcg.hip", "warm.hip", "dd.hip"]
+SOURCES = ["dense.hip", "sparse.hip", "coarse.hip", "bchol.hip", "lobpcg.hip", "warm.hip", "mrhs.hip", "dd.hip"]
 ARCH = os.environ.get("DD_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -12,6 +12,7 @@
 #include <unordered_map>
 
 #include "bchol.hpp"
+#include "mrhs.hpp"
 #include "coarse.hpp"
 #include "lobpcg.hpp"
 #include "warm.hpp"
@@ -231,9 +232,25 @@ struct GraphPcg {
         if (hS) (void)hipHostFree(hS);
     }
 };
+// Several right-hand sides in lockstep: the same scalars per column, slot-major
+// (S[slot * kMrhs + k]), and column-blocked work vectors of the finest level.
+struct BlockPcg {
+    DBuf<double> S, r, z, p, q;   // S: G_NSLOT x kMrhs; vectors: kMrhs x n
+    DBuf<double> rloc, yloc, tpart, yC;  // kMrhs copies of the level's apply workspaces
+    Batch<TrmvMItem<double>> Tm;
+    Batch<TrmvMItem<float>> Tm32;
+    double* hS = nullptr;          // pinned copy of S
+    BlockPcg() = default;
+    BlockPcg(const BlockPcg&) = delete;
+    BlockPcg& operator=(const BlockPcg&) = delete;
+    ~BlockPcg() {
+        if (hS) (void)hipHostFree(hS);
+    }
+};
 
 struct Handle {
     std::unique_ptr<GraphPcg> gp;
+    std::unique_ptr<BlockPcg> bp;  // several right-hand sides in lockstep (dd_pcg, dd_apply)
     std::vector<std::unique_ptr<Level>> lv;
     int32_t levels_req = 2;  // levels asked for at setup
     Opts opt;
@@ -1857,6 +1874,221 @@ static int krylov_graph(Handle& H, const double* b, double* xio, double rtol, in
 }
 
 // ---------------------------------------------------------------------------
+// Several right-hand sides in lockstep (two levels, additive, one system):
+// every column runs the host loop of krylov() with its scalars on the device
+// (as in the graph iteration), while the SpMV reads A and the local solves read
+// every W_i once per group of up to kMrhs columns.  Each column's arithmetic is
+// that of a single right-hand side, so every column equals its own dd_pcg call
+// bit for bit; a column that has stopped keeps its iterate (alpha = 0, no p
+// update) while the others go on.
+// ---------------------------------------------------------------------------
+__global__ void k_b_alpha(double* S, int K) {
+    const int k = threadIdx.x;
+    if (k >= K) return;
+    double* a = S + G_ALPHA * kMrhs + k;
+    if (S[G_STATE * kMrhs + k] != 0.0) {
+        *a = 0.0;
+        return;
+    }
+    const double pq = S[G_PQ * kMrhs + k];
+    if (!isfinite(pq)) {
+        S[G_STATE * kMrhs + k] = 3.0;
+        *a = 0.0;
+        return;
+    }
+    *a = S[G_RZ * kMrhs + k] / pq;
+}
+__global__ void k_b_check(double* S, int K) {
+    const int k = threadIdx.x;
+    if (k >= K || S[G_STATE * kMrhs + k] != 0.0) return;
+    S[G_ITS * kMrhs + k] += 1.0;
+    if (sqrt(S[G_RN2 * kMrhs + k]) <= S[G_THR * kMrhs + k]) S[G_STATE * kMrhs + k] = 1.0;
+    else if (S[G_ITS * kMrhs + k] >= S[G_MAXIT * kMrhs + k]) S[G_STATE * kMrhs + k] = 2.0;
+}
+__global__ void k_b_beta(double* S, int K) {
+    const int k = threadIdx.x;
+    if (k >= K || S[G_STATE * kMrhs + k] != 0.0) return;
+    S[G_BETA * kMrhs + k] = S[G_RZN * kMrhs + k] / S[G_RZ * kMrhs + k];
+    S[G_RZ * kMrhs + k] = S[G_RZN * kMrhs + k];
+}
+// column k = blockIdx.y
+__global__ void k_b_axpy2(double* x, double* r, const double* p, const double* q, const double* S, int64_t n) {
+    const int k = blockIdx.y;
+    const double a = S[G_ALPHA * kMrhs + k];
+    if (a == 0.0) return;
+    double *xk = x + k * n, *rk = r + k * n;
+    const double *pk = p + k * n, *qk = q + k * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        xk[i] += a * pk[i];
+        rk[i] -= a * qk[i];
+    }
+}
+__global__ void k_b_xpby(const double* z, double* p, const double* S, int64_t n) {
+    const int k = blockIdx.y;
+    if (S[G_STATE * kMrhs + k] != 0.0) return;
+    const double b = S[G_BETA * kMrhs + k];
+    const double* zk = z + k * n;
+    double* pk = p + k * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pk[i] = zk[i] + b * pk[i];
+}
+
+// the block state of a handle, built on first use (two levels, additive, one system)
+static BlockPcg& block_state(Handle& H, hipStream_t s) {
+    if (H.bp) return *H.bp;
+    Level& Lv = *H.lv[0];
+    auto bp = std::make_unique<BlockPcg>();
+    BlockPcg& B = *bp;
+    const int64_t n = std::max<int64_t>(1, Lv.n), tot = std::max<int64_t>(1, Lv.hoffO[Lv.N]);
+    const int64_t ptot = std::max<int64_t>(1, Lv.tpart.n);
+    B.S.alloc(G_NSLOT * kMrhs);
+    B.r.alloc(kMrhs * n);
+    B.z.alloc(kMrhs * n);
+    B.p.alloc(kMrhs * n);
+    B.q.alloc(kMrhs * n);
+    B.rloc.alloc(kMrhs * tot);
+    B.yloc.alloc(kMrhs * tot);
+    B.tpart.alloc(kMrhs * ptot);
+    DD_HIP(hipHostMalloc(&B.hS, G_NSLOT * kMrhs * sizeof(double)));
+    // the level's local-solve items, pointed at the column-blocked workspaces
+    for (const TrmvItem& t : Lv.Tb.h)
+        B.Tm.h.push_back(TrmvMItem<double>{t.W, t.ld, t.n, B.rloc.p + (t.x - Lv.rloc.p), B.yloc.p + (t.y - Lv.yloc.p),
+                                           B.tpart.p + (t.part - Lv.tpart.p), tot, tot, ptot});
+    for (const TrmvItem32& t : Lv.Tb32.h)
+        B.Tm32.h.push_back(TrmvMItem<float>{t.W, t.ld, t.n, B.rloc.p + (t.x - Lv.rloc.p),
+                                            B.yloc.p + (t.y - Lv.yloc.p), B.tpart.p + (t.part - Lv.tpart.p), tot, tot,
+                                            ptot});
+    if (!B.Tm.h.empty()) B.Tm.sync(s);
+    if (!B.Tm32.h.empty()) B.Tm32.sync(s);
+    H.bp = std::move(bp);
+    return *H.bp;
+}
+
+// z_k = M r_k for K <= kMrhs columns (stride n): the steps of apply_level per
+// column, with the local solves of all columns in one pass over the W_i.
+// Columns with stopped[k] set (PCG columns that have stopped, whose z is not
+// used again) skip the per-column coarse solve.
+static void apply_block(Handle& H, const double* r, double* z, int K, hipStream_t s,
+                        const std::vector<int>* stopped = nullptr) {
+    Level& Lv = *H.lv[0];
+    BlockPcg& B = block_state(H, s);
+    const int64_t n = Lv.n, tot = Lv.hoffO[Lv.N];
+    for (int k = 0; k < K; ++k) gather(r + k * n, Lv.omega_flat.p, tot, B.rloc.p + k * tot, s);
+    if (!B.Tm32.h.empty()) trinv_apply_multi_vb(B.Tm32, K, s);
+    if (!B.Tm.h.empty()) trinv_apply_multi_vb(B.Tm, K, s);
+    for (int k = 0; k < K; ++k) {
+        scatter_sum(B.rloc.p + k * tot, Lv.memb_ptr.p, Lv.memb.p, n, z + k * n, false, s);
+        if (Lv.nC > 0 && !(stopped && (*stopped)[k])) {
+            SubInfo S = Lv.sub();
+            restrict_coarse(S, Lv.nC, r + k * n, Lv.yC.p, s);
+            coarse_solve(H, 0, Lv.yC.p, s);
+            prolong_coarse(S, Lv.offI.p, Lv.hoffI[Lv.N], Lv.yC.p, z + k * n, s);
+        }
+    }
+}
+
+static bool block_ok(const Handle& H) {
+    return H.nsys() == 1 && H.lv.size() == 1 && H.opt.schwarz == DD_SCHWARZ_ADDITIVE;
+}
+
+// PCG on K <= kMrhs columns of b, x (stride n, x in/out) in lockstep
+static int krylov_block(Handle& H, const double* b, double* x, int K, double rtol, int maxit, int* iters,
+                        double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    BlockPcg& B = block_state(H, s);
+    double *r = B.r.p, *z = B.z.p, *p = B.p.p, *q = B.q.p, *S = B.S.p, *hS = B.hS;
+    const dim3 vg(vgrid(n), K);
+    // the start of krylov(), per column
+    std::vector<double> bn(K), rn(K);
+    dot(b, b, n, K, H.partial.p, S, s);
+    d2h(hS, S, K, s);
+    DD_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < K; ++k) {
+        bn[k] = std::sqrt(hS[k]);
+        DD_CHECK(std::isfinite(bn[k]), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+        if (bn[k] == 0.0) fill(x + k * n, n, 0.0, s);
+    }
+    spmv(A, x, r, K, s);
+    for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b + k * n, r + k * n, n);
+    dot(r, r, n, K, H.partial.p, S, s);
+    d2h(hS, S, K, s);
+    DD_HIP(hipStreamSynchronize(s));
+    std::vector<int> state(K, 0);  // 0 running, 1 converged, 2 maxit, 3 NaN
+    for (int k = 0; k < K; ++k) {
+        rn[k] = std::sqrt(hS[k]);
+        if (bn[k] == 0.0 || rn[k] <= rtol * bn[k]) state[k] = 1;
+        else if (maxit <= 0) state[k] = 2;
+    }
+    std::vector<int> its(K, 0);
+    if (std::count(state.begin(), state.end(), 0) > 0) {
+        apply_block(H, r, z, K, s);
+        DD_HIP(hipMemcpyAsync(p, z, K * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        dot(r, z, n, K, H.partial.p, S + G_RZ * kMrhs, s);
+        d2h(hS, S, G_NSLOT * kMrhs, s);
+        DD_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < K; ++k) {
+            for (int g = 0; g < G_NSLOT; ++g)
+                if (g != G_RZ) hS[g * kMrhs + k] = 0.0;
+            hS[G_THR * kMrhs + k] = rtol * bn[k];
+            hS[G_MAXIT * kMrhs + k] = maxit;
+            hS[G_STATE * kMrhs + k] = state[k];
+        }
+        h2d(S, hS, G_NSLOT * kMrhs, s);
+        std::vector<int> stopped(K);
+        for (int k = 0; k < K; ++k) stopped[k] = state[k] != 0;
+        int batch = 2;
+        for (;;) {
+            for (int j = 0; j < batch; ++j) {
+                spmv(A, p, q, K, s);
+                dot(p, q, n, K, H.partial.p, S + G_PQ * kMrhs, s);
+                hipLaunchKernelGGL(k_b_alpha, dim3(1), dim3(kMrhs), 0, s, S, K);
+                hipLaunchKernelGGL(k_b_axpy2, vg, dim3(256), 0, s, x, r, p, q, S, n);
+                dot(r, r, n, K, H.partial.p, S + G_RN2 * kMrhs, s);
+                hipLaunchKernelGGL(k_b_check, dim3(1), dim3(kMrhs), 0, s, S, K);
+                apply_block(H, r, z, K, s, &stopped);
+                dot(r, z, n, K, H.partial.p, S + G_RZN * kMrhs, s);
+                hipLaunchKernelGGL(k_b_beta, dim3(1), dim3(kMrhs), 0, s, S, K);
+                hipLaunchKernelGGL(k_b_xpby, vg, dim3(256), 0, s, z, p, S, n);
+                launch_check("block_pcg");
+            }
+            d2h(hS, S, G_NSLOT * kMrhs, s);
+            DD_HIP(hipStreamSynchronize(s));
+            bool running = false;
+            for (int k = 0; k < K; ++k) {
+                stopped[k] = hS[G_STATE * kMrhs + k] != 0.0;
+                running = running || !stopped[k];
+            }
+            if (!running) break;
+            batch = std::min(8, batch * 2);
+        }
+        for (int k = 0; k < K; ++k) {
+            DD_CHECK(hS[G_STATE * kMrhs + k] != 3.0, DD_ERR_NAN, "PCG produced NaN");
+            if (state[k] == 0) {
+                its[k] = (int)hS[G_ITS * kMrhs + k];
+                state[k] = (int)hS[G_STATE * kMrhs + k];
+            }
+        }
+    }
+    // true residuals at exit
+    spmv(A, x, r, K, s);
+    for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b + k * n, r + k * n, n);
+    dot(r, r, n, K, H.partial.p, S, s);
+    d2h(hS, S, K, s);
+    DD_HIP(hipStreamSynchronize(s));
+    int rc = DD_OK;
+    for (int k = 0; k < K; ++k) {
+        const double rel = bn[k] == 0.0 ? 0.0 : std::sqrt(hS[k]) / bn[k];
+        DD_CHECK(std::isfinite(rel), DD_ERR_NAN, "PCG produced NaN");
+        iters[k] = its[k];
+        relres[k] = rel;
+        if (state[k] != 1) rc = DD_WARN_MAXIT;
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // Right-preconditioned GMRES(restart) (R12): Arnoldi on A M with classical
 // Gram-Schmidt applied twice, so each orthogonalisation is two tall-skinny
 // products with the basis (V^T w, then w -= V h) instead of j dependent dot
@@ -2881,6 +3113,10 @@ int dd_update_values(dd_handle h, const double* val, hipStream_t s) {
     DD_HIP(hipStreamSynchronize(s));
     std::swap(h->h.lv, F.lv);
     h->h.info = F.info;
+    // the captured PCG graph and the block state point into the old levels'
+    // buffers, which go with F: both are rebuilt on next use
+    h->h.gp.reset();
+    h->h.bp.reset();
     return rc;
     DD_GUARD_END
 }
@@ -3210,7 +3446,12 @@ int dd_apply(dd_handle h, const double* r, double* z, int32_t nrhs, hipStream_t 
     DD_GUARD_BEGIN
     if (!h || !r || !z || nrhs < 1) return DD_ERR_INVALID_ARG;
     const int64_t n = h->h.lv[0]->n;
-    for (int k = 0; k < nrhs; ++k) apply_level(h->h, 0, r + (int64_t)k * n, z + (int64_t)k * n, s);
+    if (nrhs > 1 && block_ok(h->h)) {
+        for (int k0 = 0; k0 < nrhs; k0 += kMrhs)
+            apply_block(h->h, r + (int64_t)k0 * n, z + (int64_t)k0 * n, std::min(kMrhs, nrhs - k0), s);
+    } else {
+        for (int k = 0; k < nrhs; ++k) apply_level(h->h, 0, r + (int64_t)k * n, z + (int64_t)k * n, s);
+    }
     return DD_OK;
     DD_GUARD_END
 }
@@ -3239,6 +3480,25 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
             if (k == 0) {
                 H.info.last_iters = *std::max_element(it.begin(), it.end());
                 H.info.last_relres = *std::max_element(rr.begin(), rr.end());
+            }
+        }
+        return rc;
+    }
+    if (nrhs > 1 && block_ok(H)) {
+        std::vector<int> it(kMrhs);
+        std::vector<double> rr(kMrhs);
+        for (int k0 = 0; k0 < nrhs; k0 += kMrhs) {
+            const int K = std::min(kMrhs, nrhs - k0);
+            const int c = krylov_block(H, b + k0 * n, x + k0 * n, K, rtol, maxit, it.data(), rr.data(), s);
+            if (c < 0) return c;
+            if (c > 0) rc = c;
+            for (int k = 0; k < K; ++k) {
+                if (iters) iters[k0 + k] = it[k];
+                if (relres) relres[k0 + k] = rr[k];
+            }
+            if (k0 == 0) {
+                H.info.last_iters = it[0];
+                H.info.last_relres = rr[0];
             }
         }
         return rc;

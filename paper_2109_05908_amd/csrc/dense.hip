@@ -306,12 +306,6 @@ struct OpTrmvRed {
 // at or below the columns' diagonal block; its dots go to part[chunk n + j]
 // and OpTrmvTRed sums them.  Short chunks keep every wave's chain of
 // dependent loads short.
-__host__ __device__ inline int trmv_t_tiles(int n) {
-    const int ng = (n + 15) / 16, nch = (n + TRMV_CC - 1) / TRMV_CC;
-    int t = 0;
-    for (int c = 0; c < nch; ++c) t += min(ng, (TRMV_CC / 16) * (c + 1));
-    return t;
-}
 template <class TW>
 struct OpTrmvT {
     const TrmvItemT<TW>* it;

@@ -200,6 +200,13 @@ using TrmvItem32 = TrmvItemT<float>;  // FP32 factor, FP32 arithmetic, FP64 vect
 constexpr int TRMV_RB = 64;    // rows per tile of y = W x
 constexpr int TRMV_CC = 512;   // columns per partial sum of y = W x
 inline int64_t trmv_part_size(int n) { return (int64_t)((n + TRMV_CC - 1) / TRMV_CC) * n; }
+// tiles of x = W^T y: 16 columns by a chunk of TRMV_CC rows at or below their diagonal block
+__host__ __device__ inline int trmv_t_tiles(int n) {
+    const int ng = (n + 15) / 16, nch = (n + TRMV_CC - 1) / TRMV_CC;
+    int t = 0;
+    for (int c = 0; c < nch; ++c) t += min(ng, (TRMV_CC / 16) * (c + 1));
+    return t;
+}
 void trinv_apply_vb(Batch<TrmvItem>& t, hipStream_t s);
 void trinv_apply_vb(Batch<TrmvItem32>& t, hipStream_t s);
 void trmv_n_vb(Batch<TrmvItem>& t, hipStream_t s);  // y := W x   (uses part)

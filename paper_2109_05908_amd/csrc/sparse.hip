@@ -434,21 +434,36 @@ void extract(const CsrDev& A, int N, int delta, int64_t n, const uint8_t* dist, 
 // ===========================================================================
 // vectors
 // ===========================================================================
-// 8 lanes per row, column-major multi-RHS
+// 8 lanes per row, column-major multi-RHS: each matrix entry is read once for
+// up to 8 right-hand sides; every column is summed in the same order as a
+// single right-hand side, so each column's result does not depend on nrhs
 __global__ void k_spmv(CsrDev A, const double* x, double* y, int nrhs) {
     const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t row = gt >> 3;
     const int sub = threadIdx.x & 7;
     if (row >= A.n) return;
     const int b = A.rowptr[row], e = A.rowptr[row + 1];
-    for (int k = 0; k < nrhs; ++k) {
-        const double* xk = x + (int64_t)k * A.n;
-        double s = 0.0;
-        for (int q = b + sub; q < e; q += 8) s += A.val[q] * xk[A.colind[q]];
-        s += __shfl_xor(s, 1, 8);
-        s += __shfl_xor(s, 2, 8);
-        s += __shfl_xor(s, 4, 8);
-        if (sub == 0) y[row + (int64_t)k * A.n] = s;
+    for (int k0 = 0; k0 < nrhs; k0 += 8) {
+        const int kn = min(8, nrhs - k0);
+        const double* xk = x + (int64_t)k0 * A.n;
+        double s[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] = 0.0;
+        for (int q = b + sub; q < e; q += 8) {
+            const double a = A.val[q];
+            const int64_t c = A.colind[q];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < kn) s[k] += a * xk[c + (int64_t)k * A.n];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            double v = s[k];
+            v += __shfl_xor(v, 1, 8);
+            v += __shfl_xor(v, 2, 8);
+            v += __shfl_xor(v, 4, 8);
+            if (sub == 0 && k < kn) y[row + (int64_t)(k0 + k) * A.n] = v;
+        }
     }
 }
 

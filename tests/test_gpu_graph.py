@@ -86,3 +86,26 @@ def test_graph_option_ignored_with_three_levels():
     x0, i0, r0, _ = p0.pcg(b, rtol=1e-10)
     x1, i1, r1, _ = p1.pcg(b, rtol=1e-10)
     assert i0 == i1 and torch.equal(x0, x1)
+
+
+def test_graph_and_block_after_update_values():
+    """dd_update_values replaces the levels of a handle; the PCG graph captured
+    before (and the block state of several right-hand sides) pointed into the
+    old levels' buffers and must be rebuilt: after the update, one and two
+    right-hand sides give bit for bit what a fresh setup on the new values
+    gives."""
+    c0, c1 = W.config_small3d(16, 16, 0), W.config_small3d(16, 16, 1)
+    part = O.ggg_partition(c0.A, c0.N, 0)
+    assert np.array_equal(c0.A.colind, c1.A.colind)
+    b = torch.as_tensor(W.rhs(c0.A.n, 2), device="cuda")
+    B = torch.as_tensor(W.rhs(c0.A.n, 3, nrhs=2).reshape(c0.A.n, 2), device="cuda")
+    pre = Preconditioner(DeviceCSR.from_workload(c0.A), part, c0.N, 2, 0.02, graph_pcg=8)
+    pre.pcg(b, rtol=1e-10)
+    pre.pcg(B, rtol=1e-10)
+    pre.update_values(torch.as_tensor(c1.A.val))
+    fresh = Preconditioner(DeviceCSR.from_workload(c1.A), part, c0.N, 2, 0.02, graph_pcg=8)
+    for rhs in (b, B):
+        x0, i0, r0, _ = fresh.pcg(rhs, rtol=1e-10)
+        x1, i1, r1, _ = pre.pcg(rhs, rtol=1e-10)
+        log(f"[graph] after update_values: its {i1} (fresh setup {i0})")
+        assert i0 == i1 and r0 == r1 and torch.equal(x0, x1)

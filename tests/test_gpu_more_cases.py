@@ -141,3 +141,33 @@ def test_gmres_edge_cases():
     true = np.linalg.norm(b - cfg.A.to_scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
     assert code == 1 and its[0] == 3
     assert abs(true - rr[0]) <= 1e-10 * true and 1e-13 < true < 1.0
+
+
+def test_block_pcg_many_columns():
+    """Eleven right-hand sides in one dd_pcg call run as two groups of at most
+    eight columns in lockstep (A and every local inverse read once per group).
+    With a zero column, a column started from an already converged x0, FP64
+    and FP32 local solves, and a stop at maxit, every column equals its own
+    single call bit for bit (iterations, residual, iterate), and dd_apply on
+    the block equals the column-by-column apply."""
+    cfg = W.config_c1()
+    n = cfg.A.n
+    dA = DeviceCSR.from_workload(cfg.A)
+    B = torch.as_tensor(W.rhs(n, 11, nrhs=11).reshape(n, 11), device="cuda").clone()
+    B[:, 3] = 0.0
+    for prec in (0, DD_FP32):
+        pre = Preconditioner(dA, cfg.part, 16, 1, 0.1, local_prec=prec)
+        xs, _, _, _ = pre.pcg(B[:, 5].contiguous(), rtol=1e-13)
+        X0 = torch.zeros_like(B)
+        X0[:, 5] = xs
+        Z = pre.apply(B)
+        for k in range(11):
+            assert torch.equal(Z[:, k], pre.apply(B[:, k].contiguous()))
+        for rtol, maxit in ((1e-10, 1000), (1e-12, 4)):
+            X, its, rr, code = pre.pcg(B, x0=X0, rtol=rtol, maxit=maxit)
+            for k in range(11):
+                xk, itk, rrk, _ = pre.pcg(B[:, k].contiguous(), x0=X0[:, k].contiguous(), rtol=rtol, maxit=maxit)
+                assert itk[0] == its[k] and rrk[0] == rr[k], (prec, rtol, k, itk, its[k])
+                assert torch.equal(X[:, k], xk)
+            log(f"[more] 11 columns, prec {prec}, rtol {rtol}, maxit {maxit}: code {code}, its {its}")
+            assert its[3] == 0 and rr[3] == 0.0 and its[5] == 0
