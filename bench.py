@@ -40,8 +40,9 @@ PEAK_HBM_GBS = 8000.0
 # sources still hash to what was profiled.
 ROOFLINE_KERNEL = "qr_blk_upd"
 ROOFLINE_SOURCES = ["common.hpp", "dense.hpp", "dense.hip"]
-TRAFFIC = {"sha256": "2b8863b42dd6ed06", "bytes_per_launch": 3.1845e9,
-           "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6"}
+TRAFFIC = {"sha256": "23bc9c5a8ddd54bb", "bytes_per_launch": 3.6646e9, "form": "learned",
+           "workload": "diffusion3d_7pt_64^3_lognormal_sigma2_channels1e6_seed150 (held-out member of the coefficient "
+                       "family)"}
 
 
 def parse():
@@ -54,6 +55,8 @@ def parse():
     p.add_argument("--model", default=os.path.join(ROOT, "paper_2109_05908_amd", "warm_start_c4.json"))
     p.add_argument("--nev", type=int, default=32)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--form", choices=["learned", "plain_fp64"], default="learned",
+                   help="form timed as the value (plain_fp64: the reference form alone, for profiling it)")
     p.add_argument("--no-compare-forms", action="store_true",
                    help="skip the plain FP64 and random-start forms (after the timed steps)")
     p.add_argument("--cpu-reps", type=int, default=5, help="runs of the sampled oracle pool (median)")
@@ -299,7 +302,7 @@ def cpu_baseline_value(host, its):
     return out
 
 
-def roofline(met, workload_name):
+def roofline(met, workload_name, form):
     """Achieved FP64 MFMA rate of the metered kernel: algorithmic flops per
     dispatch / average event-timed dispatch duration, against the FP64 peak."""
     if met["launches"] == 0 or met["total_ms"] <= 0:
@@ -307,7 +310,8 @@ def roofline(met, workload_name):
     avg_ms = met["total_ms"] / met["launches"]
     achieved = met["flops"] / (met["total_ms"] * 1e-3) / 1e12
     traffic = None
-    if TRAFFIC and TRAFFIC["sha256"] == source_hash() and TRAFFIC["workload"] == workload_name:
+    if TRAFFIC and TRAFFIC["sha256"] == source_hash() and TRAFFIC["workload"] == workload_name \
+            and TRAFFIC["form"] == form:
         traffic = TRAFFIC["bytes_per_launch"]
     return {"bound": "mfma", "kernel": "k_tiles<OpBlkUpd> (" + ROOFLINE_KERNEL + ")", "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
@@ -444,9 +448,13 @@ def main():
         del last
         return res, wall, met
 
-    main_res, wall, met = run_form("learned", learned, args.steps, args.warmup, metered=True)
-    forms = {"learned_fp32_graph": main_res}
-    if not args.no_compare_forms:
+    if args.form == "plain_fp64":
+        main_res, wall, met = run_form("plain_fp64", {}, args.steps, args.warmup, metered=True)
+        forms = {"plain_fp64": main_res}
+    else:
+        main_res, wall, met = run_form("learned", learned, args.steps, args.warmup, metered=True)
+        forms = {"learned_fp32_graph": main_res}
+    if not args.no_compare_forms and args.form == "learned":
         forms["plain_fp64"], _, _ = run_form("plain_fp64", {}, args.steps, args.warmup)
         forms["random_start_fp32_graph"], _, _ = run_form("random_start", random_start, args.steps, 0)
         # one production feature taken away at a time
@@ -456,7 +464,8 @@ def main():
     value = main_res["setup_plus_solve_s"]
     conf.update({
         "form": (f"learned warm start (LOBPCG to 1e-4, at most {args.nev} modes per subdomain) + FP32 local "
-                 "factors and solves + PCG as a replayed HIP graph"),
+                 "factors and solves + PCG as a replayed HIP graph") if args.form == "learned" else
+                "plain FP64 (profiling run of the reference form alone)",
         "reference_form": "plain FP64: every mode with lambda > 50, dense eigen route, FP64 local solves, "
                           "host-driven PCG",
         "model": {"file": os.path.relpath(args.model, ROOT), "train_seeds": meta.get("train_seeds"),
@@ -469,7 +478,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * wall / args.steps, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (f32 local factors and solves)",
-        "data": "synthetic", "config": conf, "roofline": roofline(met, conf["workload"]),
+        "data": "synthetic", "config": conf, "roofline": roofline(met, conf["workload"], args.form),
     }
     if host is not None:
         its_plain = forms.get("plain_fp64", main_res)["pcg_iterations"]

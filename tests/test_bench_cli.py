@@ -19,23 +19,26 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 def test_roofline_fields():
     met = {"launches": 4, "total_ms": 2.0, "flops": 4 * 3.0e10, "bytes": 4 * 1.0e9}
-    r = bench.roofline(met, "not-the-profiled-workload")
+    r = bench.roofline(met, "not-the-profiled-workload", "learned")
     assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
     assert abs(r["avg_launch_ms"] - 0.5) < 1e-12
     assert abs(r["achieved"] - 60.0) < 1e-9           # 3e10 flops per 0.5 ms
     assert abs(r["frac"] - 60.0 / 78.6) < 1e-12
     assert abs(r["achieved_algorithmic_GBs"] - 2000.0) < 1e-9
     assert r["traffic"] is None                      # counters were taken on another workload
-    assert bench.roofline({"launches": 0, "total_ms": 0.0, "flops": 0.0, "bytes": 0.0}, "x") is None
+    assert bench.roofline({"launches": 0, "total_ms": 0.0, "flops": 0.0, "bytes": 0.0}, "x", "learned") is None
 
 
 def test_traffic_reported_only_for_the_profiled_sources():
     met = {"launches": 1, "total_ms": 1.0, "flops": 1.0e10, "bytes": 1.0e9}
-    r = bench.roofline(met, bench.TRAFFIC["workload"])
+    r = bench.roofline(met, bench.TRAFFIC["workload"], bench.TRAFFIC["form"])
     if bench.TRAFFIC["sha256"] == bench.source_hash():
         assert r["traffic"] == bench.TRAFFIC["bytes_per_launch"]
     else:
         assert r["traffic"] is None
+    # the counters belong to one form's dispatches: another form on the same matrix gets none
+    other = "plain_fp64" if bench.TRAFFIC["form"] == "learned" else "learned"
+    assert bench.roofline(met, bench.TRAFFIC["workload"], other)["traffic"] is None
 
 
 def test_cpu_baseline_pool_on_a_small_case():
