@@ -317,11 +317,7 @@ static void sets_and_extract(Level& Lv, dd_info_t& info, Timer& tm, Arena& Y, hi
     const CsrDev A = Lv.A();
 
     // ---- a1: sets and index maps -------------------------------------------------
-    DBuf<uint8_t> dist((size_t)n * N);
-    layers(A, Lv.part.p, N, delta, dist.p, s);
-    Lv.counts.alloc(3 * N);
-    layer_counts(dist.p, n, N, delta, Lv.counts.p, s);
-    Lv.hcounts = to_host(Lv.counts.p, 3 * N, s);
+    overlap_sets(A, Lv.part.p, N, delta, Lv.hcounts, Lv.ext, s);
     Lv.nI.resize(N); Lv.nG.resize(N); Lv.nD.resize(N); Lv.ni.resize(N); Lv.nt.resize(N);
     Lv.hoffE.assign(N + 1, 0); Lv.hoffO.assign(N + 1, 0); Lv.hoffI.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) {
@@ -334,19 +330,11 @@ static void sets_and_extract(Level& Lv, dd_info_t& info, Timer& tm, Arena& Y, hi
         Lv.hoffO[i + 1] = Lv.hoffO[i] + Lv.ni[i];
         Lv.hoffI[i + 1] = Lv.hoffI[i] + Lv.nI[i];
     }
+    Lv.counts = upload(Lv.hcounts, s);
     Lv.offE = upload(Lv.hoffE, s);
     Lv.offO = upload(Lv.hoffO, s);
     Lv.offI = upload(Lv.hoffI, s);
-    Lv.ext.alloc(Lv.hoffE[N]);
-    layer_compact(dist.p, n, N, delta, Lv.offE.p, Lv.counts.p, Lv.ext.p, s);
-    {
-        DBuf<int32_t> mc(n);
-        membership_counts(dist.p, n, N, delta, mc.p, s);
-        Lv.memb_ptr.alloc(n + 1);
-        scan_counts(mc.p, n, Lv.memb_ptr.p, s);
-    }
-    Lv.memb.alloc(Lv.hoffO[N]);
-    membership_fill(dist.p, n, N, delta, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, Lv.memb_ptr.p, Lv.memb.p, s);
+    membership(Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, N, n, Lv.memb_ptr, Lv.memb, Lv.hoffO[N], s);
     Lv.omega_flat.alloc(Lv.hoffO[N]);
     Lv.ilocal.alloc(n);
     omega_flatten(N, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, Lv.hoffO[N], Lv.omega_flat.p, Lv.ilocal.p, s);
@@ -369,10 +357,9 @@ static void sets_and_extract(Level& Lv, dd_info_t& info, Timer& tm, Arena& Y, hi
         DBuf<double*> dY(N), dA(N);
         h2d(dY.p, Y.ptr.data(), N, s);
         h2d(dA.p, Lv.L.ptr.data(), N, s);
-        extract(A, N, delta, n, dist.p, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, dY.p, dA.p, Lv.hoffO[N], s);
+        extract(A, N, Lv.offE.p, Lv.offO.p, Lv.counts.p, Lv.ext.p, dY.p, dA.p, Lv.hoffO[N], s);
         DD_HIP(hipStreamSynchronize(s));
     }
-    dist.release();
     info.phase_ms[PH_EXTRACT] += tm.lap();
 }
 

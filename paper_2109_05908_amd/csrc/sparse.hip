@@ -178,76 +178,17 @@ int validate_partition(const int32_t* part, int64_t n, int N, int32_t* dcounts, 
 }
 
 // ===========================================================================
-// Overlap layers
+// Overlap sets by frontier lists (Sec. 2).  Omega_i grows from the part I_i
+// by delta layers of A's graph and Delta_i is the next layer.  Every list is
+// one ascending segment per subdomain of a flat int32 buffer, so memory and
+// work are proportional to the sizes of the sets times their row lengths,
+// whatever the number of subdomains.
 // ===========================================================================
-__global__ void k_dist_init(const int32_t* part, int64_t n, int N, uint8_t* dist) {
-    const int64_t tot = n * (int64_t)N;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / n);
-        const int64_t v = e % n;
-        dist[e] = (part[v] == i) ? 0 : 255;
-    }
-}
 
-// dist[i][v] = k for unvisited v with a neighbour at distance k-1 (writers agree)
-__global__ void k_dist_layer(CsrDev A, int N, int k, uint8_t* dist) {
-    const int64_t n = A.n, tot = n * (int64_t)N;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        if (dist[e] != 255) continue;
-        const int i = (int)(e / n);
-        const int64_t v = e % n;
-        const uint8_t* di = dist + (int64_t)i * n;
-        for (int q = A.rowptr[v]; q < A.rowptr[v + 1]; ++q) {
-            const int c = A.colind[q];
-            if (c != v && di[c] == k - 1) {
-                dist[e] = (uint8_t)k;
-                break;
-            }
-        }
-    }
-}
-
-void layers(const CsrDev& A, const int32_t* part, int N, int delta, uint8_t* dist, hipStream_t s) {
-    const int64_t tot = A.n * (int64_t)N;
-    hipLaunchKernelGGL(k_dist_init, dim3(grid_for(tot)), dim3(256), 0, s, part, A.n, N, dist);
-    for (int k = 1; k <= delta + 1; ++k)
-        hipLaunchKernelGGL(k_dist_layer, dim3(grid_for(tot)), dim3(256), 0, s, A, N, k, dist);
-    launch_check("layers");
-}
-
-__global__ void k_layer_counts(const uint8_t* dist, int64_t n, int delta, int32_t* counts) {
-    const int i = blockIdx.x;
-    const uint8_t* di = dist + (int64_t)i * n;
-    int c0 = 0, c1 = 0, c2 = 0;
-    for (int64_t v = threadIdx.x; v < n; v += blockDim.x) {
-        const int d = di[v];
-        c0 += (d == 0);
-        c1 += (d >= 1 && d <= delta);
-        c2 += (d == delta + 1);
-    }
-    __shared__ int s0, s1, s2;
-    if (threadIdx.x == 0) { s0 = 0; s1 = 0; s2 = 0; }
-    __syncthreads();
-    atomicAdd(&s0, c0);
-    atomicAdd(&s1, c1);
-    atomicAdd(&s2, c2);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        counts[3 * i] = s0;
-        counts[3 * i + 1] = s1;
-        counts[3 * i + 2] = s2;
-    }
-}
-
-void layer_counts(const uint8_t* dist, int64_t n, int N, int delta, int32_t* counts, hipStream_t s) {
-    hipLaunchKernelGGL(k_layer_counts, dim3(N), dim3(256), 0, s, dist, n, delta, counts);
-    launch_check("layer_counts");
-}
-
-// block-wide exclusive scan of a 0/1 flag (256 threads); returns total
-__device__ int block_excl_scan(int flag, int* buf, int& excl) {
+// block-wide exclusive scan of an int value (256 threads); returns the total
+__device__ int block_excl_scan(int v, int* buf, int& excl) {
     const int t = threadIdx.x;
-    buf[t] = flag;
+    buf[t] = v;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
         const int add = (t >= off) ? buf[t - off] : 0;
@@ -255,41 +196,324 @@ __device__ int block_excl_scan(int flag, int* buf, int& excl) {
         buf[t] += add;
         __syncthreads();
     }
-    excl = buf[t] - flag;
+    excl = buf[t] - v;
     const int total = buf[255];
     __syncthreads();
     return total;
 }
 
-__global__ void __launch_bounds__(256) k_layer_compact(const uint8_t* dist, int64_t n, int delta, const int64_t* offE,
-                                                       const int32_t* counts, int32_t* ext) {
-    __shared__ int buf[256];
-    const int i = blockIdx.x;
-    const uint8_t* di = dist + (int64_t)i * n;
-    int32_t* outI = ext + offE[i];
-    int32_t* outG = outI + counts[3 * i];
-    int32_t* outD = outG + counts[3 * i + 1];
-    int b0 = 0, b1 = 0, b2 = 0;
-    for (int64_t v0 = 0; v0 < n; v0 += 256) {
-        const int64_t v = v0 + threadIdx.x;
-        const int d = (v < n) ? di[v] : 255;
-        int e0, e1, e2;
-        const int t0 = block_excl_scan(d == 0, buf, e0);
-        const int t1 = block_excl_scan(d >= 1 && d <= delta, buf, e1);
-        const int t2 = block_excl_scan(d == delta + 1, buf, e2);
-        if (d == 0) outI[b0 + e0] = (int32_t)v;
-        else if (d >= 1 && d <= delta) outG[b1 + e1] = (int32_t)v;
-        else if (d == delta + 1) outD[b2 + e2] = (int32_t)v;
-        b0 += t0;
-        b1 += t1;
-        b2 += t2;
+__device__ int lower_bound_i32(const int32_t* a, int len, int32_t x) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool seg_has(const int32_t* a, int len, int32_t x) {
+    const int p = lower_bound_i32(a, len, x);
+    return p < len && a[p] == x;
+}
+
+// Ascending sort of a[0, len) by one workgroup.  Bitonic network in the form
+// whose first comparator stage of every merge pairs mirrored positions: all
+// comparators then point upwards, so positions at or past len behave as
+// +infinity and their comparators are skipped (any length, no padding).
+__device__ void wg_sort(int32_t* a, int64_t len) {
+    int64_t P = 1;
+    while (P < len) P <<= 1;
+    for (int64_t k = 2; k <= P; k <<= 1) {
+        const int64_t h = k >> 1;
+        for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+            const int64_t i = (t / h) * k + (t % h);
+            const int64_t l = i ^ (k - 1);
+            if (l < len) {
+                const int32_t x = a[i], y = a[l];
+                if (x > y) { a[i] = y; a[l] = x; }
+            }
+        }
+        __syncthreads();
+        for (int64_t j = h >> 1; j > 0; j >>= 1) {
+            for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int64_t i = (t / j) * 2 * j + (t % j);
+                const int64_t l = i + j;
+                if (l < len) {
+                    const int32_t x = a[i], y = a[l];
+                    if (x > y) { a[i] = y; a[l] = x; }
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
-void layer_compact(const uint8_t* dist, int64_t n, int N, int delta, const int64_t* offE, const int32_t* counts,
-                   int32_t* ext, hipStream_t s) {
-    hipLaunchKernelGGL(k_layer_compact, dim3(N), dim3(256), 0, s, dist, n, delta, offE, counts, ext);
-    launch_check("layer_compact");
+constexpr int kSortLds = 8192;
+
+// merges the ascending runs x[0, na) and y[0, nb) into out[0, na + nb), one
+// workgroup: every thread finds its share of the output by a binary search on
+// its diagonal (merge path) and merges that share sequentially
+__device__ void wg_merge(const int32_t* x, int64_t na, const int32_t* y, int64_t nb, int32_t* out) {
+    const int64_t m = na + nb;
+    const int64_t per = (m + blockDim.x - 1) / blockDim.x;
+    const int64_t d0 = min(m, (int64_t)threadIdx.x * per), d1 = min(m, d0 + per);
+    if (d0 >= d1) return;
+    // i = number taken from x among the first d0 outputs
+    int64_t lo = max((int64_t)0, d0 - nb), hi = min(d0, na);
+    while (lo < hi) {
+        const int64_t i = (lo + hi) >> 1;
+        if (x[i] < y[d0 - i - 1]) lo = i + 1; else hi = i;
+    }
+    int64_t i = lo, j = d0 - lo;
+    for (int64_t d = d0; d < d1; ++d) {
+        if (j >= nb || (i < na && x[i] <= y[j])) out[d] = x[i++];
+        else out[d] = y[j++];
+    }
+}
+
+// sorts data[beg[i], end[i]) ascending, one workgroup per segment: in LDS when
+// it fits, else LDS-sized runs merged pairwise through tmp (same offsets)
+__global__ void __launch_bounds__(256) k_seg_sort(int32_t* data, int32_t* tmp, const int64_t* beg,
+                                                  const int64_t* end) {
+    __shared__ int32_t sm[kSortLds];
+    const int i = blockIdx.x;
+    int32_t* a = data + beg[i];
+    const int64_t len = end[i] - beg[i];
+    if (len < 2) return;
+    for (int64_t c0 = 0; c0 < len; c0 += kSortLds) {
+        const int64_t cl = min((int64_t)kSortLds, len - c0);
+        for (int64_t p = threadIdx.x; p < cl; p += blockDim.x) sm[p] = a[c0 + p];
+        __syncthreads();
+        wg_sort(sm, cl);
+        for (int64_t p = threadIdx.x; p < cl; p += blockDim.x) a[c0 + p] = sm[p];
+        __syncthreads();
+    }
+    if (len <= kSortLds) return;
+    int32_t* src = a;
+    int32_t* dst = tmp + beg[i];
+    for (int64_t w = kSortLds; w < len; w *= 2) {
+        for (int64_t x0 = 0; x0 < len; x0 += 2 * w) {
+            const int64_t na = min(w, len - x0);
+            const int64_t nb = min(w, len - x0 - na);
+            wg_merge(src + x0, na, src + x0 + na, nb, dst + x0);
+        }
+        __syncthreads();
+        int32_t* t = src; src = dst; dst = t;
+    }
+    if (src != a)
+        for (int64_t p = threadIdx.x; p < len; p += blockDim.x) a[p] = src[p];
+}
+
+// tmp: scratch of the same extent as data (used only by segments longer than kSortLds)
+static void seg_sort(int32_t* data, int32_t* tmp, const int64_t* beg, const int64_t* end, int nseg,
+                     hipStream_t s) {
+    if (nseg > 0) hipLaunchKernelGGL(k_seg_sort, dim3(nseg), dim3(256), 0, s, data, tmp, beg, end);
+    launch_check("seg_sort");
+}
+
+__global__ void k_part_hist(const int32_t* part, int64_t n, int32_t* cnt) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[part[v]], 1);
+}
+
+__global__ void k_part_place(const int32_t* part, int64_t n, const int64_t* off, int32_t* cursor, int32_t* L) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int i = part[v];
+        L[off[i] + atomicAdd(&cursor[i], 1)] = (int32_t)v;
+    }
+}
+
+// a neighbour of a vertex at distance k-1 is at distance k-2, k-1 or k: the
+// candidates of layer k are the neighbours of layer k-1 (L1) found neither in
+// L1 nor in layer k-2 (L2, may be null)
+struct Frontier {
+    const int32_t* L1;
+    const int64_t* off1;
+    const int32_t* L2;
+    const int64_t* off2;
+    __device__ bool fresh(int i, int32_t c) const {
+        if (seg_has(L1 + off1[i], (int)(off1[i + 1] - off1[i]), c)) return false;
+        return !(L2 && seg_has(L2 + off2[i], (int)(off2[i + 1] - off2[i]), c));
+    }
+};
+
+// cnt[i] = number of candidate entries (with repeats) of subdomain i
+__global__ void __launch_bounds__(256) k_front_len(CsrDev A, Frontier F, int64_t* cnt) {
+    __shared__ int64_t red[256];
+    const int i = blockIdx.x;
+    int64_t acc = 0;
+    for (int64_t p = F.off1[i] + threadIdx.x; p < F.off1[i + 1]; p += blockDim.x) {
+        const int32_t u = F.L1[p];
+        for (int q = A.rowptr[u]; q < A.rowptr[u + 1]; ++q) acc += F.fresh(i, A.colind[q]);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[i] = red[0];
+}
+
+// cand[coff[i] ...] = the candidate entries, in frontier and row order
+__global__ void __launch_bounds__(256) k_front_fill(CsrDev A, Frontier F, const int64_t* coff, int32_t* cand) {
+    __shared__ int buf[256];
+    const int i = blockIdx.x;
+    int64_t base = coff[i];
+    for (int64_t p0 = F.off1[i]; p0 < F.off1[i + 1]; p0 += 256) {
+        const int64_t p = p0 + threadIdx.x;
+        int cnt = 0, r0 = 0, r1 = 0;
+        if (p < F.off1[i + 1]) {
+            const int32_t u = F.L1[p];
+            r0 = A.rowptr[u];
+            r1 = A.rowptr[u + 1];
+            for (int q = r0; q < r1; ++q) cnt += F.fresh(i, A.colind[q]);
+        }
+        int e;
+        const int tot = block_excl_scan(cnt, buf, e);
+        for (int q = r0; q < r1; ++q) {
+            const int32_t c = A.colind[q];
+            if (F.fresh(i, c)) cand[base + e++] = c;
+        }
+        base += tot;
+    }
+}
+
+// In place on each sorted candidate segment: keep the first copy of every
+// vertex; kept[i] = the new length
+__global__ void __launch_bounds__(256) k_front_unique(int32_t* cand, const int64_t* coff, int32_t* kept) {
+    __shared__ int buf[256];
+    __shared__ int32_t lastv;
+    const int i = blockIdx.x;
+    int32_t* c = cand + coff[i];
+    const int64_t len = coff[i + 1] - coff[i];
+    int64_t base = 0;
+    for (int64_t p0 = 0; p0 < len; p0 += 256) {
+        const int64_t p = p0 + threadIdx.x;
+        int32_t x = 0;
+        int keep = 0;
+        if (p < len) {
+            x = c[p];
+            keep = (p == 0) || ((threadIdx.x > 0 ? c[p - 1] : lastv) != x);
+        }
+        __syncthreads();  // every read of this chunk (and of lastv) is done
+        if (threadIdx.x == 255) lastv = x;
+        int e;
+        const int tot = block_excl_scan(keep, buf, e);  // writes land below p0 + 256, reads come from above
+        if (keep) c[base + e] = x;
+        base += tot;
+    }
+    if (threadIdx.x == 0) kept[i] = (int32_t)base;
+}
+
+// dst[dbeg[i] + r] = src[sbeg[i] + r] for r < loff[i+1] - loff[i]
+__global__ void k_seg_place(const int32_t* src, const int64_t* sbeg, const int64_t* loff, const int64_t* dbeg,
+                            int32_t* dst) {
+    const int i = blockIdx.x;
+    const int64_t len = loff[i + 1] - loff[i];
+    for (int64_t r = threadIdx.x; r < len; r += blockDim.x) dst[dbeg[i] + r] = src[sbeg[i] + r];
+}
+
+namespace {
+// one list per subdomain: flat buffer plus host and device offsets
+struct SegLists {
+    DBuf<int32_t> v;
+    std::vector<int64_t> hoff;
+    DBuf<int64_t> off;
+    int64_t len(int i) const { return hoff[i + 1] - hoff[i]; }
+};
+
+std::vector<int64_t> prefix(const std::vector<int64_t>& c) {
+    std::vector<int64_t> o(c.size() + 1, 0);
+    for (size_t i = 0; i < c.size(); ++i) o[i + 1] = o[i] + c[i];
+    return o;
+}
+}  // namespace
+
+void overlap_sets(const CsrDev& A, const int32_t* part, int N, int delta, std::vector<int32_t>& hcounts,
+                  DBuf<int32_t>& ext, hipStream_t s) {
+    const int64_t n = A.n;
+    std::vector<SegLists> L(delta + 2);
+    // layer 0: the part of every subdomain, ascending
+    {
+        DBuf<int32_t> cnt(N), cur(N);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(N)), dim3(256), 0, s, cnt.p, (int64_t)N, 0);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(N)), dim3(256), 0, s, cur.p, (int64_t)N, 0);
+        hipLaunchKernelGGL(k_part_hist, dim3(grid_for(n)), dim3(256), 0, s, part, n, cnt.p);
+        std::vector<int32_t> h(N);
+        d2h(h.data(), cnt.p, N, s);
+        DD_HIP(hipStreamSynchronize(s));
+        L[0].hoff = prefix(std::vector<int64_t>(h.begin(), h.end()));
+        L[0].off = upload(L[0].hoff, s);
+        L[0].v.alloc(n);
+        hipLaunchKernelGGL(k_part_place, dim3(grid_for(n)), dim3(256), 0, s, part, n, L[0].off.p, cur.p, L[0].v.p);
+        DBuf<int32_t> tmp(n);
+        seg_sort(L[0].v.p, tmp.p, L[0].off.p, L[0].off.p + 1, N, s);
+        DD_HIP(hipStreamSynchronize(s));  // tmp is released here
+    }
+    // layer k: the neighbours of layer k-1 outside layers k-1 and k-2
+    for (int k = 1; k <= delta + 1; ++k) {
+        const SegLists* G = (k >= 2) ? &L[k - 2] : nullptr;
+        const Frontier F{L[k - 1].v.p, L[k - 1].off.p, G ? G->v.p : nullptr, G ? G->off.p : nullptr};
+        DBuf<int64_t> cl(N);
+        hipLaunchKernelGGL(k_front_len, dim3(N), dim3(256), 0, s, A, F, cl.p);
+        std::vector<int64_t> hc(N);
+        d2h(hc.data(), cl.p, N, s);
+        DD_HIP(hipStreamSynchronize(s));
+        const std::vector<int64_t> hcoff = prefix(hc);
+        DBuf<int64_t> coff = upload(hcoff, s);
+        DBuf<int32_t> cand(hcoff[N]), tmp(hcoff[N]);
+        hipLaunchKernelGGL(k_front_fill, dim3(N), dim3(256), 0, s, A, F, coff.p, cand.p);
+        seg_sort(cand.p, tmp.p, coff.p, coff.p + 1, N, s);
+        DBuf<int32_t> kept(N);
+        hipLaunchKernelGGL(k_front_unique, dim3(N), dim3(256), 0, s, cand.p, coff.p, kept.p);
+        std::vector<int32_t> hk(N);
+        d2h(hk.data(), kept.p, N, s);
+        DD_HIP(hipStreamSynchronize(s));
+        L[k].hoff = prefix(std::vector<int64_t>(hk.begin(), hk.end()));
+        L[k].off = upload(L[k].hoff, s);
+        L[k].v.alloc(L[k].hoff[N]);
+        hipLaunchKernelGGL(k_seg_place, dim3(N), dim3(256), 0, s, cand.p, coff.p, L[k].off.p, L[k].off.p,
+                           L[k].v.p);
+        DD_HIP(hipStreamSynchronize(s));  // cand, tmp and coff are released on return
+    }
+    launch_check("overlap layers");
+
+    // ext[offE[i] ...] = [I_i, Gamma_i (layers 1..delta merged), Delta_i (layer delta+1)]
+    hcounts.assign(3 * (size_t)N, 0);
+    std::vector<int64_t> offE(N + 1, 0);
+    for (int i = 0; i < N; ++i) {
+        int64_t g = 0;
+        for (int k = 1; k <= delta; ++k) g += L[k].len(i);
+        hcounts[3 * i] = (int32_t)L[0].len(i);
+        hcounts[3 * i + 1] = (int32_t)g;
+        hcounts[3 * i + 2] = (int32_t)L[delta + 1].len(i);
+        offE[i + 1] = offE[i] + L[0].len(i) + g + L[delta + 1].len(i);
+    }
+    ext.alloc(offE[N]);
+    std::vector<int64_t> dst(N), gbeg(N), gend(N);
+    for (int k = 0; k <= delta + 1; ++k) {
+        for (int i = 0; i < N; ++i) {
+            int64_t at = offE[i];
+            for (int q = 0; q < k; ++q) at += L[q].len(i);
+            dst[i] = at;
+        }
+        DBuf<int64_t> ddst = upload(dst, s);
+        hipLaunchKernelGGL(k_seg_place, dim3(N), dim3(256), 0, s, L[k].v.p, L[k].off.p, L[k].off.p, ddst.p,
+                           ext.p);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    if (delta >= 2) {  // Gamma_i gathers several ascending layers
+        for (int i = 0; i < N; ++i) {
+            gbeg[i] = offE[i] + hcounts[3 * i];
+            gend[i] = gbeg[i] + hcounts[3 * i + 1];
+        }
+        DBuf<int64_t> db = upload(gbeg, s), de = upload(gend, s);
+        DBuf<int32_t> tmp(offE[N]);
+        seg_sort(ext.p, tmp.p, db.p, de.p, N, s);
+        DD_HIP(hipStreamSynchronize(s));
+    }
+    launch_check("overlap sets");
 }
 
 __global__ void __launch_bounds__(256) k_scan_counts(const int32_t* counts, int64_t n, int64_t* off) {
@@ -321,53 +545,59 @@ void scan_counts(const int32_t* counts, int64_t n, int64_t* offsets, hipStream_t
     launch_check("scan_counts");
 }
 
-__global__ void k_memb_counts(const uint8_t* dist, int64_t n, int N, int delta, int32_t* cnt) {
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-        int c = 0;
-        for (int i = 0; i < N; ++i) c += (dist[(int64_t)i * n + g] <= delta);
-        cnt[g] = c;
+// cnt[g] += 1 for every g of Omega_i = I_i u Gamma_i, one workgroup per subdomain
+__global__ void k_memb_count(const int64_t* offE, const int32_t* counts, const int32_t* ext, int32_t* cnt) {
+    const int i = blockIdx.x;
+    const int ni = counts[3 * i] + counts[3 * i + 1];
+    for (int r = threadIdx.x; r < ni; r += blockDim.x) atomicAdd(&cnt[ext[offE[i] + r]], 1);
+}
+
+__global__ void k_memb_place(const int64_t* offE, const int64_t* offO, const int32_t* counts, const int32_t* ext,
+                             const int64_t* memb_ptr, int32_t* cursor, int64_t* memb) {
+    const int i = blockIdx.x;
+    const int ni = counts[3 * i] + counts[3 * i + 1];
+    for (int r = threadIdx.x; r < ni; r += blockDim.x) {
+        const int32_t g = ext[offE[i] + r];
+        memb[memb_ptr[g] + atomicAdd(&cursor[g], 1)] = offO[i] + r;
     }
 }
 
-void membership_counts(const uint8_t* dist, int64_t n, int N, int delta, int32_t* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_memb_counts, dim3(grid_for(n)), dim3(256), 0, s, dist, n, N, delta, cnt);
-    launch_check("memb_counts");
-}
-
-__device__ int lower_bound_i32(const int32_t* a, int len, int32_t x) {
-    int lo = 0, hi = len;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < x) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// local index of global g inside Omega~_i given its layer value
-__device__ __forceinline__ int local_index(const int32_t* exti, const int32_t* cnt3, int d, int delta, int32_t g) {
-    const int nI = cnt3[0], nG = cnt3[1], nD = cnt3[2];
-    if (d == 0) return lower_bound_i32(exti, nI, g);
-    if (d <= delta) return nI + lower_bound_i32(exti + nI, nG, g);
-    return nI + nG + lower_bound_i32(exti + nI + nG, nD, g);
-}
-
-__global__ void k_memb_fill(const uint8_t* dist, int64_t n, int N, int delta, const int64_t* offE, const int64_t* offO,
-                            const int32_t* counts, const int32_t* ext, const int64_t* memb_ptr, int64_t* memb) {
+// every node's list ascending (heap sort per thread); positions grow with the
+// subdomain index, so this is subdomain order
+__global__ void k_memb_sort(const int64_t* memb_ptr, int64_t n, int64_t* memb) {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-        int64_t pos = memb_ptr[g];
-        for (int i = 0; i < N; ++i) {
-            const int d = dist[(int64_t)i * n + g];
-            if (d <= delta) memb[pos++] = offO[i] + local_index(ext + offE[i], counts + 3 * i, d, delta, (int32_t)g);
+        int64_t* a = memb + memb_ptr[g];
+        const int64_t m = memb_ptr[g + 1] - memb_ptr[g];
+        auto sift = [a](int64_t r, int64_t end) {
+            while (2 * r + 1 < end) {
+                int64_t c = 2 * r + 1;
+                if (c + 1 < end && a[c] < a[c + 1]) ++c;
+                if (a[r] >= a[c]) return;
+                const int64_t t = a[r]; a[r] = a[c]; a[c] = t;
+                r = c;
+            }
+        };
+        for (int64_t r = m / 2 - 1; r >= 0; --r) sift(r, m);
+        for (int64_t end = m - 1; end > 0; --end) {
+            const int64_t t = a[0]; a[0] = a[end]; a[end] = t;
+            sift(0, end);
         }
     }
 }
 
-void membership_fill(const uint8_t* dist, int64_t n, int N, int delta, const int64_t* offE, const int64_t* offO,
-                     const int32_t* counts, const int32_t* ext, const int64_t* memb_ptr, int64_t* memb,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_memb_fill, dim3(grid_for(n)), dim3(256), 0, s, dist, n, N, delta, offE, offO, counts, ext,
-                       memb_ptr, memb);
-    launch_check("memb_fill");
+void membership(const int64_t* offE, const int64_t* offO, const int32_t* counts, const int32_t* ext, int N,
+                int64_t n, DBuf<int64_t>& memb_ptr, DBuf<int64_t>& memb, int64_t total, hipStream_t s) {
+    DBuf<int32_t> cnt(n);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, cnt.p, n, 0);
+    hipLaunchKernelGGL(k_memb_count, dim3(N), dim3(256), 0, s, offE, counts, ext, cnt.p);
+    memb_ptr.alloc(n + 1);
+    scan_counts(cnt.p, n, memb_ptr.p, s);
+    memb.alloc(total);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, cnt.p, n, 0);
+    hipLaunchKernelGGL(k_memb_place, dim3(N), dim3(256), 0, s, offE, offO, counts, ext, memb_ptr.p, cnt.p, memb.p);
+    hipLaunchKernelGGL(k_memb_sort, dim3(grid_for(n)), dim3(256), 0, s, memb_ptr.p, n, memb.p);
+    DD_HIP(hipStreamSynchronize(s));  // cnt is released on return
+    launch_check("membership");
 }
 
 // one block per subdomain
@@ -388,12 +618,23 @@ void omega_flatten(int N, const int64_t* offE, const int64_t* offO, const int32_
     launch_check("omega_flatten");
 }
 
+// local index of g in Omega~_i = [I_i, Gamma_i, Delta_i] (each ascending), -1 if absent
+__device__ __forceinline__ int local_index(const int32_t* exti, const int32_t* cnt3, int32_t g) {
+    const int nI = cnt3[0], nG = cnt3[1], nD = cnt3[2];
+    int p = lower_bound_i32(exti, nI, g);
+    if (p < nI && exti[p] == g) return p;
+    p = lower_bound_i32(exti + nI, nG, g);
+    if (p < nG && exti[nI + p] == g) return nI + p;
+    p = lower_bound_i32(exti + nI + nG, nD, g);
+    if (p < nD && exti[nI + nG + p] == g) return nI + nG + p;
+    return -1;
+}
+
 // ===========================================================================
 // Extraction of dense X_i^T and A_ii (3.1), one thread per local row
 // ===========================================================================
-__global__ void k_extract(CsrDev A, int N, int delta, int64_t n, const uint8_t* dist, const int64_t* offE,
-                          const int64_t* offO, const int32_t* counts, const int32_t* ext, double* const* Y,
-                          double* const* Aii, int64_t total) {
+__global__ void k_extract(CsrDev A, int N, const int64_t* offE, const int64_t* offO, const int32_t* counts,
+                          const int32_t* ext, double* const* Y, double* const* Aii, int64_t total) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
         // subdomain i with offO[i] <= q < offO[i+1]
         int lo = 0, hi = N;
@@ -408,14 +649,11 @@ __global__ void k_extract(CsrDev A, int N, int delta, int64_t n, const uint8_t* 
         const int nt = ni + cnt3[2];
         const int32_t* exti = ext + offE[i];
         const int32_t g = exti[r];
-        const uint8_t* di = dist + (int64_t)i * n;
         double* Yi = Y[i];
         double* Ai = Aii[i];
         for (int e = A.rowptr[g]; e < A.rowptr[g + 1]; ++e) {
-            const int32_t c = A.colind[e];
-            const int d = di[c];
-            if (d > delta + 1) continue;  // cannot happen for rows of Omega_i (kept for safety)
-            const int lc = local_index(exti, cnt3, d, delta, c);
+            const int lc = local_index(exti, cnt3, A.colind[e]);
+            if (lc < 0) continue;  // cannot happen for rows of Omega_i (kept for safety)
             const double a = A.val[e];
             Yi[lc + (int64_t)r * nt] = a;       // Y = X^T: Y(lc, r) = X(r, lc)
             if (lc < ni) Ai[r + (int64_t)lc * ni] = a;
@@ -423,14 +661,12 @@ __global__ void k_extract(CsrDev A, int N, int delta, int64_t n, const uint8_t* 
     }
 }
 
-void extract(const CsrDev& A, int N, int delta, int64_t n, const uint8_t* dist, const int64_t* offE,
-             const int64_t* offO, const int32_t* counts, const int32_t* ext, double* const* Y, double* const* Aii,
-             int64_t total_rows, hipStream_t s) {
-    hipLaunchKernelGGL(k_extract, dim3(grid_for(total_rows)), dim3(256), 0, s, A, N, delta, n, dist, offE, offO,
-                       counts, ext, Y, Aii, total_rows);
+void extract(const CsrDev& A, int N, const int64_t* offE, const int64_t* offO, const int32_t* counts,
+             const int32_t* ext, double* const* Y, double* const* Aii, int64_t total_rows, hipStream_t s) {
+    hipLaunchKernelGGL(k_extract, dim3(grid_for(total_rows)), dim3(256), 0, s, A, N, offE, offO, counts, ext, Y, Aii,
+                       total_rows);
     launch_check("extract");
 }
-
 // ===========================================================================
 // vectors
 // ===========================================================================

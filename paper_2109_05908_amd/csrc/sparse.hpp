@@ -2,6 +2,8 @@
 #pragma once
 #include "common.hpp"
 
+#include <vector>
+
 namespace dd {
 
 struct CsrDev {
@@ -22,24 +24,21 @@ void ggg_partition_noalloc(const CsrDev& A, int N, uint64_t seed, int32_t* part,
 // --- validation: every id in [0, N); counts per part (device int32[N]) ---
 int validate_partition(const int32_t* part, int64_t n, int N, int32_t* dcounts, hipStream_t s);
 
-// --- overlap layers: dist[i*n + v] in {0..delta+1, 255} ---
-void layers(const CsrDev& A, const int32_t* part, int N, int delta, uint8_t* dist, hipStream_t s);
-// counts[3*i + {0,1,2}] = |I_i|, |Gamma_i|, |Delta_i|
-void layer_counts(const uint8_t* dist, int64_t n, int N, int delta, int32_t* counts, hipStream_t s);
-// ext[offE[i] + ...] = [I_i, Gamma_i, Delta_i] each ascending
-void layer_compact(const uint8_t* dist, int64_t n, int N, int delta, const int64_t* offE, const int32_t* counts,
-                   int32_t* ext, hipStream_t s);
+// --- overlap sets by frontier lists (one ascending segment per subdomain) ---
+// hcounts[3*i + {0,1,2}] = |I_i|, |Gamma_i|, |Delta_i| (host); ext (allocated
+// here) holds [I_i, Gamma_i, Delta_i], each ascending, at offsets that are the
+// prefix sums of the three counts.
+void overlap_sets(const CsrDev& A, const int32_t* part, int N, int delta, std::vector<int32_t>& hcounts,
+                  DBuf<int32_t>& ext, hipStream_t s);
 
 // Exclusive prefix sum of int32 counts into int64 offsets (n+1 entries), one workgroup.
 void scan_counts(const int32_t* counts, int64_t n, int64_t* offsets, hipStream_t s);
 
 // Membership of every node: memb_ptr[g]..memb_ptr[g+1] lists positions (in the
 // concatenated Omega buffer, offO[i] + local index) of the subdomains containing g,
-// in subdomain order.
-void membership_counts(const uint8_t* dist, int64_t n, int N, int delta, int32_t* cnt, hipStream_t s);
-void membership_fill(const uint8_t* dist, int64_t n, int N, int delta, const int64_t* offE, const int64_t* offO,
-                     const int32_t* counts, const int32_t* ext, const int64_t* memb_ptr, int64_t* memb,
-                     hipStream_t s);
+// in subdomain order; total = offO[N].  Both buffers are allocated here.
+void membership(const int64_t* offE, const int64_t* offO, const int32_t* counts, const int32_t* ext, int N,
+                int64_t n, DBuf<int64_t>& memb_ptr, DBuf<int64_t>& memb, int64_t total, hipStream_t s);
 
 // omega_flat[offO[i] + r] = Omega_i[r]; ilocal[g] = position of g in I_{part[g]}
 void omega_flatten(int N, const int64_t* offE, const int64_t* offO, const int32_t* counts, const int32_t* ext,
@@ -47,9 +46,8 @@ void omega_flatten(int N, const int64_t* offE, const int64_t* offO, const int32_
 
 // Dense Y_i = X_i^T (nt x ni, ld nt) and A_ii (ni x ni, ld ni) from CSR rows;
 // buffers zero-filled by the caller.
-void extract(const CsrDev& A, int N, int delta, int64_t n, const uint8_t* dist, const int64_t* offE,
-             const int64_t* offO, const int32_t* counts, const int32_t* ext, double* const* Y, double* const* Aii,
-             int64_t total_rows, hipStream_t s);
+void extract(const CsrDev& A, int N, const int64_t* offE, const int64_t* offO, const int32_t* counts,
+             const int32_t* ext, double* const* Y, double* const* Aii, int64_t total_rows, hipStream_t s);
 
 // --- vectors ---
 void spmv(const CsrDev& A, const double* x, double* y, int nrhs, hipStream_t s);
