@@ -387,3 +387,34 @@ def config_small_elasticity(m: int = 10, p: int = 2, levels: int = 2, nev_cap: i
 def log_uniform_sizes(count: int, lo: float, hi: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))
+
+
+# --------------------------------------------------------------------------
+# Batch of independent systems of uneven size (the many-systems workload)
+# --------------------------------------------------------------------------
+C5_KINDS = ("poisson2d_5pt", "diffusion3d_7pt_contrast1e6", "elasticity3d_layered")
+
+
+def batch_system(kind: str, n_target: float, seed: int) -> CSR:
+    """One system of the batch, sized as close to n_target unknowns as its grid allows:
+    the 5-point Laplacian on an m x m grid, the 7-point log-normal diffusion with 1e6
+    channels on m^3 nodes (coefficient seed `seed`), or the layered elasticity on m^3
+    nodes (3 m^2 (m-1) unknowns after the clamped face)."""
+    if kind == "poisson2d_5pt":
+        return poisson2d(max(8, int(round(math.sqrt(n_target)))))
+    if kind == "diffusion3d_7pt_contrast1e6":
+        return diffusion3d(max(6, int(round(n_target ** (1.0 / 3.0)))), seed)
+    if kind == "elasticity3d_layered":
+        m = max(6, int(round((n_target / 3.0) ** (1.0 / 3.0))))
+        while m > 6 and 3 * m * m * (m - 1) > 1.05 * n_target:
+            m -= 1
+        return elasticity3d(m)
+    raise ValueError(kind)
+
+
+def batch_plan(count: int = 64, lo: float = 2e4, hi: float = 5e5, seed: int = 0) -> list[tuple[str, float, int]]:
+    """(kind, target size, coefficient seed) of every system: sizes log-uniform in [lo, hi]
+    (seeded), kinds in turn 2-D 5-point, 3-D high-contrast 7-point, 3-D elasticity."""
+    sizes = log_uniform_sizes(count, lo, hi, seed)
+    return [(C5_KINDS[j % 3], float(sizes[j]), 1000 + j) for j in range(count)]
+
