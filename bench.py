@@ -591,12 +591,16 @@ def main():
         main_res, wall, met = run_form("learned", learned, args.steps, args.warmup, metered=True)
         forms = {"learned_fp32_graph": main_res}
     if not args.no_compare_forms and args.form == "learned":
-        forms["plain_fp64"], _, _ = run_form("plain_fp64", {}, args.steps, args.warmup)
-        forms["random_start_fp32_graph"], _, _ = run_form("random_start", random_start, args.steps, 0)
+        # the comparison forms run after the timed steps, at most 3 steps each (medians), so that a
+        # long timed run does not hold the GPU five times as long
+        cs = min(args.steps, 3)
+        forms["plain_fp64"], _, _ = run_form("plain_fp64", {}, cs, 0)
+        forms["random_start_fp32_graph"], _, _ = run_form("random_start", random_start, cs, 0)
         # one production feature taken away at a time
         forms["learned_fp64_local_graph"], _, _ = run_form("learned_fp64_local", dict(learned, local_prec=DD_FP64),
-                                                           args.steps, 0)
-        forms["learned_fp32_host_pcg"], _, _ = run_form("learned_host_pcg", dict(learned, graph_pcg=0), args.steps, 0)
+                                                           cs, 0)
+        forms["learned_fp32_host_pcg"], _, _ = run_form("learned_host_pcg", dict(learned, graph_pcg=0), cs, 0)
+        conf["comparison_form_steps"] = cs
     value = main_res["setup_plus_solve_s"]
     conf.update({
         "form": (f"learned warm start (LOBPCG to 1e-4, at most {args.nev} modes per subdomain) + FP32 local "
