@@ -347,7 +347,8 @@ def main_batch(args):
     """The many-systems workload: every system partitioned by seeded graph growing into parts of
     about 1024 unknowns, overlap 1, lambda > 50, 2 levels; consecutive systems grouped into waves
     of at most --wave-dofs unknowns, each wave one batch handle (dd_setup_batch) solved for its
-    right-hand sides by dd_pcg (one PCG per system and column, systems in lockstep).  A form's
+    right-hand sides by dd_pcg (one PCG per system and column, systems in lockstep; the learned
+    form replays the iteration as a HIP graph).  A form's
     time is the sum over the waves of setup + solve; matrices, partitions and right-hand sides
     are on the GPU before each wave's clock starts."""
     import numpy as np
@@ -379,7 +380,8 @@ def main_batch(args):
 
     model, meta = load_model(args.model)
     form_opts = {"learned": dict(select=DD_SEL_THRESHOLD_CAP, nev_cap=args.nev, eig_solver=DD_EIG_LOBPCG,
-                                 lobpcg_tol=1e-4, warm_start=DD_START_MODEL, model=model, local_prec=DD_FP32),
+                                 lobpcg_tol=1e-4, warm_start=DD_START_MODEL, model=model, local_prec=DD_FP32,
+                                 graph_pcg=8),
                  "plain_fp64": {}}
     names = ["learned", "plain_fp64"] if args.batch_form == "both" else [args.batch_form]
 
@@ -451,7 +453,8 @@ def main_batch(args):
             "waves": len(waves), "wave_dofs_max": args.wave_dofs, "nrhs_per_system": args.nrhs,
             "solver": "dd_pcg on each batch handle: one PCG per system and right-hand side, systems in lockstep",
             "learned_form": "learned warm start (LOBPCG to 1e-4, at most 32 modes per subdomain) + FP32 local "
-                            "factors and solves, autotuned launch mapping",
+                            "factors and solves + PCG as a replayed HIP graph with per-system scalars, autotuned "
+                            "launch mapping",
             "forms": results}
     if len(names) == 2:
         conf["speedup_vs_plain_fp64"] = results["plain_fp64"]["setup_plus_solve_s"] / first["setup_plus_solve_s"]

@@ -95,12 +95,13 @@ typedef struct {
                              eigenvalue of K = S~^{-1} (above its rounding floor; 0: 1e-8); DD_EIG_LOBPCG_MATFREE,
                              absolute residual of S~, whose norm is <= 1 (0: 1e-12) */
     int32_t warm_start;   /* LOBPCG start block: DD_START_RANDOM (default), DD_START_RANGE or DD_START_MODEL */
-    int32_t graph_pcg;    /* 1..64: dd_pcg on a two-level additive handle with one system runs each iteration
-                             as one captured HIP graph (alpha, beta and the stopping test on the device),
-                             replayed in batches of at most graph_pcg between host checks, each batch sized from
-                             the residual contraction so that few iterations run past the stop; the iterates are
-                             those of the host-driven loop, bit for bit.  0 (default): host-driven.  Other
-                             handles ignore it. */
+    int32_t graph_pcg;    /* 1..64: dd_pcg on a two-level additive handle runs each iteration as one captured
+                             HIP graph (alpha, beta and the stopping test on the device), replayed in batches of
+                             at most graph_pcg between host checks, each batch sized from the residual
+                             contraction so that few iterations run past the stop; the iterates are those of
+                             the host-driven loop, bit for bit.  A batch handle (dd_setup_batch) keeps one set
+                             of scalars and one stopping test per system.  0 (default): host-driven.  Handles
+                             with more levels ignore it. */
     uint64_t seed;        /* seed of the Gaussian draws of the start blocks */
     const void* warm_start_model; /* DD_START_MODEL: a dd_model (dd_model_create); NULL falls back to random */
     int32_t reserved[8];

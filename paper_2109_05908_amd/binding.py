@@ -320,7 +320,8 @@ class Preconditioner:
     def batch(cls, As, parts, Ns, overlap: int, tau: float, levels: int = 2, local_prec: int = DD_FP64,
               select: int = DD_SEL_THRESHOLD, nev_cap: int = 0, validate: bool = False, coarsen: int = 0,
               schwarz: int = DD_SCHWARZ_ADDITIVE, eig_solver: int = DD_EIG_DENSE, lobpcg_maxit: int = 0,
-              lobpcg_tol: float = 0.0, warm_start: int = DD_START_RANDOM, seed: int = 0, model=None):
+              lobpcg_tol: float = 0.0, warm_start: int = DD_START_RANDOM, seed: int = 0, model=None,
+              graph_pcg: int = 0):
         """dd_setup_batch: independent systems As[j] (DeviceCSR) with partitions
         parts[j] into Ns[j] parts, one handle over their block-diagonal union.
         Vectors are the systems concatenated; pcg returns per-system counts."""
@@ -332,7 +333,7 @@ class Preconditioner:
         pp = (C.c_void_p * k)(*[t.data_ptr() for t in tparts])
         ns = (C.c_int32 * k)(*[int(x) for x in Ns])
         opts = _opts(local_prec, select, nev_cap, validate, coarsen, schwarz, eig_solver, lobpcg_maxit, lobpcg_tol,
-                     warm_start, seed, model)
+                     warm_start, seed, model, graph_pcg)
         h = C.c_void_p()
         self = cls.__new__(cls)
         self._model = model

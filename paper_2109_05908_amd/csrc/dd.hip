@@ -217,10 +217,11 @@ struct Level {
 enum GSlot { G_RZ, G_PQ, G_ALPHA, G_RN2, G_RZN, G_BETA, G_THR, G_ITS, G_STATE, G_MAXIT, G_NSLOT };
 struct GraphPcg {
     int chunk = 0;
+    int ns = 1;                // systems (a batch handle: one set of slots per system, S[slot * ns + k])
     hipStream_t cs = nullptr;  // capture stream (default priority)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    DBuf<double> S;            // G_NSLOT device scalars
+    DBuf<double> S;            // G_NSLOT x ns device scalars
     double* hS = nullptr;      // pinned copy
     GraphPcg() = default;
     GraphPcg(const GraphPcg&) = delete;
@@ -2390,6 +2391,173 @@ static int krylov_seg(Handle& H, size_t m, const double* b, double* x, double rt
     return all ? DD_OK : DD_WARN_MAXIT;
 }
 
+// The graph PCG of a batch handle (two levels, additive): one PCG per system as
+// in krylov_seg, every system's scalars on the device (S[slot * ns + k]) and
+// the same per-system kernels, so that each system's iterates are those of the
+// host loop bit for bit; a system that has stopped takes zero steps
+// (alpha = beta = 0), as it does there.
+__global__ void k_s_alpha(double* S, int ns) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns) return;
+    double* a = S + G_ALPHA * ns;
+    if (S[G_STATE * ns + k] != 0.0) {
+        a[k] = 0.0;
+        return;
+    }
+    const double v = S[G_RZ * ns + k] / S[G_PQ * ns + k];
+    if (!isfinite(v)) {
+        S[G_STATE * ns + k] = 3.0;
+        a[k] = 0.0;
+        return;
+    }
+    a[k] = v;
+}
+__global__ void k_s_check(double* S, int ns) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns || S[G_STATE * ns + k] != 0.0) return;
+    S[G_ITS * ns + k] += 1.0;
+    if (sqrt(S[G_RN2 * ns + k]) <= S[G_THR * ns + k]) S[G_STATE * ns + k] = 1.0;
+    else if (S[G_ITS * ns + k] >= S[G_MAXIT * ns + k]) S[G_STATE * ns + k] = 2.0;
+}
+__global__ void k_s_beta(double* S, int ns) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns) return;
+    if (S[G_STATE * ns + k] != 0.0) {
+        S[G_BETA * ns + k] = 0.0;
+        return;
+    }
+    S[G_BETA * ns + k] = S[G_RZN * ns + k] / S[G_RZ * ns + k];
+    S[G_RZ * ns + k] = S[G_RZN * ns + k];
+}
+
+static void graph_iteration_seg(Handle& H, double* S, int ns, hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const CsrDev A = Lv.A();
+    const SegView g = seg_of(H, 0);
+    double *x = Lv.kx.p, *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p, *q = Lv.kq.p;
+    const int gs = ceil_div(ns, 64);
+    spmv(A, p, q, 1, s);
+    dot_seg(p, q, g.doff, ns, H.partial.p, S + G_PQ * ns, s);
+    hipLaunchKernelGGL(k_s_alpha, dim3(gs), dim3(64), 0, s, S, ns);
+    hipLaunchKernelGGL(k_axpy2_seg, dim3(vgrid(n)), dim3(256), 0, s, x, r, p, q, S + G_ALPHA * ns, g.sid, n);
+    dot_seg(r, r, g.doff, ns, H.partial.p, S + G_RN2 * ns, s);
+    hipLaunchKernelGGL(k_s_check, dim3(gs), dim3(64), 0, s, S, ns);
+    apply_level(H, 0, r, z, s);
+    dot_seg(r, z, g.doff, ns, H.partial.p, S + G_RZN * ns, s);
+    hipLaunchKernelGGL(k_s_beta, dim3(gs), dim3(64), 0, s, S, ns);
+    hipLaunchKernelGGL(k_xpby_seg, dim3(vgrid(n)), dim3(256), 0, s, z, p, S + G_BETA * ns, g.sid, n);
+    launch_check("graph_pcg_batch");
+}
+
+static int krylov_graph_seg(Handle& H, const double* b, double* xio, double rtol, int maxit, int* iters,
+                            double* relres, hipStream_t s) {
+    Level& Lv = *H.lv[0];
+    const int64_t n = Lv.n;
+    const int ns = H.nsys();
+    const CsrDev A = Lv.A();
+    const SegView g = seg_of(H, 0);
+    const std::vector<int64_t>& off = *g.off;
+    if (!H.gp || H.gp->chunk != H.opt.graph_pcg || H.gp->ns != ns) {
+        H.gp = std::make_unique<GraphPcg>();
+        GraphPcg& G = *H.gp;
+        G.chunk = H.opt.graph_pcg;
+        G.ns = ns;
+        G.S.alloc((size_t)G_NSLOT * ns);
+        DD_HIP(hipHostMalloc(&G.hS, (size_t)G_NSLOT * ns * sizeof(double)));
+        DD_HIP(hipStreamCreateWithFlags(&G.cs, hipStreamNonBlocking));
+        DD_HIP(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
+        try {
+            graph_iteration_seg(H, G.S.p, ns, G.cs);
+        } catch (...) {
+            hipGraph_t gr = nullptr;
+            (void)hipStreamEndCapture(G.cs, &gr);
+            if (gr) (void)hipGraphDestroy(gr);
+            H.gp.reset();
+            throw;
+        }
+        DD_HIP(hipStreamEndCapture(G.cs, &G.graph));
+        DD_HIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+    }
+    GraphPcg& G = *H.gp;
+    double *x = Lv.kx.p, *r = Lv.kr.p, *z = Lv.kz.p, *p = Lv.kp.p;
+    DD_HIP(hipMemcpyAsync(x, xio, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // the start as in krylov_seg
+    std::vector<double> bn = dot_sys(H, g, b, b, s);
+    for (int k = 0; k < ns; ++k) {
+        DD_CHECK(std::isfinite(bn[k]), DD_ERR_NAN, "right-hand side contains NaN/Inf");
+        bn[k] = std::sqrt(bn[k]);
+        if (bn[k] == 0.0 && off[k + 1] > off[k]) fill(x + off[k], off[k + 1] - off[k], 0.0, s);
+    }
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    std::vector<double> rn = dot_sys(H, g, r, r, s);
+    std::vector<int> its(ns, 0);
+    std::vector<char> conv(ns, 0);
+    int left = 0;
+    for (int k = 0; k < ns; ++k) {
+        rn[k] = std::sqrt(rn[k]);
+        conv[k] = (bn[k] == 0.0 || rn[k] <= rtol * bn[k]) ? 1 : 0;
+        left += conv[k] ? 0 : 1;
+    }
+    if (left && maxit > 0) {
+        apply_level(H, 0, r, z, s);
+        DD_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        const std::vector<double> rz = dot_sys(H, g, r, z, s);
+        double* hS = G.hS;
+        std::fill(hS, hS + (size_t)G_NSLOT * ns, 0.0);
+        for (int k = 0; k < ns; ++k) {
+            hS[G_RZ * ns + k] = rz[k];
+            hS[G_THR * ns + k] = rtol * bn[k];
+            hS[G_MAXIT * ns + k] = maxit;
+            hS[G_STATE * ns + k] = conv[k] ? 1.0 : 0.0;
+        }
+        h2d(G.S.p, hS, (size_t)G_NSLOT * ns, s);
+        // batches of replays between host checks, sized from the slowest system's
+        // residual contraction
+        int batch = std::min(2, G.chunk);
+        std::vector<double> rprev(rn);
+        for (;;) {
+            for (int j = 0; j < batch; ++j) DD_HIP(hipGraphLaunch(G.exec, s));
+            d2h(hS, G.S.p, (size_t)G_NSLOT * ns, s);
+            DD_HIP(hipStreamSynchronize(s));
+            bool all = true;
+            double est = 1.0;
+            for (int k = 0; k < ns; ++k) {
+                if (hS[G_STATE * ns + k] != 0.0) continue;
+                all = false;
+                const double rcur = std::sqrt(hS[G_RN2 * ns + k]);
+                const double rate = std::pow(rcur / rprev[k], 1.0 / batch);
+                rprev[k] = rcur;
+                double e = G.chunk;
+                if (rate > 0.0 && rate < 1.0) e = std::log(hS[G_THR * ns + k] / rcur) / std::log(rate);
+                est = std::max(est, e);
+            }
+            if (all) break;
+            batch = (int)std::max(1.0, std::min<double>(G.chunk, std::floor(est)));
+        }
+        for (int k = 0; k < ns; ++k) {
+            DD_CHECK(hS[G_STATE * ns + k] != 3.0, DD_ERR_NAN, "PCG produced NaN");
+            its[k] = (int)hS[G_ITS * ns + k];
+            conv[k] = conv[k] || hS[G_STATE * ns + k] == 1.0;
+        }
+    }
+    // true residual at exit
+    spmv(A, x, r, 1, s);
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(n)), dim3(256), 0, s, b, r, n);
+    const std::vector<double> tr = dot_sys(H, g, r, r, s);
+    bool all = true;
+    for (int k = 0; k < ns; ++k) {
+        const double rel = bn[k] > 0.0 ? std::sqrt(tr[k]) / bn[k] : 0.0;
+        DD_CHECK(std::isfinite(rel), DD_ERR_NAN, "PCG produced NaN");
+        if (iters) iters[k] = its[k];
+        if (relres) relres[k] = rel;
+        all = all && conv[k];
+    }
+    DD_HIP(hipMemcpyAsync(xio, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return all ? DD_OK : DD_WARN_MAXIT;
+}
+
 __global__ void k_copy_add_i32(const int32_t* src, int32_t* dst, int64_t n, int64_t add) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = (int32_t)(src[i] + add);
@@ -3464,9 +3632,11 @@ int dd_pcg(dd_handle h, const double* b, double* x, int32_t nrhs, double rtol, i
         const int ns = H.nsys();
         std::vector<int> it(ns);
         std::vector<double> rr(ns);
+        const bool graph = H.opt.graph_pcg > 0 && H.lv.size() == 1 && H.opt.schwarz == DD_SCHWARZ_ADDITIVE;
         for (int k = 0; k < nrhs; ++k) {
-            const int c = krylov_seg(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true, it.data(),
-                                     rr.data(), s);
+            const int c = graph ? krylov_graph_seg(H, b + k * n, x + k * n, rtol, maxit, it.data(), rr.data(), s)
+                                : krylov_seg(H, 0, b + k * n, x + k * n, rtol, maxit, H.lv.size() > 1, true,
+                                             it.data(), rr.data(), s);
             if (c < 0) return c;
             if (c > 0) rc = c;
             for (int j = 0; j < ns; ++j) {

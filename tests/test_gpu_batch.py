@@ -66,6 +66,32 @@ def test_batch_matches_separate_setups_and_oracle():
     assert len(set(its)) > 1  # the systems stop at their own counts
 
 
+def test_batch_graph_pcg_equals_host_loop():
+    """graph_pcg on a batch handle: the captured iteration with one set of
+    scalars and one stopping test per system gives every system the host
+    loop's iterations, residuals and iterates bit for bit, also with FP32
+    local solves, several right-hand sides and a maxit stop."""
+    from paper_2109_05908_amd import DD_FP32
+    sysl = _systems()
+    As = [DeviceCSR.from_workload(A) for A, _, _ in sysl]
+    parts, Ns = [p for _, p, _ in sysl], [N for _, _, N in sysl]
+    ns = [A.n for A, _, _ in sysl]
+    b = np.stack([np.concatenate([W.rhs(n, 40 + 3 * j + k) for j, n in enumerate(ns)]) for k in range(3)], axis=1)
+    bt = torch.as_tensor(b, device="cuda")
+    for prec in (0, DD_FP32):
+        host = Preconditioner.batch(As, parts, Ns, 1, 0.1, local_prec=prec)
+        graph = Preconditioner.batch(As, parts, Ns, 1, 0.1, local_prec=prec, graph_pcg=8)
+        for maxit, want in ((1000, 0), (3, 1)):
+            log(f"[batch-graph] local_prec={prec} maxit={maxit}")
+            x0, i0, r0, c0 = host.pcg(bt, rtol=1e-10, maxit=maxit)
+            x1, i1, r1, c1 = graph.pcg(bt, rtol=1e-10, maxit=maxit)
+            assert c0 == c1 == want
+            assert i0 == i1 and r0 == r1
+            assert torch.equal(x0, x1)
+            if want == 0:
+                assert len(set(i0[:3])) > 1  # the systems stop at their own counts
+
+
 def test_batch_three_levels_per_system():
     """Three levels: every system's second level is partitioned on its own and
     its inner coarse solves run per system, so each system gets the hierarchy
