@@ -19,6 +19,7 @@ DD_SEL_THRESHOLD, DD_SEL_THRESHOLD_CAP = 0, 1
 DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED = 0, 1
 DD_EIG_DENSE, DD_EIG_LOBPCG, DD_EIG_LOBPCG_MATFREE = 0, 1, 2
 DD_START_RANDOM, DD_START_RANGE, DD_START_MODEL = 0, 1, 2
+DD_ERR_INVALID_ARG, DD_ERR_NOT_SPD, DD_ERR_EIG, DD_ERR_NAN, DD_ERR_OOM, DD_ERR_HIP = -1, -2, -3, -4, -5, -6
 DD_NPHASE = 12
 DD_MAX_LEVELS = 4
 DD_PHIST = 16

@@ -42,3 +42,14 @@ def test_strerror_without_gpu():
     lib.dd_strerror.restype = ctypes.c_char_p
     assert lib.dd_strerror(0) == b"ok"
     assert b"SPD" in lib.dd_strerror(-2)
+
+
+def test_binding_constants_equal_header_defines():
+    """Every numeric #define of the header that the binding mirrors has the same value there."""
+    import paper_2109_05908_amd.binding as B
+    src = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(DD_[A-Z0-9_]+)\s+(-?\d+)\b", src)}
+    mirrored = [k for k in defs if hasattr(B, k)]
+    assert len(mirrored) >= 20
+    for k in mirrored:
+        assert getattr(B, k) == defs[k], k
