@@ -544,9 +544,9 @@ def main():
     import torch
 
     import workloads as W
-    from paper_2109_05908_amd import (DD_EIG_LOBPCG, DD_FP32, DD_FP64, DD_SEL_THRESHOLD_CAP, DD_START_MODEL,
-                                      DD_START_RANDOM, DeviceCSR, Preconditioner, autotune_report, meter_read,
-                                      meter_start, partition_ggg)
+    from paper_2109_05908_amd import (DD_EIG_LOBPCG, DD_FP32, DD_FP64, DD_SCHWARZ_ADDITIVE, DD_SCHWARZ_DEFLATED,
+                                      DD_SEL_THRESHOLD_CAP, DD_START_MODEL, DD_START_RANDOM, DeviceCSR, Preconditioner,
+                                      autotune_report, meter_read, meter_start, partition_ggg)
     from paper_2109_05908_amd.train_warm_start import load_model
 
     dev = "cuda:0"
@@ -568,7 +568,10 @@ def main():
         pre = Preconditioner(dA, part, cfg.N, cfg.overlap, cfg.tau, levels=cfg.levels, **opts)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, its, rr, code = pre.pcg(b, rtol=1e-8, maxit=3000)
+        if opts.get("schwarz", DD_SCHWARZ_ADDITIVE) == DD_SCHWARZ_DEFLATED:  # not symmetric: GMRES(30)
+            x, its, rr, code = pre.gmres(b, rtol=1e-8, maxit=3000, restart=30)
+        else:
+            x, its, rr, code = pre.pcg(b, rtol=1e-8, maxit=3000)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         assert code == 0 and rr[0] <= 1e-8, (code, rr)
@@ -651,6 +654,8 @@ def main():
         forms["learned_fp64_local_graph"], _, _ = run_form("learned_fp64_local", dict(learned, local_prec=DD_FP64),
                                                            cs, 0)
         forms["learned_fp32_host_pcg"], _, _ = run_form("learned_host_pcg", dict(learned, graph_pcg=0), cs, 0)
+        # the deflated variant of the experiments under GMRES(30), with the plain FP64 setup
+        forms["deflated_gmres_fp64"], _, _ = run_form("deflated_gmres", dict(schwarz=DD_SCHWARZ_DEFLATED), cs, 0)
         conf["comparison_form_steps"] = cs
     value = main_res["setup_plus_solve_s"]
     conf.update({
