@@ -11,7 +11,7 @@ namespace dd {
 // Jacobi
 // ===========================================================================
 constexpr int JAC_LD = JAC_MAX + 1;
-constexpr int JAC_THREADS = 256;
+constexpr int JAC_THREADS = 1024;  // one workgroup per CU either way (its LDS): more threads shorten every round
 
 // Round r of the circle method on mp (even) players: pair 0 is (r, mp - 1),
 // pair j >= 1 is ((r + j) mod (mp - 1), (r - j) mod (mp - 1)); every pair of
