@@ -2,7 +2,7 @@
 
 Parity of the block solver against the oracle's dense eigensolver of (3.3)
 with the nev cap, explicit and matrix-free operator:
-* kept counts equal; kept mu >= 1e-6 within 1e-4 relative (north star bar);
+* kept counts equal; kept mu >= 1e-6 within 1e-4 relative (the kept-eigenvalue tolerance);
 * which vectors of a near-kernel cluster the cap keeps is not fixed by the
   method, so the kept span is checked to lie in the oracle's cluster: the span
   of the pencil's eigenvectors with mu below 1e3 times the largest kept mu
