@@ -343,6 +343,26 @@ def tuner_line(name):
     return None
 
 
+def pack_waves(sizes, kinds, cap):
+    """Waves of one kind each (the production form's options depend on the kind), packed first-fit by
+    decreasing size within a kind, at most cap[kind] unknowns per wave (a larger system alone).
+    sizes: (kind, n) per system; returns lists of system indices, ascending within a wave."""
+    waves = []
+    for kind in kinds:
+        bins, room = [], []
+        for j in sorted((j for j in range(len(sizes)) if sizes[j][0] == kind), key=lambda j: -sizes[j][1]):
+            n_j = sizes[j][1]
+            k = next((k for k in range(len(bins)) if room[k] >= n_j), None)
+            if k is None:
+                bins.append([])
+                room.append(cap[kind])
+                k = len(bins) - 1
+            bins[k].append(j)
+            room[k] -= n_j
+        waves += [sorted(w) for w in bins]
+    return waves
+
+
 def main_batch(args):
     """The many-systems workload: every system partitioned by seeded graph growing into parts of
     about 1024 unknowns (elasticity 648), overlap 1, lambda > 50, 2 levels; systems of one kind grouped
@@ -373,21 +393,8 @@ def main_batch(args):
         A = W.batch_system(kind, n_target, seed)
         systems.append((kind, A, max(1, int(round(A.n / per_part.get(kind, 1024))))))
         print(f"[batch] system {j}: {kind} n={A.n} parts={systems[-1][2]}", file=sys.stderr, flush=True)
-    # waves of one kind each (the production form's options depend on the kind), packed first-fit by
-    # decreasing size within a kind
-    waves = []
-    for kind in W.C5_KINDS:
-        bins, room = [], []
-        for j in sorted((j for j in range(len(systems)) if systems[j][0] == kind), key=lambda j: -systems[j][1].n):
-            n_j = systems[j][1].n
-            k = next((k for k in range(len(bins)) if room[k] >= n_j), None)
-            if k is None:
-                bins.append([])
-                room.append(wave_cap.get(kind, args.wave_dofs))
-                k = len(bins) - 1
-            bins[k].append(j)
-            room[k] -= n_j
-        waves += [sorted(w) for w in bins]
+    waves = pack_waves([(kind, A.n) for kind, A, _ in systems], W.C5_KINDS,
+                       {k: wave_cap.get(k, args.wave_dofs) for k in W.C5_KINDS})
     n_total = sum(A.n for _, A, _ in systems)
     print(f"[batch] {len(systems)} systems, n = {n_total}, {len(waves)} waves", file=sys.stderr, flush=True)
 

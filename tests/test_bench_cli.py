@@ -51,3 +51,17 @@ def test_cpu_baseline_pool_on_a_small_case():
     assert out["kind"] == "oracle" and out["cores"] >= 1 and out["value"] > 0
     assert out["setup_s"] > 0 and out["solve_s"] > 0 and out["pcg_iterations_used"] == 17
     assert out["cpu_model"] and out["blas"] and "pool of" in out["sample"]
+
+
+def test_pack_waves_one_kind_each_within_the_cap():
+    sizes = [("a", 300), ("b", 50), ("a", 250), ("a", 600), ("b", 60), ("a", 100), ("b", 500)]
+    waves = bench.pack_waves(sizes, ["a", "b"], {"a": 400, "b": 200})
+    assert sorted(j for w in waves for j in w) == list(range(len(sizes)))   # every system once
+    for w in waves:
+        assert len({sizes[j][0] for j in w}) == 1                           # one kind per wave
+        assert w == sorted(w)
+        total = sum(sizes[j][1] for j in w)
+        cap = 400 if sizes[w[0]][0] == "a" else 200
+        assert total <= cap or len(w) == 1                                  # a larger system alone
+    # first fit by decreasing size: 600 alone, then 300 + 100, then 250
+    assert [sorted(sizes[j][1] for j in w) for w in waves if sizes[w[0]][0] == "a"] == [[600], [100, 300], [250]]
