@@ -62,3 +62,19 @@ def test_sets_and_blocks_at_262144_subdomains():
         Aii_o, X_o = O.extract(A, s)
         np.testing.assert_array_equal(Aii, Aii_o)
         np.testing.assert_array_equal(X, X_o)
+
+
+@pytest.mark.parametrize("overlap", [1, 3])
+def test_sets_bit_exact_at_overlap(overlap):
+    """Gamma_i gathers layers 1..delta (merged and sorted again when delta >= 2): I, Gamma and Delta of every
+    subdomain equal the oracle's on a random graph and on a 3-D diffusion problem."""
+    from paper_2109_05908_amd import Preconditioner
+    for A, N in ((W.random_spd(600, 6, seed=11), 8), (W.diffusion3d(12, seed=2), 12)):
+        part = O.ggg_partition(A, N, 0)
+        log(f"[sets-scale] n={A.n} N={N} overlap={overlap}")
+        pre = Preconditioner(DeviceCSR.from_workload(A), part, N, overlap, 0.1)
+        for i, s in enumerate(O.subdomain_sets(A, part, N, overlap)):
+            I, G, D = pre.sets(i)
+            np.testing.assert_array_equal(I, s.I)
+            np.testing.assert_array_equal(G, s.Gamma)
+            np.testing.assert_array_equal(D, s.Delta)
